@@ -1,0 +1,206 @@
+/*
+ * a2c.h -- C ABI of the MI355X (gfx950) library that maps protein dihedral
+ * angles to atomic Cartesian coordinates and maps coordinate gradients back
+ * to angle gradients.
+ *
+ * Method: Derevyanko & Lamoureux, "TorchProteinLibrary: A computationally
+ * efficient, differentiable representation of protein structure",
+ * arXiv:1812.01108.
+ *   - backbone model ("Backbone model" section): per residue j three
+ *     transforms R(omega_j), R(phi_j), R(psi_j) place N_j, CA_j, C_j;
+ *     r_i = R_0 R_1 ... R_i 0; gradient = the sums of Eq. BackboneGradOutput;
+ *   - full-atom model ("Full-atom model" section): a graph of transforms
+ *     M_i = M_parent(i) R_i acting on standard rigid-group coordinates r°,
+ *     up to 7 dihedrals per residue (phi, psi, omega, chi1..chi4); gradient
+ *     = Eq. FAMBackward;
+ *   - every transform is R(alpha, theta, d) = Ry(theta) Tx(d) Rx(alpha)
+ *     with the 4x4 matrix printed in the backbone section.
+ *
+ * Conventions shared by every call
+ *   - Pointers prefixed d_ are device pointers (hipMalloc'ed or torch CUDA
+ *     tensors); h_ pointers are host memory.  The caller owns every device
+ *     buffer.  The library owns only the plan and the device copies of the
+ *     plan's tables, freed by a2c_plan_destroy.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     a2c_forward and a2c_backward only enqueue kernels on it: they never
+ *     allocate, never synchronise and never read device memory on the host,
+ *     so they may be captured in a hipGraph.  Plan creation, schedule changes
+ *     and autotuning upload tables and synchronise: not capturable.
+ *   - Angles are radians, any range; NaN/Inf propagate unchecked.  Planes:
+ *       0 phi, 1 psi, 2 omega, 3 chi1, 4 chi2, 5 chi3, 6 chi4.
+ *     Layout [K][R] float32, K = 3 (backbone) or 7 (full-atom), R = total
+ *     residues over all chains (chains packed back to back).
+ *   - Coordinates: layout [3][A] float32 (x plane, y plane, z plane), A =
+ *     total atoms.  Backbone: atoms 3j, 3j+1, 3j+2 of residue j are N, CA, C.
+ *     Full-atom: per residue N, CA, C, O, then side-chain atoms in the order
+ *     of the residue table; chain and residue atom offsets come from the plan.
+ *   - Each chain starts from the identity frame: its first N sits at
+ *     (d cos theta, 0, -d sin theta) of the C-N bond transform.
+ *   - Errors are returned, never raised; validation is host-side and happens
+ *     before anything is enqueued.  a2c_last_error() gives a thread-local
+ *     message for the last failing call.
+ *   - A plan is not safe for concurrent calls from several threads.
+ */
+#ifndef A2C_H
+#define A2C_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    A2C_OK = 0,
+    A2C_ERR_INVALID_ARG = -1,  /* bad pointer, size, offset or residue code  */
+    A2C_ERR_UNSUPPORTED = -2,  /* valid input the chosen schedule cannot run */
+    A2C_ERR_WORKSPACE = -3,    /* workspace missing or too small             */
+    A2C_ERR_HIP = -4,          /* a HIP runtime call failed                  */
+    A2C_ERR_STATE = -5         /* call out of order (e.g. no device)         */
+} a2c_status;
+
+typedef enum { A2C_BACKBONE = 0, A2C_FULLATOM = 1 } a2c_model;
+
+/* A2C_SCAN: the library's form -- segmented scans over 3x4 affine transforms
+ *   in registers, whole chains packed into workgroup tiles, O(N) adjoint.
+ * A2C_PLAIN: the paper's GPU design kept as a comparison (backbone only):
+ *   one workgroup per chain, a sequential transform product that stores M_i
+ *   for every atom, and the O(atoms x angles) gradient sum of
+ *   Eq. BackboneGradOutput.  Needs a workspace (a2c_plan_workspace_bytes). */
+typedef enum { A2C_SCAN = 0, A2C_PLAIN = 1 } a2c_variant;
+
+typedef struct a2c_plan a2c_plan;
+
+/* Backbone geometry, named by bonded atoms and by the vertex of each angle.
+ * The transform placing N_j uses bond C-N and theta = pi - angle(CA-C-N);
+ * the one placing CA_j uses N-CA and pi - angle(C-N-CA); the one placing C_j
+ * uses CA-C and pi - angle(N-CA-C).  Lengths in Angstrom, angles in degrees.
+ * NULL where a geometry is accepted means: 1.458, 1.525, 1.329 A and
+ * 111.2, 116.2, 121.7 degrees. */
+typedef struct {
+    double bond_n_ca, bond_ca_c, bond_c_n;
+    double angle_n_ca_c, angle_ca_c_n, angle_c_n_ca;
+} a2c_backbone_geometry;
+
+/* ---- full-atom residue table ------------------------------------------ *
+ * The paper's per-residue graph: spine frames 0 (N, placed by omega),
+ * 1 (CA, by phi), 2 (C, by psi) use the backbone geometry; side-chain frames
+ * 3..6 hang off CA or off an earlier side frame.  Each residue type lists
+ * its atoms in output order with the frame they belong to and their
+ * standard position r° in that frame, given as internal coordinates that
+ * the library converts to Cartesian r° at plan creation.               */
+#define A2C_NUM_RESIDUE_TYPES 20
+#define A2C_MAX_SIDE_FRAMES 4
+#define A2C_MAX_RESIDUE_ATOMS 14
+
+typedef struct {
+    int32_t parent;            /* 1 = CA frame, 3.. = earlier side frame      */
+    int32_t chi;               /* 1..4: torsion is chi_k (plane 2+k); 0: fixed 0 */
+    double pre_rotation_deg;   /* fixed rotation about the parent's x axis
+                                  applied before the transform (R' of the
+                                  threonine example); 0 for none           */
+    double bond;               /* parent origin atom -> this origin atom (A)  */
+    double bond_angle_deg;     /* angle (parent's predecessor, parent origin,
+                                  this origin)                               */
+} a2c_side_frame;
+
+/* Atom kinds: */
+#define A2C_ATOM_ORIGIN 0      /* at the frame origin                          */
+#define A2C_ATOM_AZIMUTH 1     /* bonded to the frame origin: length `bond`,
+                                  angle (predecessor, origin, atom) = `angle`,
+                                  torsion = frame torsion + `torsion`          */
+#define A2C_ATOM_ZMATRIX 2     /* from atoms ref[0..2] of the same frame (-1 =
+                                  the frame's predecessor atom): |ref2 - a| =
+                                  bond, angle(ref1, ref2, a) = angle,
+                                  torsion(ref0, ref1, ref2, a) = torsion      */
+typedef struct {
+    int32_t frame;             /* 0 N, 1 CA, 2 C, 3 + f = side frame f        */
+    int32_t kind;              /* A2C_ATOM_*                                   */
+    int32_t ref[3];            /* atom indices within the residue, or -1      */
+    double bond, angle_deg, torsion_deg;
+} a2c_atom_def;
+
+typedef struct {
+    int32_t n_atoms;           /* heavy atoms incl. N, CA, C, O (<= 14)        */
+    int32_t n_side_frames;     /* 0 .. 4                                        */
+    a2c_side_frame frames[A2C_MAX_SIDE_FRAMES];
+    a2c_atom_def atoms[A2C_MAX_RESIDUE_ATOMS];
+} a2c_residue_def;
+
+typedef struct {
+    a2c_residue_def residues[A2C_NUM_RESIDUE_TYPES];
+} a2c_residue_table;
+
+/* Create a plan for one packed batch of chains.
+ *   h_res_offsets  host int32[n_chains + 1]: [0] = 0, non-decreasing, last =
+ *                  R.  Zero-length chains are allowed and produce nothing.
+ *   h_seq          host uint8[R] residue codes 0..19 (table order); required
+ *                  for A2C_FULLATOM, ignored (may be NULL) for A2C_BACKBONE.
+ *   geom           backbone geometry or NULL for the defaults above.
+ *   table          residue table, required for A2C_FULLATOM.
+ *   stream         used for the table uploads; the call synchronises it.
+ * Fails with A2C_ERR_INVALID_ARG on malformed offsets or codes >= 20, and
+ * with A2C_ERR_UNSUPPORTED if a chain is longer than the longest tile the
+ * kernels can hold (4096 residues).  *out is NULL on failure.            */
+a2c_status a2c_plan_create(a2c_plan **out, a2c_model model, int32_t n_chains,
+                           const int32_t *h_res_offsets, const uint8_t *h_seq,
+                           const a2c_backbone_geometry *geom,
+                           const a2c_residue_table *table, void *stream);
+
+void a2c_plan_destroy(a2c_plan *plan);
+
+/* Total residues R and atoms A of the plan. */
+a2c_status a2c_plan_sizes(const a2c_plan *plan, int64_t *n_res, int64_t *n_atoms);
+
+/* Atom offsets: h_chain_atom_offsets int32[n_chains + 1] (may be NULL),
+ * h_res_atom_offsets int32[R + 1] (may be NULL). */
+a2c_status a2c_plan_atom_offsets(const a2c_plan *plan, int32_t *h_chain_atom_offsets,
+                                 int32_t *h_res_atom_offsets);
+
+/* Device workspace a variant needs (0 for A2C_SCAN; 48 bytes per atom for
+ * A2C_PLAIN, which stores M_i for every atom as the paper's forward does). */
+a2c_status a2c_plan_workspace_bytes(const a2c_plan *plan, a2c_variant variant,
+                                    size_t *bytes);
+
+/* Scan schedule: residues per lane (1, 2 or 4) and waves of 64 lanes per
+ * workgroup (1..16).  Whole chains are packed into tiles of at most
+ * 64 * waves * res_per_lane residues, one tile per workgroup.  Re-packs and
+ * re-uploads the tile table (synchronises `stream`).  UNSUPPORTED if some
+ * chain does not fit one tile. */
+a2c_status a2c_plan_set_schedule(a2c_plan *plan, int32_t res_per_lane,
+                                 int32_t waves_per_group, void *stream);
+a2c_status a2c_plan_get_schedule(const a2c_plan *plan, int32_t *res_per_lane,
+                                 int32_t *waves_per_group, int32_t *n_tiles);
+
+/* Forward map: d_angles [K][R] -> d_coords [3][A].
+ * d_workspace: NULL for A2C_SCAN; for A2C_PLAIN a buffer of
+ * a2c_plan_workspace_bytes that a2c_backward(A2C_PLAIN) reads later. */
+a2c_status a2c_forward(a2c_plan *plan, a2c_variant variant, const float *d_angles,
+                       float *d_coords, void *d_workspace, void *stream);
+
+/* Adjoint: given d_grad_coords = dL/dr [3][A], writes dL/dalpha [K][R]
+ * (every plane; chi planes a residue lacks are written as 0).
+ *   d_coords   the coordinates a2c_forward produced from the same angles, or
+ *              NULL: A2C_SCAN then recomputes the frames from the angles
+ *              inside the backward kernel (nothing is stored between the two
+ *              passes).  A2C_PLAIN requires the workspace its forward filled.
+ * The result is exact up to float32 rounding: for angle alpha_i of node i,
+ *   dL/dalpha_i = u_i . sum_{k in subtree(i)} (r_k - r_i) x dL/dr_k,
+ * u_i the unit bond vector the node rotates about, which equals the sums of
+ * Eq. BackboneGradOutput / Eq. FAMBackward. */
+a2c_status a2c_backward(a2c_plan *plan, a2c_variant variant, const float *d_angles,
+                        const float *d_coords, const float *d_grad_coords,
+                        float *d_grad_angles, void *d_workspace, void *stream);
+
+const char *a2c_status_string(a2c_status status);
+const char *a2c_last_error(void);
+
+/* Library version string, e.g. "a2c 0.1 gfx950". */
+const char *a2c_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* A2C_H */

@@ -1,0 +1,217 @@
+"""Dihedral angles -> Cartesian coordinates on MI355X (gfx950).
+
+Thin Python binding over the C ABI of libangles2coords.so (include/a2c.h):
+argument marshalling only; every step of the map runs in the HIP kernels.
+PyTorch supplies device memory and the current stream.
+
+    plan = Plan("backbone", lengths=[700] * 256)
+    coords = angles_to_coords(angles, plan)      # angles [3][R] -> coords [3][A]
+    coords.backward(grad)                        # angle gradient via the adjoint
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import A2C_BACKBONE, A2C_FULLATOM, A2C_PLAIN, A2C_SCAN, A2CError, check
+
+__all__ = ["Plan", "Angles2Coords", "angles_to_coords", "A2CError", "library_version",
+           "DEFAULT_GEOMETRY"]
+
+DEFAULT_GEOMETRY = {
+    "bond_N_CA": 1.458, "bond_CA_C": 1.525, "bond_C_N": 1.329,
+    "angle_N_CA_C": 111.2, "angle_CA_C_N": 116.2, "angle_C_N_CA": 121.7,
+}
+
+_VARIANTS = {"scan": A2C_SCAN, "plain": A2C_PLAIN}
+
+
+def library_version() -> str:
+    return _lib.load().a2c_version().decode()
+
+
+def _stream_ptr(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _geometry_struct(geom: dict | None):
+    if geom is None:
+        return None
+    return _lib.BackboneGeometry(geom["bond_N_CA"], geom["bond_CA_C"], geom["bond_C_N"],
+                                 geom["angle_N_CA_C"], geom["angle_CA_C_N"],
+                                 geom["angle_C_N_CA"])
+
+
+class Plan:
+    """A packed batch of chains: residue offsets, sequence (full-atom), the
+    device tables and the scan schedule.  Create once, reuse for every call
+    on batches of the same shape."""
+
+    def __init__(self, model: str = "backbone", lengths=None, offsets=None, seq=None,
+                 geometry: dict | None = None, table=None, device=None):
+        lib = _lib.load()
+        if model not in ("backbone", "fullatom"):
+            raise ValueError(f"unknown model {model!r}")
+        if (lengths is None) == (offsets is None):
+            raise ValueError("give exactly one of lengths or offsets")
+        if offsets is None:
+            lengths = np.asarray(lengths, dtype=np.int64)
+            offsets = np.zeros(len(lengths) + 1, dtype=np.int64)
+            offsets[1:] = np.cumsum(lengths)
+        off = np.ascontiguousarray(offsets, dtype=np.int32)
+        self.model = model
+        self.n_chains = len(off) - 1
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None \
+            else torch.device(device)
+        self.offsets = off
+        self.n_planes = 3 if model == "backbone" else 7
+        seq_arr = None
+        table_struct = None
+        if model == "fullatom":
+            if seq is None:
+                raise ValueError("the full-atom model needs a residue sequence")
+            seq_arr = np.ascontiguousarray(seq, dtype=np.uint8)
+            if table is None:
+                from .residues import default_table
+                table = default_table()
+            table_struct = table.to_struct() if hasattr(table, "to_struct") else table
+        self._seq = seq_arr
+        self._table = table_struct
+        geom = _geometry_struct(geometry)
+        handle = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            st = lib.a2c_plan_create(
+                ctypes.byref(handle), A2C_BACKBONE if model == "backbone" else A2C_FULLATOM,
+                self.n_chains, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                None if seq_arr is None else seq_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                None if geom is None else ctypes.byref(geom),
+                None if table_struct is None else ctypes.byref(table_struct),
+                _stream_ptr(self.device))
+        check(st, "a2c_plan_create")
+        self._h = handle
+        n_res, n_atoms = ctypes.c_int64(), ctypes.c_int64()
+        check(lib.a2c_plan_sizes(self._h, ctypes.byref(n_res), ctypes.byref(n_atoms)),
+              "a2c_plan_sizes")
+        self.n_res, self.n_atoms = n_res.value, n_atoms.value
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib.load().a2c_plan_destroy(h)
+            self._h = None
+
+    # -- plan queries ------------------------------------------------------
+    def atom_offsets(self):
+        """(chain atom offsets [n_chains+1], residue atom offsets [R+1])."""
+        ca = np.zeros(self.n_chains + 1, dtype=np.int32)
+        ra = np.zeros(self.n_res + 1, dtype=np.int32)
+        check(_lib.load().a2c_plan_atom_offsets(
+            self._h, ca.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+            ra.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))), "a2c_plan_atom_offsets")
+        return ca, ra
+
+    def workspace_bytes(self, variant: str = "scan") -> int:
+        n = ctypes.c_size_t()
+        check(_lib.load().a2c_plan_workspace_bytes(self._h, _VARIANTS[variant], ctypes.byref(n)),
+              "a2c_plan_workspace_bytes")
+        return n.value
+
+    def new_workspace(self, variant: str = "scan"):
+        n = self.workspace_bytes(variant)
+        if n == 0:
+            return None
+        return torch.empty(n // 4, dtype=torch.float32, device=self.device)
+
+    @property
+    def schedule(self):
+        k, w, t = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        check(_lib.load().a2c_plan_get_schedule(self._h, ctypes.byref(k), ctypes.byref(w),
+                                                ctypes.byref(t)), "a2c_plan_get_schedule")
+        return {"res_per_lane": k.value, "waves_per_group": w.value, "n_tiles": t.value}
+
+    def set_schedule(self, res_per_lane: int, waves_per_group: int):
+        with torch.cuda.device(self.device):
+            check(_lib.load().a2c_plan_set_schedule(self._h, res_per_lane, waves_per_group,
+                                                    _stream_ptr(self.device)),
+                  "a2c_plan_set_schedule")
+
+    # -- raw calls (no autograd) ------------------------------------------
+    def _check_tensor(self, t, shape, name):
+        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()
+                and tuple(t.shape) == tuple(shape)):
+            raise ValueError(f"{name} must be a contiguous float32 CUDA tensor of shape {shape}, "
+                             f"got {tuple(t.shape)} {t.dtype} on {t.device}")
+
+    def forward(self, angles: torch.Tensor, coords: torch.Tensor | None = None,
+                variant: str = "scan", workspace: torch.Tensor | None = None) -> torch.Tensor:
+        self._check_tensor(angles, (self.n_planes, self.n_res), "angles")
+        if coords is None:
+            coords = torch.empty((3, self.n_atoms), dtype=torch.float32, device=angles.device)
+        self._check_tensor(coords, (3, self.n_atoms), "coords")
+        check(_lib.load().a2c_forward(
+            self._h, _VARIANTS[variant], ctypes.c_void_p(angles.data_ptr()),
+            ctypes.c_void_p(coords.data_ptr()),
+            None if workspace is None else ctypes.c_void_p(workspace.data_ptr()),
+            _stream_ptr(angles.device)), "a2c_forward")
+        return coords
+
+    def backward(self, angles: torch.Tensor, grad_coords: torch.Tensor,
+                 coords: torch.Tensor | None = None, grad_angles: torch.Tensor | None = None,
+                 variant: str = "scan", workspace: torch.Tensor | None = None) -> torch.Tensor:
+        self._check_tensor(angles, (self.n_planes, self.n_res), "angles")
+        self._check_tensor(grad_coords, (3, self.n_atoms), "grad_coords")
+        if coords is not None:
+            self._check_tensor(coords, (3, self.n_atoms), "coords")
+        if grad_angles is None:
+            grad_angles = torch.empty_like(angles)
+        self._check_tensor(grad_angles, (self.n_planes, self.n_res), "grad_angles")
+        check(_lib.load().a2c_backward(
+            self._h, _VARIANTS[variant], ctypes.c_void_p(angles.data_ptr()),
+            None if coords is None else ctypes.c_void_p(coords.data_ptr()),
+            ctypes.c_void_p(grad_coords.data_ptr()), ctypes.c_void_p(grad_angles.data_ptr()),
+            None if workspace is None else ctypes.c_void_p(workspace.data_ptr()),
+            _stream_ptr(angles.device)), "a2c_backward")
+        return grad_angles
+
+
+class Angles2Coords(torch.autograd.Function):
+    """coords = Angles2Coords.apply(angles, plan, mode).
+
+    mode "coords": the backward reads the forward's coordinates (saved);
+    mode "recompute": the backward recomputes every frame from the angles and
+    nothing but the angles is kept between the passes;
+    mode "plain": the paper's GPU design (stores M_i per atom in a workspace).
+    """
+
+    @staticmethod
+    def forward(ctx, angles, plan: Plan, mode: str = "coords"):
+        angles = angles.contiguous()
+        ws = plan.new_workspace("plain") if mode == "plain" else None
+        variant = "plain" if mode == "plain" else "scan"
+        coords = plan.forward(angles, variant=variant, workspace=ws)
+        ctx.plan = plan
+        ctx.mode = mode
+        ctx.ws = ws
+        if mode == "coords":
+            ctx.save_for_backward(angles, coords)
+        else:
+            ctx.save_for_backward(angles)
+        return coords
+
+    @staticmethod
+    def backward(ctx, grad_coords):
+        plan, mode = ctx.plan, ctx.mode
+        saved = ctx.saved_tensors
+        angles = saved[0]
+        coords = saved[1] if mode == "coords" else None
+        variant = "plain" if mode == "plain" else "scan"
+        grad = plan.backward(angles, grad_coords.contiguous(), coords=coords, variant=variant,
+                             workspace=ctx.ws)
+        return grad, None, None
+
+
+def angles_to_coords(angles: torch.Tensor, plan: Plan, mode: str = "coords") -> torch.Tensor:
+    return Angles2Coords.apply(angles, plan, mode)

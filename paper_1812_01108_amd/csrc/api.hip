@@ -1,0 +1,379 @@
+// Host side of the C ABI declared in include/a2c.h: argument validation,
+// plan construction (tile packing, head bits, geometry constants, full-atom
+// tables) and kernel dispatch.  No call here that can be captured allocates
+// or synchronises.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "a2c_internal.h"
+
+namespace a2c {
+
+namespace {
+thread_local std::string g_last_error;
+
+a2c_status fail(a2c_status st, const std::string &msg)
+{
+    g_last_error = msg;
+    return st;
+}
+
+// The float32 (c, s) pair within +-2 ulps of (cos t, sin t) whose squared
+// norm is closest to 1 (ties broken by the angle error).  Independent
+// rounding of cos and sin leaves c^2 + s^2 - 1 ~ 1e-7, a scale error that
+// every residue repeats; the pair search makes it ~1e-9.
+void unit_pair(double t, float &c_out, float &s_out)
+{
+    const float c0 = (float)std::cos(t), s0 = (float)std::sin(t);
+    double best = std::numeric_limits<double>::infinity();
+    c_out = c0;
+    s_out = s0;
+    float cs[5], ss[5];
+    cs[2] = c0;
+    ss[2] = s0;
+    cs[3] = std::nextafter(c0, 2.f); cs[4] = std::nextafter(cs[3], 2.f);
+    cs[1] = std::nextafter(c0, -2.f); cs[0] = std::nextafter(cs[1], -2.f);
+    ss[3] = std::nextafter(s0, 2.f); ss[4] = std::nextafter(ss[3], 2.f);
+    ss[1] = std::nextafter(s0, -2.f); ss[0] = std::nextafter(ss[1], -2.f);
+    for (float c : cs)
+        for (float s : ss) {
+            const double e = std::fabs((double)c * c + (double)s * s - 1.0) +
+                             1e-3 * std::fabs(std::atan2((double)s, (double)c) - t);
+            if (e < best) {
+                best = e;
+                c_out = c;
+                s_out = s;
+            }
+        }
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+bool valid_angle(double v) { return std::isfinite(v) && v > 0.0 && v < 180.0; }
+
+a2c_status upload(void **dst, const void *src, size_t bytes, hipStream_t s)
+{
+    if (*dst) {
+        (void)hipFree(*dst);
+        *dst = nullptr;
+    }
+    if (bytes == 0) return A2C_OK;
+    hipError_t e = hipMalloc(dst, bytes);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+    e = hipMemcpyAsync(*dst, src, bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+    return A2C_OK;
+}
+
+// Greedy packing of whole chains, in order, into tiles of at most `cap`
+// residues.  Zero-length chains produce nothing and never open a tile.
+std::vector<int32_t> pack_tiles(const std::vector<int32_t> &off, int64_t cap)
+{
+    std::vector<int32_t> tiles;
+    const size_t n = off.size() - 1;
+    int64_t cur = 0;
+    tiles.push_back(0);
+    for (size_t c = 0; c < n; ++c) {
+        const int64_t L = off[c + 1] - off[c];
+        if (L == 0) continue;
+        if (cur > 0 && cur + L > cap) {
+            tiles.push_back(off[c]);
+            cur = 0;
+        }
+        cur += L;
+    }
+    if (cur > 0) tiles.push_back(off[n]);
+    if (tiles.size() == 1) tiles.clear();  // no residues
+    return tiles;
+}
+
+a2c_status apply_schedule(a2c_plan *p, int32_t K, int32_t W, hipStream_t s)
+{
+    const int64_t cap = (int64_t)kWave * W * K;
+    if (p->max_len > cap)
+        return fail(A2C_ERR_UNSUPPORTED, "a chain of " + std::to_string(p->max_len) +
+                                             " residues does not fit a tile of " +
+                                             std::to_string(cap));
+    std::vector<int32_t> tiles = pack_tiles(p->res_off, cap);
+    p->K = K;
+    p->W = W;
+    p->n_tiles = tiles.empty() ? 0 : (int32_t)tiles.size() - 1;
+    a2c_status st = upload((void **)&p->d_tile_res, tiles.data(), tiles.size() * sizeof(int32_t), s);
+    if (st != A2C_OK) return st;
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    return A2C_OK;
+}
+
+void default_schedule(const a2c_plan &p, int32_t &K, int32_t &W)
+{
+    K = 4;
+    const int64_t per_wave = (int64_t)kWave * K;
+    W = (int32_t)std::max<int64_t>(1, (p.max_len + per_wave - 1) / per_wave);
+}
+
+bool check_device(const a2c_plan *p)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    return dev == p->device;
+}
+
+}  // namespace
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+a2c_status hip_fail(hipError_t e, const char *what)
+{
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return A2C_ERR_HIP;
+}
+
+a2c_status build_fullatom_tables(a2c_plan *p, const a2c_residue_table *table);
+
+}  // namespace a2c
+
+using namespace a2c;
+
+extern "C" {
+
+const char *a2c_version(void) { return "a2c 0.1 gfx950"; }
+
+const char *a2c_status_string(a2c_status st)
+{
+    switch (st) {
+    case A2C_OK: return "ok";
+    case A2C_ERR_INVALID_ARG: return "invalid argument";
+    case A2C_ERR_UNSUPPORTED: return "unsupported";
+    case A2C_ERR_WORKSPACE: return "workspace missing or too small";
+    case A2C_ERR_HIP: return "HIP runtime error";
+    case A2C_ERR_STATE: return "invalid state";
+    }
+    return "unknown status";
+}
+
+const char *a2c_last_error(void) { return g_last_error.c_str(); }
+
+void a2c_plan_destroy(a2c_plan *p)
+{
+    if (!p) return;
+    (void)hipFree(p->d_tile_res);
+    (void)hipFree(p->d_head_bits);
+    (void)hipFree(p->d_res_off);
+    (void)hipFree(p->d_res_atom_off);
+    (void)hipFree(p->d_seq);
+    (void)hipFree(p->d_fa);
+    delete p;
+}
+
+a2c_status a2c_plan_create(a2c_plan **out, a2c_model model, int32_t n_chains,
+                           const int32_t *h_res_offsets, const uint8_t *h_seq,
+                           const a2c_backbone_geometry *geom, const a2c_residue_table *table,
+                           void *stream)
+{
+    if (!out) return fail(A2C_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (model != A2C_BACKBONE && model != A2C_FULLATOM)
+        return fail(A2C_ERR_INVALID_ARG, "unknown model");
+    if (n_chains < 0) return fail(A2C_ERR_INVALID_ARG, "n_chains < 0");
+    if (!h_res_offsets) return fail(A2C_ERR_INVALID_ARG, "h_res_offsets is NULL");
+    if (h_res_offsets[0] != 0) return fail(A2C_ERR_INVALID_ARG, "h_res_offsets[0] != 0");
+    int32_t max_len = 0;
+    for (int32_t c = 0; c < n_chains; ++c) {
+        const int64_t L = (int64_t)h_res_offsets[c + 1] - h_res_offsets[c];
+        if (L < 0)
+            return fail(A2C_ERR_INVALID_ARG,
+                        "h_res_offsets decreases at chain " + std::to_string(c));
+        max_len = std::max<int32_t>(max_len, (int32_t)L);
+    }
+    const int64_t R = h_res_offsets[n_chains];
+    if (R > (int64_t)std::numeric_limits<int32_t>::max() / 16)
+        return fail(A2C_ERR_UNSUPPORTED, "too many residues for int32 atom offsets");
+    if (max_len > kMaxTileResidues)
+        return fail(A2C_ERR_UNSUPPORTED, "chain longer than " + std::to_string(kMaxTileResidues) +
+                                             " residues");
+    if (model == A2C_FULLATOM) {
+        if (!table) return fail(A2C_ERR_INVALID_ARG, "full-atom plan needs a residue table");
+        if (R > 0 && !h_seq) return fail(A2C_ERR_INVALID_ARG, "full-atom plan needs h_seq");
+        for (int64_t r = 0; r < R; ++r)
+            if (h_seq[r] >= A2C_NUM_RESIDUE_TYPES)
+                return fail(A2C_ERR_INVALID_ARG, "residue code " + std::to_string(h_seq[r]) +
+                                                     " >= 20 at residue " + std::to_string(r));
+    }
+    a2c_backbone_geometry g = {1.458, 1.525, 1.329, 111.2, 116.2, 121.7};
+    if (geom) g = *geom;
+    if (!finite_pos(g.bond_n_ca) || !finite_pos(g.bond_ca_c) || !finite_pos(g.bond_c_n) ||
+        !valid_angle(g.angle_n_ca_c) || !valid_angle(g.angle_ca_c_n) ||
+        !valid_angle(g.angle_c_n_ca))
+        return fail(A2C_ERR_INVALID_ARG, "backbone geometry out of range");
+
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    hipStream_t s = (hipStream_t)stream;
+
+    a2c_plan *p = new a2c_plan();
+    p->model = model;
+    p->device = dev;
+    p->n_chains = n_chains;
+    p->R = R;
+    p->max_len = max_len;
+    p->res_off.assign(h_res_offsets, h_res_offsets + n_chains + 1);
+    // slot constants (N, CA, C): bond to the previous atom and the bond angle
+    // at the previous atom; theta = pi - angle
+    const double pi = 3.14159265358979323846;
+    const double bond[3] = {g.bond_c_n, g.bond_n_ca, g.bond_ca_c};
+    const double angle[3] = {g.angle_ca_c_n, g.angle_c_n_ca, g.angle_n_ca_c};
+    for (int k = 0; k < 3; ++k) {
+        unit_pair(pi - angle[k] * (pi / 180.0), p->bb.ct[k], p->bb.st[k]);
+        p->bb.d[k] = (float)bond[k];
+        p->bb.inv_d[k] = (float)(1.0 / bond[k]);
+    }
+
+    a2c_status st = A2C_OK;
+    if (model == A2C_BACKBONE) {
+        p->A = 3 * R;
+        p->chain_atom_off.resize(n_chains + 1);
+        for (int32_t c = 0; c <= n_chains; ++c) p->chain_atom_off[c] = 3 * h_res_offsets[c];
+    } else {
+        p->seq.assign(h_seq, h_seq + R);
+        st = build_fullatom_tables(p, table);
+        if (st != A2C_OK) {
+            a2c_plan_destroy(p);
+            return st;
+        }
+    }
+    // chain-head bits, padded by two words so a lane may read one word past
+    std::vector<uint32_t> bits((size_t)((R + 64) / 32 + 2), 0u);
+    for (int32_t c = 0; c < n_chains; ++c)
+        if (h_res_offsets[c + 1] > h_res_offsets[c])
+            bits[h_res_offsets[c] >> 5] |= 1u << (h_res_offsets[c] & 31);
+    bits[R >> 5] |= 1u << (R & 31);
+    st = upload((void **)&p->d_head_bits, bits.data(), bits.size() * sizeof(uint32_t), s);
+    if (st == A2C_OK)
+        st = upload((void **)&p->d_res_off, p->res_off.data(), p->res_off.size() * sizeof(int32_t), s);
+    if (st == A2C_OK && model == A2C_FULLATOM) {
+        st = upload((void **)&p->d_res_atom_off, p->res_atom_off.data(),
+                    p->res_atom_off.size() * sizeof(int32_t), s);
+        if (st == A2C_OK) st = upload((void **)&p->d_seq, p->seq.data(), p->seq.size(), s);
+        if (st == A2C_OK) st = upload((void **)&p->d_fa, &p->fa_host, sizeof(FATable), s);
+    }
+    if (st == A2C_OK) {
+        int32_t K, W;
+        default_schedule(*p, K, W);
+        st = apply_schedule(p, K, W, s);
+    }
+    if (st != A2C_OK) {
+        a2c_plan_destroy(p);
+        return st;
+    }
+    *out = p;
+    return A2C_OK;
+}
+
+a2c_status a2c_plan_sizes(const a2c_plan *p, int64_t *n_res, int64_t *n_atoms)
+{
+    if (!p) return fail(A2C_ERR_INVALID_ARG, "plan is NULL");
+    if (n_res) *n_res = p->R;
+    if (n_atoms) *n_atoms = p->A;
+    return A2C_OK;
+}
+
+a2c_status a2c_plan_atom_offsets(const a2c_plan *p, int32_t *h_chain_atom_offsets,
+                                 int32_t *h_res_atom_offsets)
+{
+    if (!p) return fail(A2C_ERR_INVALID_ARG, "plan is NULL");
+    if (h_chain_atom_offsets)
+        std::memcpy(h_chain_atom_offsets, p->chain_atom_off.data(),
+                    p->chain_atom_off.size() * sizeof(int32_t));
+    if (h_res_atom_offsets) {
+        if (p->model == A2C_BACKBONE)
+            for (int64_t r = 0; r <= p->R; ++r) h_res_atom_offsets[r] = (int32_t)(3 * r);
+        else
+            std::memcpy(h_res_atom_offsets, p->res_atom_off.data(),
+                        p->res_atom_off.size() * sizeof(int32_t));
+    }
+    return A2C_OK;
+}
+
+a2c_status a2c_plan_workspace_bytes(const a2c_plan *p, a2c_variant v, size_t *bytes)
+{
+    if (!p || !bytes) return fail(A2C_ERR_INVALID_ARG, "plan or bytes is NULL");
+    if (v == A2C_SCAN) *bytes = 0;
+    else if (v == A2C_PLAIN) *bytes = (size_t)p->A * 12 * sizeof(float);
+    else return fail(A2C_ERR_INVALID_ARG, "unknown variant");
+    return A2C_OK;
+}
+
+a2c_status a2c_plan_set_schedule(a2c_plan *p, int32_t K, int32_t W, void *stream)
+{
+    if (!p) return fail(A2C_ERR_INVALID_ARG, "plan is NULL");
+    if (!(K == 1 || K == 2 || K == 4))
+        return fail(A2C_ERR_INVALID_ARG, "res_per_lane must be 1, 2 or 4");
+    if (W < 1 || W > kMaxWaves) return fail(A2C_ERR_INVALID_ARG, "waves_per_group must be 1..16");
+    if (!check_device(p)) return fail(A2C_ERR_STATE, "current device is not the plan's device");
+    return apply_schedule(p, K, W, (hipStream_t)stream);
+}
+
+a2c_status a2c_plan_get_schedule(const a2c_plan *p, int32_t *K, int32_t *W, int32_t *n_tiles)
+{
+    if (!p) return fail(A2C_ERR_INVALID_ARG, "plan is NULL");
+    if (K) *K = p->K;
+    if (W) *W = p->W;
+    if (n_tiles) *n_tiles = p->n_tiles;
+    return A2C_OK;
+}
+
+a2c_status a2c_forward(a2c_plan *p, a2c_variant v, const float *d_angles, float *d_coords,
+                       void *d_workspace, void *stream)
+{
+    if (!p) return fail(A2C_ERR_INVALID_ARG, "plan is NULL");
+    if (v != A2C_SCAN && v != A2C_PLAIN) return fail(A2C_ERR_INVALID_ARG, "unknown variant");
+    if (v == A2C_PLAIN && p->model != A2C_BACKBONE)
+        return fail(A2C_ERR_UNSUPPORTED, "the plain form is the backbone comparison only");
+    if (p->R == 0) return A2C_OK;
+    if (!d_angles || !d_coords) return fail(A2C_ERR_INVALID_ARG, "NULL angles or coords");
+    if (v == A2C_PLAIN && !d_workspace)
+        return fail(A2C_ERR_WORKSPACE, "the plain form stores M_i in the workspace");
+    if (!check_device(p)) return fail(A2C_ERR_STATE, "current device is not the plan's device");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    if (v == A2C_PLAIN) e = launch_bb_forward_plain(*p, d_angles, d_coords, (float *)d_workspace, s);
+    else if (p->model == A2C_BACKBONE) e = launch_bb_forward_scan(*p, d_angles, d_coords, s);
+    else e = launch_fa_forward_scan(*p, d_angles, d_coords, s);
+    if (e != hipSuccess) return hip_fail(e, "forward launch");
+    return A2C_OK;
+}
+
+a2c_status a2c_backward(a2c_plan *p, a2c_variant v, const float *d_angles, const float *d_coords,
+                        const float *d_grad_coords, float *d_grad_angles, void *d_workspace,
+                        void *stream)
+{
+    if (!p) return fail(A2C_ERR_INVALID_ARG, "plan is NULL");
+    if (v != A2C_SCAN && v != A2C_PLAIN) return fail(A2C_ERR_INVALID_ARG, "unknown variant");
+    if (v == A2C_PLAIN && p->model != A2C_BACKBONE)
+        return fail(A2C_ERR_UNSUPPORTED, "the plain form is the backbone comparison only");
+    if (p->R == 0) return A2C_OK;
+    if (!d_grad_coords || !d_grad_angles)
+        return fail(A2C_ERR_INVALID_ARG, "NULL grad_coords or grad_angles");
+    if (!d_angles) return fail(A2C_ERR_INVALID_ARG, "NULL angles");
+    if (v == A2C_PLAIN && !d_workspace)
+        return fail(A2C_ERR_WORKSPACE, "the plain backward reads the M_i its forward stored");
+    if (!check_device(p)) return fail(A2C_ERR_STATE, "current device is not the plan's device");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    if (v == A2C_PLAIN)
+        e = launch_bb_backward_plain(*p, d_angles, d_grad_coords, d_grad_angles,
+                                     (const float *)d_workspace, s);
+    else if (p->model == A2C_BACKBONE)
+        e = launch_bb_backward_scan(*p, d_angles, d_coords, d_grad_coords, d_grad_angles, s);
+    else
+        e = launch_fa_backward_scan(*p, d_angles, d_coords, d_grad_coords, d_grad_angles, s);
+    if (e != hipSuccess) return hip_fail(e, "backward launch");
+    return A2C_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,599 @@
+// Backbone model ("Backbone model" section of the paper) on gfx950.
+//
+// Scan form.  Whole chains are packed into tiles; one workgroup of W waves
+// owns one tile and each lane owns K consecutive residues (3K transforms).
+//   1. lane-serial walk from the identity over its 3K transforms, keeping the
+//      local translation of every atom and the lane aggregate (reset at chain
+//      heads);
+//   2. segmented inclusive scan of the lane aggregates across the wave
+//      (log2(64) = 6 shuffle steps of a 3x4 affine), then of the wave totals
+//      across the workgroup through LDS;
+//   3. each lane maps its local translations through its exclusive prefix
+//      frame and stores x, y, z planes.
+// The adjoint is a reverse segmented scan of the 6-float "wrench"
+// (g_k, r_k x g_k); for transform i with bond axis u_i,
+//   dL/dalpha_i = u_i . (S_rg(i) - r_i x S_g(i)),
+//   S_g(i) = sum_{k>i} g_k, S_rg(i) = sum_{k>i} r_k x g_k (same chain),
+// which equals the sums of Eq. BackboneGradOutput because
+// M_{i-1} dR_i/dalpha M_i^-1 = M_i G_x M_i^-1 moves a point p by u_i x (p - r_i).
+//
+// Plain form: the paper's own GPU design, kept as the comparison -- one
+// workgroup per chain, a sequential product that stores M_i for every atom,
+// and a backward where each thread owns one angle and sums
+// g_k . (M_{i-1} dR_i M_i^-1 r_k) over all downstream atoms.
+#include "a2c_internal.h"
+#include "affine.h"
+
+namespace a2c {
+
+namespace {
+
+// Angle plane of each backbone slot: omega places N, phi places CA, psi places C.
+__device__ __forceinline__ int slot_plane(int s) { return s == 0 ? 2 : (s == 1 ? 0 : 1); }
+
+// K-bit mask: bit j set when residue rs + j starts a chain.  The bit array is
+// padded so that reading one word past rs + K is in bounds.
+template <int K>
+__device__ __forceinline__ uint32_t head_mask(const uint32_t *__restrict__ bits, int64_t rs)
+{
+    const int64_t w = rs >> 5;
+    const int sh = (int)(rs & 31);
+    const uint64_t lo = bits[w];
+    const uint64_t hi = (sh + K > 32) ? (uint64_t)bits[w + 1] : 0ull;
+    const uint64_t v = (hi << 32) | lo;
+    return (uint32_t)(v >> sh) & ((1u << K) - 1u);
+}
+
+struct Wrench {
+    float g0, g1, g2, m0, m1, m2;  // force and moment about the origin
+};
+
+__device__ __forceinline__ Wrench wrench_zero()
+{
+    Wrench w;
+    w.g0 = w.g1 = w.g2 = w.m0 = w.m1 = w.m2 = 0.f;
+    return w;
+}
+
+__device__ __forceinline__ void wrench_add(Wrench &a, const Wrench &b)
+{
+    a.g0 += b.g0; a.g1 += b.g1; a.g2 += b.g2;
+    a.m0 += b.m0; a.m1 += b.m1; a.m2 += b.m2;
+}
+
+__device__ __forceinline__ Wrench wrench_shfl_down(const Wrench &a, int delta)
+{
+    Wrench o;
+    o.g0 = __shfl_down(a.g0, delta, 64); o.g1 = __shfl_down(a.g1, delta, 64);
+    o.g2 = __shfl_down(a.g2, delta, 64); o.m0 = __shfl_down(a.m0, delta, 64);
+    o.m1 = __shfl_down(a.m1, delta, 64); o.m2 = __shfl_down(a.m2, delta, 64);
+    return o;
+}
+
+struct FwdShared {
+    float tot[kMaxWaves][12];
+    int tot_flag[kMaxWaves];
+    float carry[kMaxWaves][12];
+};
+
+struct BwdShared {
+    float tot[kMaxWaves][6];
+    int tot_flag[kMaxWaves];
+    float carry[kMaxWaves][6];
+};
+
+__device__ __forceinline__ void aff_store(float *dst, const Aff &m)
+{
+    dst[0] = m.r00; dst[1] = m.r10; dst[2] = m.r20;
+    dst[3] = m.r01; dst[4] = m.r11; dst[5] = m.r21;
+    dst[6] = m.r02; dst[7] = m.r12; dst[8] = m.r22;
+    dst[9] = m.t0; dst[10] = m.t1; dst[11] = m.t2;
+}
+
+__device__ __forceinline__ Aff aff_load(const float *src)
+{
+    Aff m;
+    m.r00 = src[0]; m.r10 = src[1]; m.r20 = src[2];
+    m.r01 = src[3]; m.r11 = src[4]; m.r21 = src[5];
+    m.r02 = src[6]; m.r12 = src[7]; m.r22 = src[8];
+    m.t0 = src[9]; m.t1 = src[10]; m.t2 = src[11];
+    return m;
+}
+
+// Forward frames of one lane: absolute atom positions of the lane's residues
+// (x[3j+s], ...) and the position of the atom just before the lane (prev),
+// which is the origin when the lane starts a chain.  Every thread of the
+// block must call this (it contains barriers).
+template <int K>
+__device__ __forceinline__ void bb_lane_positions(
+    const float *__restrict__ ang, const uint32_t *__restrict__ head_bits, int64_t R,
+    const BBParams &P, int64_t ts, int64_t te, FwdShared &sh,
+    float (&x)[3 * K], float (&y)[3 * K], float (&z)[3 * K],
+    float &px, float &py, float &pz, int &cnt, uint32_t &hm)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nw = blockDim.x >> 6;
+    const int64_t rs = ts + (int64_t)tid * K;
+    cnt = (int)max((int64_t)0, min((int64_t)K, te - rs));
+    const bool wave_active = ts + (int64_t)wave * kWave * K < te;
+
+    Aff m = aff_identity();
+    bool f = false;        // a chain starts inside this lane
+    int first_head = K;    // residues before it need the carry-in frame
+    hm = 0;
+    if (wave_active) {
+        if (cnt > 0) hm = head_mask<K>(head_bits, rs);
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            if (j < cnt) {
+                const float phi = ang[rs + j];
+                const float psi = ang[R + rs + j];
+                const float om = ang[2 * R + rs + j];
+                float so, co, sp, cp, ss, cs;
+                sincosf(om, &so, &co);
+                sincosf(phi, &sp, &cp);
+                sincosf(psi, &ss, &cs);
+                const bool head = (hm >> j) & 1u;
+                if (head) {
+                    m = aff_identity();
+                    if (first_head == K) first_head = j;
+                }
+                aff_apply_transform(m, P.ct[0], P.st[0], P.d[0], co, so);
+                x[3 * j] = m.t0; y[3 * j] = m.t1; z[3 * j] = m.t2;
+                aff_apply_transform(m, P.ct[1], P.st[1], P.d[1], cp, sp);
+                x[3 * j + 1] = m.t0; y[3 * j + 1] = m.t1; z[3 * j + 1] = m.t2;
+                aff_apply_transform(m, P.ct[2], P.st[2], P.d[2], cs, ss);
+                x[3 * j + 2] = m.t0; y[3 * j + 2] = m.t1; z[3 * j + 2] = m.t2;
+            }
+        }
+        f = first_head < K;
+        // the fixed rotations repeat every residue, so their float32 rounding
+        // drifts the scale of long products coherently; one polar step per
+        // lane aggregate (every 3K transforms) removes that drift
+        aff_orthonormalise(m);
+        // segmented inclusive scan over the wave: (fa, A) + (fb, B) = (fa|fb, fb ? B : A B)
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            const Aff o = aff_shfl_up(m, off);
+            const int fo = __shfl_up((int)f, off, 64);
+            if (lane >= off) {
+                const Aff c = aff_compose(o, m);
+                m = aff_select(f, m, c);
+                f = f || (fo != 0);
+            }
+        }
+        if (lane == kWave - 1) {
+            aff_store(sh.tot[wave], m);
+            sh.tot_flag[wave] = f ? 1 : 0;
+        }
+    }
+    __syncthreads();
+    if (wave == 0) {
+        // exclusive segmented scan of the wave totals (the tile starts with a
+        // chain head, so wave 0 needs no carry)
+        Aff t = aff_identity();
+        bool tf = false;
+        if (lane < nw && ts + (int64_t)lane * kWave * K < te) {
+            t = aff_load(sh.tot[lane]);
+            tf = sh.tot_flag[lane] != 0;
+        }
+#pragma unroll
+        for (int off = 1; off < kMaxWaves; off <<= 1) {
+            const Aff o = aff_shfl_up(t, off);
+            const int fo = __shfl_up((int)tf, off, 64);
+            if (lane >= off) {
+                const Aff c = aff_compose(o, t);
+                t = aff_select(tf, t, c);
+                tf = tf || (fo != 0);
+            }
+        }
+        Aff e = aff_shfl_up(t, 1);
+        if (lane == 0) e = aff_identity();
+        if (lane < nw) aff_store(sh.carry[lane], e);
+    }
+    __syncthreads();
+    px = py = pz = 0.f;
+    if (wave_active) {
+        Aff e = aff_shfl_up(m, 1);
+        int fe = __shfl_up((int)f, 1, 64);
+        if (lane == 0) {
+            e = aff_identity();
+            fe = 0;
+        }
+        const Aff cw = aff_load(sh.carry[wave]);
+        const Aff xc = aff_compose(cw, e);
+        const Aff X = fe ? e : xc;
+        // previous atom position (origin when the lane's first residue is a head)
+        if (!(hm & 1u)) { px = X.t0; py = X.t1; pz = X.t2; }
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            if (j < first_head) {
+#pragma unroll
+                for (int s = 0; s < 3; ++s) {
+                    float gx, gy, gz;
+                    aff_point(X, x[3 * j + s], y[3 * j + s], z[3 * j + s], gx, gy, gz);
+                    x[3 * j + s] = gx; y[3 * j + s] = gy; z[3 * j + s] = gz;
+                }
+            }
+        }
+    }
+}
+
+// Adjoint of one lane given absolute positions, upstream gradients and the
+// previous atom; a reverse segmented scan of wrenches across the block.
+template <int K>
+__device__ __forceinline__ void bb_lane_adjoint(
+    const uint32_t *__restrict__ head_bits, int64_t R, const BBParams &P, int64_t ts,
+    int64_t te, BwdShared &sh, const float (&x)[3 * K], const float (&y)[3 * K],
+    const float (&z)[3 * K], const float (&gx)[3 * K], const float (&gy)[3 * K],
+    const float (&gz)[3 * K], float px, float py, float pz, int cnt, uint32_t hm,
+    float *__restrict__ gang)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nw = blockDim.x >> 6;
+    const int64_t rs = ts + (int64_t)tid * K;
+    const bool wave_active = ts + (int64_t)wave * kWave * K < te;
+
+    // residue j is the last of its chain when residue j+1 starts one (the bit
+    // array also marks R, and tiles end at chain ends)
+    uint32_t lm = 0;
+    Wrench agg = wrench_zero();
+    bool f = false;
+    if (wave_active) {
+        if (cnt > 0) lm = head_mask<K>(head_bits, rs + 1);
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            if (j < cnt) {
+#pragma unroll
+                for (int s = 0; s < 3; ++s) {
+                    const int i = 3 * j + s;
+                    if (!f) {
+                        agg.g0 += gx[i]; agg.g1 += gy[i]; agg.g2 += gz[i];
+                        agg.m0 += y[i] * gz[i] - z[i] * gy[i];
+                        agg.m1 += z[i] * gx[i] - x[i] * gz[i];
+                        agg.m2 += x[i] * gy[i] - y[i] * gx[i];
+                    }
+                }
+                if ((lm >> j) & 1u) f = true;
+            }
+        }
+        // reverse segmented inclusive scan: Q_l = agg_l + (f_l ? 0 : Q_{l+1})
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            const Wrench o = wrench_shfl_down(agg, off);
+            const int fo = __shfl_down((int)f, off, 64);
+            if (lane + off < kWave) {
+                if (!f) wrench_add(agg, o);
+                f = f || (fo != 0);
+            }
+        }
+        if (lane == 0) {
+            sh.tot[wave][0] = agg.g0; sh.tot[wave][1] = agg.g1; sh.tot[wave][2] = agg.g2;
+            sh.tot[wave][3] = agg.m0; sh.tot[wave][4] = agg.m1; sh.tot[wave][5] = agg.m2;
+            sh.tot_flag[wave] = f ? 1 : 0;
+        }
+    }
+    __syncthreads();
+    if (wave == 0) {
+        Wrench t = wrench_zero();
+        bool tf = false;
+        if (lane < nw && ts + (int64_t)lane * kWave * K < te) {
+            t.g0 = sh.tot[lane][0]; t.g1 = sh.tot[lane][1]; t.g2 = sh.tot[lane][2];
+            t.m0 = sh.tot[lane][3]; t.m1 = sh.tot[lane][4]; t.m2 = sh.tot[lane][5];
+            tf = sh.tot_flag[lane] != 0;
+        }
+#pragma unroll
+        for (int off = 1; off < kMaxWaves; off <<= 1) {
+            const Wrench o = wrench_shfl_down(t, off);
+            const int fo = __shfl_down((int)tf, off, 64);
+            if (lane + off < kMaxWaves) {
+                if (!tf) wrench_add(t, o);
+                tf = tf || (fo != 0);
+            }
+        }
+        Wrench e = wrench_shfl_down(t, 1);
+        if (lane + 1 >= nw) e = wrench_zero();
+        if (lane < nw) {
+            sh.carry[lane][0] = e.g0; sh.carry[lane][1] = e.g1; sh.carry[lane][2] = e.g2;
+            sh.carry[lane][3] = e.m0; sh.carry[lane][4] = e.m1; sh.carry[lane][5] = e.m2;
+        }
+    }
+    __syncthreads();
+    if (!wave_active) return;
+    Wrench S = wrench_shfl_down(agg, 1);
+    int fs = __shfl_down((int)f, 1, 64);
+    if (lane == kWave - 1) {
+        S = wrench_zero();
+        fs = 0;
+    }
+    if (!fs) {
+        S.g0 += sh.carry[wave][0]; S.g1 += sh.carry[wave][1]; S.g2 += sh.carry[wave][2];
+        S.m0 += sh.carry[wave][3]; S.m1 += sh.carry[wave][4]; S.m2 += sh.carry[wave][5];
+    }
+#pragma unroll
+    for (int j = K - 1; j >= 0; --j) {
+        if (j < cnt) {
+            if ((lm >> j) & 1u) S = wrench_zero();
+            const bool head = (hm >> j) & 1u;
+#pragma unroll
+            for (int s = 2; s >= 0; --s) {
+                const int i = 3 * j + s;
+                float qx, qy, qz;  // atom before i
+                if (s > 0) { qx = x[i - 1]; qy = y[i - 1]; qz = z[i - 1]; }
+                else if (head) { qx = 0.f; qy = 0.f; qz = 0.f; }
+                else if (j > 0) { qx = x[i - 1]; qy = y[i - 1]; qz = z[i - 1]; }
+                else { qx = px; qy = py; qz = pz; }
+                const float ux = (x[i] - qx) * P.inv_d[s];
+                const float uy = (y[i] - qy) * P.inv_d[s];
+                const float uz = (z[i] - qz) * P.inv_d[s];
+                // torque about r_i: S_rg - r_i x S_g
+                const float tx = S.m0 - (y[i] * S.g2 - z[i] * S.g1);
+                const float ty = S.m1 - (z[i] * S.g0 - x[i] * S.g2);
+                const float tz = S.m2 - (x[i] * S.g1 - y[i] * S.g0);
+                gang[(int64_t)slot_plane(s) * R + rs + j] = ux * tx + uy * ty + uz * tz;
+                S.g0 += gx[i]; S.g1 += gy[i]; S.g2 += gz[i];
+                S.m0 += y[i] * gz[i] - z[i] * gy[i];
+                S.m1 += z[i] * gx[i] - x[i] * gz[i];
+                S.m2 += x[i] * gy[i] - y[i] * gx[i];
+            }
+        }
+    }
+}
+
+template <int K>
+__global__ __launch_bounds__(1024) void bb_forward_scan_kernel(
+    const float *__restrict__ ang, float *__restrict__ xyz, const int32_t *__restrict__ tile_res,
+    const uint32_t *__restrict__ head_bits, int64_t R, BBParams P)
+{
+    __shared__ FwdShared sh;
+    const int64_t ts = tile_res[blockIdx.x], te = tile_res[blockIdx.x + 1];
+    float x[3 * K], y[3 * K], z[3 * K];
+    float px, py, pz;
+    int cnt;
+    uint32_t hm;
+    bb_lane_positions<K>(ang, head_bits, R, P, ts, te, sh, x, y, z, px, py, pz, cnt, hm);
+    const int64_t A = 3 * R;
+    const int64_t a0 = 3 * (ts + (int64_t)threadIdx.x * K);
+#pragma unroll
+    for (int i = 0; i < 3 * K; ++i) {
+        if (i < 3 * cnt) {
+            xyz[a0 + i] = x[i];
+            xyz[A + a0 + i] = y[i];
+            xyz[2 * A + a0 + i] = z[i];
+        }
+    }
+}
+
+// Backward that recomputes the frames from the angles (no stored state).
+template <int K>
+__global__ __launch_bounds__(1024) void bb_backward_recompute_kernel(
+    const float *__restrict__ ang, const float *__restrict__ g, float *__restrict__ gang,
+    const int32_t *__restrict__ tile_res, const uint32_t *__restrict__ head_bits, int64_t R,
+    BBParams P)
+{
+    __shared__ FwdShared shf;
+    __shared__ BwdShared shb;
+    const int64_t ts = tile_res[blockIdx.x], te = tile_res[blockIdx.x + 1];
+    float x[3 * K], y[3 * K], z[3 * K];
+    float px, py, pz;
+    int cnt;
+    uint32_t hm;
+    bb_lane_positions<K>(ang, head_bits, R, P, ts, te, shf, x, y, z, px, py, pz, cnt, hm);
+    const int64_t A = 3 * R;
+    const int64_t a0 = 3 * (ts + (int64_t)threadIdx.x * K);
+    float gx[3 * K], gy[3 * K], gz[3 * K];
+#pragma unroll
+    for (int i = 0; i < 3 * K; ++i) {
+        if (i < 3 * cnt) {
+            gx[i] = g[a0 + i];
+            gy[i] = g[A + a0 + i];
+            gz[i] = g[2 * A + a0 + i];
+        } else {
+            gx[i] = gy[i] = gz[i] = 0.f;
+        }
+    }
+    bb_lane_adjoint<K>(head_bits, R, P, ts, te, shb, x, y, z, gx, gy, gz, px, py, pz, cnt, hm,
+                       gang);
+}
+
+// Backward from the coordinates the forward produced.
+template <int K>
+__global__ __launch_bounds__(1024) void bb_backward_coords_kernel(
+    const float *__restrict__ xyz, const float *__restrict__ g, float *__restrict__ gang,
+    const int32_t *__restrict__ tile_res, const uint32_t *__restrict__ head_bits, int64_t R,
+    BBParams P)
+{
+    __shared__ BwdShared shb;
+    const int64_t ts = tile_res[blockIdx.x], te = tile_res[blockIdx.x + 1];
+    const int64_t rs = ts + (int64_t)threadIdx.x * K;
+    const int cnt = (int)max((int64_t)0, min((int64_t)K, te - rs));
+    const int64_t A = 3 * R;
+    const int64_t a0 = 3 * rs;
+    float x[3 * K], y[3 * K], z[3 * K], gx[3 * K], gy[3 * K], gz[3 * K];
+#pragma unroll
+    for (int i = 0; i < 3 * K; ++i) {
+        if (i < 3 * cnt) {
+            x[i] = xyz[a0 + i]; y[i] = xyz[A + a0 + i]; z[i] = xyz[2 * A + a0 + i];
+            gx[i] = g[a0 + i]; gy[i] = g[A + a0 + i]; gz[i] = g[2 * A + a0 + i];
+        } else {
+            x[i] = y[i] = z[i] = gx[i] = gy[i] = gz[i] = 0.f;
+        }
+    }
+    uint32_t hm = 0;
+    float px = 0.f, py = 0.f, pz = 0.f;
+    if (cnt > 0) {
+        hm = head_mask<K>(head_bits, rs);
+        if (!(hm & 1u)) { px = xyz[a0 - 1]; py = xyz[A + a0 - 1]; pz = xyz[2 * A + a0 - 1]; }
+    }
+    bb_lane_adjoint<K>(head_bits, R, P, ts, te, shb, x, y, z, gx, gy, gz, px, py, pz, cnt, hm,
+                       gang);
+}
+
+// ---------------------------------------------------------------- plain form
+
+__global__ __launch_bounds__(64) void bb_forward_plain_kernel(
+    const float *__restrict__ ang, float *__restrict__ xyz, float *__restrict__ ws,
+    const int32_t *__restrict__ res_off, int64_t R, BBParams P)
+{
+    if (threadIdx.x != 0) return;
+    const int64_t r0 = res_off[blockIdx.x], r1 = res_off[blockIdx.x + 1];
+    const int64_t A = 3 * R;
+    Aff m = aff_identity();
+    for (int64_t r = r0; r < r1; ++r) {
+        if (r > r0 && ((r - r0) & 3) == 0) aff_orthonormalise(m);
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            float sa, ca;
+            sincosf(ang[(int64_t)slot_plane(s) * R + r], &sa, &ca);
+            aff_apply_transform(m, P.ct[s], P.st[s], P.d[s], ca, sa);
+            const int64_t a = 3 * r + s;
+            aff_store(ws + 12 * a, m);
+            xyz[a] = m.t0;
+            xyz[A + a] = m.t1;
+            xyz[2 * A + a] = m.t2;
+        }
+    }
+}
+
+constexpr int kPlainBlock = 256;
+
+__global__ __launch_bounds__(kPlainBlock) void bb_backward_plain_kernel(
+    const float *__restrict__ ang, const float *__restrict__ g, float *__restrict__ gang,
+    const float *__restrict__ ws, const int32_t *__restrict__ res_off, int64_t R, BBParams P)
+{
+    __shared__ float s_r[3][kPlainBlock];
+    __shared__ float s_g[3][kPlainBlock];
+    const int64_t r0 = res_off[blockIdx.x];
+    const int64_t n = 3 * (res_off[blockIdx.x + 1] - r0);  // atoms (= angles) in chain
+    const int64_t ib = (int64_t)blockIdx.y * kPlainBlock;
+    if (ib >= n) return;  // whole block past the chain end (padded launch)
+    const int64_t A = 3 * R;
+    const int64_t a0 = 3 * r0;
+    const int tid = threadIdx.x;
+    const int64_t i = ib + tid;
+    const bool active = i < n;
+    // F_i = M_{i-1} dR_i/dalpha M_i^-1 in 3x4 form: F.R = (R_{i-1} dR) R_i^T,
+    // F.t = -F.R t_i  (dR has no translation part)
+    float f00 = 0, f01 = 0, f02 = 0, f10 = 0, f11 = 0, f12 = 0, f20 = 0, f21 = 0, f22 = 0;
+    float tix = 0, tiy = 0, tiz = 0;
+    if (active) {
+        const int s = (int)(i % 3);
+        float sa, ca;
+        sincosf(ang[(int64_t)slot_plane(s) * R + r0 + i / 3], &sa, &ca);
+        const float ct = P.ct[s], st = P.st[s];
+        // dR (3x3): [[0, ca st, -sa st], [0, -sa, -ca], [0, ca ct, -sa ct]]
+        const float d01 = ca * st, d02 = -sa * st, d11 = -sa, d12 = -ca, d21 = ca * ct,
+                    d22 = -sa * ct;
+        Aff mp = aff_identity();
+        if (i > 0) mp = aff_load(ws + 12 * (a0 + i - 1));
+        const Aff mi = aff_load(ws + 12 * (a0 + i));
+        // B = R_{i-1} dR (first column is zero)
+        const float b01 = mp.r00 * d01 + mp.r01 * d11 + mp.r02 * d21;
+        const float b11 = mp.r10 * d01 + mp.r11 * d11 + mp.r12 * d21;
+        const float b21 = mp.r20 * d01 + mp.r21 * d11 + mp.r22 * d21;
+        const float b02 = mp.r00 * d02 + mp.r01 * d12 + mp.r02 * d22;
+        const float b12 = mp.r10 * d02 + mp.r11 * d12 + mp.r12 * d22;
+        const float b22 = mp.r20 * d02 + mp.r21 * d12 + mp.r22 * d22;
+        // F.R = B R_i^T: (B R^T)_{rc} = sum_k B_{rk} R_{ck}
+        f00 = b01 * mi.r01 + b02 * mi.r02;
+        f01 = b01 * mi.r11 + b02 * mi.r12;
+        f02 = b01 * mi.r21 + b02 * mi.r22;
+        f10 = b11 * mi.r01 + b12 * mi.r02;
+        f11 = b11 * mi.r11 + b12 * mi.r12;
+        f12 = b11 * mi.r21 + b12 * mi.r22;
+        f20 = b21 * mi.r01 + b22 * mi.r02;
+        f21 = b21 * mi.r11 + b22 * mi.r12;
+        f22 = b21 * mi.r21 + b22 * mi.r22;
+        tix = mi.t0; tiy = mi.t1; tiz = mi.t2;
+    }
+    float acc = 0.f;
+    for (int64_t kb = ib; kb < n; kb += kPlainBlock) {
+        const int64_t k = kb + tid;
+        if (k < n) {
+            const float *mk = ws + 12 * (a0 + k);
+            s_r[0][tid] = mk[9]; s_r[1][tid] = mk[10]; s_r[2][tid] = mk[11];
+            s_g[0][tid] = g[a0 + k]; s_g[1][tid] = g[A + a0 + k]; s_g[2][tid] = g[2 * A + a0 + k];
+        }
+        __syncthreads();
+        if (active) {
+            const int kmax = (int)min((int64_t)kPlainBlock, n - kb);
+            const int kmin = (int)max((int64_t)0, i - kb);
+            for (int kk = kmin; kk < kmax; ++kk) {
+                const float dx = s_r[0][kk] - tix, dy = s_r[1][kk] - tiy, dz = s_r[2][kk] - tiz;
+                const float vx = f00 * dx + f01 * dy + f02 * dz;
+                const float vy = f10 * dx + f11 * dy + f12 * dz;
+                const float vz = f20 * dx + f21 * dy + f22 * dz;
+                acc += s_g[0][kk] * vx + s_g[1][kk] * vy + s_g[2][kk] * vz;
+            }
+        }
+        __syncthreads();
+    }
+    if (active) gang[(int64_t)slot_plane((int)(i % 3)) * R + r0 + i / 3] = acc;
+}
+
+template <int K>
+hipError_t fwd_k(const a2c_plan &p, const float *ang, float *xyz, hipStream_t s)
+{
+    const dim3 grid(p.n_tiles), block(p.W * kWave);
+    hipLaunchKernelGGL((bb_forward_scan_kernel<K>), grid, block, 0, s, ang, xyz,
+                       p.d_tile_res, p.d_head_bits, p.R, p.bb);
+    return hipGetLastError();
+}
+
+template <int K>
+hipError_t bwd_k(const a2c_plan &p, const float *ang, const float *xyz, const float *g,
+                 float *gang, hipStream_t s)
+{
+    const dim3 grid(p.n_tiles), block(p.W * kWave);
+    if (xyz)
+        hipLaunchKernelGGL((bb_backward_coords_kernel<K>), grid, block, 0, s, xyz, g, gang,
+                           p.d_tile_res, p.d_head_bits, p.R, p.bb);
+    else
+        hipLaunchKernelGGL((bb_backward_recompute_kernel<K>), grid, block, 0, s, ang, g,
+                           gang, p.d_tile_res, p.d_head_bits, p.R, p.bb);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_bb_forward_scan(const a2c_plan &p, const float *ang, float *xyz, hipStream_t s)
+{
+    switch (p.K) {
+    case 1: return fwd_k<1>(p, ang, xyz, s);
+    case 2: return fwd_k<2>(p, ang, xyz, s);
+    case 4: return fwd_k<4>(p, ang, xyz, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_bb_backward_scan(const a2c_plan &p, const float *ang, const float *xyz,
+                                   const float *g, float *gang, hipStream_t s)
+{
+    switch (p.K) {
+    case 1: return bwd_k<1>(p, ang, xyz, g, gang, s);
+    case 2: return bwd_k<2>(p, ang, xyz, g, gang, s);
+    case 4: return bwd_k<4>(p, ang, xyz, g, gang, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_bb_forward_plain(const a2c_plan &p, const float *ang, float *xyz, float *ws,
+                                   hipStream_t s)
+{
+    hipLaunchKernelGGL(bb_forward_plain_kernel, dim3(p.n_chains), dim3(64), 0, s, ang, xyz, ws,
+                       p.d_res_off, p.R, p.bb);
+    return hipGetLastError();
+}
+
+hipError_t launch_bb_backward_plain(const a2c_plan &p, const float *ang, const float *g,
+                                    float *gang, const float *ws, hipStream_t s)
+{
+    const int64_t max_atoms = 3 * (int64_t)p.max_len;
+    const unsigned gy = (unsigned)((max_atoms + kPlainBlock - 1) / kPlainBlock);
+    if (gy == 0) return hipSuccess;
+    hipLaunchKernelGGL(bb_backward_plain_kernel, dim3(p.n_chains, gy), dim3(kPlainBlock), 0, s,
+                       ang, g, gang, ws, p.d_res_off, p.R, p.bb);
+    return hipGetLastError();
+}
+
+}  // namespace a2c
