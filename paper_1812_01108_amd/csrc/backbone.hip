@@ -73,13 +73,11 @@ __device__ __forceinline__ Wrench wrench_shfl_down(const Wrench &a, int delta)
 struct FwdShared {
     float tot[kMaxWaves][12];
     int tot_flag[kMaxWaves];
-    float carry[kMaxWaves][12];
 };
 
 struct BwdShared {
     float tot[kMaxWaves][6];
     int tot_flag[kMaxWaves];
-    float carry[kMaxWaves][6];
 };
 
 __device__ __forceinline__ void aff_store(float *dst, const Aff &m)
@@ -100,19 +98,105 @@ __device__ __forceinline__ Aff aff_load(const float *src)
     return m;
 }
 
-// Forward frames of one lane: absolute atom positions of the lane's residues
-// (x[3j+s], ...) and the position of the atom just before the lane (prev),
-// which is the origin when the lane starts a chain.  Every thread of the
-// block must call this (it contains barriers).
+__device__ __forceinline__ float lane_bcast(float v, int src_lane)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src_lane));
+}
+
+__device__ __forceinline__ Aff aff_bcast(const Aff &a, int l)
+{
+    Aff o;
+    o.r00 = lane_bcast(a.r00, l); o.r10 = lane_bcast(a.r10, l); o.r20 = lane_bcast(a.r20, l);
+    o.r01 = lane_bcast(a.r01, l); o.r11 = lane_bcast(a.r11, l); o.r21 = lane_bcast(a.r21, l);
+    o.r02 = lane_bcast(a.r02, l); o.r12 = lane_bcast(a.r12, l); o.r22 = lane_bcast(a.r22, l);
+    o.t0 = lane_bcast(a.t0, l); o.t1 = lane_bcast(a.t1, l); o.t2 = lane_bcast(a.t2, l);
+    return o;
+}
+
+// ------------------------------------------------------------ LDS staging
+// Global memory is read and written with 64 consecutive floats per wave
+// instruction; lanes own N consecutive elements in registers.  The transpose
+// goes through a per-wave LDS buffer with an odd row stride (no bank
+// conflicts on either side).
+template <int N>
+struct Stride {
+    static constexpr int value = (N & 1) ? N : N + 1;
+};
+
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Coalesced global loads of a wave's run base[0 .. 64N): element lane + 64m
+// goes to v[m].  `base` is wave-uniform and n (>= 1) is the number of valid
+// elements; indices past n are clamped so every load is unconditional
+// (straight-line code keeps all loads of all planes in flight together) and
+// their values are zeroed in the transpose.
+template <int N>
+__device__ __forceinline__ void gload(const float *__restrict__ base, int n, float (&v)[N])
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+        const int e = lane + 64 * m;
+        v[m] = base[e < n ? e : n - 1];
+    }
+}
+
+// Coalesced run (from gload) -> lane-blocked layout: lane l receives
+// elements l*N .. l*N+N-1 (0 at or past n).
+template <int N>
+__device__ __forceinline__ void to_blocked(float *buf, const float (&v)[N], int n, float (&out)[N])
+{
+    constexpr int S = Stride<N>::value;
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+        const int e = lane + 64 * m;
+        buf[e + (e / N) * (S - N)] = e < n ? v[m] : 0.f;
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int i = 0; i < N; ++i) out[i] = buf[lane * S + i];
+    wave_lds_sync();
+}
+
+// base[l*N + i] = in[i] of lane l for indices below n (base wave-uniform),
+// written with 64 consecutive floats per instruction.
+template <int N>
+__device__ __forceinline__ void stage_store(float *buf, const float (&in)[N], float *__restrict__ base,
+                                            int n)
+{
+    constexpr int S = Stride<N>::value;
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int i = 0; i < N; ++i) buf[lane * S + i] = in[i];
+    wave_lds_sync();
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+        const int e = lane + 64 * m;
+        if (e < n) base[e] = buf[e + (e / N) * (S - N)];
+    }
+    wave_lds_sync();
+}
+
+// ------------------------------------------------------------ forward scan
+// Absolute atom positions of one lane's residues (x[3j+s], ...), given its
+// angles, and the position of the atom just before the lane (the origin when
+// the lane starts a chain).  Every thread of the block calls this (one
+// workgroup barrier inside).
 template <int K>
 __device__ __forceinline__ void bb_lane_positions(
-    const float *__restrict__ ang, const uint32_t *__restrict__ head_bits, int64_t R,
-    const BBParams &P, int64_t ts, int64_t te, FwdShared &sh,
-    float (&x)[3 * K], float (&y)[3 * K], float (&z)[3 * K],
-    float &px, float &py, float &pz, int &cnt, uint32_t &hm)
+    const float (&phi)[K], const float (&psi)[K], const float (&om)[K],
+    const uint32_t *__restrict__ head_bits, const BBParams &P, int64_t ts, int64_t te,
+    FwdShared &sh, float (&x)[3 * K], float (&y)[3 * K], float (&z)[3 * K], float &px,
+    float &py, float &pz, int &cnt, uint32_t &hm)
 {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int nw = blockDim.x >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int64_t rs = ts + (int64_t)tid * K;
     cnt = (int)max((int64_t)0, min((int64_t)K, te - rs));
     const bool wave_active = ts + (int64_t)wave * kWave * K < te;
@@ -126,15 +210,11 @@ __device__ __forceinline__ void bb_lane_positions(
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             if (j < cnt) {
-                const float phi = ang[rs + j];
-                const float psi = ang[R + rs + j];
-                const float om = ang[2 * R + rs + j];
                 float so, co, sp, cp, ss, cs;
-                sincosf(om, &so, &co);
-                sincosf(phi, &sp, &cp);
-                sincosf(psi, &ss, &cs);
-                const bool head = (hm >> j) & 1u;
-                if (head) {
+                sincosf(om[j], &so, &co);
+                sincosf(phi[j], &sp, &cp);
+                sincosf(psi[j], &ss, &cs);
+                if ((hm >> j) & 1u) {
                     m = aff_identity();
                     if (first_head == K) first_head = j;
                 }
@@ -144,6 +224,10 @@ __device__ __forceinline__ void bb_lane_positions(
                 x[3 * j + 1] = m.t0; y[3 * j + 1] = m.t1; z[3 * j + 1] = m.t2;
                 aff_apply_transform(m, P.ct[2], P.st[2], P.d[2], cs, ss);
                 x[3 * j + 2] = m.t0; y[3 * j + 2] = m.t1; z[3 * j + 2] = m.t2;
+            } else {
+                x[3 * j] = y[3 * j] = z[3 * j] = 0.f;
+                x[3 * j + 1] = y[3 * j + 1] = z[3 * j + 1] = 0.f;
+                x[3 * j + 2] = y[3 * j + 2] = z[3 * j + 2] = 0.f;
             }
         }
         f = first_head < K;
@@ -168,17 +252,20 @@ __device__ __forceinline__ void bb_lane_positions(
         }
     }
     __syncthreads();
-    if (wave == 0) {
-        // exclusive segmented scan of the wave totals (the tile starts with a
-        // chain head, so wave 0 needs no carry)
+    px = py = pz = 0.f;
+    if (!wave_active) return;
+    // carry-in of this wave: segmented product of the totals of waves
+    // 0 .. wave-1, scanned redundantly by every wave (the tile starts with a
+    // chain head, so wave 0 has none)
+    Aff cw = aff_identity();
+    if (wave > 0) {
         Aff t = aff_identity();
         bool tf = false;
-        if (lane < nw && ts + (int64_t)lane * kWave * K < te) {
+        if (lane < wave) {
             t = aff_load(sh.tot[lane]);
             tf = sh.tot_flag[lane] != 0;
         }
-#pragma unroll
-        for (int off = 1; off < kMaxWaves; off <<= 1) {
+        for (int off = 1; off < wave; off <<= 1) {
             const Aff o = aff_shfl_up(t, off);
             const int fo = __shfl_up((int)tf, off, 64);
             if (lane >= off) {
@@ -187,52 +274,50 @@ __device__ __forceinline__ void bb_lane_positions(
                 tf = tf || (fo != 0);
             }
         }
-        Aff e = aff_shfl_up(t, 1);
-        if (lane == 0) e = aff_identity();
-        if (lane < nw) aff_store(sh.carry[lane], e);
+        cw = aff_bcast(t, wave - 1);
     }
-    __syncthreads();
-    px = py = pz = 0.f;
-    if (wave_active) {
-        Aff e = aff_shfl_up(m, 1);
-        int fe = __shfl_up((int)f, 1, 64);
-        if (lane == 0) {
-            e = aff_identity();
-            fe = 0;
-        }
-        const Aff cw = aff_load(sh.carry[wave]);
-        const Aff xc = aff_compose(cw, e);
-        const Aff X = fe ? e : xc;
-        // previous atom position (origin when the lane's first residue is a head)
-        if (!(hm & 1u)) { px = X.t0; py = X.t1; pz = X.t2; }
+    Aff e = aff_shfl_up(m, 1);
+    int fe = __shfl_up((int)f, 1, 64);
+    if (lane == 0) {
+        e = aff_identity();
+        fe = 0;
+    }
+    const Aff xc = aff_compose(cw, e);
+    const Aff X = fe ? e : xc;
+    // previous atom position (origin when the lane's first residue is a head)
+    if (!(hm & 1u)) { px = X.t0; py = X.t1; pz = X.t2; }
 #pragma unroll
-        for (int j = 0; j < K; ++j) {
-            if (j < first_head) {
+    for (int j = 0; j < K; ++j) {
+        if (j < first_head) {
 #pragma unroll
-                for (int s = 0; s < 3; ++s) {
-                    float gx, gy, gz;
-                    aff_point(X, x[3 * j + s], y[3 * j + s], z[3 * j + s], gx, gy, gz);
-                    x[3 * j + s] = gx; y[3 * j + s] = gy; z[3 * j + s] = gz;
-                }
+            for (int s = 0; s < 3; ++s) {
+                float gx, gy, gz;
+                aff_point(X, x[3 * j + s], y[3 * j + s], z[3 * j + s], gx, gy, gz);
+                x[3 * j + s] = gx; y[3 * j + s] = gy; z[3 * j + s] = gz;
             }
         }
     }
 }
 
-// Adjoint of one lane given absolute positions, upstream gradients and the
-// previous atom; a reverse segmented scan of wrenches across the block.
+// ------------------------------------------------------------ adjoint scan
+// Angle gradients of one lane (gr[s][j]: slot s of residue j; slot 0 is
+// omega, 1 phi, 2 psi) from absolute positions, upstream gradients and the
+// atom before the lane: a reverse segmented scan of wrenches over the tile.
+// Every thread of the block calls this (one workgroup barrier inside).
 template <int K>
 __device__ __forceinline__ void bb_lane_adjoint(
-    const uint32_t *__restrict__ head_bits, int64_t R, const BBParams &P, int64_t ts,
-    int64_t te, BwdShared &sh, const float (&x)[3 * K], const float (&y)[3 * K],
-    const float (&z)[3 * K], const float (&gx)[3 * K], const float (&gy)[3 * K],
-    const float (&gz)[3 * K], float px, float py, float pz, int cnt, uint32_t hm,
-    float *__restrict__ gang)
+    const uint32_t *__restrict__ head_bits, const BBParams &P, int64_t ts, int64_t te,
+    BwdShared &sh, const float (&x)[3 * K], const float (&y)[3 * K], const float (&z)[3 * K],
+    const float (&gx)[3 * K], const float (&gy)[3 * K], const float (&gz)[3 * K], float px,
+    float py, float pz, int cnt, uint32_t hm, float (&gr)[3][K])
 {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int nw = blockDim.x >> 6;
     const int64_t rs = ts + (int64_t)tid * K;
     const bool wave_active = ts + (int64_t)wave * kWave * K < te;
+    // active waves of the tile
+    const int nact = (int)min((int64_t)nw, (te - ts + kWave * K - 1) / (kWave * K));
 
     // residue j is the last of its chain when residue j+1 starts one (the bit
     // array also marks R, and tiles end at chain ends)
@@ -274,42 +359,38 @@ __device__ __forceinline__ void bb_lane_adjoint(
         }
     }
     __syncthreads();
-    if (wave == 0) {
+    if (!wave_active) return;
+    // carry-in from the waves after this one (segmented sum, scanned by
+    // every wave; the tile ends at a chain end, so the last wave has none)
+    Wrench cw = wrench_zero();
+    const int nafter = nact - 1 - wave;
+    if (nafter > 0) {
         Wrench t = wrench_zero();
         bool tf = false;
-        if (lane < nw && ts + (int64_t)lane * kWave * K < te) {
-            t.g0 = sh.tot[lane][0]; t.g1 = sh.tot[lane][1]; t.g2 = sh.tot[lane][2];
-            t.m0 = sh.tot[lane][3]; t.m1 = sh.tot[lane][4]; t.m2 = sh.tot[lane][5];
-            tf = sh.tot_flag[lane] != 0;
+        if (lane < nafter) {
+            const int w2 = wave + 1 + lane;
+            t.g0 = sh.tot[w2][0]; t.g1 = sh.tot[w2][1]; t.g2 = sh.tot[w2][2];
+            t.m0 = sh.tot[w2][3]; t.m1 = sh.tot[w2][4]; t.m2 = sh.tot[w2][5];
+            tf = sh.tot_flag[w2] != 0;
         }
-#pragma unroll
-        for (int off = 1; off < kMaxWaves; off <<= 1) {
+        for (int off = 1; off < nafter; off <<= 1) {
             const Wrench o = wrench_shfl_down(t, off);
             const int fo = __shfl_down((int)tf, off, 64);
-            if (lane + off < kMaxWaves) {
+            if (lane + off < kWave) {
                 if (!tf) wrench_add(t, o);
                 tf = tf || (fo != 0);
             }
         }
-        Wrench e = wrench_shfl_down(t, 1);
-        if (lane + 1 >= nw) e = wrench_zero();
-        if (lane < nw) {
-            sh.carry[lane][0] = e.g0; sh.carry[lane][1] = e.g1; sh.carry[lane][2] = e.g2;
-            sh.carry[lane][3] = e.m0; sh.carry[lane][4] = e.m1; sh.carry[lane][5] = e.m2;
-        }
+        cw.g0 = lane_bcast(t.g0, 0); cw.g1 = lane_bcast(t.g1, 0); cw.g2 = lane_bcast(t.g2, 0);
+        cw.m0 = lane_bcast(t.m0, 0); cw.m1 = lane_bcast(t.m1, 0); cw.m2 = lane_bcast(t.m2, 0);
     }
-    __syncthreads();
-    if (!wave_active) return;
     Wrench S = wrench_shfl_down(agg, 1);
     int fs = __shfl_down((int)f, 1, 64);
     if (lane == kWave - 1) {
         S = wrench_zero();
         fs = 0;
     }
-    if (!fs) {
-        S.g0 += sh.carry[wave][0]; S.g1 += sh.carry[wave][1]; S.g2 += sh.carry[wave][2];
-        S.m0 += sh.carry[wave][3]; S.m1 += sh.carry[wave][4]; S.m2 += sh.carry[wave][5];
-    }
+    if (!fs) wrench_add(S, cw);
 #pragma unroll
     for (int j = K - 1; j >= 0; --j) {
         if (j < cnt) {
@@ -330,14 +411,31 @@ __device__ __forceinline__ void bb_lane_adjoint(
                 const float tx = S.m0 - (y[i] * S.g2 - z[i] * S.g1);
                 const float ty = S.m1 - (z[i] * S.g0 - x[i] * S.g2);
                 const float tz = S.m2 - (x[i] * S.g1 - y[i] * S.g0);
-                gang[(int64_t)slot_plane(s) * R + rs + j] = ux * tx + uy * ty + uz * tz;
+                gr[s][j] = ux * tx + uy * ty + uz * tz;
                 S.g0 += gx[i]; S.g1 += gy[i]; S.g2 += gz[i];
                 S.m0 += y[i] * gz[i] - z[i] * gy[i];
                 S.m1 += z[i] * gx[i] - x[i] * gz[i];
                 S.m2 += x[i] * gy[i] - y[i] * gx[i];
             }
+        } else {
+            gr[0][j] = gr[1][j] = gr[2][j] = 0.f;
         }
     }
+}
+
+template <int K>
+__device__ __forceinline__ void store_angle_grads(float *buf, float (&gr)[3][K], float *gang,
+                                                  int64_t R, int64_t rbase, int nres)
+{
+    stage_store<K>(buf, gr[1], gang + rbase, nres);           // phi  (slot CA)
+    stage_store<K>(buf, gr[2], gang + R + rbase, nres);       // psi  (slot C)
+    stage_store<K>(buf, gr[0], gang + 2 * R + rbase, nres);   // omega (slot N)
+}
+
+template <int K>
+constexpr size_t stage_bytes(int waves)
+{
+    return (size_t)waves * kWave * Stride<3 * K>::value * sizeof(float);
 }
 
 template <int K>
@@ -345,22 +443,35 @@ __global__ __launch_bounds__(1024) void bb_forward_scan_kernel(
     const float *__restrict__ ang, float *__restrict__ xyz, const int32_t *__restrict__ tile_res,
     const uint32_t *__restrict__ head_bits, int64_t R, BBParams P)
 {
+    extern __shared__ float stage_mem[];
     __shared__ FwdShared sh;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    float *buf = stage_mem + wave * kWave * Stride<3 * K>::value;
     const int64_t ts = tile_res[blockIdx.x], te = tile_res[blockIdx.x + 1];
+    const int64_t rbase = ts + (int64_t)wave * kWave * K;
+    const bool active = rbase < te;
+    const int nres = (int)min((int64_t)kWave * K, te - rbase);  // residues of this wave
+    float phi[K], psi[K], om[K];
+    if (active) {
+        float v0[K], v1[K], v2[K];
+        gload<K>(ang + rbase, nres, v0);
+        gload<K>(ang + R + rbase, nres, v1);
+        gload<K>(ang + 2 * R + rbase, nres, v2);
+        to_blocked<K>(buf, v0, nres, phi);
+        to_blocked<K>(buf, v1, nres, psi);
+        to_blocked<K>(buf, v2, nres, om);
+    }
     float x[3 * K], y[3 * K], z[3 * K];
     float px, py, pz;
     int cnt;
     uint32_t hm;
-    bb_lane_positions<K>(ang, head_bits, R, P, ts, te, sh, x, y, z, px, py, pz, cnt, hm);
-    const int64_t A = 3 * R;
-    const int64_t a0 = 3 * (ts + (int64_t)threadIdx.x * K);
-#pragma unroll
-    for (int i = 0; i < 3 * K; ++i) {
-        if (i < 3 * cnt) {
-            xyz[a0 + i] = x[i];
-            xyz[A + a0 + i] = y[i];
-            xyz[2 * A + a0 + i] = z[i];
-        }
+    bb_lane_positions<K>(phi, psi, om, head_bits, P, ts, te, sh, x, y, z, px, py, pz, cnt, hm);
+    if (active) {
+        const int64_t A = 3 * R;
+        float *out = xyz + 3 * rbase;
+        stage_store<3 * K>(buf, x, out, 3 * nres);
+        stage_store<3 * K>(buf, y, out + A, 3 * nres);
+        stage_store<3 * K>(buf, z, out + 2 * A, 3 * nres);
     }
 }
 
@@ -371,29 +482,42 @@ __global__ __launch_bounds__(1024) void bb_backward_recompute_kernel(
     const int32_t *__restrict__ tile_res, const uint32_t *__restrict__ head_bits, int64_t R,
     BBParams P)
 {
+    extern __shared__ float stage_mem[];
     __shared__ FwdShared shf;
     __shared__ BwdShared shb;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    float *buf = stage_mem + wave * kWave * Stride<3 * K>::value;
     const int64_t ts = tile_res[blockIdx.x], te = tile_res[blockIdx.x + 1];
+    const int64_t rbase = ts + (int64_t)wave * kWave * K;
+    const bool active = rbase < te;
+    const int nres = (int)min((int64_t)kWave * K, te - rbase);
+    const int64_t A = 3 * R;
+    float phi[K], psi[K], om[K];
+    float gx[3 * K], gy[3 * K], gz[3 * K];
+    if (active) {
+        float v0[K], v1[K], v2[K], w0[3 * K], w1[3 * K], w2[3 * K];
+        const float *gb = g + 3 * rbase;
+        gload<K>(ang + rbase, nres, v0);
+        gload<K>(ang + R + rbase, nres, v1);
+        gload<K>(ang + 2 * R + rbase, nres, v2);
+        gload<3 * K>(gb, 3 * nres, w0);
+        gload<3 * K>(gb + A, 3 * nres, w1);
+        gload<3 * K>(gb + 2 * A, 3 * nres, w2);
+        to_blocked<K>(buf, v0, nres, phi);
+        to_blocked<K>(buf, v1, nres, psi);
+        to_blocked<K>(buf, v2, nres, om);
+        to_blocked<3 * K>(buf, w0, 3 * nres, gx);
+        to_blocked<3 * K>(buf, w1, 3 * nres, gy);
+        to_blocked<3 * K>(buf, w2, 3 * nres, gz);
+    }
     float x[3 * K], y[3 * K], z[3 * K];
     float px, py, pz;
     int cnt;
     uint32_t hm;
-    bb_lane_positions<K>(ang, head_bits, R, P, ts, te, shf, x, y, z, px, py, pz, cnt, hm);
-    const int64_t A = 3 * R;
-    const int64_t a0 = 3 * (ts + (int64_t)threadIdx.x * K);
-    float gx[3 * K], gy[3 * K], gz[3 * K];
-#pragma unroll
-    for (int i = 0; i < 3 * K; ++i) {
-        if (i < 3 * cnt) {
-            gx[i] = g[a0 + i];
-            gy[i] = g[A + a0 + i];
-            gz[i] = g[2 * A + a0 + i];
-        } else {
-            gx[i] = gy[i] = gz[i] = 0.f;
-        }
-    }
-    bb_lane_adjoint<K>(head_bits, R, P, ts, te, shb, x, y, z, gx, gy, gz, px, py, pz, cnt, hm,
-                       gang);
+    bb_lane_positions<K>(phi, psi, om, head_bits, P, ts, te, shf, x, y, z, px, py, pz, cnt, hm);
+    float gr[3][K];
+    bb_lane_adjoint<K>(head_bits, P, ts, te, shb, x, y, z, gx, gy, gz, px, py, pz, cnt, hm, gr);
+    if (active) store_angle_grads<K>(buf, gr, gang, R, rbase, nres);
 }
 
 // Backward from the coordinates the forward produced.
@@ -403,30 +527,56 @@ __global__ __launch_bounds__(1024) void bb_backward_coords_kernel(
     const int32_t *__restrict__ tile_res, const uint32_t *__restrict__ head_bits, int64_t R,
     BBParams P)
 {
+    extern __shared__ float stage_mem[];
     __shared__ BwdShared shb;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    float *buf = stage_mem + wave * kWave * Stride<3 * K>::value;
     const int64_t ts = tile_res[blockIdx.x], te = tile_res[blockIdx.x + 1];
-    const int64_t rs = ts + (int64_t)threadIdx.x * K;
+    const int64_t rbase = ts + (int64_t)wave * kWave * K;
+    const bool active = rbase < te;
+    const int nres = (int)min((int64_t)kWave * K, te - rbase);
+    const int64_t rs = ts + (int64_t)tid * K;
     const int cnt = (int)max((int64_t)0, min((int64_t)K, te - rs));
     const int64_t A = 3 * R;
-    const int64_t a0 = 3 * rs;
     float x[3 * K], y[3 * K], z[3 * K], gx[3 * K], gy[3 * K], gz[3 * K];
-#pragma unroll
-    for (int i = 0; i < 3 * K; ++i) {
-        if (i < 3 * cnt) {
-            x[i] = xyz[a0 + i]; y[i] = xyz[A + a0 + i]; z[i] = xyz[2 * A + a0 + i];
-            gx[i] = g[a0 + i]; gy[i] = g[A + a0 + i]; gz[i] = g[2 * A + a0 + i];
-        } else {
-            x[i] = y[i] = z[i] = gx[i] = gy[i] = gz[i] = 0.f;
-        }
-    }
     uint32_t hm = 0;
     float px = 0.f, py = 0.f, pz = 0.f;
-    if (cnt > 0) {
-        hm = head_mask<K>(head_bits, rs);
-        if (!(hm & 1u)) { px = xyz[a0 - 1]; py = xyz[A + a0 - 1]; pz = xyz[2 * A + a0 - 1]; }
+    if (active) {
+        const float *xb = xyz + 3 * rbase;
+        const float *gb = g + 3 * rbase;
+        {
+            float w0[3 * K], w1[3 * K], w2[3 * K];
+            gload<3 * K>(xb, 3 * nres, w0);
+            gload<3 * K>(xb + A, 3 * nres, w1);
+            gload<3 * K>(xb + 2 * A, 3 * nres, w2);
+            to_blocked<3 * K>(buf, w0, 3 * nres, x);
+            to_blocked<3 * K>(buf, w1, 3 * nres, y);
+            to_blocked<3 * K>(buf, w2, 3 * nres, z);
+        }
+        {
+            float w0[3 * K], w1[3 * K], w2[3 * K];
+            gload<3 * K>(gb, 3 * nres, w0);
+            gload<3 * K>(gb + A, 3 * nres, w1);
+            gload<3 * K>(gb + 2 * A, 3 * nres, w2);
+            to_blocked<3 * K>(buf, w0, 3 * nres, gx);
+            to_blocked<3 * K>(buf, w1, 3 * nres, gy);
+            to_blocked<3 * K>(buf, w2, 3 * nres, gz);
+        }
+        if (cnt > 0) hm = head_mask<K>(head_bits, rs);
+        // the atom before the lane: last atom of the previous lane, or of the
+        // previous wave's run for lane 0 (the origin when a chain starts here)
+        const float lx = __shfl_up(x[3 * K - 1], 1, 64);
+        const float ly = __shfl_up(y[3 * K - 1], 1, 64);
+        const float lz = __shfl_up(z[3 * K - 1], 1, 64);
+        if (cnt > 0 && !(hm & 1u)) {
+            if (lane > 0) { px = lx; py = ly; pz = lz; }
+            else { px = xb[-1]; py = xb[A - 1]; pz = xb[2 * A - 1]; }
+        }
     }
-    bb_lane_adjoint<K>(head_bits, R, P, ts, te, shb, x, y, z, gx, gy, gz, px, py, pz, cnt, hm,
-                       gang);
+    float gr[3][K];
+    bb_lane_adjoint<K>(head_bits, P, ts, te, shb, x, y, z, gx, gy, gz, px, py, pz, cnt, hm, gr);
+    if (active) store_angle_grads<K>(buf, gr, gang, R, rbase, nres);
 }
 
 // ---------------------------------------------------------------- plain form
@@ -535,7 +685,7 @@ template <int K>
 hipError_t fwd_k(const a2c_plan &p, const float *ang, float *xyz, hipStream_t s)
 {
     const dim3 grid(p.n_tiles), block(p.W * kWave);
-    hipLaunchKernelGGL((bb_forward_scan_kernel<K>), grid, block, 0, s, ang, xyz,
+    hipLaunchKernelGGL((bb_forward_scan_kernel<K>), grid, block, stage_bytes<K>(p.W), s, ang, xyz,
                        p.d_tile_res, p.d_head_bits, p.R, p.bb);
     return hipGetLastError();
 }
@@ -545,11 +695,12 @@ hipError_t bwd_k(const a2c_plan &p, const float *ang, const float *xyz, const fl
                  float *gang, hipStream_t s)
 {
     const dim3 grid(p.n_tiles), block(p.W * kWave);
+    const size_t lds = stage_bytes<K>(p.W);
     if (xyz)
-        hipLaunchKernelGGL((bb_backward_coords_kernel<K>), grid, block, 0, s, xyz, g, gang,
+        hipLaunchKernelGGL((bb_backward_coords_kernel<K>), grid, block, lds, s, xyz, g, gang,
                            p.d_tile_res, p.d_head_bits, p.R, p.bb);
     else
-        hipLaunchKernelGGL((bb_backward_recompute_kernel<K>), grid, block, 0, s, ang, g,
+        hipLaunchKernelGGL((bb_backward_recompute_kernel<K>), grid, block, lds, s, ang, g,
                            gang, p.d_tile_res, p.d_head_bits, p.R, p.bb);
     return hipGetLastError();
 }
