@@ -99,3 +99,74 @@ def backbone_backward(offsets, angles, geom: dict, grad_coords, n_threads: int =
 
 def openmp_enabled() -> bool:
     return bool(_load().oracle_openmp_enabled())
+
+
+# ---------------------------------------------------------------- full atom
+_FA = None
+
+
+def _load_fa():
+    global _FA
+    lib = _load()
+    if _FA is None:
+        from . import residue_table as rt
+        P = ctypes.POINTER
+        lib.oracle_fullatom_forward.argtypes = [ctypes.c_int32, _I32, _U8, _D, _D,
+                                                P(rt.OracleTable), _I32, _D, ctypes.c_int]
+        lib.oracle_fullatom_backward.argtypes = [ctypes.c_int32, _I32, _U8, _D, _D,
+                                                 P(rt.OracleTable), _I32, _D, _D, ctypes.c_int,
+                                                 ctypes.c_int]
+        _FA = rt.load()
+    return lib, _FA
+
+
+def load_residue_table():
+    """(ctypes table, per-type info) read from the residue data file."""
+    return _load_fa()[1]
+
+
+def fullatom_atom_offsets(seq):
+    from . import residue_table as rt
+    return rt.atom_offsets(seq, _load_fa()[1][0])
+
+
+def fullatom_forward(offsets, seq, angles, geom: dict, n_threads: int = 0):
+    """coords [3][A] float64 and residue atom offsets [R+1] for angle planes
+    [7][R] (phi, psi, omega, chi1..chi4) and residue codes seq[R]."""
+    lib, (tab, _) = _load_fa()
+    off = np.ascontiguousarray(offsets, dtype=np.int32)
+    sq = np.ascontiguousarray(seq, dtype=np.uint8)
+    ang = _d(angles)
+    R = int(off[-1])
+    assert ang.shape == (7, R) and sq.shape == (R,)
+    aoff = fullatom_atom_offsets(sq)
+    A = int(aoff[-1])
+    out = np.empty((3, A))
+    g = backbone_geometry_vector(geom)
+    lib.oracle_fullatom_forward(len(off) - 1, _ptr(off, _I32), _ptr(sq, _U8), _ptr(ang, _D),
+                                _ptr(g, _D), ctypes.byref(tab), _ptr(aoff, _I32), _ptr(out, _D),
+                                n_threads)
+    return out, aoff
+
+
+def fullatom_backward(offsets, seq, angles, geom: dict, grad_coords, n_threads: int = 0,
+                      direct: bool = False):
+    """Angle gradient [7][R] of L = sum g . r (chi planes a residue lacks are 0).
+    direct=True evaluates Eq. FAMBackward term by term (O(N^2), small inputs)."""
+    lib, (tab, _) = _load_fa()
+    off = np.ascontiguousarray(offsets, dtype=np.int32)
+    sq = np.ascontiguousarray(seq, dtype=np.uint8)
+    ang = _d(angles)
+    R = int(off[-1])
+    aoff = fullatom_atom_offsets(sq)
+    gc = _d(grad_coords)
+    assert gc.shape == (3, int(aoff[-1]))
+    out = np.zeros((7, R))
+    g = backbone_geometry_vector(geom)
+    rc = lib.oracle_fullatom_backward(len(off) - 1, _ptr(off, _I32), _ptr(sq, _U8),
+                                      _ptr(ang, _D), _ptr(g, _D), ctypes.byref(tab),
+                                      _ptr(aoff, _I32), _ptr(gc, _D), _ptr(out, _D),
+                                      1 if direct else 0, n_threads)
+    if rc != 0:
+        raise MemoryError("oracle full-atom backward failed")
+    return out
