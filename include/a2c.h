@@ -193,6 +193,20 @@ a2c_status a2c_backward(a2c_plan *plan, a2c_variant variant, const float *d_angl
                         const float *d_coords, const float *d_grad_coords,
                         float *d_grad_angles, void *d_workspace, void *stream);
 
+/* Host-only check of a residue table (no device needed): validates it as
+ * a2c_plan_create would and reports, per residue type, the atom count
+ * (n_atoms int32[20], may be NULL) and the standard position r° of every
+ * atom in its own frame (local_xyz float[20][14][3] by output slot, may be
+ * NULL), as the library derives them from the internal coordinates.
+ * Spine-frame predecessor distances use the default backbone geometry.
+ * Constraints beyond the struct's own: atoms 0, 1, 2 are N, CA, C at the
+ * spine frame origins; side frame 0 hangs off CA (only it may have a
+ * pre-rotation), side frame f > 0 off side frame f - 1 with chi = f + 1 or
+ * 0; every frame has exactly one atom at its origin; z-matrix references
+ * are earlier atoms of the same frame or the frame's predecessor. */
+a2c_status a2c_residue_table_info(const a2c_residue_table *table, int32_t *n_atoms,
+                                  float *local_xyz);
+
 const char *a2c_status_string(a2c_status status);
 const char *a2c_last_error(void);
 

@@ -25,7 +25,8 @@ ATOM_ORIGIN, ATOM_AZIMUTH, ATOM_ZMATRIX = 0, 1, 2
 EXPORTS = (
     "a2c_plan_create", "a2c_plan_destroy", "a2c_plan_sizes", "a2c_plan_atom_offsets",
     "a2c_plan_workspace_bytes", "a2c_plan_set_schedule", "a2c_plan_get_schedule",
-    "a2c_forward", "a2c_backward", "a2c_status_string", "a2c_last_error", "a2c_version",
+    "a2c_forward", "a2c_backward", "a2c_residue_table_info", "a2c_status_string",
+    "a2c_last_error", "a2c_version",
 )
 
 
@@ -88,6 +89,8 @@ def load():
                  "a2c_plan_set_schedule", "a2c_plan_get_schedule", "a2c_forward",
                  "a2c_backward"):
         getattr(lib, name).restype = ctypes.c_int
+    lib.a2c_residue_table_info.argtypes = [P(ResidueTable), P(i32), P(ctypes.c_float)]
+    lib.a2c_residue_table_info.restype = ctypes.c_int
     lib.a2c_status_string.argtypes = [ctypes.c_int]
     lib.a2c_status_string.restype = ctypes.c_char_p
     lib.a2c_last_error.argtypes = []

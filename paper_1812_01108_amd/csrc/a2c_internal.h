@@ -22,20 +22,26 @@ struct BBParams {
     float ct[3], st[3], d[3], inv_d[3];
 };
 
-// Full-atom constants (device memory, one block per residue type).
-struct FAResidue {
+// Full-atom constants of one residue type.  Frames: 0 N, 1 CA, 2 C (spine,
+// backbone geometry) and 3 + f for side frame f; side frames form a chain
+// CA -> 0 -> 1 -> ... (frame f hangs off f-1), frame 0 through a fixed
+// rotation about CA's x axis.  Atoms are grouped by frame.
+struct FAType {
     int32_t n_atoms;
     int32_t n_side;
-    int32_t side_parent[4];     // 1 = CA frame, 3.. side frames
-    int32_t side_plane[4];      // angle plane, or -1 for a fixed torsion of 0
-    float side_pre_c[4], side_pre_s[4];  // fixed pre-rotation about x
-    float side_ct[4], side_st[4], side_d[4];
-    int32_t atom_frame[14];
-    float atom_x[14], atom_y[14], atom_z[14];
+    int32_t side_chi[4];            // 1: torsion chi_{f+1} (plane 3 + f); 0: fixed 0
+    float pre_c, pre_s;             // fixed rotation of side frame 0
+    float ct[4], st[4], d[4], inv_d[4];
+    int32_t fbegin[7], fcount[7];   // atoms of frame k in the sorted lists
+    int32_t origin_slot[7];         // residue slot of the atom at frame k's origin
+    int32_t slot[A2C_MAX_RESIDUE_ATOMS];  // output slot of each sorted atom
+    float rx[A2C_MAX_RESIDUE_ATOMS], ry[A2C_MAX_RESIDUE_ATOMS], rz[A2C_MAX_RESIDUE_ATOMS];
 };
 
 struct FATable {
-    FAResidue res[A2C_NUM_RESIDUE_TYPES];
+    FAType t[A2C_NUM_RESIDUE_TYPES];
+    int32_t max_count[7];           // max atoms per frame over the types
+    int32_t max_side;
 };
 
 }  // namespace a2c
@@ -66,6 +72,8 @@ struct a2c_plan {
 namespace a2c {
 
 void set_error(const std::string &msg);
+// float32 (cos t, sin t) pair with squared norm closest to 1
+void unit_pair(double t, float &c, float &s);
 a2c_status hip_fail(hipError_t e, const char *what);
 
 // Launchers (each returns hipSuccess or the launch error)

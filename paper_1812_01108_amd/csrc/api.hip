@@ -22,35 +22,6 @@ a2c_status fail(a2c_status st, const std::string &msg)
     return st;
 }
 
-// The float32 (c, s) pair within +-2 ulps of (cos t, sin t) whose squared
-// norm is closest to 1 (ties broken by the angle error).  Independent
-// rounding of cos and sin leaves c^2 + s^2 - 1 ~ 1e-7, a scale error that
-// every residue repeats; the pair search makes it ~1e-9.
-void unit_pair(double t, float &c_out, float &s_out)
-{
-    const float c0 = (float)std::cos(t), s0 = (float)std::sin(t);
-    double best = std::numeric_limits<double>::infinity();
-    c_out = c0;
-    s_out = s0;
-    float cs[5], ss[5];
-    cs[2] = c0;
-    ss[2] = s0;
-    cs[3] = std::nextafter(c0, 2.f); cs[4] = std::nextafter(cs[3], 2.f);
-    cs[1] = std::nextafter(c0, -2.f); cs[0] = std::nextafter(cs[1], -2.f);
-    ss[3] = std::nextafter(s0, 2.f); ss[4] = std::nextafter(ss[3], 2.f);
-    ss[1] = std::nextafter(s0, -2.f); ss[0] = std::nextafter(ss[1], -2.f);
-    for (float c : cs)
-        for (float s : ss) {
-            const double e = std::fabs((double)c * c + (double)s * s - 1.0) +
-                             1e-3 * std::fabs(std::atan2((double)s, (double)c) - t);
-            if (e < best) {
-                best = e;
-                c_out = c;
-                s_out = s;
-            }
-        }
-}
-
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 bool valid_angle(double v) { return std::isfinite(v) && v > 0.0 && v < 180.0; }
 
@@ -110,7 +81,7 @@ a2c_status apply_schedule(a2c_plan *p, int32_t K, int32_t W, hipStream_t s)
 
 void default_schedule(const a2c_plan &p, int32_t &K, int32_t &W)
 {
-    K = 4;
+    K = p.model == A2C_BACKBONE ? 4 : 2;
     const int64_t per_wave = (int64_t)kWave * K;
     W = (int32_t)std::max<int64_t>(1, (p.max_len + per_wave - 1) / per_wave);
 }
@@ -123,6 +94,35 @@ bool check_device(const a2c_plan *p)
 }
 
 }  // namespace
+
+// The float32 (c, s) pair within +-2 ulps of (cos t, sin t) whose squared
+// norm is closest to 1 (ties broken by the angle error).  Independent
+// rounding of cos and sin leaves c^2 + s^2 - 1 ~ 1e-7, a scale error that
+// every residue repeats; the pair search makes it ~1e-9.
+void unit_pair(double t, float &c_out, float &s_out)
+{
+    const float c0 = (float)std::cos(t), s0 = (float)std::sin(t);
+    double best = std::numeric_limits<double>::infinity();
+    c_out = c0;
+    s_out = s0;
+    float cs[5], ss[5];
+    cs[2] = c0;
+    ss[2] = s0;
+    cs[3] = std::nextafter(c0, 2.f); cs[4] = std::nextafter(cs[3], 2.f);
+    cs[1] = std::nextafter(c0, -2.f); cs[0] = std::nextafter(cs[1], -2.f);
+    ss[3] = std::nextafter(s0, 2.f); ss[4] = std::nextafter(ss[3], 2.f);
+    ss[1] = std::nextafter(s0, -2.f); ss[0] = std::nextafter(ss[1], -2.f);
+    for (float c : cs)
+        for (float s : ss) {
+            const double e = std::fabs((double)c * c + (double)s * s - 1.0) +
+                             1e-3 * std::fabs(std::atan2((double)s, (double)c) - t);
+            if (e < best) {
+                best = e;
+                c_out = c;
+                s_out = s;
+            }
+        }
+}
 
 void set_error(const std::string &msg) { g_last_error = msg; }
 
@@ -192,8 +192,9 @@ a2c_status a2c_plan_create(a2c_plan **out, a2c_model model, int32_t n_chains,
     const int64_t R = h_res_offsets[n_chains];
     if (R > (int64_t)std::numeric_limits<int32_t>::max() / 16)
         return fail(A2C_ERR_UNSUPPORTED, "too many residues for int32 atom offsets");
-    if (max_len > kMaxTileResidues)
-        return fail(A2C_ERR_UNSUPPORTED, "chain longer than " + std::to_string(kMaxTileResidues) +
+    const int32_t max_tile = model == A2C_BACKBONE ? kMaxTileResidues : kMaxTileResidues / 2;
+    if (max_len > max_tile)
+        return fail(A2C_ERR_UNSUPPORTED, "chain longer than " + std::to_string(max_tile) +
                                              " residues");
     if (model == A2C_FULLATOM) {
         if (!table) return fail(A2C_ERR_INVALID_ARG, "full-atom plan needs a residue table");
@@ -210,14 +211,9 @@ a2c_status a2c_plan_create(a2c_plan **out, a2c_model model, int32_t n_chains,
         !valid_angle(g.angle_c_n_ca))
         return fail(A2C_ERR_INVALID_ARG, "backbone geometry out of range");
 
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     hipStream_t s = (hipStream_t)stream;
-
     a2c_plan *p = new a2c_plan();
     p->model = model;
-    p->device = dev;
     p->n_chains = n_chains;
     p->R = R;
     p->max_len = max_len;
@@ -246,6 +242,14 @@ a2c_status a2c_plan_create(a2c_plan **out, a2c_model model, int32_t n_chains,
             return st;
         }
     }
+    // host tables are complete: now the device
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        a2c_plan_destroy(p);
+        return hip_fail(e, "hipGetDevice");
+    }
+    p->device = dev;
     // chain-head bits, padded by two words so a lane may read one word past
     std::vector<uint32_t> bits((size_t)((R + 64) / 32 + 2), 0u);
     for (int32_t c = 0; c < n_chains; ++c)
@@ -313,6 +317,8 @@ a2c_status a2c_plan_set_schedule(a2c_plan *p, int32_t K, int32_t W, void *stream
     if (!p) return fail(A2C_ERR_INVALID_ARG, "plan is NULL");
     if (!(K == 1 || K == 2 || K == 4))
         return fail(A2C_ERR_INVALID_ARG, "res_per_lane must be 1, 2 or 4");
+    if (p->model == A2C_FULLATOM && K == 4)
+        return fail(A2C_ERR_INVALID_ARG, "the full-atom kernels take res_per_lane 1 or 2");
     if (W < 1 || W > kMaxWaves) return fail(A2C_ERR_INVALID_ARG, "waves_per_group must be 1..16");
     if (!check_device(p)) return fail(A2C_ERR_STATE, "current device is not the plan's device");
     return apply_schedule(p, K, W, (hipStream_t)stream);

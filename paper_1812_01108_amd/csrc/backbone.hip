@@ -21,8 +21,7 @@
 // workgroup per chain, a sequential product that stores M_i for every atom,
 // and a backward where each thread owns one angle and sums
 // g_k . (M_{i-1} dR_i M_i^-1 r_k) over all downstream atoms.
-#include "a2c_internal.h"
-#include "affine.h"
+#include "scan.h"
 
 namespace a2c {
 
@@ -31,163 +30,9 @@ namespace {
 // Angle plane of each backbone slot: omega places N, phi places CA, psi places C.
 __device__ __forceinline__ int slot_plane(int s) { return s == 0 ? 2 : (s == 1 ? 0 : 1); }
 
-// K-bit mask: bit j set when residue rs + j starts a chain.  The bit array is
-// padded so that reading one word past rs + K is in bounds.
-template <int K>
-__device__ __forceinline__ uint32_t head_mask(const uint32_t *__restrict__ bits, int64_t rs)
-{
-    const int64_t w = rs >> 5;
-    const int sh = (int)(rs & 31);
-    const uint64_t lo = bits[w];
-    const uint64_t hi = (sh + K > 32) ? (uint64_t)bits[w + 1] : 0ull;
-    const uint64_t v = (hi << 32) | lo;
-    return (uint32_t)(v >> sh) & ((1u << K) - 1u);
-}
-
-struct Wrench {
-    float g0, g1, g2, m0, m1, m2;  // force and moment about the origin
-};
-
-__device__ __forceinline__ Wrench wrench_zero()
-{
-    Wrench w;
-    w.g0 = w.g1 = w.g2 = w.m0 = w.m1 = w.m2 = 0.f;
-    return w;
-}
-
-__device__ __forceinline__ void wrench_add(Wrench &a, const Wrench &b)
-{
-    a.g0 += b.g0; a.g1 += b.g1; a.g2 += b.g2;
-    a.m0 += b.m0; a.m1 += b.m1; a.m2 += b.m2;
-}
-
-__device__ __forceinline__ Wrench wrench_shfl_down(const Wrench &a, int delta)
-{
-    Wrench o;
-    o.g0 = __shfl_down(a.g0, delta, 64); o.g1 = __shfl_down(a.g1, delta, 64);
-    o.g2 = __shfl_down(a.g2, delta, 64); o.m0 = __shfl_down(a.m0, delta, 64);
-    o.m1 = __shfl_down(a.m1, delta, 64); o.m2 = __shfl_down(a.m2, delta, 64);
-    return o;
-}
-
-struct FwdShared {
-    float tot[kMaxWaves][12];
-    int tot_flag[kMaxWaves];
-};
-
-struct BwdShared {
-    float tot[kMaxWaves][6];
-    int tot_flag[kMaxWaves];
-};
-
-__device__ __forceinline__ void aff_store(float *dst, const Aff &m)
-{
-    dst[0] = m.r00; dst[1] = m.r10; dst[2] = m.r20;
-    dst[3] = m.r01; dst[4] = m.r11; dst[5] = m.r21;
-    dst[6] = m.r02; dst[7] = m.r12; dst[8] = m.r22;
-    dst[9] = m.t0; dst[10] = m.t1; dst[11] = m.t2;
-}
-
-__device__ __forceinline__ Aff aff_load(const float *src)
-{
-    Aff m;
-    m.r00 = src[0]; m.r10 = src[1]; m.r20 = src[2];
-    m.r01 = src[3]; m.r11 = src[4]; m.r21 = src[5];
-    m.r02 = src[6]; m.r12 = src[7]; m.r22 = src[8];
-    m.t0 = src[9]; m.t1 = src[10]; m.t2 = src[11];
-    return m;
-}
-
-__device__ __forceinline__ float lane_bcast(float v, int src_lane)
-{
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src_lane));
-}
-
-__device__ __forceinline__ Aff aff_bcast(const Aff &a, int l)
-{
-    Aff o;
-    o.r00 = lane_bcast(a.r00, l); o.r10 = lane_bcast(a.r10, l); o.r20 = lane_bcast(a.r20, l);
-    o.r01 = lane_bcast(a.r01, l); o.r11 = lane_bcast(a.r11, l); o.r21 = lane_bcast(a.r21, l);
-    o.r02 = lane_bcast(a.r02, l); o.r12 = lane_bcast(a.r12, l); o.r22 = lane_bcast(a.r22, l);
-    o.t0 = lane_bcast(a.t0, l); o.t1 = lane_bcast(a.t1, l); o.t2 = lane_bcast(a.t2, l);
-    return o;
-}
-
-// ------------------------------------------------------------ LDS staging
-// Global memory is read and written with 64 consecutive floats per wave
-// instruction; lanes own N consecutive elements in registers.  The transpose
-// goes through a per-wave LDS buffer with an odd row stride (no bank
-// conflicts on either side).
-template <int N>
-struct Stride {
-    static constexpr int value = (N & 1) ? N : N + 1;
-};
-
-__device__ __forceinline__ void wave_lds_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Coalesced global loads of a wave's run base[0 .. 64N): element lane + 64m
-// goes to v[m].  `base` is wave-uniform and n (>= 1) is the number of valid
-// elements; indices past n are clamped so every load is unconditional
-// (straight-line code keeps all loads of all planes in flight together) and
-// their values are zeroed in the transpose.
-template <int N>
-__device__ __forceinline__ void gload(const float *__restrict__ base, int n, float (&v)[N])
-{
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int m = 0; m < N; ++m) {
-        const int e = lane + 64 * m;
-        v[m] = base[e < n ? e : n - 1];
-    }
-}
-
-// Coalesced run (from gload) -> lane-blocked layout: lane l receives
-// elements l*N .. l*N+N-1 (0 at or past n).
-template <int N>
-__device__ __forceinline__ void to_blocked(float *buf, const float (&v)[N], int n, float (&out)[N])
-{
-    constexpr int S = Stride<N>::value;
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int m = 0; m < N; ++m) {
-        const int e = lane + 64 * m;
-        buf[e + (e / N) * (S - N)] = e < n ? v[m] : 0.f;
-    }
-    wave_lds_sync();
-#pragma unroll
-    for (int i = 0; i < N; ++i) out[i] = buf[lane * S + i];
-    wave_lds_sync();
-}
-
-// base[l*N + i] = in[i] of lane l for indices below n (base wave-uniform),
-// written with 64 consecutive floats per instruction.
-template <int N>
-__device__ __forceinline__ void stage_store(float *buf, const float (&in)[N], float *__restrict__ base,
-                                            int n)
-{
-    constexpr int S = Stride<N>::value;
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int i = 0; i < N; ++i) buf[lane * S + i] = in[i];
-    wave_lds_sync();
-#pragma unroll
-    for (int m = 0; m < N; ++m) {
-        const int e = lane + 64 * m;
-        if (e < n) base[e] = buf[e + (e / N) * (S - N)];
-    }
-    wave_lds_sync();
-}
-
-// ------------------------------------------------------------ forward scan
 // Absolute atom positions of one lane's residues (x[3j+s], ...), given its
 // angles, and the position of the atom just before the lane (the origin when
-// the lane starts a chain).  Every thread of the block calls this (one
-// workgroup barrier inside).
+// the lane starts a chain).  Every thread of the block calls this.
 template <int K>
 __device__ __forceinline__ void bb_lane_positions(
     const float (&phi)[K], const float (&psi)[K], const float (&om)[K],
@@ -195,14 +40,13 @@ __device__ __forceinline__ void bb_lane_positions(
     FwdShared &sh, float (&x)[3 * K], float (&y)[3 * K], float (&z)[3 * K], float &px,
     float &py, float &pz, int &cnt, uint32_t &hm)
 {
-    const int tid = threadIdx.x, lane = tid & 63;
+    const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int64_t rs = ts + (int64_t)tid * K;
     cnt = (int)max((int64_t)0, min((int64_t)K, te - rs));
     const bool wave_active = ts + (int64_t)wave * kWave * K < te;
 
     Aff m = aff_identity();
-    bool f = false;        // a chain starts inside this lane
     int first_head = K;    // residues before it need the carry-in frame
     hm = 0;
     if (wave_active) {
@@ -230,60 +74,14 @@ __device__ __forceinline__ void bb_lane_positions(
                 x[3 * j + 2] = y[3 * j + 2] = z[3 * j + 2] = 0.f;
             }
         }
-        f = first_head < K;
         // the fixed rotations repeat every residue, so their float32 rounding
         // drifts the scale of long products coherently; one polar step per
         // lane aggregate (every 3K transforms) removes that drift
         aff_orthonormalise(m);
-        // segmented inclusive scan over the wave: (fa, A) + (fb, B) = (fa|fb, fb ? B : A B)
-#pragma unroll
-        for (int off = 1; off < kWave; off <<= 1) {
-            const Aff o = aff_shfl_up(m, off);
-            const int fo = __shfl_up((int)f, off, 64);
-            if (lane >= off) {
-                const Aff c = aff_compose(o, m);
-                m = aff_select(f, m, c);
-                f = f || (fo != 0);
-            }
-        }
-        if (lane == kWave - 1) {
-            aff_store(sh.tot[wave], m);
-            sh.tot_flag[wave] = f ? 1 : 0;
-        }
     }
-    __syncthreads();
+    const Aff X = block_exclusive_prefix(m, first_head < K, wave_active, sh);
     px = py = pz = 0.f;
     if (!wave_active) return;
-    // carry-in of this wave: segmented product of the totals of waves
-    // 0 .. wave-1, scanned redundantly by every wave (the tile starts with a
-    // chain head, so wave 0 has none)
-    Aff cw = aff_identity();
-    if (wave > 0) {
-        Aff t = aff_identity();
-        bool tf = false;
-        if (lane < wave) {
-            t = aff_load(sh.tot[lane]);
-            tf = sh.tot_flag[lane] != 0;
-        }
-        for (int off = 1; off < wave; off <<= 1) {
-            const Aff o = aff_shfl_up(t, off);
-            const int fo = __shfl_up((int)tf, off, 64);
-            if (lane >= off) {
-                const Aff c = aff_compose(o, t);
-                t = aff_select(tf, t, c);
-                tf = tf || (fo != 0);
-            }
-        }
-        cw = aff_bcast(t, wave - 1);
-    }
-    Aff e = aff_shfl_up(m, 1);
-    int fe = __shfl_up((int)f, 1, 64);
-    if (lane == 0) {
-        e = aff_identity();
-        fe = 0;
-    }
-    const Aff xc = aff_compose(cw, e);
-    const Aff X = fe ? e : xc;
     // previous atom position (origin when the lane's first residue is a head)
     if (!(hm & 1u)) { px = X.t0; py = X.t1; pz = X.t2; }
 #pragma unroll
@@ -299,11 +97,10 @@ __device__ __forceinline__ void bb_lane_positions(
     }
 }
 
-// ------------------------------------------------------------ adjoint scan
 // Angle gradients of one lane (gr[s][j]: slot s of residue j; slot 0 is
 // omega, 1 phi, 2 psi) from absolute positions, upstream gradients and the
 // atom before the lane: a reverse segmented scan of wrenches over the tile.
-// Every thread of the block calls this (one workgroup barrier inside).
+// Every thread of the block calls this.
 template <int K>
 __device__ __forceinline__ void bb_lane_adjoint(
     const uint32_t *__restrict__ head_bits, const BBParams &P, int64_t ts, int64_t te,
@@ -311,12 +108,11 @@ __device__ __forceinline__ void bb_lane_adjoint(
     const float (&gx)[3 * K], const float (&gy)[3 * K], const float (&gz)[3 * K], float px,
     float py, float pz, int cnt, uint32_t hm, float (&gr)[3][K])
 {
-    const int tid = threadIdx.x, lane = tid & 63;
+    const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int nw = blockDim.x >> 6;
     const int64_t rs = ts + (int64_t)tid * K;
     const bool wave_active = ts + (int64_t)wave * kWave * K < te;
-    // active waves of the tile
     const int nact = (int)min((int64_t)nw, (te - ts + kWave * K - 1) / (kWave * K));
 
     // residue j is the last of its chain when residue j+1 starts one (the bit
@@ -332,65 +128,14 @@ __device__ __forceinline__ void bb_lane_adjoint(
 #pragma unroll
                 for (int s = 0; s < 3; ++s) {
                     const int i = 3 * j + s;
-                    if (!f) {
-                        agg.g0 += gx[i]; agg.g1 += gy[i]; agg.g2 += gz[i];
-                        agg.m0 += y[i] * gz[i] - z[i] * gy[i];
-                        agg.m1 += z[i] * gx[i] - x[i] * gz[i];
-                        agg.m2 += x[i] * gy[i] - y[i] * gx[i];
-                    }
+                    if (!f) wrench_add_point(agg, x[i], y[i], z[i], gx[i], gy[i], gz[i]);
                 }
                 if ((lm >> j) & 1u) f = true;
             }
         }
-        // reverse segmented inclusive scan: Q_l = agg_l + (f_l ? 0 : Q_{l+1})
-#pragma unroll
-        for (int off = 1; off < kWave; off <<= 1) {
-            const Wrench o = wrench_shfl_down(agg, off);
-            const int fo = __shfl_down((int)f, off, 64);
-            if (lane + off < kWave) {
-                if (!f) wrench_add(agg, o);
-                f = f || (fo != 0);
-            }
-        }
-        if (lane == 0) {
-            sh.tot[wave][0] = agg.g0; sh.tot[wave][1] = agg.g1; sh.tot[wave][2] = agg.g2;
-            sh.tot[wave][3] = agg.m0; sh.tot[wave][4] = agg.m1; sh.tot[wave][5] = agg.m2;
-            sh.tot_flag[wave] = f ? 1 : 0;
-        }
     }
-    __syncthreads();
+    Wrench S = block_exclusive_suffix(agg, f, wave_active, nact, sh);
     if (!wave_active) return;
-    // carry-in from the waves after this one (segmented sum, scanned by
-    // every wave; the tile ends at a chain end, so the last wave has none)
-    Wrench cw = wrench_zero();
-    const int nafter = nact - 1 - wave;
-    if (nafter > 0) {
-        Wrench t = wrench_zero();
-        bool tf = false;
-        if (lane < nafter) {
-            const int w2 = wave + 1 + lane;
-            t.g0 = sh.tot[w2][0]; t.g1 = sh.tot[w2][1]; t.g2 = sh.tot[w2][2];
-            t.m0 = sh.tot[w2][3]; t.m1 = sh.tot[w2][4]; t.m2 = sh.tot[w2][5];
-            tf = sh.tot_flag[w2] != 0;
-        }
-        for (int off = 1; off < nafter; off <<= 1) {
-            const Wrench o = wrench_shfl_down(t, off);
-            const int fo = __shfl_down((int)tf, off, 64);
-            if (lane + off < kWave) {
-                if (!tf) wrench_add(t, o);
-                tf = tf || (fo != 0);
-            }
-        }
-        cw.g0 = lane_bcast(t.g0, 0); cw.g1 = lane_bcast(t.g1, 0); cw.g2 = lane_bcast(t.g2, 0);
-        cw.m0 = lane_bcast(t.m0, 0); cw.m1 = lane_bcast(t.m1, 0); cw.m2 = lane_bcast(t.m2, 0);
-    }
-    Wrench S = wrench_shfl_down(agg, 1);
-    int fs = __shfl_down((int)f, 1, 64);
-    if (lane == kWave - 1) {
-        S = wrench_zero();
-        fs = 0;
-    }
-    if (!fs) wrench_add(S, cw);
 #pragma unroll
     for (int j = K - 1; j >= 0; --j) {
         if (j < cnt) {
@@ -407,15 +152,8 @@ __device__ __forceinline__ void bb_lane_adjoint(
                 const float ux = (x[i] - qx) * P.inv_d[s];
                 const float uy = (y[i] - qy) * P.inv_d[s];
                 const float uz = (z[i] - qz) * P.inv_d[s];
-                // torque about r_i: S_rg - r_i x S_g
-                const float tx = S.m0 - (y[i] * S.g2 - z[i] * S.g1);
-                const float ty = S.m1 - (z[i] * S.g0 - x[i] * S.g2);
-                const float tz = S.m2 - (x[i] * S.g1 - y[i] * S.g0);
-                gr[s][j] = ux * tx + uy * ty + uz * tz;
-                S.g0 += gx[i]; S.g1 += gy[i]; S.g2 += gz[i];
-                S.m0 += y[i] * gz[i] - z[i] * gy[i];
-                S.m1 += z[i] * gx[i] - x[i] * gz[i];
-                S.m2 += x[i] * gy[i] - y[i] * gx[i];
+                gr[s][j] = wrench_torque(S, x[i], y[i], z[i], ux, uy, uz);
+                wrench_add_point(S, x[i], y[i], z[i], gx[i], gy[i], gz[i]);
             }
         } else {
             gr[0][j] = gr[1][j] = gr[2][j] = 0.f;

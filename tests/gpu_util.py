@@ -43,3 +43,13 @@ def run_backbone(plan, angles, g, mode="coords", variant="scan"):
                          workspace=ws)
     torch.cuda.synchronize()
     return coords.cpu().numpy(), grad.cpu().numpy()
+
+
+def run_fullatom(plan, angles, g, mode="coords"):
+    """Full-atom forward + backward; returns numpy (coords, grad [7][R])."""
+    a = to_dev(angles)
+    gg = to_dev(g)
+    coords = plan.forward(a)
+    grad = plan.backward(a, gg, coords=coords if mode == "coords" else None)
+    torch.cuda.synchronize()
+    return coords.cpu().numpy(), grad.cpu().numpy()

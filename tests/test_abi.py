@@ -92,3 +92,43 @@ def test_bad_geometry_rejected():
                              off.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                              None, ctypes.byref(g), None, None)
     assert st == -1 and "geometry" in lib.a2c_last_error().decode()
+
+
+def test_residue_table_rigid_groups_match_oracle():
+    """The library's rigid-group coordinates r°, derived from the table's
+    internal coordinates by its own code (NeRF vectors), equal the oracle's
+    (derived with the paper's 4x4 transforms) to float32 rounding."""
+    import oracle
+    from paper_1812_01108_amd import _lib
+    from paper_1812_01108_amd.residues import default_table
+    lib = _lib.load()
+    tab = default_table().to_struct()
+    n_atoms = (ctypes.c_int32 * 20)()
+    xyz = np.zeros((20, 14, 3), dtype=np.float32)
+    st = lib.a2c_residue_table_info(ctypes.byref(tab), n_atoms,
+                                    xyz.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
+    assert st == 0, lib.a2c_last_error()
+    otab, info = oracle.load_residue_table()
+    for t in range(20):
+        assert n_atoms[t] == otab.n_atoms[t] == len(info[t]["atoms"])
+        for a in range(n_atoms[t]):
+            ref = np.array([otab.atom_r[t][a][q] for q in range(3)])
+            assert np.max(np.abs(xyz[t, a] - ref)) < 1e-5, (info[t]["name"], a)
+
+
+@pytest.mark.parametrize("mutate,msg", [
+    (lambda rd: setattr(rd.frames[1], "parent", 1), "hang off"),
+    (lambda rd: setattr(rd.frames[1], "chi", 3), "chi"),
+    (lambda rd: setattr(rd.atoms[8], "ref", (ctypes.c_int32 * 3)(4, 5, 6)), "z-matrix"),
+    (lambda rd: setattr(rd.atoms[0], "kind", 1), "atoms 0, 1, 2"),
+    (lambda rd: setattr(rd, "n_atoms", 15), "n_atoms"),
+])
+def test_bad_residue_tables_rejected(mutate, msg):
+    from paper_1812_01108_amd import _lib
+    from paper_1812_01108_amd.residues import default_table
+    lib = _lib.load()
+    tab = default_table().to_struct()
+    mutate(tab.residues[4])          # PHE: two side frames, z-matrix ring atoms
+    st = lib.a2c_residue_table_info(ctypes.byref(tab), None, None)
+    assert st == -1
+    assert msg in lib.a2c_last_error().decode()
