@@ -24,13 +24,21 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
-# algorithmic bytes per residue of each kernel (float32): angles 12 B,
-# coordinates 36 B, upstream gradient 36 B, angle gradient 12 B
-BYTES_PER_RES = {
-    "forward": 12 + 36,
-    "backward_coords": 36 + 36 + 12,
-    "backward_recompute": 12 + 36 + 12,
-}
+# Algorithmic bytes per launch (float32): what each kernel must move.
+# Backbone, per residue: angles 12 B, coordinates 36 B, upstream gradient
+# 36 B, angle gradient 12 B.  Full-atom, per residue: angles 4 (3 + n_chi) B,
+# residue code 1 B, residue atom offset 4 B, 12 B per atom for coordinates
+# and for their gradient, 28 B of angle gradient (seven planes).
+def algorithmic_bytes(model, kernel, R, A=None, n_chi_total=None):
+    if model == "backbone":
+        per = {"forward": 12 + 36, "backward_coords": 36 + 36 + 12,
+               "backward_recompute": 12 + 36 + 12}[kernel]
+        return per * R
+    ang = 4 * (3 * R + n_chi_total)
+    meta = 5 * R
+    return {"forward": ang + meta + 12 * A,
+            "backward_recompute": ang + meta + 12 * A + 28 * R,
+            "backward_coords": meta + 24 * A + 28 * R}[kernel]
 
 
 def parse():
@@ -39,22 +47,31 @@ def parse():
     p.add_argument("--steps", type=int, default=200)
     p.add_argument("--warmup", type=int, default=20)
     p.add_argument("--workload", default="backbone_256x700")
-    p.add_argument("--mode", default="recompute", choices=["coords", "recompute"])
-    p.add_argument("--schedule", default=None, help="K,W (residues per lane, waves per group)")
+    p.add_argument("--mode", default=None, choices=["coords", "recompute"],
+                   help="adjoint reads the forward's coordinates, or recomputes the frames "
+                        "(default: coords; recompute for the training-step workload)")
+    p.add_argument("--schedule", default=None, help="K,W (residues per lane, waves per group); "
+                   "default: autotuned")
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="only run a plain 256 MiB device copy (HBM counter calibration)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-plain", action="store_true")
     p.add_argument("--kernel-reps", type=int, default=50)
     return p.parse_args()
 
 
-def make_step(a2c, plan, angles, grad_up, mode):
+def make_step(a2c, plan, angles, grad_up, mode, target=None):
+    """One step: forward through the autograd Function, then the adjoint for
+    the fixed upstream gradient, or (with a target) for the loss
+    sum |r - t|^2, whose gradient 2 (r - t) is formed inside the step."""
     import torch
 
     x = angles.clone().requires_grad_(True)
 
     def step():
         out = a2c.angles_to_coords(x, plan, mode=mode)
-        (gx,) = torch.autograd.grad(out, x, grad_up)
+        g = grad_up if target is None else 2.0 * (out - target)
+        (gx,) = torch.autograd.grad(out, x, g)
         return out, gx
 
     return step
@@ -132,34 +149,57 @@ def traffic_from_profiles(kernel_key, src_path, n_units):
         return None
 
 
-def cpu_baseline(inp, g_np, gpu_coords, gpu_grad, budget_s=12.0):
+def chain_grad_rel(gpu, ref, off):
+    worst = 0.0
+    for c in range(len(off) - 1):
+        r0, r1 = off[c], off[c + 1]
+        if r1 > r0:
+            sc = np.max(np.abs(ref[:, r0:r1]))
+            d = float(np.max(np.abs(gpu[:, r0:r1] - ref[:, r0:r1])))
+            worst = max(worst, d / sc if sc > 0 else d)
+    return worst
+
+
+def cpu_baseline(model, inp, g_np, gpu_coords, gpu_grad, budget_s=12.0):
+    """The FP64 oracle (forward + O(N) adjoint, OpenMP over chains) on the
+    full batch, repeated for about budget_s seconds of host time."""
     import oracle
     from workloads import BACKBONE_GEOMETRY
 
     cores = len(os.sched_getaffinity(0))
-    off, ang = inp["offsets"], inp["angles"]
+    off, ang, seq = inp["offsets"], inp["angles"], inp["seq"]
     R = int(off[-1])
     n, t_total = 0, 0.0
     ref = gref = None
     while t_total < budget_s and n < 1000:
         t0 = time.perf_counter()
-        ref = oracle.backbone_forward(off, ang, BACKBONE_GEOMETRY, n_threads=cores)
-        gref = oracle.backbone_backward(off, ang, BACKBONE_GEOMETRY, g_np, n_threads=cores)
+        if model == "backbone":
+            ref = oracle.backbone_forward(off, ang, BACKBONE_GEOMETRY, n_threads=cores)
+            gref = oracle.backbone_backward(off, ang, BACKBONE_GEOMETRY, g_np, n_threads=cores)
+        else:
+            ref, _ = oracle.fullatom_forward(off, seq, ang, BACKBONE_GEOMETRY, n_threads=cores)
+            gref = oracle.fullatom_backward(off, seq, ang, BACKBONE_GEOMETRY, g_np,
+                                            n_threads=cores)
         t_total += time.perf_counter() - t0
         n += 1
-    parity = None
-    if gpu_coords is not None:
-        cerr = float(np.max(np.abs(gpu_coords - ref)))
-        worst = 0.0
-        for c in range(len(off) - 1):
-            r0, r1 = off[c], off[c + 1]
-            if r1 > r0:
-                s = np.max(np.abs(gref[:, r0:r1]))
-                worst = max(worst, float(np.max(np.abs(gpu_grad[:, r0:r1] - gref[:, r0:r1])) / s))
-        parity = {"max_abs_coord_A": cerr, "max_chain_grad_rel": worst}
+    parity = {"max_abs_coord_A": float(np.max(np.abs(gpu_coords - ref))),
+              "max_chain_grad_rel": chain_grad_rel(gpu_grad, gref, off)}
     return {"value": n * R / t_total, "unit": "residues/s", "cores": cores, "kind": "oracle",
-            "sample": f"full batch ({R} residues) x {n} repeats, FP64 forward + O(N) adjoint, "
-                      f"OpenMP over chains"}, parity
+            "sample": f"full batch ({R} residues) x {n} repeats, FP64 {model} forward + O(N) "
+                      f"adjoint, OpenMP over chains"}, parity
+
+
+def copy_calibration(torch):
+    """A plain device copy of 256 MiB, ten times: under rocprofv3 --pmc its
+    FETCH_SIZE / WRITE_SIZE per dispatch give the counters' scale against a
+    known byte count."""
+    n = 64 * 1024 * 1024
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(10):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 10}))
 
 
 def main():
@@ -171,40 +211,69 @@ def main():
         sys.exit(2)
     import torch
 
+    if args.copy_calibration:
+        copy_calibration(torch)
+        return
+
     import paper_1812_01108_amd as a2c
     from workloads import CONFIGS, make_inputs, upstream_grad
 
     cfg = CONFIGS[args.workload]
-    if cfg.model != "backbone":
-        print("only backbone workloads are benchmarked by this script", file=sys.stderr)
-        sys.exit(2)
+    model = cfg.model
+    training = args.workload == "ragged_fullatom_512"
+    mode = args.mode if args.mode else ("recompute" if training else "coords")
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     inp = make_inputs(cfg)
     R = inp["n_res"]
-    plan = a2c.Plan("backbone", offsets=inp["offsets"], device=dev)
+    plan = a2c.Plan(model, offsets=inp["offsets"], seq=inp["seq"], device=dev)
+    angles = torch.from_numpy(inp["angles"]).to(dev)
+    target = None
+    if training:
+        # target: the layer on perturbed angles, then a random rigid motion
+        # per chain (built once, outside the timed region)
+        from workloads import target_perturbation
+        pert, quat, trans = target_perturbation(cfg.seed, inp["angles"], inp["n_chains"])
+        t_xyz = plan.forward(torch.from_numpy(pert).to(dev))
+        ca, _ = plan.atom_offsets()
+        counts = torch.from_numpy(np.diff(ca).astype(np.int64)).to(dev)
+        q = torch.from_numpy(quat).to(dev, torch.float64)
+        w, x, y, z = q.unbind(1)
+        rot = torch.stack([1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+                           2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+                           2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)],
+                          1).view(-1, 3, 3).float()
+        rot_a = torch.repeat_interleave(rot, counts, dim=0)
+        tr_a = torch.repeat_interleave(torch.from_numpy(trans).to(dev).float(), counts, dim=0)
+        target = torch.stack([rot_a[:, i, 0] * t_xyz[0] + rot_a[:, i, 1] * t_xyz[1] +
+                              rot_a[:, i, 2] * t_xyz[2] + tr_a[:, i] for i in range(3)])
+        torch.cuda.synchronize()
+    g_np = upstream_grad(cfg.seed, plan.n_atoms)
+    grad_up = torch.from_numpy(g_np).to(dev)
     if args.schedule:
         k, w = (int(v) for v in args.schedule.split(","))
         plan.set_schedule(k, w)
-    angles = torch.from_numpy(inp["angles"]).to(dev)
-    g_np = upstream_grad(cfg.seed, plan.n_atoms)
-    grad_up = torch.from_numpy(g_np).to(dev)
+    else:
+        plan.autotune(angles, grad_up, from_coords=mode == "coords", reps=5)
 
     # scan form, whole step in one graph
-    step = make_step(a2c, plan, angles, grad_up, args.mode)
+    step = make_step(a2c, plan, angles, grad_up, mode, target)
     graph, outs = capture(step)
     dt = time_graph(graph, args.steps, args.warmup)
     ms = dt * 1000.0 / args.steps
     value = R * args.steps / dt
     gpu_coords = outs[0].detach().cpu().numpy()
     gpu_grad = outs[1].detach().cpu().numpy()
+    if training:
+        g_np = 2.0 * (gpu_coords.astype(np.float64) - target.cpu().numpy())
+        grad_up = torch.from_numpy(g_np.astype(np.float32)).to(dev)
 
     # per-kernel durations for the roofline
     coords_buf = torch.empty((3, plan.n_atoms), device=dev)
     gang = torch.empty_like(angles)
     plan.forward(angles, coords_buf)
     fwd_us = kernel_avg_us(lambda: plan.forward(angles, coords_buf), args.kernel_reps)
-    if args.mode == "coords":
+    if mode == "coords":
         bwd_us = kernel_avg_us(lambda: plan.backward(angles, grad_up, coords=coords_buf,
                                                      grad_angles=gang), args.kernel_reps)
         bwd_key = "backward_coords"
@@ -214,16 +283,22 @@ def main():
         bwd_key = "backward_recompute"
     kern = {"forward": fwd_us, bwd_key: bwd_us}
     dom = max(kern, key=kern.get)
-    achieved = BYTES_PER_RES[dom] * R / (kern[dom] * 1e-6) / 1e9
-    src = os.path.join(ROOT, "paper_1812_01108_amd", "csrc", "backbone.hip")
+    n_chi_total = None
+    if model == "fullatom":
+        from paper_1812_01108_amd.residues import default_table
+        n_chi_total = int(np.sum(np.array(default_table().n_chi)[inp["seq"]]))
+    nbytes = algorithmic_bytes(model, dom, R, plan.n_atoms, n_chi_total)
+    achieved = nbytes / (kern[dom] * 1e-6) / 1e9
+    src = os.path.join(ROOT, "paper_1812_01108_amd", "csrc",
+                       "backbone.hip" if model == "backbone" else "fullatom.hip")
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic_from_profiles(dom, src, R), "kernel": dom,
+            "traffic": traffic_from_profiles(f"{cfg.name}:{dom}", src, R), "kernel": dom,
             "kernel_us": {k: round(v, 3) for k, v in kern.items()},
-            "bytes_per_residue": BYTES_PER_RES[dom]}
+            "bytes_per_launch": nbytes}
 
     plain = None
-    if not args.no_plain:
+    if model == "backbone" and not args.no_plain:
         pstep = make_step(a2c, plan, angles, grad_up, "plain")
         pgraph, _ = capture(pstep, warm=1)
         psteps = max(3, min(args.steps, 20))
@@ -234,7 +309,7 @@ def main():
 
     cpu, parity = (None, None)
     if not args.no_cpu_baseline:
-        cpu, parity = cpu_baseline(inp, g_np, gpu_coords, gpu_grad)
+        cpu, parity = cpu_baseline(model, inp, g_np, gpu_coords, gpu_grad)
 
     sched = plan.schedule
     line = {
@@ -242,8 +317,9 @@ def main():
         "value": value, "unit": "residues/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": cfg.name, "model": "backbone", "n_chains": inp["n_chains"],
-                   "residues": R, "angles": cfg.angles, "adjoint": args.mode,
+        "config": {"workload": cfg.name, "model": model, "n_chains": inp["n_chains"],
+                   "residues": R, "atoms": plan.n_atoms, "angles": cfg.angles,
+                   "adjoint": mode, "loss_in_graph": training,
                    "res_per_lane": sched["res_per_lane"],
                    "waves_per_group": sched["waves_per_group"], "tiles": sched["n_tiles"]},
         "roofline": roof,

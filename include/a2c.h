@@ -173,6 +173,25 @@ a2c_status a2c_plan_set_schedule(a2c_plan *plan, int32_t res_per_lane,
 a2c_status a2c_plan_get_schedule(const a2c_plan *plan, int32_t *res_per_lane,
                                  int32_t *waves_per_group, int32_t *n_tiles);
 
+/* Autotuner: times forward + backward (A2C_SCAN) for every valid schedule on
+ * the caller's buffers and keeps the fastest on the plan.
+ *   d_angles, d_coords, d_grad_coords, d_grad_angles: buffers of the plan's
+ *     sizes; their contents are overwritten (coords and grad_angles) or read.
+ *   backward_from_coords: nonzero times a2c_backward with d_coords (the
+ *     forward's output), zero times the recompute form.
+ *   reps: timed repetitions per candidate (>= 1).
+ *   cache_path: text file of earlier choices, keyed by device name, model,
+ *     residue count, longest chain, chain count and backward form; NULL for
+ *     none.  A hit skips the timing; a miss appends the new choice.  An
+ *     unreadable or malformed cache is ignored.
+ *   out_res_per_lane, out_waves_per_group (may be NULL): the choice.
+ * Synchronises `stream`; not capturable.  Call it before capturing a graph. */
+a2c_status a2c_plan_autotune(a2c_plan *plan, const float *d_angles, float *d_coords,
+                             const float *d_grad_coords, float *d_grad_angles,
+                             int32_t backward_from_coords, int32_t reps, const char *cache_path,
+                             int32_t *out_res_per_lane, int32_t *out_waves_per_group,
+                             void *stream);
+
 /* Forward map: d_angles [K][R] -> d_coords [3][A].
  * d_workspace: NULL for A2C_SCAN; for A2C_PLAIN a buffer of
  * a2c_plan_workspace_bytes that a2c_backward(A2C_PLAIN) reads later. */

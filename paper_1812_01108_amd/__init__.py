@@ -99,8 +99,8 @@ class Plan:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            _lib.load().a2c_plan_destroy(h)
+        if h is not None and h.value and _lib is not None and _lib._lib is not None:
+            _lib._lib.a2c_plan_destroy(h)
             self._h = None
 
     # -- plan queries ------------------------------------------------------
@@ -137,6 +137,26 @@ class Plan:
             check(_lib.load().a2c_plan_set_schedule(self._h, res_per_lane, waves_per_group,
                                                     _stream_ptr(self.device)),
                   "a2c_plan_set_schedule")
+
+    def autotune(self, angles: torch.Tensor, grad_coords: torch.Tensor | None = None,
+                 from_coords: bool = True, reps: int = 5, cache_path: str | None = None):
+        """Time every valid schedule on these buffers and keep the fastest
+        (synchronises; call before capturing a graph).  Returns the schedule."""
+        self._check_tensor(angles, (self.n_planes, self.n_res), "angles")
+        coords = torch.empty((3, self.n_atoms), dtype=torch.float32, device=angles.device)
+        if grad_coords is None:
+            grad_coords = torch.ones_like(coords)
+        self._check_tensor(grad_coords, (3, self.n_atoms), "grad_coords")
+        grad = torch.empty_like(angles)
+        k, w = ctypes.c_int32(), ctypes.c_int32()
+        with torch.cuda.device(self.device):
+            check(_lib.load().a2c_plan_autotune(
+                self._h, ctypes.c_void_p(angles.data_ptr()), ctypes.c_void_p(coords.data_ptr()),
+                ctypes.c_void_p(grad_coords.data_ptr()), ctypes.c_void_p(grad.data_ptr()),
+                1 if from_coords else 0, reps,
+                None if cache_path is None else cache_path.encode(), ctypes.byref(k),
+                ctypes.byref(w), _stream_ptr(self.device)), "a2c_plan_autotune")
+        return self.schedule
 
     # -- raw calls (no autograd) ------------------------------------------
     def _check_tensor(self, t, shape, name):

@@ -25,6 +25,7 @@ ATOM_ORIGIN, ATOM_AZIMUTH, ATOM_ZMATRIX = 0, 1, 2
 EXPORTS = (
     "a2c_plan_create", "a2c_plan_destroy", "a2c_plan_sizes", "a2c_plan_atom_offsets",
     "a2c_plan_workspace_bytes", "a2c_plan_set_schedule", "a2c_plan_get_schedule",
+    "a2c_plan_autotune",
     "a2c_forward", "a2c_backward", "a2c_residue_table_info", "a2c_status_string",
     "a2c_last_error", "a2c_version",
 )
@@ -83,6 +84,9 @@ def load():
     lib.a2c_plan_workspace_bytes.argtypes = [vp, ctypes.c_int, P(sz)]
     lib.a2c_plan_set_schedule.argtypes = [vp, i32, i32, vp]
     lib.a2c_plan_get_schedule.argtypes = [vp, P(i32), P(i32), P(i32)]
+    lib.a2c_plan_autotune.argtypes = [vp, vp, vp, vp, vp, i32, i32, ctypes.c_char_p, P(i32),
+                                      P(i32), vp]
+    lib.a2c_plan_autotune.restype = ctypes.c_int
     lib.a2c_forward.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp]
     lib.a2c_backward.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp, vp, vp]
     for name in ("a2c_plan_sizes", "a2c_plan_atom_offsets", "a2c_plan_workspace_bytes",

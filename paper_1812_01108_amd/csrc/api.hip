@@ -134,6 +134,11 @@ a2c_status hip_fail(hipError_t e, const char *what)
 
 a2c_status build_fullatom_tables(a2c_plan *p, const a2c_residue_table *table);
 
+a2c_status plan_apply_schedule(a2c_plan *p, int32_t K, int32_t W, hipStream_t s)
+{
+    return apply_schedule(p, K, W, s);
+}
+
 }  // namespace a2c
 
 using namespace a2c;

@@ -1,0 +1,151 @@
+// Schedule autotuner: times forward + backward for every valid (residues per
+// lane, waves per workgroup) with HIP events and keeps the fastest; choices
+// can be kept in a small text cache.
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "a2c_internal.h"
+
+namespace a2c {
+a2c_status plan_apply_schedule(a2c_plan *p, int32_t K, int32_t W, hipStream_t s);
+}
+
+using namespace a2c;
+
+namespace {
+
+std::string cache_key(const a2c_plan *p, int from_coords)
+{
+    hipDeviceProp_t prop;
+    std::string dev = "unknown";
+    if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) dev = prop.gcnArchName;
+    for (char &c : dev)
+        if (c == ' ' || c == ':') c = '_';
+    std::ostringstream k;
+    k << dev << ' ' << (p->model == A2C_BACKBONE ? "backbone" : "fullatom") << ' ' << p->R << ' '
+      << p->max_len << ' ' << p->n_chains << ' ' << (from_coords ? "coords" : "recompute");
+    return k.str();
+}
+
+bool cache_lookup(const char *path, const std::string &key, int32_t &K, int32_t &W)
+{
+    if (!path) return false;
+    std::ifstream f(path);
+    if (!f) return false;
+    std::string line;
+    bool found = false;
+    while (std::getline(f, line)) {
+        if (line.compare(0, key.size(), key) != 0 || line.size() <= key.size() ||
+            line[key.size()] != ' ')
+            continue;
+        int k = 0, w = 0;
+        if (std::sscanf(line.c_str() + key.size(), " %d %d", &k, &w) == 2) {
+            K = k;
+            W = w;
+            found = true;  // the last matching line wins
+        }
+    }
+    return found;
+}
+
+void cache_store(const char *path, const std::string &key, int32_t K, int32_t W)
+{
+    if (!path) return;
+    std::ofstream f(path, std::ios::app);
+    if (f) f << key << ' ' << K << ' ' << W << '\n';
+}
+
+}  // namespace
+
+extern "C" a2c_status a2c_plan_autotune(a2c_plan *p, const float *d_angles, float *d_coords,
+                                        const float *d_grad_coords, float *d_grad_angles,
+                                        int32_t from_coords, int32_t reps, const char *cache_path,
+                                        int32_t *out_K, int32_t *out_W, void *stream)
+{
+    if (!p) {
+        set_error("plan is NULL");
+        return A2C_ERR_INVALID_ARG;
+    }
+    if (reps < 1) {
+        set_error("reps must be >= 1");
+        return A2C_ERR_INVALID_ARG;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (p->R == 0) {
+        if (out_K) *out_K = p->K;
+        if (out_W) *out_W = p->W;
+        return A2C_OK;
+    }
+    if (!d_angles || !d_coords || !d_grad_coords || !d_grad_angles) {
+        set_error("NULL buffer");
+        return A2C_ERR_INVALID_ARG;
+    }
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != p->device) {
+        set_error("current device is not the plan's device");
+        return A2C_ERR_STATE;
+    }
+    const std::string key = cache_key(p, from_coords);
+    int32_t K = 0, W = 0;
+    if (cache_lookup(cache_path, key, K, W)) {
+        if (plan_apply_schedule(p, K, W, s) == A2C_OK) {
+            if (out_K) *out_K = K;
+            if (out_W) *out_W = W;
+            return A2C_OK;
+        }
+    }
+    const int Ks[3] = {1, 2, 4};
+    const int Ws[8] = {1, 2, 3, 4, 6, 8, 12, 16};
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return hip_fail(hipGetLastError(), "hipEventCreate");
+    float best = 1e30f;
+    int32_t bK = p->K, bW = p->W;
+    a2c_status st = A2C_OK;
+    for (int k : Ks) {
+        if (p->model == A2C_FULLATOM && k == 4) continue;
+        for (int w : Ws) {
+            if ((int64_t)kWave * k * w < p->max_len) continue;
+            st = plan_apply_schedule(p, k, w, s);
+            if (st != A2C_OK) break;
+            float cand = 1e30f;
+            for (int trial = 0; trial < 3 && st == A2C_OK; ++trial) {
+                (void)hipEventRecord(e0, s);
+                for (int r = 0; r < reps && st == A2C_OK; ++r) {
+                    st = a2c_forward(p, A2C_SCAN, d_angles, d_coords, nullptr, s);
+                    if (st == A2C_OK)
+                        st = a2c_backward(p, A2C_SCAN, d_angles, from_coords ? d_coords : nullptr,
+                                          d_grad_coords, d_grad_angles, nullptr, s);
+                }
+                (void)hipEventRecord(e1, s);
+                if (hipEventSynchronize(e1) != hipSuccess) {
+                    st = hip_fail(hipGetLastError(), "hipEventSynchronize");
+                    break;
+                }
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                if (trial > 0) cand = std::min(cand, ms);  // first trial warms up
+            }
+            if (st != A2C_OK) break;
+            if (cand < best) {
+                best = cand;
+                bK = k;
+                bW = w;
+            }
+        }
+        if (st != A2C_OK) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != A2C_OK) return st;
+    st = plan_apply_schedule(p, bK, bW, s);
+    if (st != A2C_OK) return st;
+    cache_store(cache_path, key, bK, bW);
+    if (out_K) *out_K = bK;
+    if (out_W) *out_W = bW;
+    return A2C_OK;
+}

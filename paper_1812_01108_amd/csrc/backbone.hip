@@ -51,22 +51,41 @@ __device__ __forceinline__ void bb_lane_positions(
     hm = 0;
     if (wave_active) {
         if (cnt > 0) hm = head_mask<K>(head_bits, rs);
+        // sin/cos of all 3K angles up front, with one wave-uniform choice
+        // between the branch-free reduction and sincosf (huge or non-finite
+        // arguments), so the independent evaluations interleave
+        float so[K], co[K], sp[K], cp[K], ss[K], cs[K];
+        bool ok = true;
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            ok = ok && sincos_fast_ok(om[j]) && sincos_fast_ok(phi[j]) && sincos_fast_ok(psi[j]);
+        if (__all(ok)) {
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                sincos_fast(om[j], so[j], co[j]);
+                sincos_fast(phi[j], sp[j], cp[j]);
+                sincos_fast(psi[j], ss[j], cs[j]);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                sincosf(om[j], &so[j], &co[j]);
+                sincosf(phi[j], &sp[j], &cp[j]);
+                sincosf(psi[j], &ss[j], &cs[j]);
+            }
+        }
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             if (j < cnt) {
-                float so, co, sp, cp, ss, cs;
-                sincosf(om[j], &so, &co);
-                sincosf(phi[j], &sp, &cp);
-                sincosf(psi[j], &ss, &cs);
                 if ((hm >> j) & 1u) {
                     m = aff_identity();
                     if (first_head == K) first_head = j;
                 }
-                aff_apply_transform(m, P.ct[0], P.st[0], P.d[0], co, so);
+                aff_apply_transform(m, P.ct[0], P.st[0], P.d[0], co[j], so[j]);
                 x[3 * j] = m.t0; y[3 * j] = m.t1; z[3 * j] = m.t2;
-                aff_apply_transform(m, P.ct[1], P.st[1], P.d[1], cp, sp);
+                aff_apply_transform(m, P.ct[1], P.st[1], P.d[1], cp[j], sp[j]);
                 x[3 * j + 1] = m.t0; y[3 * j + 1] = m.t1; z[3 * j + 1] = m.t2;
-                aff_apply_transform(m, P.ct[2], P.st[2], P.d[2], cs, ss);
+                aff_apply_transform(m, P.ct[2], P.st[2], P.d[2], cs[j], ss[j]);
                 x[3 * j + 2] = m.t0; y[3 * j + 2] = m.t1; z[3 * j + 2] = m.t2;
             } else {
                 x[3 * j] = y[3 * j] = z[3 * j] = 0.f;

@@ -283,12 +283,33 @@ __device__ __forceinline__ Aff fa_lane_aggregate(const float *__restrict__ ang, 
 {
     Aff m = aff_identity();
     first_head = K;
+    float phi[K], psi[K], om[K];
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        phi[j] = j < cnt ? ang[rs + j] : 0.f;
+        psi[j] = j < cnt ? ang[R + rs + j] : 0.f;
+        om[j] = j < cnt ? ang[2 * R + rs + j] : 0.f;
+        ok = ok && sincos_fast_ok(om[j]) && sincos_fast_ok(phi[j]) && sincos_fast_ok(psi[j]);
+    }
+    if (__all(ok)) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            sincos_fast(phi[j], in[j].sp, in[j].cp);
+            sincos_fast(psi[j], in[j].ss, in[j].cs);
+            sincos_fast(om[j], in[j].so, in[j].co);
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            sincosf(phi[j], &in[j].sp, &in[j].cp);
+            sincosf(psi[j], &in[j].ss, &in[j].cs);
+            sincosf(om[j], &in[j].so, &in[j].co);
+        }
+    }
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         if (j < cnt) {
-            sincosf(ang[rs + j], &in[j].sp, &in[j].cp);
-            sincosf(ang[R + rs + j], &in[j].ss, &in[j].cs);
-            sincosf(ang[2 * R + rs + j], &in[j].so, &in[j].co);
             if ((hm >> j) & 1u) {
                 m = aff_identity();
                 if (first_head == K) first_head = j;
@@ -305,7 +326,10 @@ __device__ __forceinline__ Aff fa_lane_aggregate(const float *__restrict__ ang, 
 __device__ __forceinline__ void side_step(Aff &sf, const FAType &ft, int f, float chi)
 {
     float c = 1.f, s = 0.f;
-    if (ft.side_chi[f]) sincosf(chi, &s, &c);
+    if (ft.side_chi[f]) {
+        if (__all(sincos_fast_ok(chi))) sincos_fast(chi, s, c);
+        else sincosf(chi, &s, &c);
+    }
     aff_apply_transform(sf, ft.ct[f], ft.st[f], ft.d[f], c, s);
 }
 

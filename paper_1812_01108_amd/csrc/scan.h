@@ -13,6 +13,7 @@
 #pragma once
 #include "a2c_internal.h"
 #include "affine.h"
+#include "sincos.h"
 
 namespace a2c {
 
@@ -104,6 +105,69 @@ __device__ __forceinline__ Aff aff_load(const float *src)
     return m;
 }
 
+// ------------------------------------------------------------ DPP moves
+// Cross-lane moves within the wave through the DPP path of the VALU (no LDS
+// round trip): row_shr/row_shl:n shift inside rows of 16 lanes, row_bcast:15
+// and row_bcast:31 carry the last lane of a row (of rows 0-1) to the next
+// rows, wave_shr/wave_shl:1 shift the whole wave by one lane.  Lanes without
+// a source read 0; callers only use lanes that have one.
+constexpr int kDppRowShr = 0x110, kDppRowShl = 0x100, kDppBcast15 = 0x142, kDppBcast31 = 0x143,
+              kDppWaveShr1 = 0x138, kDppWaveShl1 = 0x130;
+
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ float dpp_f(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, false));
+}
+
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ int dpp_i(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, ROW_MASK, 0xf, false);
+}
+
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ Aff aff_dpp(const Aff &a)
+{
+    Aff o;
+    o.r00 = dpp_f<CTRL, ROW_MASK>(a.r00); o.r10 = dpp_f<CTRL, ROW_MASK>(a.r10);
+    o.r20 = dpp_f<CTRL, ROW_MASK>(a.r20); o.r01 = dpp_f<CTRL, ROW_MASK>(a.r01);
+    o.r11 = dpp_f<CTRL, ROW_MASK>(a.r11); o.r21 = dpp_f<CTRL, ROW_MASK>(a.r21);
+    o.r02 = dpp_f<CTRL, ROW_MASK>(a.r02); o.r12 = dpp_f<CTRL, ROW_MASK>(a.r12);
+    o.r22 = dpp_f<CTRL, ROW_MASK>(a.r22); o.t0 = dpp_f<CTRL, ROW_MASK>(a.t0);
+    o.t1 = dpp_f<CTRL, ROW_MASK>(a.t1); o.t2 = dpp_f<CTRL, ROW_MASK>(a.t2);
+    return o;
+}
+
+template <int CTRL>
+__device__ __forceinline__ Wrench wrench_dpp(const Wrench &a)
+{
+    Wrench o;
+    o.g0 = dpp_f<CTRL>(a.g0); o.g1 = dpp_f<CTRL>(a.g1); o.g2 = dpp_f<CTRL>(a.g2);
+    o.m0 = dpp_f<CTRL>(a.m0); o.m1 = dpp_f<CTRL>(a.m1); o.m2 = dpp_f<CTRL>(a.m2);
+    return o;
+}
+
+// one step of the segmented affine scan: lanes with `take` combine with the
+// value o received from earlier lanes
+__device__ __forceinline__ void aff_scan_combine(Aff &m, bool &f, const Aff &o, int fo, bool take)
+{
+    if (take) {
+        const Aff c = aff_compose(o, m);
+        m = aff_select(f, m, c);
+        f = f || (fo != 0);
+    }
+}
+
+__device__ __forceinline__ void wrench_scan_combine(Wrench &w, bool &f, const Wrench &o, int fo,
+                                                    bool take)
+{
+    if (take) {
+        if (!f) wrench_add(w, o);
+        f = f || (fo != 0);
+    }
+}
+
 __device__ __forceinline__ float lane_bcast(float v, int src_lane)
 {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src_lane));
@@ -132,16 +196,16 @@ __device__ __forceinline__ Aff block_exclusive_prefix(Aff m, bool f, bool wave_a
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (wave_active) {
-#pragma unroll
-        for (int off = 1; off < kWave; off <<= 1) {
-            const Aff o = aff_shfl_up(m, off);
-            const int fo = __shfl_up((int)f, off, 64);
-            if (lane >= off) {
-                const Aff c = aff_compose(o, m);
-                m = aff_select(f, m, c);
-                f = f || (fo != 0);
-            }
-        }
+        // inclusive scan: four shifts inside rows of 16, then the row totals
+        const int rl = lane & 15;
+        aff_scan_combine(m, f, aff_dpp<kDppRowShr + 1>(m), dpp_i<kDppRowShr + 1>(f), rl >= 1);
+        aff_scan_combine(m, f, aff_dpp<kDppRowShr + 2>(m), dpp_i<kDppRowShr + 2>(f), rl >= 2);
+        aff_scan_combine(m, f, aff_dpp<kDppRowShr + 4>(m), dpp_i<kDppRowShr + 4>(f), rl >= 4);
+        aff_scan_combine(m, f, aff_dpp<kDppRowShr + 8>(m), dpp_i<kDppRowShr + 8>(f), rl >= 8);
+        aff_scan_combine(m, f, aff_dpp<kDppBcast15, 0xa>(m), dpp_i<kDppBcast15, 0xa>(f),
+                         (lane & 16) != 0);
+        aff_scan_combine(m, f, aff_dpp<kDppBcast31, 0xc>(m), dpp_i<kDppBcast31, 0xc>(f),
+                         lane >= 32);
         if (lane == kWave - 1) {
             aff_store(sh.tot[wave], m);
             sh.tot_flag[wave] = f ? 1 : 0;
@@ -170,8 +234,8 @@ __device__ __forceinline__ Aff block_exclusive_prefix(Aff m, bool f, bool wave_a
         }
         cw = aff_bcast(t, wave - 1);
     }
-    Aff e = aff_shfl_up(m, 1);
-    int fe = __shfl_up((int)f, 1, 64);
+    Aff e = aff_dpp<kDppWaveShr1>(m);
+    int fe = dpp_i<kDppWaveShr1>(f);
     if (lane == 0) {
         e = aff_identity();
         fe = 0;
@@ -192,14 +256,35 @@ __device__ __forceinline__ Wrench block_exclusive_suffix(Wrench agg, bool f, boo
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (wave_active) {
-#pragma unroll
-        for (int off = 1; off < kWave; off <<= 1) {
-            const Wrench o = wrench_shfl_down(agg, off);
-            const int fo = __shfl_down((int)f, off, 64);
-            if (lane + off < kWave) {
-                if (!f) wrench_add(agg, o);
-                f = f || (fo != 0);
-            }
+        // inclusive reverse scan: four shifts inside rows, then the suffix
+        // totals of rows 1 and 3 (lanes 16, 48) and of rows 2-3 (lane 32)
+        const int rl = lane & 15;
+        wrench_scan_combine(agg, f, wrench_dpp<kDppRowShl + 1>(agg), dpp_i<kDppRowShl + 1>(f), rl < 15);
+        wrench_scan_combine(agg, f, wrench_dpp<kDppRowShl + 2>(agg), dpp_i<kDppRowShl + 2>(f), rl < 14);
+        wrench_scan_combine(agg, f, wrench_dpp<kDppRowShl + 4>(agg), dpp_i<kDppRowShl + 4>(f), rl < 12);
+        wrench_scan_combine(agg, f, wrench_dpp<kDppRowShl + 8>(agg), dpp_i<kDppRowShl + 8>(f), rl < 8);
+        {
+            const int src = lane < 16 ? 16 : 48;
+            Wrench o;
+            const float a0 = lane_bcast(agg.g0, 16), b0 = lane_bcast(agg.g0, 48);
+            const float a1 = lane_bcast(agg.g1, 16), b1 = lane_bcast(agg.g1, 48);
+            const float a2 = lane_bcast(agg.g2, 16), b2 = lane_bcast(agg.g2, 48);
+            const float a3 = lane_bcast(agg.m0, 16), b3 = lane_bcast(agg.m0, 48);
+            const float a4 = lane_bcast(agg.m1, 16), b4 = lane_bcast(agg.m1, 48);
+            const float a5 = lane_bcast(agg.m2, 16), b5 = lane_bcast(agg.m2, 48);
+            const int fa = __builtin_amdgcn_readlane((int)f, 16), fb = __builtin_amdgcn_readlane((int)f, 48);
+            const bool lo = src == 16;
+            o.g0 = lo ? a0 : b0; o.g1 = lo ? a1 : b1; o.g2 = lo ? a2 : b2;
+            o.m0 = lo ? a3 : b3; o.m1 = lo ? a4 : b4; o.m2 = lo ? a5 : b5;
+            wrench_scan_combine(agg, f, o, lo ? fa : fb, (lane & 16) == 0);
+        }
+        {
+            Wrench o;
+            o.g0 = lane_bcast(agg.g0, 32); o.g1 = lane_bcast(agg.g1, 32);
+            o.g2 = lane_bcast(agg.g2, 32); o.m0 = lane_bcast(agg.m0, 32);
+            o.m1 = lane_bcast(agg.m1, 32); o.m2 = lane_bcast(agg.m2, 32);
+            const int fo = __builtin_amdgcn_readlane((int)f, 32);
+            wrench_scan_combine(agg, f, o, fo, lane < 32);
         }
         if (lane == 0) {
             sh.tot[wave][0] = agg.g0; sh.tot[wave][1] = agg.g1; sh.tot[wave][2] = agg.g2;
@@ -233,8 +318,8 @@ __device__ __forceinline__ Wrench block_exclusive_suffix(Wrench agg, bool f, boo
         cw.g0 = lane_bcast(t.g0, 0); cw.g1 = lane_bcast(t.g1, 0); cw.g2 = lane_bcast(t.g2, 0);
         cw.m0 = lane_bcast(t.m0, 0); cw.m1 = lane_bcast(t.m1, 0); cw.m2 = lane_bcast(t.m2, 0);
     }
-    Wrench S = wrench_shfl_down(agg, 1);
-    int fs = __shfl_down((int)f, 1, 64);
+    Wrench S = wrench_dpp<kDppWaveShl1>(agg);
+    int fs = dpp_i<kDppWaveShl1>(f);
     if (lane == kWave - 1) {
         S = wrench_zero();
         fs = 0;

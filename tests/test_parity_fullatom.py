@@ -84,8 +84,9 @@ def test_full_size_workloads(name):
 
 
 def test_fullatom_backbone_matches_backbone_model():
-    """Backbone atoms of the full-atom path equal the backbone path's output
-    bit for bit (same spine arithmetic)."""
+    """Backbone atoms of the full-atom path agree with the backbone path's
+    output (the paper's own comparison of the two models); the two kernels
+    round in different orders, so they agree to the float32 parity bound."""
     a2c = _a2c()
     off, seq, ang = _batch([300, 77, 500], 107)
     fa = a2c.Plan("fullatom", offsets=off, seq=seq)
@@ -98,7 +99,7 @@ def test_fullatom_backbone_matches_backbone_model():
     xb = bb.forward(a3).cpu().numpy()
     _, ra = fa.atom_offsets()
     for s in range(3):
-        assert np.max(np.abs(xf[:, ra[:-1] + s] - xb[:, s::3])) < 1e-4
+        assert np.max(np.abs(xf[:, ra[:-1] + s] - xb[:, s::3])) < COORD_TOL_A
 
 
 @pytest.mark.parametrize("mode", ["coords", "recompute"])
