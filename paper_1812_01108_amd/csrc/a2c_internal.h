@@ -6,7 +6,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/a2c.h"
+#include "a2c.h"
 
 namespace a2c {
 

@@ -36,21 +36,16 @@ __device__ __forceinline__ int slot_plane(int s) { return s == 0 ? 2 : (s == 1 ?
 template <int K>
 __device__ __forceinline__ void bb_lane_positions(
     const float (&phi)[K], const float (&psi)[K], const float (&om)[K],
-    const uint32_t *__restrict__ head_bits, const BBParams &P, int64_t ts, int64_t te,
-    FwdShared &sh, float (&x)[3 * K], float (&y)[3 * K], float (&z)[3 * K], float &px,
-    float &py, float &pz, int &cnt, uint32_t &hm)
+    const BBParams &P, int64_t ts, int64_t te, FwdShared &sh, float (&x)[3 * K], float (&y)[3 * K], float (&z)[3 * K], float &px,
+    float &py, float &pz, int cnt, uint32_t hm)
 {
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int64_t rs = ts + (int64_t)tid * K;
-    cnt = (int)max((int64_t)0, min((int64_t)K, te - rs));
     const bool wave_active = ts + (int64_t)wave * kWave * K < te;
 
     Aff m = aff_identity();
     int first_head = K;    // residues before it need the carry-in frame
-    hm = 0;
     if (wave_active) {
-        if (cnt > 0) hm = head_mask<K>(head_bits, rs);
         // sin/cos of all 3K angles up front, with one wave-uniform choice
         // between the branch-free reduction and sincosf (huge or non-finite
         // arguments), so the independent evaluations interleave
@@ -122,25 +117,22 @@ __device__ __forceinline__ void bb_lane_positions(
 // Every thread of the block calls this.
 template <int K>
 __device__ __forceinline__ void bb_lane_adjoint(
-    const uint32_t *__restrict__ head_bits, const BBParams &P, int64_t ts, int64_t te,
+    const BBParams &P, int64_t ts, int64_t te,
     BwdShared &sh, const float (&x)[3 * K], const float (&y)[3 * K], const float (&z)[3 * K],
     const float (&gx)[3 * K], const float (&gy)[3 * K], const float (&gz)[3 * K], float px,
-    float py, float pz, int cnt, uint32_t hm, float (&gr)[3][K])
+    float py, float pz, int cnt, uint32_t hm, uint32_t lm, float (&gr)[3][K])
 {
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int nw = blockDim.x >> 6;
-    const int64_t rs = ts + (int64_t)tid * K;
     const bool wave_active = ts + (int64_t)wave * kWave * K < te;
     const int nact = (int)min((int64_t)nw, (te - ts + kWave * K - 1) / (kWave * K));
 
-    // residue j is the last of its chain when residue j+1 starts one (the bit
-    // array also marks R, and tiles end at chain ends)
-    uint32_t lm = 0;
+    // lm: residue j is the last of its chain when residue j+1 starts one (the
+    // bit array also marks R, and tiles end at chain ends)
     Wrench agg = wrench_zero();
     bool f = false;
     if (wave_active) {
-        if (cnt > 0) lm = head_mask<K>(head_bits, rs + 1);
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             if (j < cnt) {
@@ -208,6 +200,11 @@ __global__ __launch_bounds__(1024) void bb_forward_scan_kernel(
     const int64_t rbase = ts + (int64_t)wave * kWave * K;
     const bool active = rbase < te;
     const int nres = (int)min((int64_t)kWave * K, te - rbase);  // residues of this wave
+    const int64_t rs = ts + (int64_t)threadIdx.x * K;
+    const int cnt = (int)max((int64_t)0, min((int64_t)K, te - rs));
+    // chain-head bits before the angle loads: the LDS transposes below are
+    // fenced, and a load issued after them would wait for the angles
+    const uint32_t hm = cnt > 0 ? head_mask<K>(head_bits, rs) : 0u;
     float phi[K], psi[K], om[K];
     if (active) {
         float v0[K], v1[K], v2[K];
@@ -220,9 +217,7 @@ __global__ __launch_bounds__(1024) void bb_forward_scan_kernel(
     }
     float x[3 * K], y[3 * K], z[3 * K];
     float px, py, pz;
-    int cnt;
-    uint32_t hm;
-    bb_lane_positions<K>(phi, psi, om, head_bits, P, ts, te, sh, x, y, z, px, py, pz, cnt, hm);
+    bb_lane_positions<K>(phi, psi, om, P, ts, te, sh, x, y, z, px, py, pz, cnt, hm);
     if (active) {
         const int64_t A = 3 * R;
         float *out = xyz + 3 * rbase;
@@ -249,6 +244,10 @@ __global__ __launch_bounds__(1024) void bb_backward_recompute_kernel(
     const bool active = rbase < te;
     const int nres = (int)min((int64_t)kWave * K, te - rbase);
     const int64_t A = 3 * R;
+    const int64_t rs = ts + (int64_t)threadIdx.x * K;
+    const int cnt = (int)max((int64_t)0, min((int64_t)K, te - rs));
+    const uint32_t hm = cnt > 0 ? head_mask<K>(head_bits, rs) : 0u;
+    const uint32_t lm = cnt > 0 ? head_mask<K>(head_bits, rs + 1) : 0u;
     float phi[K], psi[K], om[K];
     float gx[3 * K], gy[3 * K], gz[3 * K];
     if (active) {
@@ -269,11 +268,9 @@ __global__ __launch_bounds__(1024) void bb_backward_recompute_kernel(
     }
     float x[3 * K], y[3 * K], z[3 * K];
     float px, py, pz;
-    int cnt;
-    uint32_t hm;
-    bb_lane_positions<K>(phi, psi, om, head_bits, P, ts, te, shf, x, y, z, px, py, pz, cnt, hm);
+    bb_lane_positions<K>(phi, psi, om, P, ts, te, shf, x, y, z, px, py, pz, cnt, hm);
     float gr[3][K];
-    bb_lane_adjoint<K>(head_bits, P, ts, te, shb, x, y, z, gx, gy, gz, px, py, pz, cnt, hm, gr);
+    bb_lane_adjoint<K>(P, ts, te, shb, x, y, z, gx, gy, gz, px, py, pz, cnt, hm, lm, gr);
     if (active) store_angle_grads<K>(buf, gr, gang, R, rbase, nres);
 }
 
@@ -297,7 +294,14 @@ __global__ __launch_bounds__(1024) void bb_backward_coords_kernel(
     const int cnt = (int)max((int64_t)0, min((int64_t)K, te - rs));
     const int64_t A = 3 * R;
     float x[3 * K], y[3 * K], z[3 * K], gx[3 * K], gy[3 * K], gz[3 * K];
-    uint32_t hm = 0;
+    const uint32_t hm = cnt > 0 ? head_mask<K>(head_bits, rs) : 0u;
+    const uint32_t lm = cnt > 0 ? head_mask<K>(head_bits, rs + 1) : 0u;
+    // the atom before lane 0 of the wave (read before the fenced transposes)
+    float px0 = 0.f, py0 = 0.f, pz0 = 0.f;
+    if (lane == 0 && cnt > 0 && !(hm & 1u)) {
+        const float *xb = xyz + 3 * rs;
+        px0 = xb[-1]; py0 = xb[A - 1]; pz0 = xb[2 * A - 1];
+    }
     float px = 0.f, py = 0.f, pz = 0.f;
     if (active) {
         const float *xb = xyz + 3 * rbase;
@@ -320,19 +324,18 @@ __global__ __launch_bounds__(1024) void bb_backward_coords_kernel(
             to_blocked<3 * K>(buf, w1, 3 * nres, gy);
             to_blocked<3 * K>(buf, w2, 3 * nres, gz);
         }
-        if (cnt > 0) hm = head_mask<K>(head_bits, rs);
         // the atom before the lane: last atom of the previous lane, or of the
         // previous wave's run for lane 0 (the origin when a chain starts here)
-        const float lx = __shfl_up(x[3 * K - 1], 1, 64);
-        const float ly = __shfl_up(y[3 * K - 1], 1, 64);
-        const float lz = __shfl_up(z[3 * K - 1], 1, 64);
+        const float lx = dpp_f<kDppWaveShr1>(x[3 * K - 1]);
+        const float ly = dpp_f<kDppWaveShr1>(y[3 * K - 1]);
+        const float lz = dpp_f<kDppWaveShr1>(z[3 * K - 1]);
         if (cnt > 0 && !(hm & 1u)) {
             if (lane > 0) { px = lx; py = ly; pz = lz; }
-            else { px = xb[-1]; py = xb[A - 1]; pz = xb[2 * A - 1]; }
+            else { px = px0; py = py0; pz = pz0; }
         }
     }
     float gr[3][K];
-    bb_lane_adjoint<K>(head_bits, P, ts, te, shb, x, y, z, gx, gy, gz, px, py, pz, cnt, hm, gr);
+    bb_lane_adjoint<K>(P, ts, te, shb, x, y, z, gx, gy, gz, px, py, pz, cnt, hm, lm, gr);
     if (active) store_angle_grads<K>(buf, gr, gang, R, rbase, nres);
 }
 
