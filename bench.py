@@ -133,16 +133,18 @@ def kernel_avg_us(launch, reps):
     return best
 
 
-def traffic_from_profiles(kernel_key, src_path, n_units):
+def traffic_from_profiles(kernel_key, src_path, n_units, schedule):
     """HBM bytes per launch from committed rocprofv3 counter summaries, valid
-    only while the kernel source they were taken from is unchanged."""
+    only while the kernel source they were taken from is unchanged and for
+    the schedule they were taken with."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     try:
         rec = json.load(open(path)).get(kernel_key)
         sha = hashlib.sha256(open(src_path, "rb").read()).hexdigest()[:16]
-        if not rec or rec.get("source_sha") != sha or rec.get("units") != n_units:
+        if (not rec or rec.get("source_sha") != sha or rec.get("units") != n_units
+                or rec.get("schedule") != list(schedule)):
             return None
         return rec["bytes_per_launch"]
     except Exception:
@@ -293,7 +295,10 @@ def main():
                        "backbone.hip" if model == "backbone" else "fullatom.hip")
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic_from_profiles(f"{cfg.name}:{dom}", src, R), "kernel": dom,
+            "traffic": traffic_from_profiles(
+                f"{cfg.name}:{dom}", src, R,
+                (plan.schedule["res_per_lane"], plan.schedule["waves_per_group"])),
+            "kernel": dom,
             "kernel_us": {k: round(v, 3) for k, v in kern.items()},
             "bytes_per_launch": nbytes}
 
