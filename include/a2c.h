@@ -140,9 +140,12 @@ typedef struct {
  *   geom           backbone geometry or NULL for the defaults above.
  *   table          residue table, required for A2C_FULLATOM.
  *   stream         used for the table uploads; the call synchronises it.
- * Fails with A2C_ERR_INVALID_ARG on malformed offsets or codes >= 20, and
- * with A2C_ERR_UNSUPPORTED if a chain is longer than the longest tile the
- * kernels can hold (4096 residues).  *out is NULL on failure.            */
+ * Picks a default schedule (a2c_plan_set_schedule) that runs the longest
+ * chain.  Fails with A2C_ERR_INVALID_ARG on malformed offsets or codes >= 20,
+ * and with A2C_ERR_UNSUPPORTED, before any device call, if a chain is longer
+ * than 64 chunks of the widest schedule (262144 residues for A2C_BACKBONE,
+ * 131072 for A2C_FULLATOM), or if the full-atom default schedule cannot stage
+ * its atoms in LDS.  *out is NULL on failure.                             */
 a2c_status a2c_plan_create(a2c_plan **out, a2c_model model, int32_t n_chains,
                            const int32_t *h_res_offsets, const uint8_t *h_seq,
                            const a2c_backbone_geometry *geom,
@@ -163,18 +166,27 @@ a2c_status a2c_plan_atom_offsets(const a2c_plan *plan, int32_t *h_chain_atom_off
 a2c_status a2c_plan_workspace_bytes(const a2c_plan *plan, a2c_variant variant,
                                     size_t *bytes);
 
-/* Scan schedule: residues per lane (1, 2 or 4) and waves of 64 lanes per
- * workgroup (1..16).  Whole chains are packed into tiles of at most
- * 64 * waves * res_per_lane residues, one tile per workgroup.  Re-packs and
- * re-uploads the tile table (synchronises `stream`).  UNSUPPORTED if some
- * chain does not fit one tile. */
+/* Scan schedule: residues per lane (1, 2 or 4 for A2C_BACKBONE; 1 or 2 for
+ * A2C_FULLATOM) and waves of 64 lanes per workgroup (1..16).  A chunk is
+ * 64 * waves * res_per_lane consecutive residues.  Chains of at most one
+ * chunk are packed whole, in order, into tiles of at most one chunk; a longer
+ * chain gets a tile of its own, which one workgroup walks chunk by chunk
+ * (at most 64 chunks), carrying the frame (forward) and the wrench (adjoint)
+ * from chunk to chunk.  One workgroup per tile.  Re-packs and re-uploads the
+ * tile table (synchronises `stream`).  UNSUPPORTED, leaving the plan's
+ * schedule as it was, if the longest chain needs more than 64 chunks or, for
+ * A2C_FULLATOM, if the waves' atoms of one chunk (three float planes each)
+ * exceed 136 KiB of LDS per workgroup.  (The full-atom adjoint from
+ * coordinates stages six planes; where those do not fit, it recomputes the
+ * frames from the angles instead, with the same result.) */
 a2c_status a2c_plan_set_schedule(a2c_plan *plan, int32_t res_per_lane,
                                  int32_t waves_per_group, void *stream);
 a2c_status a2c_plan_get_schedule(const a2c_plan *plan, int32_t *res_per_lane,
                                  int32_t *waves_per_group, int32_t *n_tiles);
 
-/* Autotuner: times forward + backward (A2C_SCAN) for every valid schedule on
- * the caller's buffers and keeps the fastest on the plan.
+/* Autotuner: times forward + backward (A2C_SCAN) for every schedule that
+ * a2c_plan_set_schedule accepts for the plan, on the caller's buffers, and
+ * keeps the fastest on the plan.
  *   d_angles, d_coords, d_grad_coords, d_grad_angles: buffers of the plan's
  *     sizes; their contents are overwritten (coords and grad_angles) or read.
  *   backward_from_coords: nonzero times a2c_backward with d_coords (the
@@ -211,6 +223,42 @@ a2c_status a2c_forward(a2c_plan *plan, a2c_variant variant, const float *d_angle
 a2c_status a2c_backward(a2c_plan *plan, a2c_variant variant, const float *d_angles,
                         const float *d_coords, const float *d_grad_coords,
                         float *d_grad_angles, void *d_workspace, void *stream);
+
+/* ----------------------------------------------------------------- LRMSD
+ * The loss the paper pairs with the map (section "Loss function"): for each
+ * chain c of the plan, with x the target and y the input coordinates of its
+ * N atoms, x~ and y~ the sets centred on their means and
+ * R = sum_i x~_i y~_i^T,
+ *   LRMSD_c = min over rigid motions of the root-mean-square deviation
+ *           = sqrt((sum |x~|^2 + sum |y~|^2 - 2 lambda) / N),
+ * lambda the largest eigenvalue of the section's 4x4 matrix T(R), q its unit
+ * eigenvector and U(q) the section's rotation, which maps the target onto
+ * the input (U x~_i ~ y~_i).  The gradient with respect to the input is
+ *   dLRMSD_c / dy_i = (y~_i - U x~_i) / (N LRMSD_c),
+ * taken as 0 for a chain with LRMSD_c = 0 or no atoms.  (The section prints
+ * the derivative with respect to the target without the 1 / (N LRMSD)
+ * factor.)  Sums are accumulated in float64; at a repeated largest
+ * eigenvalue U is one of the optimal rotations and the gradient is not
+ * unique.
+ *
+ * Workspace: a device buffer of a2c_lrmsd_workspace_bytes, owned by the
+ * caller; a2c_lrmsd_forward fills it (per-chain U, means and 1 / (N LRMSD))
+ * and a2c_lrmsd_backward reads it, so the backward needs the same buffer,
+ * untouched, and the same coordinates and target. */
+a2c_status a2c_lrmsd_workspace_bytes(const a2c_plan *plan, size_t *bytes);
+
+/* d_coords, d_target: [3][A] float32 planes (the plan's atom layout);
+ * d_lrmsd: float32[n_chains] per-chain LRMSD.  Two kernels on `stream`, no
+ * allocation, no synchronisation (capturable). */
+a2c_status a2c_lrmsd_forward(a2c_plan *plan, const float *d_coords, const float *d_target,
+                             float *d_lrmsd, void *d_workspace, void *stream);
+
+/* d_grad_lrmsd: float32[n_chains] upstream gradient of each LRMSD_c;
+ * writes d_grad_coords [3][A] = sum_c d_grad_lrmsd[c] dLRMSD_c / dy (zero for
+ * atoms of empty or zero-LRMSD chains).  One kernel on `stream`. */
+a2c_status a2c_lrmsd_backward(a2c_plan *plan, const float *d_coords, const float *d_target,
+                              const float *d_grad_lrmsd, float *d_grad_coords,
+                              const void *d_workspace, void *stream);
 
 /* Host-only check of a residue table (no device needed): validates it as
  * a2c_plan_create would and reports, per residue type, the atom count

@@ -18,8 +18,8 @@ import torch
 from . import _lib
 from ._lib import A2C_BACKBONE, A2C_FULLATOM, A2C_PLAIN, A2C_SCAN, A2CError, check
 
-__all__ = ["Plan", "Angles2Coords", "angles_to_coords", "A2CError", "library_version",
-           "DEFAULT_GEOMETRY"]
+__all__ = ["Plan", "Angles2Coords", "angles_to_coords", "LRMSD", "lrmsd", "A2CError",
+           "library_version", "DEFAULT_GEOMETRY"]
 
 DEFAULT_GEOMETRY = {
     "bond_N_CA": 1.458, "bond_CA_C": 1.525, "bond_C_N": 1.329,
@@ -195,6 +195,72 @@ class Plan:
             None if workspace is None else ctypes.c_void_p(workspace.data_ptr()),
             _stream_ptr(angles.device)), "a2c_backward")
         return grad_angles
+
+
+    # -- LRMSD loss -------------------------------------------------------
+    def lrmsd_workspace(self) -> torch.Tensor | None:
+        n = ctypes.c_size_t()
+        check(_lib.load().a2c_lrmsd_workspace_bytes(self._h, ctypes.byref(n)),
+              "a2c_lrmsd_workspace_bytes")
+        if n.value == 0:
+            return None
+        return torch.empty(n.value // 4, dtype=torch.float32, device=self.device)
+
+    def lrmsd_forward(self, coords: torch.Tensor, target: torch.Tensor, workspace=None,
+                      out: torch.Tensor | None = None) -> torch.Tensor:
+        """Per-chain LRMSD [n_chains] between coords (input) and target; fills
+        `workspace` (from lrmsd_workspace) for lrmsd_backward."""
+        self._check_tensor(coords, (3, self.n_atoms), "coords")
+        self._check_tensor(target, (3, self.n_atoms), "target")
+        if out is None:
+            out = torch.empty(self.n_chains, dtype=torch.float32, device=coords.device)
+        self._check_tensor(out, (self.n_chains,), "out")
+        check(_lib.load().a2c_lrmsd_forward(
+            self._h, ctypes.c_void_p(coords.data_ptr()), ctypes.c_void_p(target.data_ptr()),
+            ctypes.c_void_p(out.data_ptr()),
+            None if workspace is None else ctypes.c_void_p(workspace.data_ptr()),
+            _stream_ptr(coords.device)), "a2c_lrmsd_forward")
+        return out
+
+    def lrmsd_backward(self, coords: torch.Tensor, target: torch.Tensor,
+                       grad_lrmsd: torch.Tensor, workspace,
+                       grad_coords: torch.Tensor | None = None) -> torch.Tensor:
+        self._check_tensor(coords, (3, self.n_atoms), "coords")
+        self._check_tensor(target, (3, self.n_atoms), "target")
+        self._check_tensor(grad_lrmsd, (self.n_chains,), "grad_lrmsd")
+        if grad_coords is None:
+            grad_coords = torch.zeros_like(coords)
+        self._check_tensor(grad_coords, (3, self.n_atoms), "grad_coords")
+        check(_lib.load().a2c_lrmsd_backward(
+            self._h, ctypes.c_void_p(coords.data_ptr()), ctypes.c_void_p(target.data_ptr()),
+            ctypes.c_void_p(grad_lrmsd.data_ptr()), ctypes.c_void_p(grad_coords.data_ptr()),
+            None if workspace is None else ctypes.c_void_p(workspace.data_ptr()),
+            _stream_ptr(coords.device)), "a2c_lrmsd_backward")
+        return grad_coords
+
+
+class LRMSD(torch.autograd.Function):
+    """lrmsd = LRMSD.apply(coords, target, plan): per-chain LRMSD [n_chains];
+    the gradient flows to coords (the target is a constant)."""
+
+    @staticmethod
+    def forward(ctx, coords, target, plan: Plan):
+        coords, target = coords.contiguous(), target.contiguous()
+        ws = plan.lrmsd_workspace()
+        out = plan.lrmsd_forward(coords, target, ws)
+        ctx.plan, ctx.ws = plan, ws
+        ctx.save_for_backward(coords, target)
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        coords, target = ctx.saved_tensors
+        g = ctx.plan.lrmsd_backward(coords, target, grad_out.contiguous(), ctx.ws)
+        return g, None, None
+
+
+def lrmsd(coords: torch.Tensor, target: torch.Tensor, plan: Plan) -> torch.Tensor:
+    return LRMSD.apply(coords, target, plan)
 
 
 class Angles2Coords(torch.autograd.Function):

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libangles2coords.so")
-SOURCES = ["api.hip", "backbone.hip", "fullatom.hip", "autotune.hip"]
+SOURCES = ["api.hip", "backbone.hip", "fullatom.hip", "autotune.hip", "lrmsd.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-Wall", "-Wno-unused-function",

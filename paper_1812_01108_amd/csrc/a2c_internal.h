@@ -12,7 +12,12 @@ namespace a2c {
 
 constexpr int kWave = 64;
 constexpr int kMaxWaves = 16;
-constexpr int kMaxTileResidues = kWave * kMaxWaves * 4;  // 4096
+constexpr int kMaxChunks = 64;        // chunks of 64 W K residues per tile
+// dynamic LDS allowed to the full-atom kernels (160 KB per workgroup on
+// gfx950, less the static tables)
+constexpr int kMaxDynamicLds = 136 * 1024;
+// LRMSD: atoms per segment (one workgroup of 256 lanes, 16 atoms per lane)
+constexpr int kLrSegAtoms = 4096;
 
 // Backbone slot constants in float32, slot order N (omega), CA (phi), C (psi).
 // (ct, st) is a float32 pair chosen so that ct^2 + st^2 is as close to 1 as
@@ -58,6 +63,8 @@ struct a2c_plan {
     std::vector<uint8_t> seq;
     // schedule
     int32_t K = 4, W = 4, n_tiles = 0;
+    int32_t fa_stage_atoms = 0;          // per-wave staging (floats per plane)
+    bool multi_chunk = false;            // some tile spans several chunks
     // device tables
     int32_t *d_tile_res = nullptr;       // n_tiles + 1 residue offsets of tiles
     uint32_t *d_head_bits = nullptr;     // bit r: residue r starts a chain (bit R set)
@@ -67,6 +74,14 @@ struct a2c_plan {
     a2c::FATable *d_fa = nullptr;        // full-atom constants
     a2c::BBParams bb{};
     a2c::FATable fa_host{};
+    // LRMSD segments: runs of at most kLrSegAtoms atoms of one chain
+    int32_t lr_n_seg = 0;
+    std::vector<int32_t> lr_seg_atom;    // lr_n_seg + 1 first atoms (last = A)
+    std::vector<int32_t> lr_seg_chain;   // lr_n_seg chain of each segment
+    std::vector<int32_t> lr_chain_seg;   // n_chains + 1 first segment of each chain
+    int32_t *d_lr_seg_atom = nullptr;
+    int32_t *d_lr_seg_chain = nullptr;
+    int32_t *d_lr_chain_seg = nullptr;
 };
 
 namespace a2c {
@@ -87,5 +102,9 @@ hipError_t launch_bb_backward_plain(const a2c_plan &p, const float *ang, const f
 hipError_t launch_fa_forward_scan(const a2c_plan &p, const float *ang, float *xyz, hipStream_t s);
 hipError_t launch_fa_backward_scan(const a2c_plan &p, const float *ang, const float *xyz,
                                    const float *g, float *gang, hipStream_t s);
+size_t fa_dynamic_lds(const a2c_plan &p);
+void build_lrmsd_segments(a2c_plan &p);
+size_t lrmsd_workspace_bytes(const a2c_plan &p);
+void fa_allow_large_lds();
 
 }  // namespace a2c

@@ -39,8 +39,10 @@ a2c_status upload(void **dst, const void *src, size_t bytes, hipStream_t s)
     return A2C_OK;
 }
 
-// Greedy packing of whole chains, in order, into tiles of at most `cap`
-// residues.  Zero-length chains produce nothing and never open a tile.
+// Greedy packing of whole chains, in order, into tiles: chains of at most one
+// chunk (`cap` residues) share tiles of at most `cap` residues; a longer chain
+// gets a tile of its own, which the kernels walk chunk by chunk.  Zero-length
+// chains produce nothing and never open a tile.
 std::vector<int32_t> pack_tiles(const std::vector<int32_t> &off, int64_t cap)
 {
     std::vector<int32_t> tiles;
@@ -50,11 +52,15 @@ std::vector<int32_t> pack_tiles(const std::vector<int32_t> &off, int64_t cap)
     for (size_t c = 0; c < n; ++c) {
         const int64_t L = off[c + 1] - off[c];
         if (L == 0) continue;
-        if (cur > 0 && cur + L > cap) {
+        if (cur > 0 && (cur + L > cap || L > cap)) {
             tiles.push_back(off[c]);
             cur = 0;
         }
         cur += L;
+        if (L > cap) {  // a long chain closes its own tile
+            tiles.push_back(off[c + 1]);
+            cur = 0;
+        }
     }
     if (cur > 0) tiles.push_back(off[n]);
     if (tiles.size() == 1) tiles.clear();  // no residues
@@ -63,12 +69,40 @@ std::vector<int32_t> pack_tiles(const std::vector<int32_t> &off, int64_t cap)
 
 a2c_status apply_schedule(a2c_plan *p, int32_t K, int32_t W, hipStream_t s)
 {
-    const int64_t cap = (int64_t)kWave * W * K;
-    if (p->max_len > cap)
+    const int64_t cap = (int64_t)kWave * W * K;  // residues per chunk
+    if (p->max_len > cap * kMaxChunks)
         return fail(A2C_ERR_UNSUPPORTED, "a chain of " + std::to_string(p->max_len) +
-                                             " residues does not fit a tile of " +
-                                             std::to_string(cap));
+                                             " residues needs more than " +
+                                             std::to_string(kMaxChunks) + " chunks of " +
+                                             std::to_string(cap) + " residues");
     std::vector<int32_t> tiles = pack_tiles(p->res_off, cap);
+    int32_t stage_atoms = 0;
+    if (p->model == A2C_FULLATOM) {
+        // largest atom run of one wave in one chunk: the per-wave staging size
+        const int64_t per_wave = (int64_t)kWave * K;
+        for (size_t t = 0; t + 1 < tiles.size(); ++t)
+            for (int64_t cs = tiles[t]; cs < tiles[t + 1]; cs += cap) {
+                const int64_t ce = std::min<int64_t>(cs + cap, tiles[t + 1]);
+                for (int64_t rb = cs; rb < ce; rb += per_wave) {
+                    const int64_t re = std::min<int64_t>(rb + per_wave, ce);
+                    stage_atoms = std::max<int32_t>(
+                        stage_atoms, p->res_atom_off[re] - p->res_atom_off[rb]);
+                }
+            }
+        stage_atoms = std::max<int32_t>(stage_atoms, 1);
+        // three planes (forward, recompute adjoint); the coordinate-mode
+        // adjoint stages six and uses the recompute form where they do not fit
+        const size_t lds = (size_t)W * 3 * stage_atoms * sizeof(float);
+        if (lds > (size_t)kMaxDynamicLds)
+            return fail(A2C_ERR_UNSUPPORTED,
+                        "full-atom staging of " + std::to_string(stage_atoms) +
+                            " atoms per wave needs " + std::to_string(lds) +
+                            " bytes of LDS; use fewer waves or residues per lane");
+    }
+    p->fa_stage_atoms = stage_atoms;
+    p->multi_chunk = false;
+    for (size_t t = 0; t + 1 < tiles.size(); ++t)
+        if (tiles[t + 1] - tiles[t] > cap) p->multi_chunk = true;
     p->K = K;
     p->W = W;
     p->n_tiles = tiles.empty() ? 0 : (int32_t)tiles.size() - 1;
@@ -79,11 +113,20 @@ a2c_status apply_schedule(a2c_plan *p, int32_t K, int32_t W, hipStream_t s)
     return A2C_OK;
 }
 
+// One chunk per chain where a 16-wave chunk holds it; full-atom keeps four
+// waves so the per-wave atom staging stays small, and widens the chunk only
+// when its longest chain would need more than kMaxChunks chunks.
 void default_schedule(const a2c_plan &p, int32_t &K, int32_t &W)
 {
-    K = p.model == A2C_BACKBONE ? 4 : 2;
+    K = p.model == A2C_BACKBONE ? 4 : 1;
     const int64_t per_wave = (int64_t)kWave * K;
-    W = (int32_t)std::max<int64_t>(1, (p.max_len + per_wave - 1) / per_wave);
+    const int64_t wmax = p.model == A2C_BACKBONE ? kMaxWaves : 4;
+    W = (int32_t)std::min<int64_t>(wmax, std::max<int64_t>(1, (p.max_len + per_wave - 1) / per_wave));
+    while ((int64_t)p.max_len > (int64_t)kWave * W * K * kMaxChunks) {
+        if (W < kMaxWaves) W = std::min<int32_t>(kMaxWaves, 2 * W);
+        else if (K < 2) K = 2;
+        else break;  // plan_create has already rejected longer chains
+    }
 }
 
 bool check_device(const a2c_plan *p)
@@ -171,6 +214,9 @@ void a2c_plan_destroy(a2c_plan *p)
     (void)hipFree(p->d_res_atom_off);
     (void)hipFree(p->d_seq);
     (void)hipFree(p->d_fa);
+    (void)hipFree(p->d_lr_seg_atom);
+    (void)hipFree(p->d_lr_seg_chain);
+    (void)hipFree(p->d_lr_chain_seg);
     delete p;
 }
 
@@ -197,7 +243,7 @@ a2c_status a2c_plan_create(a2c_plan **out, a2c_model model, int32_t n_chains,
     const int64_t R = h_res_offsets[n_chains];
     if (R > (int64_t)std::numeric_limits<int32_t>::max() / 16)
         return fail(A2C_ERR_UNSUPPORTED, "too many residues for int32 atom offsets");
-    const int32_t max_tile = model == A2C_BACKBONE ? kMaxTileResidues : kMaxTileResidues / 2;
+    const int32_t max_tile = kMaxChunks * kWave * kMaxWaves * (model == A2C_BACKBONE ? 4 : 2);
     if (max_len > max_tile)
         return fail(A2C_ERR_UNSUPPORTED, "chain longer than " + std::to_string(max_tile) +
                                              " residues");
@@ -270,6 +316,18 @@ a2c_status a2c_plan_create(a2c_plan **out, a2c_model model, int32_t n_chains,
         if (st == A2C_OK) st = upload((void **)&p->d_seq, p->seq.data(), p->seq.size(), s);
         if (st == A2C_OK) st = upload((void **)&p->d_fa, &p->fa_host, sizeof(FATable), s);
     }
+    if (st == A2C_OK) {
+        build_lrmsd_segments(*p);
+        st = upload((void **)&p->d_lr_seg_atom, p->lr_seg_atom.data(),
+                    p->lr_seg_atom.size() * sizeof(int32_t), s);
+        if (st == A2C_OK)
+            st = upload((void **)&p->d_lr_seg_chain, p->lr_seg_chain.data(),
+                        p->lr_seg_chain.size() * sizeof(int32_t), s);
+        if (st == A2C_OK)
+            st = upload((void **)&p->d_lr_chain_seg, p->lr_chain_seg.data(),
+                        p->lr_chain_seg.size() * sizeof(int32_t), s);
+    }
+    if (st == A2C_OK && model == A2C_FULLATOM) fa_allow_large_lds();
     if (st == A2C_OK) {
         int32_t K, W;
         default_schedule(*p, K, W);

@@ -109,8 +109,11 @@ extern "C" a2c_status a2c_plan_autotune(a2c_plan *p, const float *d_angles, floa
     for (int k : Ks) {
         if (p->model == A2C_FULLATOM && k == 4) continue;
         for (int w : Ws) {
-            if ((int64_t)kWave * k * w < p->max_len) continue;
             st = plan_apply_schedule(p, k, w, s);
+            if (st == A2C_ERR_UNSUPPORTED) {  // too many chunks, or staging beyond LDS
+                st = A2C_OK;
+                continue;
+            }
             if (st != A2C_OK) break;
             float cand = 1e30f;
             for (int trial = 0; trial < 3 && st == A2C_OK; ++trial) {

@@ -33,15 +33,14 @@ __device__ __forceinline__ int slot_plane(int s) { return s == 0 ? 2 : (s == 1 ?
 // Absolute atom positions of one lane's residues (x[3j+s], ...), given its
 // angles, and the position of the atom just before the lane (the origin when
 // the lane starts a chain).  Every thread of the block calls this.
-template <int K>
+template <int K, bool MULTI>
 __device__ __forceinline__ void bb_lane_positions(
     const float (&phi)[K], const float (&psi)[K], const float (&om)[K],
-    const BBParams &P, int64_t ts, int64_t te, FwdShared &sh, float (&x)[3 * K], float (&y)[3 * K], float (&z)[3 * K], float &px,
-    float &py, float &pz, int cnt, uint32_t hm)
+    const BBParams &P, int nact, FwdShared &sh, Aff &carry, float (&x)[3 * K],
+    float (&y)[3 * K], float (&z)[3 * K], float &px, float &py, float &pz, int cnt, uint32_t hm)
 {
-    const int tid = threadIdx.x;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const bool wave_active = ts + (int64_t)wave * kWave * K < te;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const bool wave_active = wave < nact;
 
     Aff m = aff_identity();
     int first_head = K;    // residues before it need the carry-in frame
@@ -93,7 +92,7 @@ __device__ __forceinline__ void bb_lane_positions(
         // lane aggregate (every 3K transforms) removes that drift
         aff_orthonormalise(m);
     }
-    const Aff X = block_exclusive_prefix(m, first_head < K, wave_active, sh);
+    const Aff X = block_exclusive_prefix<MULTI>(m, first_head < K, nact, sh, carry);
     px = py = pz = 0.f;
     if (!wave_active) return;
     // previous atom position (origin when the lane's first residue is a head)
@@ -115,18 +114,15 @@ __device__ __forceinline__ void bb_lane_positions(
 // omega, 1 phi, 2 psi) from absolute positions, upstream gradients and the
 // atom before the lane: a reverse segmented scan of wrenches over the tile.
 // Every thread of the block calls this.
-template <int K>
+template <int K, bool MULTI>
 __device__ __forceinline__ void bb_lane_adjoint(
-    const BBParams &P, int64_t ts, int64_t te,
-    BwdShared &sh, const float (&x)[3 * K], const float (&y)[3 * K], const float (&z)[3 * K],
+    const BBParams &P, int nact, BwdShared &sh, Wrench &carry,
+    const float (&x)[3 * K], const float (&y)[3 * K], const float (&z)[3 * K],
     const float (&gx)[3 * K], const float (&gy)[3 * K], const float (&gz)[3 * K], float px,
     float py, float pz, int cnt, uint32_t hm, uint32_t lm, float (&gr)[3][K])
 {
-    const int tid = threadIdx.x;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int nw = blockDim.x >> 6;
-    const bool wave_active = ts + (int64_t)wave * kWave * K < te;
-    const int nact = (int)min((int64_t)nw, (te - ts + kWave * K - 1) / (kWave * K));
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const bool wave_active = wave < nact;
 
     // lm: residue j is the last of its chain when residue j+1 starts one (the
     // bit array also marks R, and tiles end at chain ends)
@@ -145,7 +141,7 @@ __device__ __forceinline__ void bb_lane_adjoint(
             }
         }
     }
-    Wrench S = block_exclusive_suffix(agg, f, wave_active, nact, sh);
+    Wrench S = block_exclusive_suffix<MULTI>(agg, f, nact, sh, carry);
     if (!wave_active) return;
 #pragma unroll
     for (int j = K - 1; j >= 0; --j) {
@@ -187,156 +183,235 @@ constexpr size_t stage_bytes(int waves)
     return (size_t)waves * kWave * Stride<3 * K>::value * sizeof(float);
 }
 
+// Chunk c of a tile: residues [cs, ce) handled by the waves wave < nact.
+struct Chunk {
+    int64_t cs, ce;
+    int nact;
+};
+
 template <int K>
+__device__ __forceinline__ Chunk chunk_of(int64_t ts, int64_t te, int c)
+{
+    const int nw = blockDim.x >> 6;
+    const int64_t ch = (int64_t)kWave * K * nw;
+    Chunk k;
+    k.cs = ts + (int64_t)c * ch;
+    k.ce = min(k.cs + ch, te);
+    k.nact = (int)min((int64_t)nw, (k.ce - k.cs + kWave * K - 1) / (kWave * K));
+    return k;
+}
+
+template <int K>
+__device__ __forceinline__ int chunks_of(int64_t ts, int64_t te)
+{
+    const int64_t ch = (int64_t)kWave * K * (blockDim.x >> 6);
+    return (int)((te - ts + ch - 1) / ch);
+}
+
+// Angles of one wave's run -> lane-blocked phi, psi, omega.
+template <int K>
+__device__ __forceinline__ void load_angles(float *buf, const float *__restrict__ ang, int64_t R,
+                                            int64_t rbase, int nres, float (&phi)[K],
+                                            float (&psi)[K], float (&om)[K])
+{
+    float v0[K], v1[K], v2[K];
+    gload<K>(ang + rbase, nres, v0);
+    gload<K>(ang + R + rbase, nres, v1);
+    gload<K>(ang + 2 * R + rbase, nres, v2);
+    to_blocked<K>(buf, v0, nres, phi);
+    to_blocked<K>(buf, v1, nres, psi);
+    to_blocked<K>(buf, v2, nres, om);
+}
+
+template <int K, bool MULTI>
 __global__ __launch_bounds__(1024) void bb_forward_scan_kernel(
     const float *__restrict__ ang, float *__restrict__ xyz, const int32_t *__restrict__ tile_res,
     const uint32_t *__restrict__ head_bits, int64_t R, BBParams P)
 {
     extern __shared__ float stage_mem[];
-    __shared__ FwdShared sh;
+    __shared__ FwdShared sh[2];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     float *buf = stage_mem + wave * kWave * Stride<3 * K>::value;
     const int64_t ts = tile_res[blockIdx.x], te = tile_res[blockIdx.x + 1];
-    const int64_t rbase = ts + (int64_t)wave * kWave * K;
-    const bool active = rbase < te;
-    const int nres = (int)min((int64_t)kWave * K, te - rbase);  // residues of this wave
-    const int64_t rs = ts + (int64_t)threadIdx.x * K;
-    const int cnt = (int)max((int64_t)0, min((int64_t)K, te - rs));
-    // chain-head bits before the angle loads: the LDS transposes below are
-    // fenced, and a load issued after them would wait for the angles
-    const uint32_t hm = cnt > 0 ? head_mask<K>(head_bits, rs) : 0u;
-    float phi[K], psi[K], om[K];
-    if (active) {
-        float v0[K], v1[K], v2[K];
-        gload<K>(ang + rbase, nres, v0);
-        gload<K>(ang + R + rbase, nres, v1);
-        gload<K>(ang + 2 * R + rbase, nres, v2);
-        to_blocked<K>(buf, v0, nres, phi);
-        to_blocked<K>(buf, v1, nres, psi);
-        to_blocked<K>(buf, v2, nres, om);
-    }
-    float x[3 * K], y[3 * K], z[3 * K];
-    float px, py, pz;
-    bb_lane_positions<K>(phi, psi, om, P, ts, te, sh, x, y, z, px, py, pz, cnt, hm);
-    if (active) {
-        const int64_t A = 3 * R;
-        float *out = xyz + 3 * rbase;
-        stage_store<3 * K>(buf, x, out, 3 * nres);
-        stage_store<3 * K>(buf, y, out + A, 3 * nres);
-        stage_store<3 * K>(buf, z, out + 2 * A, 3 * nres);
+    const int64_t A = 3 * R;
+    // MULTI = false: every tile is one chunk (straight-line code)
+    const int nch = MULTI ? chunks_of<K>(ts, te) : 1;
+    Aff carry = aff_identity();
+    for (int c = 0; c < nch; ++c) {
+        const Chunk k = chunk_of<K>(ts, te, c);
+        const int64_t rbase = k.cs + (int64_t)wave * kWave * K;
+        const bool active = wave < k.nact;
+        const int nres = active ? (int)min((int64_t)kWave * K, k.ce - rbase) : 0;
+        const int64_t rs = k.cs + (int64_t)threadIdx.x * K;
+        const int cnt = (int)max((int64_t)0, min((int64_t)K, k.ce - rs));
+        // chain-head bits before the angle loads: the LDS transposes below
+        // are fenced, and a load issued after them would wait for the angles
+        const uint32_t hm = cnt > 0 ? head_mask<K>(head_bits, rs) : 0u;
+        float phi[K], psi[K], om[K];
+        if (active) load_angles<K>(buf, ang, R, rbase, nres, phi, psi, om);
+        float x[3 * K], y[3 * K], z[3 * K];
+        float px, py, pz;
+        bb_lane_positions<K, MULTI>(phi, psi, om, P, k.nact, sh[c & 1], carry, x, y, z, px, py, pz,
+                             cnt, hm);
+        if (active) {
+            float *out = xyz + 3 * rbase;
+            stage_store<3 * K>(buf, x, out, 3 * nres);
+            stage_store<3 * K>(buf, y, out + A, 3 * nres);
+            stage_store<3 * K>(buf, z, out + 2 * A, 3 * nres);
+        }
     }
 }
 
 // Backward that recomputes the frames from the angles (no stored state).
-template <int K>
+// Tiles of several chunks first run the forward scan alone to record each
+// chunk's carry-in frame, then visit the chunks last to first.
+template <int K, bool MULTI>
 __global__ __launch_bounds__(1024) void bb_backward_recompute_kernel(
     const float *__restrict__ ang, const float *__restrict__ g, float *__restrict__ gang,
     const int32_t *__restrict__ tile_res, const uint32_t *__restrict__ head_bits, int64_t R,
     BBParams P)
 {
     extern __shared__ float stage_mem[];
-    __shared__ FwdShared shf;
-    __shared__ BwdShared shb;
+    __shared__ FwdShared shf[2];
+    __shared__ BwdShared shb[2];
+    __shared__ float fwd_carry[kMaxChunks][12];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     float *buf = stage_mem + wave * kWave * Stride<3 * K>::value;
     const int64_t ts = tile_res[blockIdx.x], te = tile_res[blockIdx.x + 1];
-    const int64_t rbase = ts + (int64_t)wave * kWave * K;
-    const bool active = rbase < te;
-    const int nres = (int)min((int64_t)kWave * K, te - rbase);
     const int64_t A = 3 * R;
-    const int64_t rs = ts + (int64_t)threadIdx.x * K;
-    const int cnt = (int)max((int64_t)0, min((int64_t)K, te - rs));
-    const uint32_t hm = cnt > 0 ? head_mask<K>(head_bits, rs) : 0u;
-    const uint32_t lm = cnt > 0 ? head_mask<K>(head_bits, rs + 1) : 0u;
-    float phi[K], psi[K], om[K];
-    float gx[3 * K], gy[3 * K], gz[3 * K];
-    if (active) {
-        float v0[K], v1[K], v2[K], w0[3 * K], w1[3 * K], w2[3 * K];
-        const float *gb = g + 3 * rbase;
-        gload<K>(ang + rbase, nres, v0);
-        gload<K>(ang + R + rbase, nres, v1);
-        gload<K>(ang + 2 * R + rbase, nres, v2);
-        gload<3 * K>(gb, 3 * nres, w0);
-        gload<3 * K>(gb + A, 3 * nres, w1);
-        gload<3 * K>(gb + 2 * A, 3 * nres, w2);
-        to_blocked<K>(buf, v0, nres, phi);
-        to_blocked<K>(buf, v1, nres, psi);
-        to_blocked<K>(buf, v2, nres, om);
-        to_blocked<3 * K>(buf, w0, 3 * nres, gx);
-        to_blocked<3 * K>(buf, w1, 3 * nres, gy);
-        to_blocked<3 * K>(buf, w2, 3 * nres, gz);
+    // MULTI = false: every tile is one chunk (straight-line code)
+    const int nch = MULTI ? chunks_of<K>(ts, te) : 1;
+    if (nch > 1) {
+        Aff carry = aff_identity();
+        for (int c = 0; c < nch; ++c) {
+            if (threadIdx.x == 0) aff_store(fwd_carry[c], carry);
+            const Chunk k = chunk_of<K>(ts, te, c);
+            const int64_t rbase = k.cs + (int64_t)wave * kWave * K;
+            const bool active = wave < k.nact;
+            const int nres = active ? (int)min((int64_t)kWave * K, k.ce - rbase) : 0;
+            const int64_t rs = k.cs + (int64_t)threadIdx.x * K;
+            const int cnt = (int)max((int64_t)0, min((int64_t)K, k.ce - rs));
+            const uint32_t hm = cnt > 0 ? head_mask<K>(head_bits, rs) : 0u;
+            float phi[K], psi[K], om[K];
+            if (active) load_angles<K>(buf, ang, R, rbase, nres, phi, psi, om);
+            float x[3 * K], y[3 * K], z[3 * K];
+            float px, py, pz;
+            bb_lane_positions<K, MULTI>(phi, psi, om, P, k.nact, shf[c & 1], carry, x, y, z, px, py, pz,
+                                 cnt, hm);
+        }
     }
-    float x[3 * K], y[3 * K], z[3 * K];
-    float px, py, pz;
-    bb_lane_positions<K>(phi, psi, om, P, ts, te, shf, x, y, z, px, py, pz, cnt, hm);
-    float gr[3][K];
-    bb_lane_adjoint<K>(P, ts, te, shb, x, y, z, gx, gy, gz, px, py, pz, cnt, hm, lm, gr);
-    if (active) store_angle_grads<K>(buf, gr, gang, R, rbase, nres);
+    Wrench rcarry = wrench_zero();
+    for (int c = nch - 1; c >= 0; --c) {
+        const Chunk k = chunk_of<K>(ts, te, c);
+        const int64_t rbase = k.cs + (int64_t)wave * kWave * K;
+        const bool active = wave < k.nact;
+        const int nres = active ? (int)min((int64_t)kWave * K, k.ce - rbase) : 0;
+        const int64_t rs = k.cs + (int64_t)threadIdx.x * K;
+        const int cnt = (int)max((int64_t)0, min((int64_t)K, k.ce - rs));
+        const uint32_t hm = cnt > 0 ? head_mask<K>(head_bits, rs) : 0u;
+        const uint32_t lm = cnt > 0 ? head_mask<K>(head_bits, rs + 1) : 0u;
+        float phi[K], psi[K], om[K];
+        float gx[3 * K], gy[3 * K], gz[3 * K];
+        if (active) {
+            float v0[K], v1[K], v2[K], w0[3 * K], w1[3 * K], w2[3 * K];
+            const float *gb = g + 3 * rbase;
+            gload<K>(ang + rbase, nres, v0);
+            gload<K>(ang + R + rbase, nres, v1);
+            gload<K>(ang + 2 * R + rbase, nres, v2);
+            gload<3 * K>(gb, 3 * nres, w0);
+            gload<3 * K>(gb + A, 3 * nres, w1);
+            gload<3 * K>(gb + 2 * A, 3 * nres, w2);
+            to_blocked<K>(buf, v0, nres, phi);
+            to_blocked<K>(buf, v1, nres, psi);
+            to_blocked<K>(buf, v2, nres, om);
+            to_blocked<3 * K>(buf, w0, 3 * nres, gx);
+            to_blocked<3 * K>(buf, w1, 3 * nres, gy);
+            to_blocked<3 * K>(buf, w2, 3 * nres, gz);
+        }
+        Aff fcarry = aff_identity();
+        if (nch > 1) fcarry = aff_load(fwd_carry[c]);
+        float x[3 * K], y[3 * K], z[3 * K];
+        float px, py, pz;
+        // buffers alternate with the pass above: its last chunk used shf[(nch-1) & 1]
+        bb_lane_positions<K, MULTI>(phi, psi, om, P, k.nact, shf[(c + 1) & 1], fcarry, x, y, z, px, py,
+                             pz, cnt, hm);
+        float gr[3][K];
+        bb_lane_adjoint<K, MULTI>(P, k.nact, shb[c & 1], rcarry, x, y, z, gx, gy, gz, px, py, pz, cnt,
+                           hm, lm, gr);
+        if (active) store_angle_grads<K>(buf, gr, gang, R, rbase, nres);
+    }
 }
 
-// Backward from the coordinates the forward produced.
-template <int K>
+// Backward from the coordinates the forward produced (chunks last to first).
+template <int K, bool MULTI>
 __global__ __launch_bounds__(1024) void bb_backward_coords_kernel(
     const float *__restrict__ xyz, const float *__restrict__ g, float *__restrict__ gang,
     const int32_t *__restrict__ tile_res, const uint32_t *__restrict__ head_bits, int64_t R,
     BBParams P)
 {
     extern __shared__ float stage_mem[];
-    __shared__ BwdShared shb;
+    __shared__ BwdShared shb[2];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     float *buf = stage_mem + wave * kWave * Stride<3 * K>::value;
     const int64_t ts = tile_res[blockIdx.x], te = tile_res[blockIdx.x + 1];
-    const int64_t rbase = ts + (int64_t)wave * kWave * K;
-    const bool active = rbase < te;
-    const int nres = (int)min((int64_t)kWave * K, te - rbase);
-    const int64_t rs = ts + (int64_t)tid * K;
-    const int cnt = (int)max((int64_t)0, min((int64_t)K, te - rs));
     const int64_t A = 3 * R;
-    float x[3 * K], y[3 * K], z[3 * K], gx[3 * K], gy[3 * K], gz[3 * K];
-    const uint32_t hm = cnt > 0 ? head_mask<K>(head_bits, rs) : 0u;
-    const uint32_t lm = cnt > 0 ? head_mask<K>(head_bits, rs + 1) : 0u;
-    // the atom before lane 0 of the wave (read before the fenced transposes)
-    float px0 = 0.f, py0 = 0.f, pz0 = 0.f;
-    if (lane == 0 && cnt > 0 && !(hm & 1u)) {
-        const float *xb = xyz + 3 * rs;
-        px0 = xb[-1]; py0 = xb[A - 1]; pz0 = xb[2 * A - 1];
+    // MULTI = false: every tile is one chunk (straight-line code)
+    const int nch = MULTI ? chunks_of<K>(ts, te) : 1;
+    Wrench rcarry = wrench_zero();
+    for (int c = nch - 1; c >= 0; --c) {
+        const Chunk k = chunk_of<K>(ts, te, c);
+        const int64_t rbase = k.cs + (int64_t)wave * kWave * K;
+        const bool active = wave < k.nact;
+        const int nres = active ? (int)min((int64_t)kWave * K, k.ce - rbase) : 0;
+        const int64_t rs = k.cs + (int64_t)tid * K;
+        const int cnt = (int)max((int64_t)0, min((int64_t)K, k.ce - rs));
+        float x[3 * K], y[3 * K], z[3 * K], gx[3 * K], gy[3 * K], gz[3 * K];
+        const uint32_t hm = cnt > 0 ? head_mask<K>(head_bits, rs) : 0u;
+        const uint32_t lm = cnt > 0 ? head_mask<K>(head_bits, rs + 1) : 0u;
+        // the atom before lane 0 of the wave (read before the fenced transposes)
+        float px0 = 0.f, py0 = 0.f, pz0 = 0.f;
+        if (lane == 0 && cnt > 0 && !(hm & 1u)) {
+            const float *xb = xyz + 3 * rs;
+            px0 = xb[-1]; py0 = xb[A - 1]; pz0 = xb[2 * A - 1];
+        }
+        float px = 0.f, py = 0.f, pz = 0.f;
+        if (active) {
+            const float *xb = xyz + 3 * rbase;
+            const float *gb = g + 3 * rbase;
+            {
+                float w0[3 * K], w1[3 * K], w2[3 * K];
+                gload<3 * K>(xb, 3 * nres, w0);
+                gload<3 * K>(xb + A, 3 * nres, w1);
+                gload<3 * K>(xb + 2 * A, 3 * nres, w2);
+                to_blocked<3 * K>(buf, w0, 3 * nres, x);
+                to_blocked<3 * K>(buf, w1, 3 * nres, y);
+                to_blocked<3 * K>(buf, w2, 3 * nres, z);
+            }
+            {
+                float w0[3 * K], w1[3 * K], w2[3 * K];
+                gload<3 * K>(gb, 3 * nres, w0);
+                gload<3 * K>(gb + A, 3 * nres, w1);
+                gload<3 * K>(gb + 2 * A, 3 * nres, w2);
+                to_blocked<3 * K>(buf, w0, 3 * nres, gx);
+                to_blocked<3 * K>(buf, w1, 3 * nres, gy);
+                to_blocked<3 * K>(buf, w2, 3 * nres, gz);
+            }
+            // the atom before the lane: last atom of the previous lane, or of
+            // the previous run for lane 0 (the origin when a chain starts here)
+            const float lx = dpp_f<kDppWaveShr1>(x[3 * K - 1]);
+            const float ly = dpp_f<kDppWaveShr1>(y[3 * K - 1]);
+            const float lz = dpp_f<kDppWaveShr1>(z[3 * K - 1]);
+            if (cnt > 0 && !(hm & 1u)) {
+                if (lane > 0) { px = lx; py = ly; pz = lz; }
+                else { px = px0; py = py0; pz = pz0; }
+            }
+        }
+        float gr[3][K];
+        bb_lane_adjoint<K, MULTI>(P, k.nact, shb[c & 1], rcarry, x, y, z, gx, gy, gz, px, py, pz, cnt,
+                           hm, lm, gr);
+        if (active) store_angle_grads<K>(buf, gr, gang, R, rbase, nres);
     }
-    float px = 0.f, py = 0.f, pz = 0.f;
-    if (active) {
-        const float *xb = xyz + 3 * rbase;
-        const float *gb = g + 3 * rbase;
-        {
-            float w0[3 * K], w1[3 * K], w2[3 * K];
-            gload<3 * K>(xb, 3 * nres, w0);
-            gload<3 * K>(xb + A, 3 * nres, w1);
-            gload<3 * K>(xb + 2 * A, 3 * nres, w2);
-            to_blocked<3 * K>(buf, w0, 3 * nres, x);
-            to_blocked<3 * K>(buf, w1, 3 * nres, y);
-            to_blocked<3 * K>(buf, w2, 3 * nres, z);
-        }
-        {
-            float w0[3 * K], w1[3 * K], w2[3 * K];
-            gload<3 * K>(gb, 3 * nres, w0);
-            gload<3 * K>(gb + A, 3 * nres, w1);
-            gload<3 * K>(gb + 2 * A, 3 * nres, w2);
-            to_blocked<3 * K>(buf, w0, 3 * nres, gx);
-            to_blocked<3 * K>(buf, w1, 3 * nres, gy);
-            to_blocked<3 * K>(buf, w2, 3 * nres, gz);
-        }
-        // the atom before the lane: last atom of the previous lane, or of the
-        // previous wave's run for lane 0 (the origin when a chain starts here)
-        const float lx = dpp_f<kDppWaveShr1>(x[3 * K - 1]);
-        const float ly = dpp_f<kDppWaveShr1>(y[3 * K - 1]);
-        const float lz = dpp_f<kDppWaveShr1>(z[3 * K - 1]);
-        if (cnt > 0 && !(hm & 1u)) {
-            if (lane > 0) { px = lx; py = ly; pz = lz; }
-            else { px = px0; py = py0; pz = pz0; }
-        }
-    }
-    float gr[3][K];
-    bb_lane_adjoint<K>(P, ts, te, shb, x, y, z, gx, gy, gz, px, py, pz, cnt, hm, lm, gr);
-    if (active) store_angle_grads<K>(buf, gr, gang, R, rbase, nres);
 }
 
 // ---------------------------------------------------------------- plain form
@@ -441,12 +516,33 @@ __global__ __launch_bounds__(kPlainBlock) void bb_backward_plain_kernel(
     if (active) gang[(int64_t)slot_plane((int)(i % 3)) * R + r0 + i / 3] = acc;
 }
 
+template <int K, bool MULTI>
+hipError_t fwd_km(const a2c_plan &p, const float *ang, float *xyz, hipStream_t s)
+{
+    const dim3 grid(p.n_tiles), block(p.W * kWave);
+    hipLaunchKernelGGL((bb_forward_scan_kernel<K, MULTI>), grid, block, stage_bytes<K>(p.W), s,
+                       ang, xyz, p.d_tile_res, p.d_head_bits, p.R, p.bb);
+    return hipGetLastError();
+}
+
 template <int K>
 hipError_t fwd_k(const a2c_plan &p, const float *ang, float *xyz, hipStream_t s)
 {
+    return p.multi_chunk ? fwd_km<K, true>(p, ang, xyz, s) : fwd_km<K, false>(p, ang, xyz, s);
+}
+
+template <int K, bool MULTI>
+hipError_t bwd_km(const a2c_plan &p, const float *ang, const float *xyz, const float *g,
+                  float *gang, hipStream_t s)
+{
     const dim3 grid(p.n_tiles), block(p.W * kWave);
-    hipLaunchKernelGGL((bb_forward_scan_kernel<K>), grid, block, stage_bytes<K>(p.W), s, ang, xyz,
-                       p.d_tile_res, p.d_head_bits, p.R, p.bb);
+    const size_t lds = stage_bytes<K>(p.W);
+    if (xyz)
+        hipLaunchKernelGGL((bb_backward_coords_kernel<K, MULTI>), grid, block, lds, s, xyz, g,
+                           gang, p.d_tile_res, p.d_head_bits, p.R, p.bb);
+    else
+        hipLaunchKernelGGL((bb_backward_recompute_kernel<K, MULTI>), grid, block, lds, s, ang, g,
+                           gang, p.d_tile_res, p.d_head_bits, p.R, p.bb);
     return hipGetLastError();
 }
 
@@ -454,15 +550,8 @@ template <int K>
 hipError_t bwd_k(const a2c_plan &p, const float *ang, const float *xyz, const float *g,
                  float *gang, hipStream_t s)
 {
-    const dim3 grid(p.n_tiles), block(p.W * kWave);
-    const size_t lds = stage_bytes<K>(p.W);
-    if (xyz)
-        hipLaunchKernelGGL((bb_backward_coords_kernel<K>), grid, block, lds, s, xyz, g, gang,
-                           p.d_tile_res, p.d_head_bits, p.R, p.bb);
-    else
-        hipLaunchKernelGGL((bb_backward_recompute_kernel<K>), grid, block, lds, s, ang, g,
-                           gang, p.d_tile_res, p.d_head_bits, p.R, p.bb);
-    return hipGetLastError();
+    return p.multi_chunk ? bwd_km<K, true>(p, ang, xyz, g, gang, s)
+                         : bwd_km<K, false>(p, ang, xyz, g, gang, s);
 }
 
 }  // namespace

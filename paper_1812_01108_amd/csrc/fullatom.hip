@@ -221,50 +221,116 @@ __device__ __forceinline__ void aff_rot_x(Aff &m, float c, float s)
     m.r02 = b0; m.r12 = b1; m.r22 = b2;
 }
 
-// Emit the atoms of frame k of type t placed by F.
+// Per-wave LDS staging of a wave's atom run [A0, A0 + n): plane p of atom
+// e (relative to A0) lives at st[p * ns + e].
+struct Stage {
+    float *st;
+    int ns;   // floats per plane
+};
+
+// Coalesced copy between a global run (3 planes, plane stride A) and the
+// wave's staging buffer, eight rows of 64 atoms at a time: all loads of a
+// batch are issued before the first store (indices past the run are clamped
+// to its last atom), so a batch costs one memory latency, not eight.
+constexpr int kStageBatch = 8;
+
+__device__ __forceinline__ void run_to_lds(const Stage &sg, int plane0, const float *__restrict__ src,
+                                           int64_t A, int64_t A0, int n)
+{
+    const int lane = lane_id();
+    const float *s0 = src + A0, *s1 = src + A + A0, *s2 = src + 2 * A + A0;
+    float *d0 = sg.st + plane0 * sg.ns, *d1 = d0 + sg.ns, *d2 = d1 + sg.ns;
+    for (int base = 0; base < n; base += kStageBatch * kWave) {
+        float v0[kStageBatch], v1[kStageBatch], v2[kStageBatch];
+#pragma unroll
+        for (int u = 0; u < kStageBatch; ++u) {
+            const int e = min(base + lane + u * kWave, n - 1);
+            v0[u] = s0[e];
+            v1[u] = s1[e];
+            v2[u] = s2[e];
+        }
+#pragma unroll
+        for (int u = 0; u < kStageBatch; ++u) {
+            const int e = base + lane + u * kWave;
+            if (e < n) {
+                d0[e] = v0[u];
+                d1[e] = v1[u];
+                d2[e] = v2[u];
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ void lds_to_run(const Stage &sg, float *__restrict__ dst, int64_t A,
+                                           int64_t A0, int n)
+{
+    const int lane = lane_id();
+    float *o0 = dst + A0, *o1 = dst + A + A0, *o2 = dst + 2 * A + A0;
+    const float *s0 = sg.st, *s1 = s0 + sg.ns, *s2 = s1 + sg.ns;
+    for (int base = 0; base < n; base += kStageBatch * kWave) {
+        float v0[kStageBatch], v1[kStageBatch], v2[kStageBatch];
+#pragma unroll
+        for (int u = 0; u < kStageBatch; ++u) {
+            const int e = min(base + lane + u * kWave, n - 1);
+            v0[u] = s0[e];
+            v1[u] = s1[e];
+            v2[u] = s2[e];
+        }
+#pragma unroll
+        for (int u = 0; u < kStageBatch; ++u) {
+            const int e = base + lane + u * kWave;
+            if (e < n) {
+                o0[e] = v0[u];
+                o1[e] = v1[u];
+                o2[e] = v2[u];
+            }
+        }
+    }
+}
+
+// Emit the atoms of frame k of type t placed by F into the staging buffer.
 __device__ __forceinline__ void emit_frame(const FATable &tab, const FAType &ft, int k,
-                                           const Aff &F, float *__restrict__ xyz, int64_t A,
-                                           int64_t aoff)
+                                           const Aff &F, const Stage &sg, int aloc)
 {
     for (int i = 0; i < tab.max_count[k]; ++i) {
         if (i < ft.fcount[k]) {
             const int q = ft.fbegin[k] + i;
             float x, y, z;
             aff_point(F, ft.rx[q], ft.ry[q], ft.rz[q], x, y, z);
-            const int64_t a = aoff + ft.slot[q];
-            xyz[a] = x;
-            xyz[A + a] = y;
-            xyz[2 * A + a] = z;
+            const int e = aloc + ft.slot[q];
+            sg.st[e] = x;
+            sg.st[sg.ns + e] = y;
+            sg.st[2 * sg.ns + e] = z;
         }
     }
 }
 
-// Wrench of the atoms of frame k placed by F, with upstream gradients g.
+// Wrench of the atoms of frame k placed by F, upstream gradients staged in
+// planes 0..2.
 __device__ __forceinline__ void frame_wrench(const FATable &tab, const FAType &ft, int k,
-                                             const Aff &F, const float *__restrict__ g, int64_t A,
-                                             int64_t aoff, Wrench &w)
+                                             const Aff &F, const Stage &sg, int aloc, Wrench &w)
 {
     for (int i = 0; i < tab.max_count[k]; ++i) {
         if (i < ft.fcount[k]) {
             const int q = ft.fbegin[k] + i;
             float x, y, z;
             aff_point(F, ft.rx[q], ft.ry[q], ft.rz[q], x, y, z);
-            const int64_t a = aoff + ft.slot[q];
-            wrench_add_point(w, x, y, z, g[a], g[A + a], g[2 * A + a]);
+            const int e = aloc + ft.slot[q];
+            wrench_add_point(w, x, y, z, sg.st[e], sg.st[sg.ns + e], sg.st[2 * sg.ns + e]);
         }
     }
 }
 
-// Wrench of the atoms of frame k read from the forward's coordinates.
+// Wrench of the atoms of frame k with positions staged in planes 3..5 and
+// upstream gradients in planes 0..2.
 __device__ __forceinline__ void frame_wrench_xyz(const FATable &tab, const FAType &ft, int k,
-                                                 const float *__restrict__ xyz,
-                                                 const float *__restrict__ g, int64_t A,
-                                                 int64_t aoff, Wrench &w)
+                                                 const Stage &sg, int aloc, Wrench &w)
 {
     for (int i = 0; i < tab.max_count[k]; ++i) {
         if (i < ft.fcount[k]) {
-            const int64_t a = aoff + ft.slot[ft.fbegin[k] + i];
-            wrench_add_point(w, xyz[a], xyz[A + a], xyz[2 * A + a], g[a], g[A + a], g[2 * A + a]);
+            const int e = aloc + ft.slot[ft.fbegin[k] + i];
+            wrench_add_point(w, sg.st[3 * sg.ns + e], sg.st[4 * sg.ns + e], sg.st[5 * sg.ns + e],
+                             sg.st[e], sg.st[sg.ns + e], sg.st[2 * sg.ns + e]);
         }
     }
 }
@@ -273,8 +339,8 @@ struct ResidueIn {
     float co, so, cp, sp, cs, ss;  // cos/sin of omega, phi, psi
 };
 
-// Lane-serial spine aggregate of K residues; returns whether a chain starts
-// in the lane.  Keeps the spine cos/sin per residue for the re-walk.
+// Lane-serial spine aggregate of K residues (reset at chain heads), with one
+// polar step; keeps the spine cos/sin per residue for the re-walk.
 template <int K>
 __device__ __forceinline__ Aff fa_lane_aggregate(const float *__restrict__ ang, int64_t R,
                                                  int64_t rs, int cnt, uint32_t hm,
@@ -333,58 +399,119 @@ __device__ __forceinline__ void side_step(Aff &sf, const FAType &ft, int f, floa
     aff_apply_transform(sf, ft.ct[f], ft.st[f], ft.d[f], c, s);
 }
 
+// Chunk c of a tile: residues [cs, ce) handled by the waves wave < nact.
+struct FAChunk {
+    int64_t cs, ce;
+    int nact;
+};
+
 template <int K>
+__device__ __forceinline__ FAChunk fa_chunk(int64_t ts, int64_t te, int c)
+{
+    const int nw = blockDim.x >> 6;
+    const int64_t ch = (int64_t)kWave * K * nw;
+    FAChunk k;
+    k.cs = ts + (int64_t)c * ch;
+    k.ce = min(k.cs + ch, te);
+    k.nact = (int)min((int64_t)nw, (k.ce - k.cs + kWave * K - 1) / (kWave * K));
+    return k;
+}
+
+template <int K>
+__device__ __forceinline__ int fa_chunks(int64_t ts, int64_t te)
+{
+    const int64_t ch = (int64_t)kWave * K * (blockDim.x >> 6);
+    return (int)((te - ts + ch - 1) / ch);
+}
+
+// Per-lane bookkeeping of one chunk.
+template <int K>
+struct LaneRun {
+    int64_t rs, rbase, A0;
+    int cnt, nres, natoms;
+    bool active;
+    uint32_t hm, lm;
+};
+
+template <int K>
+__device__ __forceinline__ LaneRun<K> lane_run(const FAChunk &k,
+                                               const uint32_t *__restrict__ head_bits,
+                                               const int32_t *__restrict__ res_aoff)
+{
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    LaneRun<K> L;
+    L.rbase = k.cs + (int64_t)wave * kWave * K;
+    L.active = wave < k.nact;
+    L.nres = L.active ? (int)min((int64_t)kWave * K, k.ce - L.rbase) : 0;
+    L.rs = k.cs + (int64_t)threadIdx.x * K;
+    L.cnt = (int)max((int64_t)0, min((int64_t)K, k.ce - L.rs));
+    L.hm = L.cnt > 0 ? head_mask<K>(head_bits, L.rs) : 0u;
+    L.lm = L.cnt > 0 ? head_mask<K>(head_bits, L.rs + 1) : 0u;
+    L.A0 = 0;
+    L.natoms = 0;
+    if (L.active) {
+        L.A0 = __builtin_amdgcn_readfirstlane(res_aoff[L.rbase]);
+        L.natoms = __builtin_amdgcn_readfirstlane(res_aoff[L.rbase + L.nres]) - (int)L.A0;
+    }
+    return L;
+}
+
+template <int K, bool MULTI>
 __global__ __launch_bounds__(1024) void fa_forward_kernel(
     const float *__restrict__ ang, float *__restrict__ xyz, const int32_t *__restrict__ tile_res,
     const uint32_t *__restrict__ head_bits, const int32_t *__restrict__ res_aoff,
     const uint8_t *__restrict__ seq, const FATable *__restrict__ gtab, int64_t R, int64_t A,
-    BBParams P)
+    BBParams P, int stage_atoms)
 {
+    extern __shared__ float stage_mem[];
     __shared__ FATable tab;
-    __shared__ FwdShared sh;
+    __shared__ FwdShared sh[2];
     load_table(tab, gtab);
-    const int tid = threadIdx.x;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const Stage sg{stage_mem + (size_t)wave * 3 * stage_atoms, stage_atoms};
     const int64_t ts = tile_res[blockIdx.x], te = tile_res[blockIdx.x + 1];
-    const int64_t rs = ts + (int64_t)tid * K;
-    const int cnt = (int)max((int64_t)0, min((int64_t)K, te - rs));
-    const bool wave_active = ts + (int64_t)wave * kWave * K < te;
-    uint32_t hm = 0;
-    ResidueIn in[K];
-    int first_head = K;
-    Aff m = aff_identity();
-    if (wave_active) {
-        if (cnt > 0) hm = head_mask<K>(head_bits, rs);
-        m = fa_lane_aggregate<K>(ang, R, rs, cnt, hm, P, in, first_head);
-    }
-    const Aff X = block_exclusive_prefix(m, first_head < K, wave_active, sh);
-    if (!wave_active) return;
-    Aff cur = X;
+    // MULTI = false: every tile is one chunk (straight-line code)
+    const int nch = MULTI ? fa_chunks<K>(ts, te) : 1;
+    Aff carry = aff_identity();
+    for (int c = 0; c < nch; ++c) {
+        const FAChunk k = fa_chunk<K>(ts, te, c);
+        const LaneRun<K> L = lane_run<K>(k, head_bits, res_aoff);
+        ResidueIn in[K];
+        int first_head = K;
+        Aff m = aff_identity();
+        if (L.active) m = fa_lane_aggregate<K>(ang, R, L.rs, L.cnt, L.hm, P, in, first_head);
+        const Aff X = block_exclusive_prefix<MULTI>(m, first_head < K, k.nact, sh[c & 1], carry);
+        if (!L.active) continue;
+        Aff cur = X;
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
-        if (j < cnt) {
-            const int64_t r = rs + j;
-            const FAType &ft = tab.t[seq[r]];
-            const int64_t aoff = res_aoff[r];
-            if ((hm >> j) & 1u) cur = aff_identity();
-            aff_apply_transform(cur, P.ct[0], P.st[0], P.d[0], in[j].co, in[j].so);
-            emit_frame(tab, ft, 0, cur, xyz, A, aoff);
-            aff_apply_transform(cur, P.ct[1], P.st[1], P.d[1], in[j].cp, in[j].sp);
-            emit_frame(tab, ft, 1, cur, xyz, A, aoff);
-            if (ft.n_side > 0) {
-                Aff sf = cur;
-                aff_rot_x(sf, ft.pre_c, ft.pre_s);
+        for (int j = 0; j < K; ++j) {
+            if (j < L.cnt) {
+                const int64_t r = L.rs + j;
+                const FAType &ft = tab.t[seq[r]];
+                const int aloc = res_aoff[r] - (int)L.A0;
+                if ((L.hm >> j) & 1u) cur = aff_identity();
+                aff_apply_transform(cur, P.ct[0], P.st[0], P.d[0], in[j].co, in[j].so);
+                emit_frame(tab, ft, 0, cur, sg, aloc);
+                aff_apply_transform(cur, P.ct[1], P.st[1], P.d[1], in[j].cp, in[j].sp);
+                emit_frame(tab, ft, 1, cur, sg, aloc);
+                if (ft.n_side > 0) {
+                    Aff sf = cur;
+                    aff_rot_x(sf, ft.pre_c, ft.pre_s);
 #pragma unroll
-                for (int f = 0; f < A2C_MAX_SIDE_FRAMES; ++f) {
-                    if (f < tab.max_side && f < ft.n_side) {
-                        side_step(sf, ft, f, ang[(3 + f) * R + r]);
-                        emit_frame(tab, ft, 3 + f, sf, xyz, A, aoff);
+                    for (int f = 0; f < A2C_MAX_SIDE_FRAMES; ++f) {
+                        if (f < tab.max_side && f < ft.n_side) {
+                            side_step(sf, ft, f, ang[(3 + f) * R + r]);
+                            emit_frame(tab, ft, 3 + f, sf, sg, aloc);
+                        }
                     }
                 }
+                aff_apply_transform(cur, P.ct[2], P.st[2], P.d[2], in[j].cs, in[j].ss);
+                emit_frame(tab, ft, 2, cur, sg, aloc);
             }
-            aff_apply_transform(cur, P.ct[2], P.st[2], P.d[2], in[j].cs, in[j].ss);
-            emit_frame(tab, ft, 2, cur, xyz, A, aoff);
         }
+        wave_lds_sync();
+        lds_to_run(sg, xyz, A, L.A0, L.natoms);
+        wave_lds_sync();
     }
 }
 
@@ -408,7 +535,6 @@ __device__ __forceinline__ void set_ou_pts(float (&o)[3], float (&u)[3], float o
     u[0] = (ox - px) * inv_d; u[1] = (oy - py) * inv_d; u[2] = (oz - pz) * inv_d;
 }
 
-template <int K>
 __device__ __forceinline__ void fa_store_grads(float *__restrict__ gang, int64_t R, int64_t r,
                                                const SpineNode &sn, const Wrench &S_after,
                                                const float (&gchi)[4], Wrench &S_out)
@@ -426,154 +552,212 @@ __device__ __forceinline__ void fa_store_grads(float *__restrict__ gang, int64_t
 }
 
 // Backward: the side chains' subtree sums give the chi gradients, the spine
-// groups feed a reverse scan over residues.  RECOMPUTE: frames from the
-// angles; otherwise positions and axes from the forward's coordinates.
-template <int K, bool RECOMPUTE>
+// groups feed a reverse scan over residues, chunks last to first.
+// RECOMPUTE: frames from the angles (tiles of several chunks first record
+// each chunk's forward carry); otherwise positions and axes from the
+// forward's coordinates.
+template <int K, bool RECOMPUTE, bool MULTI>
 __global__ __launch_bounds__(1024) void fa_backward_kernel(
     const float *__restrict__ ang, const float *__restrict__ xyz, const float *__restrict__ g,
     float *__restrict__ gang, const int32_t *__restrict__ tile_res,
     const uint32_t *__restrict__ head_bits, const int32_t *__restrict__ res_aoff,
     const uint8_t *__restrict__ seq, const FATable *__restrict__ gtab, int64_t R, int64_t A,
-    BBParams P)
+    BBParams P, int stage_atoms)
 {
+    extern __shared__ float stage_mem[];
     __shared__ FATable tab;
-    __shared__ FwdShared shf;
-    __shared__ BwdShared shb;
+    __shared__ FwdShared shf[2];
+    __shared__ BwdShared shb[2];
+    __shared__ float fwd_carry[RECOMPUTE ? kMaxChunks : 1][12];
     load_table(tab, gtab);
-    const int tid = threadIdx.x;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int nw = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int planes = RECOMPUTE ? 3 : 6;
+    const Stage sg{stage_mem + (size_t)wave * planes * stage_atoms, stage_atoms};
     const int64_t ts = tile_res[blockIdx.x], te = tile_res[blockIdx.x + 1];
-    const int64_t rs = ts + (int64_t)tid * K;
-    const int cnt = (int)max((int64_t)0, min((int64_t)K, te - rs));
-    const bool wave_active = ts + (int64_t)wave * kWave * K < te;
-    const int nact = (int)min((int64_t)nw, (te - ts + kWave * K - 1) / (kWave * K));
-    uint32_t hm = 0, lm = 0;
-    if (wave_active && cnt > 0) {
-        hm = head_mask<K>(head_bits, rs);
-        lm = head_mask<K>(head_bits, rs + 1);
+    // MULTI = false: every tile is one chunk (straight-line code)
+    const int nch = MULTI ? fa_chunks<K>(ts, te) : 1;
+    if (RECOMPUTE && nch > 1) {
+        Aff carry = aff_identity();
+        for (int c = 0; c < nch; ++c) {
+            if (threadIdx.x == 0) aff_store(fwd_carry[c], carry);
+            const FAChunk k = fa_chunk<K>(ts, te, c);
+            const LaneRun<K> L = lane_run<K>(k, head_bits, res_aoff);
+            ResidueIn in[K];
+            int first_head = K;
+            Aff m = aff_identity();
+            if (L.active) m = fa_lane_aggregate<K>(ang, R, L.rs, L.cnt, L.hm, P, in, first_head);
+            (void)block_exclusive_prefix<MULTI>(m, first_head < K, k.nact, shf[c & 1], carry);
+        }
     }
-    Aff X = aff_identity();
-    ResidueIn in[K];
-    if (RECOMPUTE) {
-        int first_head = K;
-        Aff m = aff_identity();
-        if (wave_active) m = fa_lane_aggregate<K>(ang, R, rs, cnt, hm, P, in, first_head);
-        X = block_exclusive_prefix(m, first_head < K, wave_active, shf);
-    }
-    SpineNode sn[K];
-    float gchi[K][4];
-    Wrench agg = wrench_zero();
-    bool f_end = false;
-    if (wave_active) {
-        Aff cur = X;
-        // position of the C atom before the lane (coordinate mode)
+    Wrench rcarry = wrench_zero();
+    for (int c = nch - 1; c >= 0; --c) {
+        const FAChunk k = fa_chunk<K>(ts, te, c);
+        const LaneRun<K> L = lane_run<K>(k, head_bits, res_aoff);
+        Aff X = aff_identity();
+        ResidueIn in[K];
+        if (RECOMPUTE) {
+            int first_head = K;
+            Aff m = aff_identity();
+            if (L.active) m = fa_lane_aggregate<K>(ang, R, L.rs, L.cnt, L.hm, P, in, first_head);
+            Aff fcarry = aff_identity();
+            if (nch > 1) fcarry = aff_load(fwd_carry[c]);
+            // buffers alternate with the pass above: its last chunk used shf[(nch-1) & 1]
+            X = block_exclusive_prefix<MULTI>(m, first_head < K, k.nact, shf[(c + 1) & 1], fcarry);
+        }
+        // the C atom before the lane's first residue (coordinate mode): in
+        // the staged run for lanes > 0, from global memory for lane 0
         float pcx = 0.f, pcy = 0.f, pcz = 0.f;
-        if (!RECOMPUTE && cnt > 0 && !(hm & 1u)) {
-            const int64_t ac = res_aoff[rs - 1] + 2;
+        if (!RECOMPUTE && lane == 0 && L.cnt > 0 && !(L.hm & 1u)) {
+            const int64_t ac = res_aoff[L.rs - 1] + 2;
             pcx = xyz[ac]; pcy = xyz[A + ac]; pcz = xyz[2 * A + ac];
         }
+        SpineNode sn[K];
+        float gchi[K][4];
+        Wrench agg = wrench_zero();
+        bool f_end = false;
+        if (L.active) {
+            run_to_lds(sg, 0, g, A, L.A0, L.natoms);
+            if (!RECOMPUTE) run_to_lds(sg, 3, xyz, A, L.A0, L.natoms);
+            wave_lds_sync();
+            if (!RECOMPUTE && lane > 0 && L.cnt > 0 && !(L.hm & 1u)) {
+                const int e = res_aoff[L.rs - 1] + 2 - (int)L.A0;
+                pcx = sg.st[3 * sg.ns + e]; pcy = sg.st[4 * sg.ns + e]; pcz = sg.st[5 * sg.ns + e];
+            }
+            Aff cur = X;
 #pragma unroll
-        for (int j = 0; j < K; ++j) {
-            gchi[j][0] = gchi[j][1] = gchi[j][2] = gchi[j][3] = 0.f;
-            sn[j].wN = sn[j].wCA = sn[j].wC = wrench_zero();
-            if (j < cnt) {
-                const int64_t r = rs + j;
-                const FAType &ft = tab.t[seq[r]];
-                const int64_t aoff = res_aoff[r];
-                const bool head = (hm >> j) & 1u;
-                // side-chain frames: origin/axis per frame and own wrenches
-                Wrench ws[A2C_MAX_SIDE_FRAMES];
-                float so[A2C_MAX_SIDE_FRAMES][3], su[A2C_MAX_SIDE_FRAMES][3];
-                if (RECOMPUTE) {
-                    if (head) cur = aff_identity();
-                    aff_apply_transform(cur, P.ct[0], P.st[0], P.d[0], in[j].co, in[j].so);
-                    set_ou(sn[j].oN, sn[j].uN, cur);
-                    frame_wrench(tab, ft, 0, cur, g, A, aoff, sn[j].wN);
-                    aff_apply_transform(cur, P.ct[1], P.st[1], P.d[1], in[j].cp, in[j].sp);
-                    set_ou(sn[j].oCA, sn[j].uCA, cur);
-                    frame_wrench(tab, ft, 1, cur, g, A, aoff, sn[j].wCA);
-                    Aff sf = cur;
-                    aff_rot_x(sf, ft.pre_c, ft.pre_s);
+            for (int j = 0; j < K; ++j) {
+                gchi[j][0] = gchi[j][1] = gchi[j][2] = gchi[j][3] = 0.f;
+                sn[j].wN = sn[j].wCA = sn[j].wC = wrench_zero();
+                if (j < L.cnt) {
+                    const int64_t r = L.rs + j;
+                    const FAType &ft = tab.t[seq[r]];
+                    const int aloc = res_aoff[r] - (int)L.A0;
+                    const bool head = (L.hm >> j) & 1u;
+                    // side-chain frames: origin/axis per frame and own wrenches
+                    Wrench ws[A2C_MAX_SIDE_FRAMES];
+                    float so[A2C_MAX_SIDE_FRAMES][3], su[A2C_MAX_SIDE_FRAMES][3];
+                    if (RECOMPUTE) {
+                        if (head) cur = aff_identity();
+                        aff_apply_transform(cur, P.ct[0], P.st[0], P.d[0], in[j].co, in[j].so);
+                        set_ou(sn[j].oN, sn[j].uN, cur);
+                        frame_wrench(tab, ft, 0, cur, sg, aloc, sn[j].wN);
+                        aff_apply_transform(cur, P.ct[1], P.st[1], P.d[1], in[j].cp, in[j].sp);
+                        set_ou(sn[j].oCA, sn[j].uCA, cur);
+                        frame_wrench(tab, ft, 1, cur, sg, aloc, sn[j].wCA);
+                        Aff sf = cur;
+                        aff_rot_x(sf, ft.pre_c, ft.pre_s);
 #pragma unroll
-                    for (int f = 0; f < A2C_MAX_SIDE_FRAMES; ++f) {
-                        ws[f] = wrench_zero();
+                        for (int f = 0; f < A2C_MAX_SIDE_FRAMES; ++f) {
+                            ws[f] = wrench_zero();
+                            if (f < tab.max_side && f < ft.n_side) {
+                                side_step(sf, ft, f, ang[(3 + f) * R + r]);
+                                so[f][0] = sf.t0; so[f][1] = sf.t1; so[f][2] = sf.t2;
+                                su[f][0] = sf.r00; su[f][1] = sf.r10; su[f][2] = sf.r20;
+                                frame_wrench(tab, ft, 3 + f, sf, sg, aloc, ws[f]);
+                            }
+                        }
+                        aff_apply_transform(cur, P.ct[2], P.st[2], P.d[2], in[j].cs, in[j].ss);
+                        set_ou(sn[j].oC, sn[j].uC, cur);
+                        frame_wrench(tab, ft, 2, cur, sg, aloc, sn[j].wC);
+                    } else {
+                        const float *px = sg.st + 3 * sg.ns, *py = sg.st + 4 * sg.ns,
+                                    *pz = sg.st + 5 * sg.ns;
+                        const float nx = px[aloc], ny = py[aloc], nz = pz[aloc];
+                        const float cax = px[aloc + 1], cay = py[aloc + 1], caz = pz[aloc + 1];
+                        const float cx = px[aloc + 2], cy = py[aloc + 2], cz = pz[aloc + 2];
+                        if (head) { pcx = 0.f; pcy = 0.f; pcz = 0.f; }
+                        set_ou_pts(sn[j].oN, sn[j].uN, nx, ny, nz, pcx, pcy, pcz, P.inv_d[0]);
+                        set_ou_pts(sn[j].oCA, sn[j].uCA, cax, cay, caz, nx, ny, nz, P.inv_d[1]);
+                        set_ou_pts(sn[j].oC, sn[j].uC, cx, cy, cz, cax, cay, caz, P.inv_d[2]);
+                        frame_wrench_xyz(tab, ft, 0, sg, aloc, sn[j].wN);
+                        frame_wrench_xyz(tab, ft, 1, sg, aloc, sn[j].wCA);
+                        frame_wrench_xyz(tab, ft, 2, sg, aloc, sn[j].wC);
+                        float ppx = cax, ppy = cay, ppz = caz;
+#pragma unroll
+                        for (int f = 0; f < A2C_MAX_SIDE_FRAMES; ++f) {
+                            ws[f] = wrench_zero();
+                            if (f < tab.max_side && f < ft.n_side) {
+                                const int eo = aloc + ft.origin_slot[3 + f];
+                                const float ox = px[eo], oy = py[eo], oz = pz[eo];
+                                so[f][0] = ox; so[f][1] = oy; so[f][2] = oz;
+                                su[f][0] = (ox - ppx) * ft.inv_d[f];
+                                su[f][1] = (oy - ppy) * ft.inv_d[f];
+                                su[f][2] = (oz - ppz) * ft.inv_d[f];
+                                ppx = ox; ppy = oy; ppz = oz;
+                                frame_wrench_xyz(tab, ft, 3 + f, sg, aloc, ws[f]);
+                            }
+                        }
+                        pcx = cx; pcy = cy; pcz = cz;
+                    }
+                    // chi gradients: side frames form a chain, subtree = suffix
+                    Wrench Ss = wrench_zero();
+#pragma unroll
+                    for (int f = A2C_MAX_SIDE_FRAMES - 1; f >= 0; --f) {
                         if (f < tab.max_side && f < ft.n_side) {
-                            side_step(sf, ft, f, ang[(3 + f) * R + r]);
-                            so[f][0] = sf.t0; so[f][1] = sf.t1; so[f][2] = sf.t2;
-                            su[f][0] = sf.r00; su[f][1] = sf.r10; su[f][2] = sf.r20;
-                            frame_wrench(tab, ft, 3 + f, sf, g, A, aoff, ws[f]);
+                            wrench_add(Ss, ws[f]);
+                            if (ft.side_chi[f])
+                                gchi[j][f] = wrench_torque(Ss, so[f][0], so[f][1], so[f][2],
+                                                           su[f][0], su[f][1], su[f][2]);
                         }
                     }
-                    aff_apply_transform(cur, P.ct[2], P.st[2], P.d[2], in[j].cs, in[j].ss);
-                    set_ou(sn[j].oC, sn[j].uC, cur);
-                    frame_wrench(tab, ft, 2, cur, g, A, aoff, sn[j].wC);
-                } else {
-                    const float nx = xyz[aoff], ny = xyz[A + aoff], nz = xyz[2 * A + aoff];
-                    const float cax = xyz[aoff + 1], cay = xyz[A + aoff + 1], caz = xyz[2 * A + aoff + 1];
-                    const float cx = xyz[aoff + 2], cy = xyz[A + aoff + 2], cz = xyz[2 * A + aoff + 2];
-                    if (head) { pcx = 0.f; pcy = 0.f; pcz = 0.f; }
-                    set_ou_pts(sn[j].oN, sn[j].uN, nx, ny, nz, pcx, pcy, pcz, P.inv_d[0]);
-                    set_ou_pts(sn[j].oCA, sn[j].uCA, cax, cay, caz, nx, ny, nz, P.inv_d[1]);
-                    set_ou_pts(sn[j].oC, sn[j].uC, cx, cy, cz, cax, cay, caz, P.inv_d[2]);
-                    frame_wrench_xyz(tab, ft, 0, xyz, g, A, aoff, sn[j].wN);
-                    frame_wrench_xyz(tab, ft, 1, xyz, g, A, aoff, sn[j].wCA);
-                    frame_wrench_xyz(tab, ft, 2, xyz, g, A, aoff, sn[j].wC);
-                    float ppx = cax, ppy = cay, ppz = caz;
-#pragma unroll
-                    for (int f = 0; f < A2C_MAX_SIDE_FRAMES; ++f) {
-                        ws[f] = wrench_zero();
-                        if (f < tab.max_side && f < ft.n_side) {
-                            const int64_t ao = aoff + ft.origin_slot[3 + f];
-                            const float ox = xyz[ao], oy = xyz[A + ao], oz = xyz[2 * A + ao];
-                            so[f][0] = ox; so[f][1] = oy; so[f][2] = oz;
-                            su[f][0] = (ox - ppx) * ft.inv_d[f];
-                            su[f][1] = (oy - ppy) * ft.inv_d[f];
-                            su[f][2] = (oz - ppz) * ft.inv_d[f];
-                            ppx = ox; ppy = oy; ppz = oz;
-                            frame_wrench_xyz(tab, ft, 3 + f, xyz, g, A, aoff, ws[f]);
-                        }
+                    wrench_add(sn[j].wCA, Ss);
+                    if (!f_end) {
+                        wrench_add(agg, sn[j].wN);
+                        wrench_add(agg, sn[j].wCA);
+                        wrench_add(agg, sn[j].wC);
                     }
-                    pcx = cx; pcy = cy; pcz = cz;
+                    if ((L.lm >> j) & 1u) f_end = true;
                 }
-                // chi gradients: side frames form a chain, subtree = suffix
-                Wrench Ss = wrench_zero();
+            }
+            wave_lds_sync();
+        }
+        Wrench S = block_exclusive_suffix<MULTI>(agg, f_end, k.nact, shb[c & 1], rcarry);
+        if (!L.active) continue;
 #pragma unroll
-                for (int f = A2C_MAX_SIDE_FRAMES - 1; f >= 0; --f) {
-                    if (f < tab.max_side && f < ft.n_side) {
-                        wrench_add(Ss, ws[f]);
-                        if (ft.side_chi[f])
-                            gchi[j][f] = wrench_torque(Ss, so[f][0], so[f][1], so[f][2], su[f][0],
-                                                       su[f][1], su[f][2]);
-                    }
-                }
-                wrench_add(sn[j].wCA, Ss);
-                if (!f_end) {
-                    wrench_add(agg, sn[j].wN);
-                    wrench_add(agg, sn[j].wCA);
-                    wrench_add(agg, sn[j].wC);
-                }
-                if ((lm >> j) & 1u) f_end = true;
+        for (int j = K - 1; j >= 0; --j) {
+            if (j < L.cnt) {
+                if ((L.lm >> j) & 1u) S = wrench_zero();
+                fa_store_grads(gang, R, L.rs + j, sn[j], S, gchi[j], S);
             }
         }
     }
-    Wrench S = block_exclusive_suffix(agg, f_end, wave_active, nact, shb);
-    if (!wave_active) return;
-#pragma unroll
-    for (int j = K - 1; j >= 0; --j) {
-        if (j < cnt) {
-            if ((lm >> j) & 1u) S = wrench_zero();
-            fa_store_grads<K>(gang, R, rs + j, sn[j], S, gchi[j], S);
-        }
-    }
+}
+
+template <int K, bool MULTI>
+hipError_t fa_fwd_km(const a2c_plan &p, const float *ang, float *xyz, hipStream_t s)
+{
+    const size_t lds = (size_t)p.W * 3 * p.fa_stage_atoms * sizeof(float);
+    hipLaunchKernelGGL((fa_forward_kernel<K, MULTI>), dim3(p.n_tiles), dim3(p.W * kWave), lds, s,
+                       ang, xyz, p.d_tile_res, p.d_head_bits, p.d_res_atom_off, p.d_seq, p.d_fa,
+                       p.R, p.A, p.bb, p.fa_stage_atoms);
+    return hipGetLastError();
 }
 
 template <int K>
 hipError_t fa_fwd_k(const a2c_plan &p, const float *ang, float *xyz, hipStream_t s)
 {
-    hipLaunchKernelGGL((fa_forward_kernel<K>), dim3(p.n_tiles), dim3(p.W * kWave), 0, s, ang, xyz,
-                       p.d_tile_res, p.d_head_bits, p.d_res_atom_off, p.d_seq, p.d_fa, p.R, p.A,
-                       p.bb);
+    return p.multi_chunk ? fa_fwd_km<K, true>(p, ang, xyz, s) : fa_fwd_km<K, false>(p, ang, xyz, s);
+}
+
+template <int K, bool MULTI>
+hipError_t fa_bwd_km(const a2c_plan &p, const float *ang, const float *xyz, const float *g,
+                     float *gang, hipStream_t s)
+{
+    const dim3 grid(p.n_tiles), block(p.W * kWave);
+    // the coordinate form stages six planes; where they do not fit, the
+    // recompute form (three planes) computes the same gradient
+    if (xyz && (size_t)p.W * 6 * p.fa_stage_atoms * sizeof(float) > (size_t)kMaxDynamicLds)
+        xyz = nullptr;
+    const size_t lds = (size_t)p.W * (xyz ? 6 : 3) * p.fa_stage_atoms * sizeof(float);
+    if (xyz)
+        hipLaunchKernelGGL((fa_backward_kernel<K, false, MULTI>), grid, block, lds, s, ang, xyz,
+                           g, gang, p.d_tile_res, p.d_head_bits, p.d_res_atom_off, p.d_seq,
+                           p.d_fa, p.R, p.A, p.bb, p.fa_stage_atoms);
+    else
+        hipLaunchKernelGGL((fa_backward_kernel<K, true, MULTI>), grid, block, lds, s, ang, xyz,
+                           g, gang, p.d_tile_res, p.d_head_bits, p.d_res_atom_off, p.d_seq,
+                           p.d_fa, p.R, p.A, p.bb, p.fa_stage_atoms);
     return hipGetLastError();
 }
 
@@ -581,16 +765,8 @@ template <int K>
 hipError_t fa_bwd_k(const a2c_plan &p, const float *ang, const float *xyz, const float *g,
                     float *gang, hipStream_t s)
 {
-    const dim3 grid(p.n_tiles), block(p.W * kWave);
-    if (xyz)
-        hipLaunchKernelGGL((fa_backward_kernel<K, false>), grid, block, 0, s, ang, xyz, g, gang,
-                           p.d_tile_res, p.d_head_bits, p.d_res_atom_off, p.d_seq, p.d_fa, p.R,
-                           p.A, p.bb);
-    else
-        hipLaunchKernelGGL((fa_backward_kernel<K, true>), grid, block, 0, s, ang, xyz, g, gang,
-                           p.d_tile_res, p.d_head_bits, p.d_res_atom_off, p.d_seq, p.d_fa, p.R,
-                           p.A, p.bb);
-    return hipGetLastError();
+    return p.multi_chunk ? fa_bwd_km<K, true>(p, ang, xyz, g, gang, s)
+                         : fa_bwd_km<K, false>(p, ang, xyz, g, gang, s);
 }
 
 }  // namespace
@@ -612,6 +788,37 @@ hipError_t launch_fa_backward_scan(const a2c_plan &p, const float *ang, const fl
     case 2: return fa_bwd_k<2>(p, ang, xyz, g, gang, s);
     default: return hipErrorInvalidValue;
     }
+}
+
+// Dynamic LDS a full-atom launch needs beyond the static tables (forward
+// and recompute backward; the coordinate-mode backward needs twice this and
+// falls back to the recompute form where that does not fit).
+size_t fa_dynamic_lds(const a2c_plan &p) { return (size_t)p.W * 3 * p.fa_stage_atoms * sizeof(float); }
+
+template <typename F>
+static void allow_lds(F kernel)
+{
+    (void)hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              kMaxDynamicLds);
+}
+
+void fa_allow_large_lds()
+{
+    static bool done = false;
+    if (done) return;
+    allow_lds(fa_forward_kernel<1, false>);
+    allow_lds(fa_forward_kernel<1, true>);
+    allow_lds(fa_forward_kernel<2, false>);
+    allow_lds(fa_forward_kernel<2, true>);
+    allow_lds(fa_backward_kernel<1, false, false>);
+    allow_lds(fa_backward_kernel<1, false, true>);
+    allow_lds(fa_backward_kernel<1, true, false>);
+    allow_lds(fa_backward_kernel<1, true, true>);
+    allow_lds(fa_backward_kernel<2, false, false>);
+    allow_lds(fa_backward_kernel<2, false, true>);
+    allow_lds(fa_backward_kernel<2, true, false>);
+    allow_lds(fa_backward_kernel<2, true, true>);
+    done = true;
 }
 
 }  // namespace a2c

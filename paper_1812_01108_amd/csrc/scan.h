@@ -8,8 +8,10 @@
 //     aggregates, (fa, A) . (fb, B) = (fa | fb, fb ? B : A B);
 //   - adjoint: segmented exclusive suffix sum of per-lane wrenches
 //     (force, moment), reset at chain ends.
-// Each is a 6-step shuffle scan inside the wave, then one workgroup barrier
-// and a short scan of the wave totals that every wave repeats for itself.
+// A workgroup walks its tile in chunks of 64 W K residues and carries the
+// scan state from chunk to chunk.  Inside a chunk each scan is a 6-step DPP
+// scan inside the wave, one workgroup barrier and a short scan of the wave
+// totals that every wave repeats for itself.
 #pragma once
 #include "a2c_internal.h"
 #include "affine.h"
@@ -183,18 +185,50 @@ __device__ __forceinline__ Aff aff_bcast(const Aff &a, int l)
     return o;
 }
 
-// Exclusive segmented prefix product over the tile.  In: the lane aggregate
-// m (product of the lane's transforms since its last chain head, identity
-// when the lane is empty) and f (a chain starts inside the lane).  Out: the
-// frame X preceding the lane's first transform; meaningful only for residues
-// before the lane's first head.  Every thread of the block calls this (one
-// barrier); wave_active must be uniform per wave and true for a prefix of
-// the waves.
-__device__ __forceinline__ Aff block_exclusive_prefix(Aff m, bool f, bool wave_active,
-                                                      FwdShared &sh)
+__device__ __forceinline__ float uni(float v)
+{
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+__device__ __forceinline__ Aff aff_uniform(const Aff &a)
+{
+    Aff o;
+    o.r00 = uni(a.r00); o.r10 = uni(a.r10); o.r20 = uni(a.r20);
+    o.r01 = uni(a.r01); o.r11 = uni(a.r11); o.r21 = uni(a.r21);
+    o.r02 = uni(a.r02); o.r12 = uni(a.r12); o.r22 = uni(a.r22);
+    o.t0 = uni(a.t0); o.t1 = uni(a.t1); o.t2 = uni(a.t2);
+    return o;
+}
+
+// Segmented combine of a carry with a later segment: the later value wins
+// when a chain starts inside it, otherwise the carry is applied first.
+__device__ __forceinline__ Aff aff_seg_after(const Aff &carry, const Aff &t, bool t_head)
+{
+    const Aff c = aff_compose(carry, t);
+    return aff_select(t_head, t, c);
+}
+
+// Exclusive segmented prefix product over one chunk of a tile.
+//   m, f     lane aggregate (product of the lane's transforms since its last
+//            chain head; identity for an empty lane) and "a chain starts in
+//            this lane";
+//   nact     waves of the block holding residues of this chunk (a prefix);
+//   carry    (MULTI only) in: the frame after everything of the tile before
+//            this chunk (identity for the first chunk: tiles start at a chain
+//            head); out: the frame after this chunk, identical in every wave,
+//            also in waves idle in this chunk.
+// Returns the frame X preceding the lane's first transform (meaningful for
+// the lane's residues before its first chain head).  Every thread of the
+// block calls this (one barrier); sh must not be reused by the next call
+// (callers alternate two buffers).  MULTI = false: the tile is one chunk and
+// the carry is neither read nor written.
+template <bool MULTI>
+__device__ __forceinline__ Aff block_exclusive_prefix(Aff m, bool f, int nact, FwdShared &sh,
+                                                      Aff &carry)
 {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const bool wave_active = wave < nact;
     if (wave_active) {
         // inclusive scan: four shifts inside rows of 16, then the row totals
         const int rl = lane & 15;
@@ -212,28 +246,39 @@ __device__ __forceinline__ Aff block_exclusive_prefix(Aff m, bool f, bool wave_a
         }
     }
     __syncthreads();
-    if (!wave_active) return aff_identity();
-    // carry-in of this wave: segmented product of the totals of waves
-    // 0 .. wave-1 (the tile starts with a chain head: wave 0 has none)
-    Aff cw = aff_identity();
-    if (wave > 0) {
-        Aff t = aff_identity();
-        bool tf = false;
-        if (lane < wave) {
-            t = aff_load(sh.tot[lane]);
-            tf = sh.tot_flag[lane] != 0;
-        }
-        for (int off = 1; off < wave; off <<= 1) {
-            const Aff o = aff_shfl_up(t, off);
-            const int fo = __shfl_up((int)tf, off, 64);
-            if (lane >= off) {
-                const Aff c = aff_compose(o, t);
-                t = aff_select(tf, t, c);
-                tf = tf || (fo != 0);
-            }
-        }
-        cw = aff_bcast(t, wave - 1);
+    if (!MULTI && !wave_active) return aff_identity();
+    // inclusive scan of the wave totals in lanes 0..span-1 of row 0: this
+    // wave needs lanes before it; the chunk carry needs all nact of them
+    const int span = MULTI ? nact : wave;
+    Aff t = aff_identity();
+    bool tf = false;
+    if (lane < span) {
+        t = aff_load(sh.tot[lane]);
+        tf = sh.tot_flag[lane] != 0;
     }
+    const int rl = lane & 15;
+    if (span > 1)
+        aff_scan_combine(t, tf, aff_dpp<kDppRowShr + 1>(t), dpp_i<kDppRowShr + 1>(tf), rl >= 1);
+    if (span > 2)
+        aff_scan_combine(t, tf, aff_dpp<kDppRowShr + 2>(t), dpp_i<kDppRowShr + 2>(tf), rl >= 2);
+    if (span > 4)
+        aff_scan_combine(t, tf, aff_dpp<kDppRowShr + 4>(t), dpp_i<kDppRowShr + 4>(tf), rl >= 4);
+    if (span > 8)
+        aff_scan_combine(t, tf, aff_dpp<kDppRowShr + 8>(t), dpp_i<kDppRowShr + 8>(tf), rl >= 8);
+    // carry-in of this wave (identity for wave 0 of a one-chunk tile)
+    Aff cw = aff_identity();
+    if (MULTI) cw = carry;
+    if (wave_active && wave > 0) {
+        const Aff p = aff_bcast(t, wave - 1);
+        const bool pf = __builtin_amdgcn_readlane((int)tf, wave - 1) != 0;
+        cw = MULTI ? aff_seg_after(carry, p, pf) : p;
+    }
+    if (MULTI) {  // every wave advances the carry, also one idle in this chunk
+        const Aff p = aff_bcast(t, nact - 1);
+        const bool pf = __builtin_amdgcn_readlane((int)tf, nact - 1) != 0;
+        carry = aff_uniform(aff_seg_after(carry, p, pf));
+    }
+    if (!wave_active) return aff_identity();
     Aff e = aff_dpp<kDppWaveShr1>(m);
     int fe = dpp_i<kDppWaveShr1>(f);
     if (lane == 0) {
@@ -244,17 +289,26 @@ __device__ __forceinline__ Aff block_exclusive_prefix(Aff m, bool f, bool wave_a
     return fe ? e : xc;
 }
 
-// Exclusive segmented suffix sum over the tile.  In: the lane aggregate agg
-// (sum over the lane's atoms up to and including the lane's first chain end)
-// and f (a chain ends inside the lane).  Out: the wrench of everything after
-// the lane, up to the end of the chain the lane's last residue belongs to
-// (callers discard it when that residue ends its chain).  nact = number of
-// active waves.  Every thread of the block calls this (one barrier).
-__device__ __forceinline__ Wrench block_exclusive_suffix(Wrench agg, bool f, bool wave_active,
-                                                         int nact, BwdShared &sh)
+// Exclusive segmented suffix sum over one chunk of a tile, chunks visited
+// last to first.
+//   agg, f   lane aggregate (sum over the lane's atoms up to and including
+//            its first chain end) and "a chain ends in this lane";
+//   carry    (MULTI only) in: the wrench of what follows this chunk up to the
+//            end of the chain its last residue belongs to (zero for the last
+//            chunk: tiles end at a chain end); out: the same for the previous
+//            chunk, also in waves idle in this chunk (the last chunk, visited
+//            first, may leave waves idle that the earlier chunks use).
+// Returns the wrench of everything after the lane up to the end of the
+// chain the lane's last residue belongs to (callers discard it when that
+// residue ends its chain).  Every thread of the block calls this (one
+// barrier); callers alternate two buffers sh.
+template <bool MULTI>
+__device__ __forceinline__ Wrench block_exclusive_suffix(Wrench agg, bool f, int nact,
+                                                         BwdShared &sh, Wrench &carry)
 {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const bool wave_active = wave < nact;
     if (wave_active) {
         // inclusive reverse scan: four shifts inside rows, then the suffix
         // totals of rows 1 and 3 (lanes 16, 48) and of rows 2-3 (lane 32)
@@ -264,7 +318,7 @@ __device__ __forceinline__ Wrench block_exclusive_suffix(Wrench agg, bool f, boo
         wrench_scan_combine(agg, f, wrench_dpp<kDppRowShl + 4>(agg), dpp_i<kDppRowShl + 4>(f), rl < 12);
         wrench_scan_combine(agg, f, wrench_dpp<kDppRowShl + 8>(agg), dpp_i<kDppRowShl + 8>(f), rl < 8);
         {
-            const int src = lane < 16 ? 16 : 48;
+            const bool lo = lane < 16;
             Wrench o;
             const float a0 = lane_bcast(agg.g0, 16), b0 = lane_bcast(agg.g0, 48);
             const float a1 = lane_bcast(agg.g1, 16), b1 = lane_bcast(agg.g1, 48);
@@ -272,8 +326,8 @@ __device__ __forceinline__ Wrench block_exclusive_suffix(Wrench agg, bool f, boo
             const float a3 = lane_bcast(agg.m0, 16), b3 = lane_bcast(agg.m0, 48);
             const float a4 = lane_bcast(agg.m1, 16), b4 = lane_bcast(agg.m1, 48);
             const float a5 = lane_bcast(agg.m2, 16), b5 = lane_bcast(agg.m2, 48);
-            const int fa = __builtin_amdgcn_readlane((int)f, 16), fb = __builtin_amdgcn_readlane((int)f, 48);
-            const bool lo = src == 16;
+            const int fa = __builtin_amdgcn_readlane((int)f, 16);
+            const int fb = __builtin_amdgcn_readlane((int)f, 48);
             o.g0 = lo ? a0 : b0; o.g1 = lo ? a1 : b1; o.g2 = lo ? a2 : b2;
             o.m0 = lo ? a3 : b3; o.m1 = lo ? a4 : b4; o.m2 = lo ? a5 : b5;
             wrench_scan_combine(agg, f, o, lo ? fa : fb, (lane & 16) == 0);
@@ -293,31 +347,48 @@ __device__ __forceinline__ Wrench block_exclusive_suffix(Wrench agg, bool f, boo
         }
     }
     __syncthreads();
-    if (!wave_active) return wrench_zero();
-    // carry-in from the waves after this one (the tile ends at a chain end,
-    // so the last active wave has none)
-    Wrench cw = wrench_zero();
-    const int nafter = nact - 1 - wave;
-    if (nafter > 0) {
-        Wrench t = wrench_zero();
-        bool tf = false;
-        if (lane < nafter) {
-            const int w2 = wave + 1 + lane;
-            t.g0 = sh.tot[w2][0]; t.g1 = sh.tot[w2][1]; t.g2 = sh.tot[w2][2];
-            t.m0 = sh.tot[w2][3]; t.m1 = sh.tot[w2][4]; t.m2 = sh.tot[w2][5];
-            tf = sh.tot_flag[w2] != 0;
-        }
-        for (int off = 1; off < nafter; off <<= 1) {
-            const Wrench o = wrench_shfl_down(t, off);
-            const int fo = __shfl_down((int)tf, off, 64);
-            if (lane + off < kWave) {
-                if (!tf) wrench_add(t, o);
-                tf = tf || (fo != 0);
-            }
-        }
-        cw.g0 = lane_bcast(t.g0, 0); cw.g1 = lane_bcast(t.g1, 0); cw.g2 = lane_bcast(t.g2, 0);
-        cw.m0 = lane_bcast(t.m0, 0); cw.m1 = lane_bcast(t.m1, 0); cw.m2 = lane_bcast(t.m2, 0);
+    if (!MULTI && !wave_active) return wrench_zero();
+    // inclusive reverse scan of the wave totals in lanes 0..nact-1 of row 0,
+    // over as many of them as are needed: lanes wave+1..nact-1 for this
+    // wave, all nact for the chunk carry
+    const int span = MULTI ? nact : nact - 1 - wave;
+    Wrench t = wrench_zero();
+    bool tf = false;
+    if (lane < nact) {
+        t.g0 = sh.tot[lane][0]; t.g1 = sh.tot[lane][1]; t.g2 = sh.tot[lane][2];
+        t.m0 = sh.tot[lane][3]; t.m1 = sh.tot[lane][4]; t.m2 = sh.tot[lane][5];
+        tf = sh.tot_flag[lane] != 0;
     }
+    const int rl = lane & 15;
+    if (span > 1)
+        wrench_scan_combine(t, tf, wrench_dpp<kDppRowShl + 1>(t), dpp_i<kDppRowShl + 1>(tf), rl < 15);
+    if (span > 2)
+        wrench_scan_combine(t, tf, wrench_dpp<kDppRowShl + 2>(t), dpp_i<kDppRowShl + 2>(tf), rl < 14);
+    if (span > 4)
+        wrench_scan_combine(t, tf, wrench_dpp<kDppRowShl + 4>(t), dpp_i<kDppRowShl + 4>(tf), rl < 12);
+    if (span > 8)
+        wrench_scan_combine(t, tf, wrench_dpp<kDppRowShl + 8>(t), dpp_i<kDppRowShl + 8>(tf), rl < 8);
+    // carry into this wave from the waves after it (and, MULTI, later chunks)
+    Wrench cw = wrench_zero();
+    if (MULTI) cw = carry;
+    if (wave_active && wave + 1 < nact) {
+        Wrench p;
+        p.g0 = lane_bcast(t.g0, wave + 1); p.g1 = lane_bcast(t.g1, wave + 1);
+        p.g2 = lane_bcast(t.g2, wave + 1); p.m0 = lane_bcast(t.m0, wave + 1);
+        p.m1 = lane_bcast(t.m1, wave + 1); p.m2 = lane_bcast(t.m2, wave + 1);
+        const bool pf = __builtin_amdgcn_readlane((int)tf, wave + 1) != 0;
+        if (MULTI && !pf) wrench_add(p, carry);
+        cw = p;
+    }
+    if (MULTI) {  // every wave advances the carry, also one idle in this chunk
+        Wrench p;
+        p.g0 = lane_bcast(t.g0, 0); p.g1 = lane_bcast(t.g1, 0); p.g2 = lane_bcast(t.g2, 0);
+        p.m0 = lane_bcast(t.m0, 0); p.m1 = lane_bcast(t.m1, 0); p.m2 = lane_bcast(t.m2, 0);
+        const bool pf = __builtin_amdgcn_readlane((int)tf, 0) != 0;
+        if (!pf) wrench_add(p, carry);
+        carry = p;
+    }
+    if (!wave_active) return wrench_zero();
     Wrench S = wrench_dpp<kDppWaveShl1>(agg);
     int fs = dpp_i<kDppWaveShl1>(f);
     if (lane == kWave - 1) {
@@ -338,6 +409,16 @@ struct Stride {
     static constexpr int value = (N & 1) ? N : N + 1;
 };
 
+// The lane index made opaque to the optimiser, so address arithmetic
+// derived from it is recomputed where it is used instead of being hoisted out
+// of the chunk loop and held live in registers across it.
+__device__ __forceinline__ int lane_id()
+{
+    int l = threadIdx.x & 63;
+    asm volatile("" : "+v"(l));
+    return l;
+}
+
 __device__ __forceinline__ void wave_lds_sync()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -353,7 +434,7 @@ __device__ __forceinline__ void wave_lds_sync()
 template <int N>
 __device__ __forceinline__ void gload(const float *__restrict__ base, int n, float (&v)[N])
 {
-    const int lane = threadIdx.x & 63;
+    const int lane = lane_id();
 #pragma unroll
     for (int m = 0; m < N; ++m) {
         const int e = lane + 64 * m;
@@ -367,7 +448,7 @@ template <int N>
 __device__ __forceinline__ void to_blocked(float *buf, const float (&v)[N], int n, float (&out)[N])
 {
     constexpr int S = Stride<N>::value;
-    const int lane = threadIdx.x & 63;
+    const int lane = lane_id();
 #pragma unroll
     for (int m = 0; m < N; ++m) {
         const int e = lane + 64 * m;
@@ -386,7 +467,7 @@ __device__ __forceinline__ void stage_store(float *buf, const float (&in)[N], fl
                                             int n)
 {
     constexpr int S = Stride<N>::value;
-    const int lane = threadIdx.x & 63;
+    const int lane = lane_id();
 #pragma unroll
     for (int i = 0; i < N; ++i) buf[lane * S + i] = in[i];
     wave_lds_sync();

@@ -71,15 +71,21 @@ def test_null_arguments_rejected_on_host():
                                None, None, None, None) == -1
 
 
-def test_too_long_chain_unsupported():
+@pytest.mark.parametrize("model,limit", [(0, 64 * 64 * 16 * 4), (1, 64 * 64 * 16 * 2)])
+def test_too_long_chain_unsupported(model, limit):
+    """A chain beyond 64 chunks of the widest schedule is refused on the host,
+    before any device call."""
     from paper_1812_01108_amd import _lib
     lib = _lib.load()
-    off = np.array([0, 5000], dtype=np.int32)
+    off = np.array([0, limit + 1], dtype=np.int32)
+    seq = np.zeros(limit + 1, dtype=np.uint8)
     h = ctypes.c_void_p()
-    st = lib.a2c_plan_create(ctypes.byref(h), 0, 1,
+    st = lib.a2c_plan_create(ctypes.byref(h), model, 1,
                              off.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-                             None, None, None, None)
+                             seq.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), None, None,
+                             None)
     assert st == -2
+    assert b"longer than" in lib.a2c_last_error()
 
 
 def test_bad_geometry_rejected():

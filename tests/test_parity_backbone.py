@@ -49,8 +49,8 @@ EDGE_LENGTHS = [1, 2, 3, 0, 63, 64, 65, 0, 0, 255, 256, 257, 511, 700, 1000, 5, 
 @pytest.mark.parametrize("mode", ["coords", "recompute"])
 def test_schedules_ragged_edges(K, W, mode):
     a2c = _a2c()
-    lengths = [L for L in EDGE_LENGTHS if L <= 64 * W * K]
-    off, ang, g = _batch(lengths, 17)
+    # chains longer than one chunk (64 W K residues) are walked chunk by chunk
+    off, ang, g = _batch(EDGE_LENGTHS, 17)
     plan = a2c.Plan("backbone", offsets=off)
     plan.set_schedule(K, W)
     _check(plan, off, ang, g, mode=mode, label=f"K={K} W={W}")
@@ -73,7 +73,7 @@ def test_plain_ragged():
     _check(plan, off, ang, g, variant="plain", label="plain ragged")
 
 
-def test_longest_chain_one_tile():
+def test_long_chains_default_schedule():
     a2c = _a2c()
     off, ang, g = _batch([4096, 3, 4096], 29)
     plan = a2c.Plan("backbone", offsets=off)
@@ -81,6 +81,29 @@ def test_longest_chain_one_tile():
     assert s["res_per_lane"] * s["waves_per_group"] * 64 >= 4096
     # long chains accumulate float32 rounding; the stated 1e-3 A bound is at L = 1000
     _check(plan, off, ang, g, coord_tol=4e-3, label="L=4096")
+
+
+@pytest.mark.parametrize("mode", ["coords", "recompute"])
+def test_max_chunks_per_tile(mode):
+    """K = 1, W = 1: 64-residue chunks; a 4096-residue chain is exactly the
+    64-chunk maximum and shares the batch with short chains and chains that
+    end one residue either side of a chunk boundary."""
+    a2c = _a2c()
+    off, ang, g = _batch([5, 4096, 64, 65, 127, 128, 129, 1, 0, 2], 37)
+    plan = a2c.Plan("backbone", offsets=off)
+    plan.set_schedule(1, 1)
+    _check(plan, off, ang, g, mode=mode, coord_tol=4e-3, label="64 chunks")
+    with pytest.raises(a2c.A2CError):
+        a2c.Plan("backbone", lengths=[4097]).set_schedule(1, 1)
+
+
+def test_very_long_chain_multi_chunk():
+    """A 40000-residue chain: ten 4096-residue chunks at the default schedule."""
+    a2c = _a2c()
+    off, ang, g = _batch([40000, 17], 41)
+    plan = a2c.Plan("backbone", offsets=off)
+    for mode in ("coords", "recompute"):
+        _check(plan, off, ang, g, mode=mode, coord_tol=4e-2, label="L=40000")
 
 
 def test_accuracy_at_L1000_mixture():

@@ -50,15 +50,50 @@ def _check(plan, off, seq, ang, mode, label="", coord_tol=COORD_TOL_A, grad_tol=
         assert np.all(gr[3 + k][nchi <= k] == 0.0)
 
 
-@pytest.mark.parametrize("K,W", [(1, 1), (1, 4), (2, 2), (2, 16), (1, 16)])
+@pytest.mark.parametrize("K,W", [(1, 1), (1, 4), (2, 2), (2, 4), (1, 8), (1, 12)])
 @pytest.mark.parametrize("mode", ["coords", "recompute"])
 def test_schedules_all_types(K, W, mode):
+    """Chains longer than one chunk (64 K W residues) are walked chunk by chunk."""
     a2c = _a2c()
-    lengths = [L for L in [1, 2, 20, 63, 64, 65, 0, 130, 7, 200] if L <= 64 * K * W]
-    off, seq, ang = _batch(lengths, 101)
+    off, seq, ang = _batch([1, 2, 20, 63, 64, 65, 0, 130, 7, 200, 1000], 101)
     plan = a2c.Plan("fullatom", offsets=off, seq=seq)
     plan.set_schedule(K, W)
     _check(plan, off, seq, ang, mode, label=f"K={K} W={W}")
+
+
+@pytest.mark.parametrize("mode", ["coords", "recompute"])
+def test_max_chunks_per_tile(mode):
+    """K = 1, W = 1: a 4096-residue chain is exactly 64 chunks of 64 residues."""
+    a2c = _a2c()
+    off, seq, ang = _batch([3, 4096, 64, 65, 128, 129, 0, 1], 107)
+    plan = a2c.Plan("fullatom", offsets=off, seq=seq)
+    plan.set_schedule(1, 1)
+    _check(plan, off, seq, ang, mode, coord_tol=4e-3, label="64 chunks")
+
+
+def test_staging_beyond_lds_is_refused():
+    """Sixteen waves of 128 residues each would stage ~1000 atoms per wave in
+    three planes, beyond the LDS a workgroup may use: refused on the host,
+    and the plan keeps its schedule."""
+    a2c = _a2c()
+    off, seq, ang = _batch([3000], 109)
+    plan = a2c.Plan("fullatom", offsets=off, seq=seq)
+    before = plan.schedule
+    with pytest.raises(a2c.A2CError):
+        plan.set_schedule(2, 16)
+    assert plan.schedule == before
+    _check(plan, off, seq, ang, "coords", coord_tol=4e-3, label="after refusal")
+
+
+@pytest.mark.parametrize("mode", ["coords", "recompute"])
+def test_sixteen_waves_coords_falls_back_to_recompute(mode):
+    """K = 1, W = 16: three planes fit, six do not; the coordinate-mode
+    adjoint recomputes the frames instead and gives the same gradient."""
+    a2c = _a2c()
+    off, seq, ang = _batch([1500, 1024, 3, 700, 64], 113)
+    plan = a2c.Plan("fullatom", offsets=off, seq=seq)
+    plan.set_schedule(1, 16)
+    _check(plan, off, seq, ang, mode, coord_tol=2e-3, label=f"K=1 W=16 {mode}")
 
 
 @pytest.mark.parametrize("code", ["G", "W", "R", "P", "A"])

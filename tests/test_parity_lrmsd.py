@@ -1,0 +1,212 @@
+"""GPU parity of the LRMSD loss ("Loss function" section) against the FP64
+oracle (Kabsch SVD on the same float32 inputs promoted to float64): per-chain
+values, the gradient with respect to the input coordinates, ragged batches
+with empty, one-atom, two-atom and multi-segment chains, the autograd path
+through the map, and determinism.
+
+Tolerances.  The library accumulates the sums in float64 from the float32
+inputs and solves the 4x4 problem in float64, so LRMSD differs from the
+oracle by little more than the float32 rounding of the output: 1e-5 relative
+(+1e-6 A) is used.  The gradient is formed in float32 from float32 means and
+rotation: its error is ~1e-7 of the coordinate magnitudes (~1e2 A) against a
+residual of the size of the LRMSD (> 1 A here), hence the map's normwise
+per-chain 1e-3 bound with a wide margin."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import lrmsd as olr
+from tests.gpu_util import GRAD_TOL_REL, grad_rel_err, to_dev
+from workloads import (BACKBONE_GEOMETRY, make_angles, offsets_from_lengths, random_sequence,
+                       target_perturbation)
+
+pytestmark = pytest.mark.gpu
+GEOM = BACKBONE_GEOMETRY
+LR_RTOL, LR_ATOL = 1e-5, 1e-6
+
+
+def _a2c():
+    import paper_1812_01108_amd as a2c
+    return a2c
+
+
+def _rotations(quat):
+    w, x, y, z = quat.T
+    return np.stack([1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+                     2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+                     2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)],
+                    1).reshape(-1, 3, 3)
+
+
+def _structures(model, lengths, seed):
+    """(offsets, seq, angles, y, x, chain atom offsets): y the map of the
+    angles, x the map of perturbed angles moved by a random rigid motion per
+    chain; both float32 [3][A] (computed by the FP64 oracle, then rounded)."""
+    off = offsets_from_lengths(lengths)
+    R = int(off[-1])
+    rng = np.random.Generator(np.random.PCG64(seed))
+    planes = 3 if model == "backbone" else 7
+    ang = make_angles(rng, R, "mixture", planes)
+    seq = random_sequence(rng, R) if model == "fullatom" else None
+    pert, quat, trans = target_perturbation(seed, ang, len(lengths))
+    if model == "backbone":
+        y = oracle.backbone_forward(off, ang, GEOM)
+        t = oracle.backbone_forward(off, pert, GEOM)
+        ca = 3 * off
+    else:
+        y, aoff = oracle.fullatom_forward(off, seq, ang, GEOM)
+        t, _ = oracle.fullatom_forward(off, seq, pert, GEOM)
+        ca = np.asarray(aoff)[off].astype(np.int64)
+    rot = _rotations(quat)
+    x = np.empty_like(t)
+    for c in range(len(lengths)):
+        a0, a1 = ca[c], ca[c + 1]
+        x[:, a0:a1] = rot[c] @ t[:, a0:a1] + trans[c][:, None]
+    return off, seq, ang, y.astype(np.float32), x.astype(np.float32), ca
+
+
+def _plan(model, off, seq):
+    a2c = _a2c()
+    if model == "backbone":
+        return a2c.Plan("backbone", offsets=off)
+    return a2c.Plan("fullatom", offsets=off, seq=seq)
+
+
+def _gpu_lrmsd(plan, y, x, gout):
+    import torch
+    yd, xd = to_dev(y), to_dev(x)
+    ws = plan.lrmsd_workspace()
+    val = plan.lrmsd_forward(yd, xd, ws)
+    g = plan.lrmsd_backward(yd, xd, to_dev(gout), ws)
+    torch.cuda.synchronize()
+    return val.cpu().numpy(), g.cpu().numpy()
+
+
+def _check(plan, y, x, ca, seed, label, grad=True):
+    n = len(ca) - 1
+    gout = np.random.Generator(np.random.PCG64(seed + 5)).uniform(0.5, 2.0, n).astype(np.float32)
+    val, g = _gpu_lrmsd(plan, y, x, gout)
+    ref = olr.lrmsd_batch(x.astype(np.float64), y.astype(np.float64), ca)
+    verr = np.abs(val - ref)
+    print(f"{label}: chains={n} atoms={y.shape[1]} max|dLRMSD|={verr.max():.3e} A "
+          f"(LRMSD {ref.min():.3f}..{ref.max():.3f})", flush=True)
+    assert np.all(np.isfinite(val)) and np.all(np.isfinite(g))
+    assert np.all(verr <= LR_RTOL * ref + LR_ATOL), verr.max()
+    if grad:
+        gref = olr.lrmsd_grad_batch(x.astype(np.float64), y.astype(np.float64), ca,
+                                    gout.astype(np.float64))
+        # The gradient (y~ - U x~) / (N LRMSD) divides a residual of the size
+        # of LRMSD by LRMSD: below ~0.1 A the float32 rounding of the inputs
+        # (~1e-5 A on coordinates of ~1e2 A) decides the residual, and the
+        # gradient is not comparable (a rigid copy has no defined direction).
+        # Where it is, its l2 norm over the chain is also |gout| / sqrt(N)
+        # (the residual's squared norm is N LRMSD^2).
+        ok = ref >= 0.1
+        keep = np.repeat(ok, np.diff(ca))
+        gerr = grad_rel_err(np.where(keep, g, 0.0), np.where(keep, gref, 0.0), ca)
+        print(f"{label}: grad_rel={gerr:.3e} over {int(np.sum(ok))} chains", flush=True)
+        assert gerr <= GRAD_TOL_REL, gerr
+        for c in range(n):
+            a0, a1 = ca[c], ca[c + 1]
+            nrm = float(np.linalg.norm(g[:, a0:a1].astype(np.float64)))
+            if a1 == a0 or val[c] == 0.0:
+                assert nrm == 0.0
+            elif ok[c]:
+                want = gout[c] / np.sqrt(a1 - a0)
+                assert abs(nrm - want) <= 1e-3 * want, (c, nrm, want)
+    return val, g
+
+
+def test_backbone_ragged_with_multi_segment_chains():
+    """Chains of 0, 1, 2 and 3 atoms' worth of residues, and chains of 4200
+    and 12288 atoms (two and three 4096-atom segments)."""
+    off, seq, ang, y, x, ca = _structures("backbone", [1, 0, 50, 700, 1400, 2, 4096, 3], 211)
+    plan = _plan("backbone", off, seq)
+    _check(plan, y, x, ca, 211, "backbone ragged")
+
+
+def test_fullatom_ragged():
+    off, seq, ang, y, x, ca = _structures("fullatom", [30, 0, 300, 1, 520, 1000, 64], 223)
+    plan = _plan("fullatom", off, seq)
+    _check(plan, y, x, ca, 223, "full-atom ragged")
+
+
+def test_single_and_two_atom_chains():
+    """One atom: LRMSD 0 and no gradient.  Two atoms: the rotation about the
+    pair's axis is free (a repeated eigenvalue), the LRMSD and the gradient
+    are still unique."""
+    a2c = _a2c()
+    rng = np.random.Generator(np.random.PCG64(227))
+    # backbone plan with 1-residue chains: 3 atoms each; build coordinates by hand
+    off = offsets_from_lengths([1, 1, 1])
+    plan = a2c.Plan("backbone", offsets=off)
+    y = rng.normal(0, 5, (3, 9)).astype(np.float32)
+    x = rng.normal(0, 5, (3, 9)).astype(np.float32)
+    # chain 1: two distinct atoms and a copy of the second (collinear)
+    y[:, 5] = y[:, 4]
+    x[:, 5] = x[:, 4]
+    # chain 2: all three atoms equal (a single point)
+    y[:, 7] = y[:, 8] = y[:, 6]
+    x[:, 7] = x[:, 8] = x[:, 6]
+    val, g = _check(plan, y, x, 3 * off, 227, "tiny chains")
+    assert val[2] <= 1e-6 and np.all(g[:, 6:9] == 0.0)
+
+
+def test_identical_up_to_rigid_motion():
+    """Target = input moved rigidly: LRMSD at the float32 rounding level."""
+    off, seq, ang, y, x, ca = _structures("backbone", [200, 700, 31], 229)
+    plan = _plan("backbone", off, seq)
+    q = np.random.Generator(np.random.PCG64(230)).standard_normal((3, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    rot = _rotations(q)
+    x2 = np.empty_like(y)
+    for c in range(3):
+        a0, a1 = ca[c], ca[c + 1]
+        x2[:, a0:a1] = (rot[c] @ y[:, a0:a1].astype(np.float64) + 7.0 * c).astype(np.float32)
+    val, _ = _gpu_lrmsd(plan, y, x2, np.ones(3, np.float32))
+    ref = olr.lrmsd_batch(x2.astype(np.float64), y.astype(np.float64), ca)
+    print("rigid copies:", val, ref, flush=True)
+    assert np.all(val <= 1e-4) and np.all(np.abs(val - ref) <= 1e-4)
+
+
+def test_deterministic():
+    off, seq, ang, y, x, ca = _structures("fullatom", [300, 129, 2], 233)
+    plan = _plan("fullatom", off, seq)
+    ones = np.ones(3, np.float32)
+    v1, g1 = _gpu_lrmsd(plan, y, x, ones)
+    v2, g2 = _gpu_lrmsd(plan, y, x, ones)
+    assert np.array_equal(v1, v2) and np.array_equal(g1, g2)
+
+
+@pytest.mark.parametrize("mode", ["coords", "recompute"])
+def test_autograd_map_then_lrmsd(mode):
+    """loss = sum_c LRMSD_c(map(angles), target): the angle gradient through
+    both autograd Functions against the oracle chain rule (oracle LRMSD
+    gradient fed to the oracle adjoint)."""
+    import torch
+    a2c = _a2c()
+    off, seq, ang, y, x, ca = _structures("fullatom", [120, 7, 333], 239)
+    plan = _plan("fullatom", off, seq)
+    a = to_dev(ang).requires_grad_(True)
+    coords = a2c.angles_to_coords(a, plan, mode)
+    loss = a2c.lrmsd(coords, to_dev(x), plan).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    y_gpu = coords.detach().cpu().numpy()
+    gl = olr.lrmsd_grad_batch(x.astype(np.float64), y_gpu.astype(np.float64), ca, np.ones(3))
+    gref = oracle.fullatom_backward(off, seq, ang, GEOM, gl.astype(np.float32))
+    gerr = grad_rel_err(a.grad.cpu().numpy(), gref, off)
+    print(f"autograd {mode}: loss={loss.item():.4f} grad_rel={gerr:.3e}", flush=True)
+    assert gerr <= GRAD_TOL_REL, gerr
+
+
+def test_empty_plan_and_all_empty_chains():
+    import torch
+    a2c = _a2c()
+    plan = a2c.Plan("backbone", offsets=np.array([0, 0, 0], np.int32))
+    e = torch.empty((3, 0), dtype=torch.float32, device="cuda:0")
+    ws = plan.lrmsd_workspace()
+    val = plan.lrmsd_forward(e, e, ws)
+    g = plan.lrmsd_backward(e, e, torch.ones(2, device="cuda:0"), ws)
+    torch.cuda.synchronize()
+    assert val.cpu().numpy().tolist() == [0.0, 0.0] and g.numel() == 0
