@@ -57,19 +57,27 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-plain", action="store_true")
     p.add_argument("--kernel-reps", type=int, default=50)
+    p.add_argument("--loss", default="mse", choices=["mse", "lrmsd"],
+                   help="training-step workload: sum |r - t|^2 (default) or the per-chain "
+                        "LRMSD of the Loss function section, summed over chains")
     return p.parse_args()
 
 
-def make_step(a2c, plan, angles, grad_up, mode, target=None):
+def make_step(a2c, plan, angles, grad_up, mode, target=None, loss="mse"):
     """One step: forward through the autograd Function, then the adjoint for
-    the fixed upstream gradient, or (with a target) for the loss
-    sum |r - t|^2, whose gradient 2 (r - t) is formed inside the step."""
+    the fixed upstream gradient, or (with a target) for a loss formed inside
+    the step: sum |r - t|^2 (gradient 2 (r - t)), or sum over chains of the
+    LRMSD (its forward and backward kernels run inside the step)."""
     import torch
 
     x = angles.clone().requires_grad_(True)
 
     def step():
         out = a2c.angles_to_coords(x, plan, mode=mode)
+        if target is not None and loss == "lrmsd":
+            lval = a2c.lrmsd(out, target, plan).sum()
+            (gx,) = torch.autograd.grad(lval, x)
+            return out, gx
         g = grad_up if target is None else 2.0 * (out - target)
         (gx,) = torch.autograd.grad(out, x, g)
         return out, gx
@@ -259,16 +267,37 @@ def main():
         plan.autotune(angles, grad_up, from_coords=mode == "coords", reps=5)
 
     # scan form, whole step in one graph
-    step = make_step(a2c, plan, angles, grad_up, mode, target)
+    loss = args.loss if training else None
+    step = make_step(a2c, plan, angles, grad_up, mode, target, loss or "mse")
     graph, outs = capture(step)
     dt = time_graph(graph, args.steps, args.warmup)
     ms = dt * 1000.0 / args.steps
     value = R * args.steps / dt
     gpu_coords = outs[0].detach().cpu().numpy()
     gpu_grad = outs[1].detach().cpu().numpy()
-    if training:
+    lr_info = None
+    if training and loss == "mse":
         g_np = 2.0 * (gpu_coords.astype(np.float64) - target.cpu().numpy())
         grad_up = torch.from_numpy(g_np.astype(np.float32)).to(dev)
+    elif training:
+        # the loss gradient the step fed to the adjoint, and the LRMSD
+        # kernels' durations (forward reads both sets: 24 B per atom;
+        # backward reads both and writes the gradient: 36 B per atom)
+        xyz_t = outs[0].detach()
+        ws = plan.lrmsd_workspace()
+        lr_out = plan.lrmsd_forward(xyz_t, target, ws)
+        ones = torch.ones(plan.n_chains, device=dev)
+        grad_up = plan.lrmsd_backward(xyz_t, target, ones, ws)
+        lf = kernel_avg_us(lambda: plan.lrmsd_forward(xyz_t, target, ws, lr_out),
+                           args.kernel_reps)
+        lb = kernel_avg_us(lambda: plan.lrmsd_backward(xyz_t, target, ones, ws, grad_up),
+                           args.kernel_reps)
+        A = plan.n_atoms
+        lr_info = {"forward_us": round(lf, 3), "backward_us": round(lb, 3),
+                   "forward_GBs": round(24 * A / (lf * 1e-6) / 1e9, 1),
+                   "backward_GBs": round(36 * A / (lb * 1e-6) / 1e9, 1),
+                   "mean_lrmsd_A": float(lr_out.mean())}
+        torch.cuda.synchronize()
 
     # per-kernel durations for the roofline
     coords_buf = torch.empty((3, plan.n_atoms), device=dev)
@@ -314,6 +343,14 @@ def main():
 
     cpu, parity = (None, None)
     if not args.no_cpu_baseline:
+        if loss == "lrmsd":
+            # the oracle's LRMSD gradient of the step's coordinates, fed to
+            # the oracle adjoint inside the baseline's parity check
+            from oracle import lrmsd as olr
+            ca, _ = plan.atom_offsets()
+            g_np = olr.lrmsd_grad_batch(target.cpu().numpy().astype(np.float64),
+                                        gpu_coords.astype(np.float64), ca,
+                                        np.ones(plan.n_chains)).astype(np.float32)
         cpu, parity = cpu_baseline(model, inp, g_np, gpu_coords, gpu_grad)
 
     sched = plan.schedule
@@ -324,10 +361,11 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": cfg.name, "model": model, "n_chains": inp["n_chains"],
                    "residues": R, "atoms": plan.n_atoms, "angles": cfg.angles,
-                   "adjoint": mode, "loss_in_graph": training,
+                   "adjoint": mode, "loss_in_graph": loss,
                    "res_per_lane": sched["res_per_lane"],
                    "waves_per_group": sched["waves_per_group"], "tiles": sched["n_tiles"]},
         "roofline": roof,
+        "lrmsd": lr_info,
         "plain_gpu": plain,
         "speedup_vs_plain": (value / plain["value"]) if plain else None,
         "cpu_baseline": cpu,

@@ -186,7 +186,9 @@ a2c_status a2c_plan_get_schedule(const a2c_plan *plan, int32_t *res_per_lane,
 
 /* Autotuner: times forward + backward (A2C_SCAN) for every schedule that
  * a2c_plan_set_schedule accepts for the plan, on the caller's buffers, and
- * keeps the fastest on the plan.
+ * keeps the fastest on the plan (candidates in order of residues per lane,
+ * then waves; a later one must be 3 % faster than the best so far to replace
+ * it, so near-ties resolve to the smaller schedule).
  *   d_angles, d_coords, d_grad_coords, d_grad_angles: buffers of the plan's
  *     sizes; their contents are overwritten (coords and grad_angles) or read.
  *   backward_from_coords: nonzero times a2c_backward with d_coords (the

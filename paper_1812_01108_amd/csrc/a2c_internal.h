@@ -16,6 +16,10 @@ constexpr int kMaxChunks = 64;        // chunks of 64 W K residues per tile
 // dynamic LDS allowed to the full-atom kernels (160 KB per workgroup on
 // gfx950, less the static tables)
 constexpr int kMaxDynamicLds = 136 * 1024;
+// Launch-bound classes of the scan kernels: up to 8 waves per workgroup
+// (512 lanes) a kernel may use up to 256 VGPRs without spilling; 16 waves
+// cap it at 128.  Launchers pick the class from the schedule's wave count.
+constexpr int kLbSmall = 512, kLbLarge = 1024;
 // LRMSD: atoms per segment (one workgroup of 256 lanes, 16 atoms per lane)
 constexpr int kLrSegAtoms = 4096;
 

@@ -134,7 +134,10 @@ extern "C" a2c_status a2c_plan_autotune(a2c_plan *p, const float *d_angles, floa
                 if (trial > 0) cand = std::min(cand, ms);  // first trial warms up
             }
             if (st != A2C_OK) break;
-            if (cand < best) {
+            // a later candidate (more residues per lane or waves) must be
+            // 3 % faster to win: near-ties keep the smaller schedule, so the
+            // choice does not flip with timing noise
+            if (cand < 0.97f * best) {
                 best = cand;
                 bK = k;
                 bW = w;

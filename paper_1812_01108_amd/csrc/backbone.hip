@@ -44,9 +44,14 @@ __device__ __forceinline__ void bb_lane_positions(
 
     Aff m = aff_identity();
     int first_head = K;    // residues before it need the carry-in frame
+    // zero first, write only valid residues below: stores to the same
+    // element from two branches get merged through a select of addresses,
+    // which forces the arrays out of registers into scratch memory
+#pragma unroll
+    for (int i = 0; i < 3 * K; ++i) x[i] = y[i] = z[i] = 0.f;
     if (wave_active) {
         // sin/cos of all 3K angles up front, with one wave-uniform choice
-        // between the branch-free reduction and sincosf (huge or non-finite
+        // between the branch-free reduction and the library (huge or non-finite
         // arguments), so the independent evaluations interleave
         float so[K], co[K], sp[K], cp[K], ss[K], cs[K];
         bool ok = true;
@@ -63,9 +68,9 @@ __device__ __forceinline__ void bb_lane_positions(
         } else {
 #pragma unroll
             for (int j = 0; j < K; ++j) {
-                sincosf(om[j], &so[j], &co[j]);
-                sincosf(phi[j], &sp[j], &cp[j]);
-                sincosf(psi[j], &ss[j], &cs[j]);
+                sincos_accurate(om[j], so[j], co[j]);
+                sincos_accurate(phi[j], sp[j], cp[j]);
+                sincos_accurate(psi[j], ss[j], cs[j]);
             }
         }
 #pragma unroll
@@ -81,10 +86,6 @@ __device__ __forceinline__ void bb_lane_positions(
                 x[3 * j + 1] = m.t0; y[3 * j + 1] = m.t1; z[3 * j + 1] = m.t2;
                 aff_apply_transform(m, P.ct[2], P.st[2], P.d[2], cs[j], ss[j]);
                 x[3 * j + 2] = m.t0; y[3 * j + 2] = m.t1; z[3 * j + 2] = m.t2;
-            } else {
-                x[3 * j] = y[3 * j] = z[3 * j] = 0.f;
-                x[3 * j + 1] = y[3 * j + 1] = z[3 * j + 1] = 0.f;
-                x[3 * j + 2] = y[3 * j + 2] = z[3 * j + 2] = 0.f;
             }
         }
         // the fixed rotations repeat every residue, so their float32 rounding
@@ -223,8 +224,8 @@ __device__ __forceinline__ void load_angles(float *buf, const float *__restrict_
     to_blocked<K>(buf, v2, nres, om);
 }
 
-template <int K, bool MULTI>
-__global__ __launch_bounds__(1024) void bb_forward_scan_kernel(
+template <int K, bool MULTI, int LB>
+__global__ __launch_bounds__(LB) void bb_forward_scan_kernel(
     const float *__restrict__ ang, float *__restrict__ xyz, const int32_t *__restrict__ tile_res,
     const uint32_t *__restrict__ head_bits, int64_t R, BBParams P)
 {
@@ -265,8 +266,8 @@ __global__ __launch_bounds__(1024) void bb_forward_scan_kernel(
 // Backward that recomputes the frames from the angles (no stored state).
 // Tiles of several chunks first run the forward scan alone to record each
 // chunk's carry-in frame, then visit the chunks last to first.
-template <int K, bool MULTI>
-__global__ __launch_bounds__(1024) void bb_backward_recompute_kernel(
+template <int K, bool MULTI, int LB>
+__global__ __launch_bounds__(LB) void bb_backward_recompute_kernel(
     const float *__restrict__ ang, const float *__restrict__ g, float *__restrict__ gang,
     const int32_t *__restrict__ tile_res, const uint32_t *__restrict__ head_bits, int64_t R,
     BBParams P)
@@ -343,8 +344,8 @@ __global__ __launch_bounds__(1024) void bb_backward_recompute_kernel(
 }
 
 // Backward from the coordinates the forward produced (chunks last to first).
-template <int K, bool MULTI>
-__global__ __launch_bounds__(1024) void bb_backward_coords_kernel(
+template <int K, bool MULTI, int LB>
+__global__ __launch_bounds__(LB) void bb_backward_coords_kernel(
     const float *__restrict__ xyz, const float *__restrict__ g, float *__restrict__ gang,
     const int32_t *__restrict__ tile_res, const uint32_t *__restrict__ head_bits, int64_t R,
     BBParams P)
@@ -429,7 +430,7 @@ __global__ __launch_bounds__(64) void bb_forward_plain_kernel(
 #pragma unroll
         for (int s = 0; s < 3; ++s) {
             float sa, ca;
-            sincosf(ang[(int64_t)slot_plane(s) * R + r], &sa, &ca);
+            sincos_accurate(ang[(int64_t)slot_plane(s) * R + r], sa, ca);
             aff_apply_transform(m, P.ct[s], P.st[s], P.d[s], ca, sa);
             const int64_t a = 3 * r + s;
             aff_store(ws + 12 * a, m);
@@ -464,7 +465,7 @@ __global__ __launch_bounds__(kPlainBlock) void bb_backward_plain_kernel(
     if (active) {
         const int s = (int)(i % 3);
         float sa, ca;
-        sincosf(ang[(int64_t)slot_plane(s) * R + r0 + i / 3], &sa, &ca);
+        sincos_accurate(ang[(int64_t)slot_plane(s) * R + r0 + i / 3], sa, ca);
         const float ct = P.ct[s], st = P.st[s];
         // dR (3x3): [[0, ca st, -sa st], [0, -sa, -ca], [0, ca ct, -sa ct]]
         const float d01 = ca * st, d02 = -sa * st, d11 = -sa, d12 = -ca, d21 = ca * ct,
@@ -516,33 +517,38 @@ __global__ __launch_bounds__(kPlainBlock) void bb_backward_plain_kernel(
     if (active) gang[(int64_t)slot_plane((int)(i % 3)) * R + r0 + i / 3] = acc;
 }
 
-template <int K, bool MULTI>
-hipError_t fwd_km(const a2c_plan &p, const float *ang, float *xyz, hipStream_t s)
+template <int K, bool MULTI, int LB>
+hipError_t fwd_kml(const a2c_plan &p, const float *ang, float *xyz, hipStream_t s)
 {
     const dim3 grid(p.n_tiles), block(p.W * kWave);
-    hipLaunchKernelGGL((bb_forward_scan_kernel<K, MULTI>), grid, block, stage_bytes<K>(p.W), s,
-                       ang, xyz, p.d_tile_res, p.d_head_bits, p.R, p.bb);
+    hipLaunchKernelGGL((bb_forward_scan_kernel<K, MULTI, LB>), grid, block, stage_bytes<K>(p.W),
+                       s, ang, xyz, p.d_tile_res, p.d_head_bits, p.R, p.bb);
     return hipGetLastError();
 }
 
 template <int K>
 hipError_t fwd_k(const a2c_plan &p, const float *ang, float *xyz, hipStream_t s)
 {
-    return p.multi_chunk ? fwd_km<K, true>(p, ang, xyz, s) : fwd_km<K, false>(p, ang, xyz, s);
+    const bool small = p.W * kWave <= kLbSmall;
+    if (p.multi_chunk)
+        return small ? fwd_kml<K, true, kLbSmall>(p, ang, xyz, s)
+                     : fwd_kml<K, true, kLbLarge>(p, ang, xyz, s);
+    return small ? fwd_kml<K, false, kLbSmall>(p, ang, xyz, s)
+                 : fwd_kml<K, false, kLbLarge>(p, ang, xyz, s);
 }
 
-template <int K, bool MULTI>
-hipError_t bwd_km(const a2c_plan &p, const float *ang, const float *xyz, const float *g,
-                  float *gang, hipStream_t s)
+template <int K, bool MULTI, int LB>
+hipError_t bwd_kml(const a2c_plan &p, const float *ang, const float *xyz, const float *g,
+                   float *gang, hipStream_t s)
 {
     const dim3 grid(p.n_tiles), block(p.W * kWave);
     const size_t lds = stage_bytes<K>(p.W);
     if (xyz)
-        hipLaunchKernelGGL((bb_backward_coords_kernel<K, MULTI>), grid, block, lds, s, xyz, g,
-                           gang, p.d_tile_res, p.d_head_bits, p.R, p.bb);
+        hipLaunchKernelGGL((bb_backward_coords_kernel<K, MULTI, LB>), grid, block, lds, s, xyz,
+                           g, gang, p.d_tile_res, p.d_head_bits, p.R, p.bb);
     else
-        hipLaunchKernelGGL((bb_backward_recompute_kernel<K, MULTI>), grid, block, lds, s, ang, g,
-                           gang, p.d_tile_res, p.d_head_bits, p.R, p.bb);
+        hipLaunchKernelGGL((bb_backward_recompute_kernel<K, MULTI, LB>), grid, block, lds, s, ang,
+                           g, gang, p.d_tile_res, p.d_head_bits, p.R, p.bb);
     return hipGetLastError();
 }
 
@@ -550,8 +556,12 @@ template <int K>
 hipError_t bwd_k(const a2c_plan &p, const float *ang, const float *xyz, const float *g,
                  float *gang, hipStream_t s)
 {
-    return p.multi_chunk ? bwd_km<K, true>(p, ang, xyz, g, gang, s)
-                         : bwd_km<K, false>(p, ang, xyz, g, gang, s);
+    const bool small = p.W * kWave <= kLbSmall;
+    if (p.multi_chunk)
+        return small ? bwd_kml<K, true, kLbSmall>(p, ang, xyz, g, gang, s)
+                     : bwd_kml<K, true, kLbLarge>(p, ang, xyz, g, gang, s);
+    return small ? bwd_kml<K, false, kLbSmall>(p, ang, xyz, g, gang, s)
+                 : bwd_kml<K, false, kLbLarge>(p, ang, xyz, g, gang, s);
 }
 
 }  // namespace

@@ -368,9 +368,9 @@ __device__ __forceinline__ Aff fa_lane_aggregate(const float *__restrict__ ang, 
     } else {
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-            sincosf(phi[j], &in[j].sp, &in[j].cp);
-            sincosf(psi[j], &in[j].ss, &in[j].cs);
-            sincosf(om[j], &in[j].so, &in[j].co);
+            sincos_accurate(phi[j], in[j].sp, in[j].cp);
+            sincos_accurate(psi[j], in[j].ss, in[j].cs);
+            sincos_accurate(om[j], in[j].so, in[j].co);
         }
     }
 #pragma unroll
@@ -394,7 +394,7 @@ __device__ __forceinline__ void side_step(Aff &sf, const FAType &ft, int f, floa
     float c = 1.f, s = 0.f;
     if (ft.side_chi[f]) {
         if (__all(sincos_fast_ok(chi))) sincos_fast(chi, s, c);
-        else sincosf(chi, &s, &c);
+        else sincos_accurate(chi, s, c);
     }
     aff_apply_transform(sf, ft.ct[f], ft.st[f], ft.d[f], c, s);
 }
@@ -456,8 +456,8 @@ __device__ __forceinline__ LaneRun<K> lane_run(const FAChunk &k,
     return L;
 }
 
-template <int K, bool MULTI>
-__global__ __launch_bounds__(1024) void fa_forward_kernel(
+template <int K, bool MULTI, int LB>
+__global__ __launch_bounds__(LB) void fa_forward_kernel(
     const float *__restrict__ ang, float *__restrict__ xyz, const int32_t *__restrict__ tile_res,
     const uint32_t *__restrict__ head_bits, const int32_t *__restrict__ res_aoff,
     const uint8_t *__restrict__ seq, const FATable *__restrict__ gtab, int64_t R, int64_t A,
@@ -556,8 +556,8 @@ __device__ __forceinline__ void fa_store_grads(float *__restrict__ gang, int64_t
 // RECOMPUTE: frames from the angles (tiles of several chunks first record
 // each chunk's forward carry); otherwise positions and axes from the
 // forward's coordinates.
-template <int K, bool RECOMPUTE, bool MULTI>
-__global__ __launch_bounds__(1024) void fa_backward_kernel(
+template <int K, bool RECOMPUTE, bool MULTI, int LB>
+__global__ __launch_bounds__(LB) void fa_backward_kernel(
     const float *__restrict__ ang, const float *__restrict__ xyz, const float *__restrict__ g,
     float *__restrict__ gang, const int32_t *__restrict__ tile_res,
     const uint32_t *__restrict__ head_bits, const int32_t *__restrict__ res_aoff,
@@ -724,14 +724,21 @@ __global__ __launch_bounds__(1024) void fa_backward_kernel(
     }
 }
 
+template <int K, bool MULTI, int LB>
+hipError_t fa_fwd_kml(const a2c_plan &p, const float *ang, float *xyz, hipStream_t s)
+{
+    const size_t lds = (size_t)p.W * 3 * p.fa_stage_atoms * sizeof(float);
+    hipLaunchKernelGGL((fa_forward_kernel<K, MULTI, LB>), dim3(p.n_tiles), dim3(p.W * kWave),
+                       lds, s, ang, xyz, p.d_tile_res, p.d_head_bits, p.d_res_atom_off, p.d_seq,
+                       p.d_fa, p.R, p.A, p.bb, p.fa_stage_atoms);
+    return hipGetLastError();
+}
+
 template <int K, bool MULTI>
 hipError_t fa_fwd_km(const a2c_plan &p, const float *ang, float *xyz, hipStream_t s)
 {
-    const size_t lds = (size_t)p.W * 3 * p.fa_stage_atoms * sizeof(float);
-    hipLaunchKernelGGL((fa_forward_kernel<K, MULTI>), dim3(p.n_tiles), dim3(p.W * kWave), lds, s,
-                       ang, xyz, p.d_tile_res, p.d_head_bits, p.d_res_atom_off, p.d_seq, p.d_fa,
-                       p.R, p.A, p.bb, p.fa_stage_atoms);
-    return hipGetLastError();
+    return p.W * kWave <= kLbSmall ? fa_fwd_kml<K, MULTI, kLbSmall>(p, ang, xyz, s)
+                                   : fa_fwd_kml<K, MULTI, kLbLarge>(p, ang, xyz, s);
 }
 
 template <int K>
@@ -740,25 +747,37 @@ hipError_t fa_fwd_k(const a2c_plan &p, const float *ang, float *xyz, hipStream_t
     return p.multi_chunk ? fa_fwd_km<K, true>(p, ang, xyz, s) : fa_fwd_km<K, false>(p, ang, xyz, s);
 }
 
-template <int K, bool MULTI>
-hipError_t fa_bwd_km(const a2c_plan &p, const float *ang, const float *xyz, const float *g,
-                     float *gang, hipStream_t s)
+template <int K, bool RECOMPUTE, bool MULTI, int LB>
+void fa_bwd_launch(const a2c_plan &p, const float *ang, const float *xyz, const float *g,
+                   float *gang, hipStream_t s)
 {
-    const dim3 grid(p.n_tiles), block(p.W * kWave);
+    const size_t lds = (size_t)p.W * (RECOMPUTE ? 3 : 6) * p.fa_stage_atoms * sizeof(float);
+    hipLaunchKernelGGL((fa_backward_kernel<K, RECOMPUTE, MULTI, LB>), dim3(p.n_tiles),
+                       dim3(p.W * kWave), lds, s, ang, xyz, g, gang, p.d_tile_res, p.d_head_bits,
+                       p.d_res_atom_off, p.d_seq, p.d_fa, p.R, p.A, p.bb, p.fa_stage_atoms);
+}
+
+template <int K, bool MULTI, int LB>
+hipError_t fa_bwd_kml(const a2c_plan &p, const float *ang, const float *xyz, const float *g,
+                      float *gang, hipStream_t s)
+{
     // the coordinate form stages six planes; where they do not fit, the
     // recompute form (three planes) computes the same gradient
     if (xyz && (size_t)p.W * 6 * p.fa_stage_atoms * sizeof(float) > (size_t)kMaxDynamicLds)
         xyz = nullptr;
-    const size_t lds = (size_t)p.W * (xyz ? 6 : 3) * p.fa_stage_atoms * sizeof(float);
     if (xyz)
-        hipLaunchKernelGGL((fa_backward_kernel<K, false, MULTI>), grid, block, lds, s, ang, xyz,
-                           g, gang, p.d_tile_res, p.d_head_bits, p.d_res_atom_off, p.d_seq,
-                           p.d_fa, p.R, p.A, p.bb, p.fa_stage_atoms);
+        fa_bwd_launch<K, false, MULTI, LB>(p, ang, xyz, g, gang, s);
     else
-        hipLaunchKernelGGL((fa_backward_kernel<K, true, MULTI>), grid, block, lds, s, ang, xyz,
-                           g, gang, p.d_tile_res, p.d_head_bits, p.d_res_atom_off, p.d_seq,
-                           p.d_fa, p.R, p.A, p.bb, p.fa_stage_atoms);
+        fa_bwd_launch<K, true, MULTI, LB>(p, ang, xyz, g, gang, s);
     return hipGetLastError();
+}
+
+template <int K, bool MULTI>
+hipError_t fa_bwd_km(const a2c_plan &p, const float *ang, const float *xyz, const float *g,
+                     float *gang, hipStream_t s)
+{
+    return p.W * kWave <= kLbSmall ? fa_bwd_kml<K, MULTI, kLbSmall>(p, ang, xyz, g, gang, s)
+                                   : fa_bwd_kml<K, MULTI, kLbLarge>(p, ang, xyz, g, gang, s);
 }
 
 template <int K>
@@ -802,22 +821,26 @@ static void allow_lds(F kernel)
                               kMaxDynamicLds);
 }
 
+template <int K, bool MULTI, int LB>
+static void allow_lds_km()
+{
+    allow_lds(fa_forward_kernel<K, MULTI, LB>);
+    allow_lds(fa_backward_kernel<K, false, MULTI, LB>);
+    allow_lds(fa_backward_kernel<K, true, MULTI, LB>);
+}
+
 void fa_allow_large_lds()
 {
     static bool done = false;
     if (done) return;
-    allow_lds(fa_forward_kernel<1, false>);
-    allow_lds(fa_forward_kernel<1, true>);
-    allow_lds(fa_forward_kernel<2, false>);
-    allow_lds(fa_forward_kernel<2, true>);
-    allow_lds(fa_backward_kernel<1, false, false>);
-    allow_lds(fa_backward_kernel<1, false, true>);
-    allow_lds(fa_backward_kernel<1, true, false>);
-    allow_lds(fa_backward_kernel<1, true, true>);
-    allow_lds(fa_backward_kernel<2, false, false>);
-    allow_lds(fa_backward_kernel<2, false, true>);
-    allow_lds(fa_backward_kernel<2, true, false>);
-    allow_lds(fa_backward_kernel<2, true, true>);
+    allow_lds_km<1, false, kLbSmall>();
+    allow_lds_km<1, true, kLbSmall>();
+    allow_lds_km<2, false, kLbSmall>();
+    allow_lds_km<2, true, kLbSmall>();
+    allow_lds_km<1, false, kLbLarge>();
+    allow_lds_km<1, true, kLbLarge>();
+    allow_lds_km<2, false, kLbLarge>();
+    allow_lds_km<2, true, kLbLarge>();
     done = true;
 }
 

@@ -8,14 +8,23 @@
 // whose coefficients were fitted for this library by a discrete minimax
 // (Lawson-weighted least squares) in double and rounded to float32.  For
 // |x| <= 1e5 the absolute error is below 8e-8 (about 1.5 ulp on (-pi, pi]).
-// Callers take sincosf instead when any lane of the wave holds an argument
-// outside that range or a non-finite one.
+// Callers take sincos_accurate instead when any lane of the wave holds an
+// argument outside that range or a non-finite one.
 #pragma once
 #include <hip/hip_runtime.h>
 
 namespace a2c {
 
 constexpr float kSinCosFastLimit = 1.0e5f;
+
+// The library's sinf and cosf, taken by value: sincosf returns one result
+// through a pointer, which makes the caller's destination array addressable
+// and moves it to scratch memory for the whole kernel.
+__device__ __forceinline__ void sincos_accurate(float x, float &s, float &c)
+{
+    s = sinf(x);
+    c = cosf(x);
+}
 
 __device__ __forceinline__ void sincos_fast(float x, float &s, float &c)
 {
