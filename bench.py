@@ -57,6 +57,9 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-plain", action="store_true")
     p.add_argument("--kernel-reps", type=int, default=50)
+    p.add_argument("--fused", action="store_true",
+                   help="training-step workload, squared-distance loss: one fused kernel "
+                        "(forward, loss gradient and adjoint; a2c_mse_step) per step")
     p.add_argument("--loss", default="mse", choices=["mse", "lrmsd"],
                    help="training-step workload: sum |r - t|^2 (default) or the per-chain "
                         "LRMSD of the Loss function section, summed over chains")
@@ -268,7 +271,24 @@ def main():
 
     # scan form, whole step in one graph
     loss = args.loss if training else None
-    step = make_step(a2c, plan, angles, grad_up, mode, target, loss or "mse")
+    if args.fused and (not training or loss != "mse"):
+        sys.exit("--fused applies to the training-step workload with the squared-distance loss")
+    if args.fused:
+        fused_xyz = torch.empty((3, plan.n_atoms), dtype=torch.float32, device=dev)
+        fused_grad = torch.empty_like(angles)
+        fused_tiles = torch.zeros(max(plan.schedule["n_tiles"], 1), device=dev)
+
+        def step():
+            a2c._lib.check(a2c._lib.load().a2c_mse_step(
+                plan._h, a2c.ctypes.c_void_p(angles.data_ptr()),
+                a2c.ctypes.c_void_p(target.data_ptr()),
+                a2c.ctypes.c_void_p(fused_xyz.data_ptr()),
+                a2c.ctypes.c_void_p(fused_tiles.data_ptr()),
+                a2c.ctypes.c_void_p(fused_grad.data_ptr()),
+                a2c._stream_ptr(dev)), "a2c_mse_step")
+            return fused_xyz, fused_grad
+    else:
+        step = make_step(a2c, plan, angles, grad_up, mode, target, loss or "mse")
     graph, outs = capture(step)
     dt = time_graph(graph, args.steps, args.warmup)
     ms = dt * 1000.0 / args.steps
@@ -313,12 +333,20 @@ def main():
                                args.kernel_reps)
         bwd_key = "backward_recompute"
     kern = {"forward": fwd_us, bwd_key: bwd_us}
+    if args.fused:
+        kern = {"fused_step": kernel_avg_us(step, args.kernel_reps)}
     dom = max(kern, key=kern.get)
     n_chi_total = None
     if model == "fullatom":
         from paper_1812_01108_amd.residues import default_table
         n_chi_total = int(np.sum(np.array(default_table().n_chi)[inp["seq"]]))
-    nbytes = algorithmic_bytes(model, dom, R, plan.n_atoms, n_chi_total)
+    if args.fused:
+        # angles, codes and offsets, the target (12 B per atom), the
+        # coordinates written (12 B per atom) and the angle gradient
+        nbytes = (algorithmic_bytes(model, "forward", R, plan.n_atoms, n_chi_total)
+                  + 12 * plan.n_atoms + 28 * R)
+    else:
+        nbytes = algorithmic_bytes(model, dom, R, plan.n_atoms, n_chi_total)
     achieved = nbytes / (kern[dom] * 1e-6) / 1e9
     src = os.path.join(ROOT, "paper_1812_01108_amd", "csrc",
                        "backbone.hip" if model == "backbone" else "fullatom.hip")
@@ -361,7 +389,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": cfg.name, "model": model, "n_chains": inp["n_chains"],
                    "residues": R, "atoms": plan.n_atoms, "angles": cfg.angles,
-                   "adjoint": mode, "loss_in_graph": loss,
+                   "adjoint": "fused" if args.fused else mode, "loss_in_graph": loss,
                    "res_per_lane": sched["res_per_lane"],
                    "waves_per_group": sched["waves_per_group"], "tiles": sched["n_tiles"]},
         "roofline": roof,

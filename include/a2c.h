@@ -226,6 +226,23 @@ a2c_status a2c_backward(a2c_plan *plan, a2c_variant variant, const float *d_angl
                         const float *d_coords, const float *d_grad_coords,
                         float *d_grad_angles, void *d_workspace, void *stream);
 
+/* Fused training step for the squared-distance loss
+ *   L = sum over atoms a of |r_a - t_a|^2
+ * (r the map of d_angles, t = d_target [3][A]): one kernel per tile
+ * recomputes the frames, forms the loss gradient 2 (r - t) in registers and
+ * runs the adjoint above, so neither the coordinates nor their gradient
+ * make a round trip through memory.  Same result as a2c_forward, then
+ * dL/dr = 2 (r - t), then a2c_backward, up to float32 rounding.
+ *   d_coords      [3][A] receives r, or NULL (not written);
+ *   d_loss_tiles  float[n_tiles] (a2c_plan_get_schedule) receives each
+ *                 tile's share of L, or NULL; L is their sum (tiles hold
+ *                 whole chains or one long chain; shares are deterministic);
+ *   d_grad_angles [K][R] receives dL/dalpha.
+ * Enqueues one kernel on `stream`; no allocation (capturable). */
+a2c_status a2c_mse_step(a2c_plan *plan, const float *d_angles, const float *d_target,
+                        float *d_coords, float *d_loss_tiles, float *d_grad_angles,
+                        void *stream);
+
 /* ----------------------------------------------------------------- LRMSD
  * The loss the paper pairs with the map (section "Loss function"): for each
  * chain c of the plan, with x the target and y the input coordinates of its

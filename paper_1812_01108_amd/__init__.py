@@ -197,6 +197,31 @@ class Plan:
         return grad_angles
 
 
+    # -- fused training step ------------------------------------------
+    def mse_step(self, angles: torch.Tensor, target: torch.Tensor,
+                 coords: torch.Tensor | None = None, loss: bool = True,
+                 grad_angles: torch.Tensor | None = None):
+        """One fused pass for L = sum |r - t|^2: returns (L as a 0-dim tensor
+        or None, dL/dangles); writes r into `coords` when given."""
+        self._check_tensor(angles, (self.n_planes, self.n_res), "angles")
+        self._check_tensor(target, (3, self.n_atoms), "target")
+        if coords is not None:
+            self._check_tensor(coords, (3, self.n_atoms), "coords")
+        if grad_angles is None:
+            grad_angles = torch.empty_like(angles)
+        self._check_tensor(grad_angles, (self.n_planes, self.n_res), "grad_angles")
+        tiles = None
+        if loss:
+            tiles = torch.zeros(max(self.schedule["n_tiles"], 1), dtype=torch.float32,
+                                device=angles.device)
+        check(_lib.load().a2c_mse_step(
+            self._h, ctypes.c_void_p(angles.data_ptr()), ctypes.c_void_p(target.data_ptr()),
+            None if coords is None else ctypes.c_void_p(coords.data_ptr()),
+            None if tiles is None else ctypes.c_void_p(tiles.data_ptr()),
+            ctypes.c_void_p(grad_angles.data_ptr()), _stream_ptr(angles.device)),
+            "a2c_mse_step")
+        return (tiles.sum() if loss else None), grad_angles
+
     # -- LRMSD loss -------------------------------------------------------
     def lrmsd_workspace(self) -> torch.Tensor | None:
         n = ctypes.c_size_t()

@@ -20,6 +20,10 @@ constexpr int kMaxDynamicLds = 136 * 1024;
 // (512 lanes) a kernel may use up to 256 VGPRs without spilling; 16 waves
 // cap it at 128.  Launchers pick the class from the schedule's wave count.
 constexpr int kLbSmall = 512, kLbLarge = 1024;
+// Source of the upstream coordinate gradient in the recompute adjoints: read
+// from memory, or 2 (r - t) of the squared distance to a target (the fused
+// training step).
+constexpr int kGradLoad = 0, kGradMse = 1;
 // LRMSD: atoms per segment (one workgroup of 256 lanes, 16 atoms per lane)
 constexpr int kLrSegAtoms = 4096;
 
@@ -103,6 +107,10 @@ hipError_t launch_bb_forward_plain(const a2c_plan &p, const float *ang, float *x
                                    hipStream_t s);
 hipError_t launch_bb_backward_plain(const a2c_plan &p, const float *ang, const float *g,
                                     float *gang, const float *ws, hipStream_t s);
+hipError_t launch_bb_mse_step(const a2c_plan &p, const float *ang, const float *tgt, float *xyz,
+                              float *loss_part, float *gang, hipStream_t s);
+hipError_t launch_fa_mse_step(const a2c_plan &p, const float *ang, const float *tgt, float *xyz,
+                              float *loss_part, float *gang, hipStream_t s);
 hipError_t launch_fa_forward_scan(const a2c_plan &p, const float *ang, float *xyz, hipStream_t s);
 hipError_t launch_fa_backward_scan(const a2c_plan &p, const float *ang, const float *xyz,
                                    const float *g, float *gang, hipStream_t s);

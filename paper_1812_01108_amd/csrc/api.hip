@@ -445,4 +445,21 @@ a2c_status a2c_backward(a2c_plan *p, a2c_variant v, const float *d_angles, const
     return A2C_OK;
 }
 
+a2c_status a2c_mse_step(a2c_plan *p, const float *d_angles, const float *d_target,
+                        float *d_coords, float *d_loss_tiles, float *d_grad_angles, void *stream)
+{
+    if (!p) return fail(A2C_ERR_INVALID_ARG, "plan is NULL");
+    if (p->R == 0) return A2C_OK;
+    if (!d_angles || !d_target || !d_grad_angles)
+        return fail(A2C_ERR_INVALID_ARG, "NULL angles, target or grad_angles");
+    if (!check_device(p)) return fail(A2C_ERR_STATE, "current device is not the plan's device");
+    hipStream_t s = (hipStream_t)stream;
+    const hipError_t e =
+        p->model == A2C_BACKBONE
+            ? launch_bb_mse_step(*p, d_angles, d_target, d_coords, d_loss_tiles, d_grad_angles, s)
+            : launch_fa_mse_step(*p, d_angles, d_target, d_coords, d_loss_tiles, d_grad_angles, s);
+    if (e != hipSuccess) return hip_fail(e, "training step launch");
+    return A2C_OK;
+}
+
 }  // extern "C"

@@ -266,9 +266,16 @@ __global__ __launch_bounds__(LB) void bb_forward_scan_kernel(
 // Backward that recomputes the frames from the angles (no stored state).
 // Tiles of several chunks first run the forward scan alone to record each
 // chunk's carry-in frame, then visit the chunks last to first.
-template <int K, bool MULTI, int LB>
+//   GM = kGradLoad: the upstream gradient is read from g;
+//   GM = kGradMse:  g points at a target t and the upstream gradient is that
+//                   of the squared distance, 2 (r - t), formed in registers
+//                   from the recomputed positions (the fused training step);
+//                   xyz_out (may be NULL) receives the positions, loss_part
+//                   (may be NULL) the tile's sum of |r - t|^2.
+template <int K, bool MULTI, int LB, int GM>
 __global__ __launch_bounds__(LB) void bb_backward_recompute_kernel(
     const float *__restrict__ ang, const float *__restrict__ g, float *__restrict__ gang,
+    float *__restrict__ xyz_out, float *__restrict__ loss_part,
     const int32_t *__restrict__ tile_res, const uint32_t *__restrict__ head_bits, int64_t R,
     BBParams P)
 {
@@ -276,6 +283,8 @@ __global__ __launch_bounds__(LB) void bb_backward_recompute_kernel(
     __shared__ FwdShared shf[2];
     __shared__ BwdShared shb[2];
     __shared__ float fwd_carry[kMaxChunks][12];
+    __shared__ float loss_tot[GM == kGradMse ? kMaxWaves : 1];
+    float loss = 0.f;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     float *buf = stage_mem + wave * kWave * Stride<3 * K>::value;
     const int64_t ts = tile_res[blockIdx.x], te = tile_res[blockIdx.x + 1];
@@ -336,10 +345,34 @@ __global__ __launch_bounds__(LB) void bb_backward_recompute_kernel(
         // buffers alternate with the pass above: its last chunk used shf[(nch-1) & 1]
         bb_lane_positions<K, MULTI>(phi, psi, om, P, k.nact, shf[(c + 1) & 1], fcarry, x, y, z, px, py,
                              pz, cnt, hm);
+        if (GM == kGradMse) {
+            // gx.. hold the target: the loss gradient 2 (r - t) of valid atoms
+#pragma unroll
+            for (int i = 0; i < 3 * K; ++i) {
+                const float dx = x[i] - gx[i], dy = y[i] - gy[i], dz = z[i] - gz[i];
+                const bool v = i < 3 * cnt;
+                loss += v ? dx * dx + dy * dy + dz * dz : 0.f;
+                gx[i] = v ? 2.f * dx : 0.f;
+                gy[i] = v ? 2.f * dy : 0.f;
+                gz[i] = v ? 2.f * dz : 0.f;
+            }
+            if (xyz_out && active) {
+                float *out = xyz_out + 3 * rbase;
+                stage_store<3 * K>(buf, x, out, 3 * nres);
+                stage_store<3 * K>(buf, y, out + A, 3 * nres);
+                stage_store<3 * K>(buf, z, out + 2 * A, 3 * nres);
+            }
+        }
         float gr[3][K];
         bb_lane_adjoint<K, MULTI>(P, k.nact, shb[c & 1], rcarry, x, y, z, gx, gy, gz, px, py, pz, cnt,
                            hm, lm, gr);
         if (active) store_angle_grads<K>(buf, gr, gang, R, rbase, nres);
+    }
+    if constexpr (GM == kGradMse) {
+        if (loss_part) {
+            const float t = block_sum(loss, loss_tot);
+            if (threadIdx.x == 0) loss_part[blockIdx.x] = t;
+        }
     }
 }
 
@@ -547,9 +580,32 @@ hipError_t bwd_kml(const a2c_plan &p, const float *ang, const float *xyz, const 
         hipLaunchKernelGGL((bb_backward_coords_kernel<K, MULTI, LB>), grid, block, lds, s, xyz,
                            g, gang, p.d_tile_res, p.d_head_bits, p.R, p.bb);
     else
-        hipLaunchKernelGGL((bb_backward_recompute_kernel<K, MULTI, LB>), grid, block, lds, s, ang,
-                           g, gang, p.d_tile_res, p.d_head_bits, p.R, p.bb);
+        hipLaunchKernelGGL((bb_backward_recompute_kernel<K, MULTI, LB, kGradLoad>), grid, block,
+                           lds, s, ang, g, gang, nullptr, nullptr, p.d_tile_res, p.d_head_bits,
+                           p.R, p.bb);
     return hipGetLastError();
+}
+
+template <int K, bool MULTI, int LB>
+hipError_t mse_kml(const a2c_plan &p, const float *ang, const float *tgt, float *xyz,
+                   float *loss_part, float *gang, hipStream_t s)
+{
+    hipLaunchKernelGGL((bb_backward_recompute_kernel<K, MULTI, LB, kGradMse>), dim3(p.n_tiles),
+                       dim3(p.W * kWave), stage_bytes<K>(p.W), s, ang, tgt, gang, xyz, loss_part,
+                       p.d_tile_res, p.d_head_bits, p.R, p.bb);
+    return hipGetLastError();
+}
+
+template <int K>
+hipError_t mse_k(const a2c_plan &p, const float *ang, const float *tgt, float *xyz,
+                 float *loss_part, float *gang, hipStream_t s)
+{
+    const bool small = p.W * kWave <= kLbSmall;
+    if (p.multi_chunk)
+        return small ? mse_kml<K, true, kLbSmall>(p, ang, tgt, xyz, loss_part, gang, s)
+                     : mse_kml<K, true, kLbLarge>(p, ang, tgt, xyz, loss_part, gang, s);
+    return small ? mse_kml<K, false, kLbSmall>(p, ang, tgt, xyz, loss_part, gang, s)
+                 : mse_kml<K, false, kLbLarge>(p, ang, tgt, xyz, loss_part, gang, s);
 }
 
 template <int K>
@@ -583,6 +639,17 @@ hipError_t launch_bb_backward_scan(const a2c_plan &p, const float *ang, const fl
     case 1: return bwd_k<1>(p, ang, xyz, g, gang, s);
     case 2: return bwd_k<2>(p, ang, xyz, g, gang, s);
     case 4: return bwd_k<4>(p, ang, xyz, g, gang, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_bb_mse_step(const a2c_plan &p, const float *ang, const float *tgt, float *xyz,
+                              float *loss_part, float *gang, hipStream_t s)
+{
+    switch (p.K) {
+    case 1: return mse_k<1>(p, ang, tgt, xyz, loss_part, gang, s);
+    case 2: return mse_k<2>(p, ang, tgt, xyz, loss_part, gang, s);
+    case 4: return mse_k<4>(p, ang, tgt, xyz, loss_part, gang, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -321,6 +321,30 @@ __device__ __forceinline__ void frame_wrench(const FATable &tab, const FAType &f
     }
 }
 
+// The fused training step: the stage holds the target t of each atom; the
+// wrench of frame k's atoms takes the loss gradient 2 (r - t), the loss
+// accumulates |r - t|^2, and the staged target is replaced by r (so the
+// stage ends up holding the coordinates).
+__device__ __forceinline__ void frame_wrench_mse(const FATable &tab, const FAType &ft, int k,
+                                                 const Aff &F, const Stage &sg, int aloc,
+                                                 Wrench &w, float &loss)
+{
+    for (int i = 0; i < tab.max_count[k]; ++i) {
+        if (i < ft.fcount[k]) {
+            const int q = ft.fbegin[k] + i;
+            float x, y, z;
+            aff_point(F, ft.rx[q], ft.ry[q], ft.rz[q], x, y, z);
+            const int e = aloc + ft.slot[q];
+            const float dx = x - sg.st[e], dy = y - sg.st[sg.ns + e], dz = z - sg.st[2 * sg.ns + e];
+            loss += dx * dx + dy * dy + dz * dz;
+            wrench_add_point(w, x, y, z, 2.f * dx, 2.f * dy, 2.f * dz);
+            sg.st[e] = x;
+            sg.st[sg.ns + e] = y;
+            sg.st[2 * sg.ns + e] = z;
+        }
+    }
+}
+
 // Wrench of the atoms of frame k with positions staged in planes 3..5 and
 // upstream gradients in planes 0..2.
 __device__ __forceinline__ void frame_wrench_xyz(const FATable &tab, const FAType &ft, int k,
@@ -556,19 +580,27 @@ __device__ __forceinline__ void fa_store_grads(float *__restrict__ gang, int64_t
 // RECOMPUTE: frames from the angles (tiles of several chunks first record
 // each chunk's forward carry); otherwise positions and axes from the
 // forward's coordinates.
-template <int K, bool RECOMPUTE, bool MULTI, int LB>
+// GM = kGradMse (with RECOMPUTE): g points at a target t and the upstream
+// gradient is 2 (r - t), formed from the recomputed positions (the fused
+// training step); xyz_out (may be NULL) receives the positions, loss_part
+// (may be NULL) the tile's sum of |r - t|^2.
+template <int K, bool RECOMPUTE, bool MULTI, int LB, int GM = kGradLoad>
 __global__ __launch_bounds__(LB) void fa_backward_kernel(
     const float *__restrict__ ang, const float *__restrict__ xyz, const float *__restrict__ g,
-    float *__restrict__ gang, const int32_t *__restrict__ tile_res,
+    float *__restrict__ gang, float *__restrict__ xyz_out, float *__restrict__ loss_part,
+    const int32_t *__restrict__ tile_res,
     const uint32_t *__restrict__ head_bits, const int32_t *__restrict__ res_aoff,
     const uint8_t *__restrict__ seq, const FATable *__restrict__ gtab, int64_t R, int64_t A,
     BBParams P, int stage_atoms)
 {
+    static_assert(GM == kGradLoad || RECOMPUTE, "the fused step recomputes the frames");
     extern __shared__ float stage_mem[];
     __shared__ FATable tab;
     __shared__ FwdShared shf[2];
     __shared__ BwdShared shb[2];
     __shared__ float fwd_carry[RECOMPUTE ? kMaxChunks : 1][12];
+    __shared__ float loss_tot[GM == kGradMse ? kMaxWaves : 1];
+    float loss = 0.f;
     load_table(tab, gtab);
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -641,10 +673,12 @@ __global__ __launch_bounds__(LB) void fa_backward_kernel(
                         if (head) cur = aff_identity();
                         aff_apply_transform(cur, P.ct[0], P.st[0], P.d[0], in[j].co, in[j].so);
                         set_ou(sn[j].oN, sn[j].uN, cur);
-                        frame_wrench(tab, ft, 0, cur, sg, aloc, sn[j].wN);
+                        if (GM == kGradMse) frame_wrench_mse(tab, ft, 0, cur, sg, aloc, sn[j].wN, loss);
+                        else frame_wrench(tab, ft, 0, cur, sg, aloc, sn[j].wN);
                         aff_apply_transform(cur, P.ct[1], P.st[1], P.d[1], in[j].cp, in[j].sp);
                         set_ou(sn[j].oCA, sn[j].uCA, cur);
-                        frame_wrench(tab, ft, 1, cur, sg, aloc, sn[j].wCA);
+                        if (GM == kGradMse) frame_wrench_mse(tab, ft, 1, cur, sg, aloc, sn[j].wCA, loss);
+                        else frame_wrench(tab, ft, 1, cur, sg, aloc, sn[j].wCA);
                         Aff sf = cur;
                         aff_rot_x(sf, ft.pre_c, ft.pre_s);
 #pragma unroll
@@ -654,12 +688,14 @@ __global__ __launch_bounds__(LB) void fa_backward_kernel(
                                 side_step(sf, ft, f, ang[(3 + f) * R + r]);
                                 so[f][0] = sf.t0; so[f][1] = sf.t1; so[f][2] = sf.t2;
                                 su[f][0] = sf.r00; su[f][1] = sf.r10; su[f][2] = sf.r20;
-                                frame_wrench(tab, ft, 3 + f, sf, sg, aloc, ws[f]);
+                                if (GM == kGradMse) frame_wrench_mse(tab, ft, 3 + f, sf, sg, aloc, ws[f], loss);
+                        else frame_wrench(tab, ft, 3 + f, sf, sg, aloc, ws[f]);
                             }
                         }
                         aff_apply_transform(cur, P.ct[2], P.st[2], P.d[2], in[j].cs, in[j].ss);
                         set_ou(sn[j].oC, sn[j].uC, cur);
-                        frame_wrench(tab, ft, 2, cur, sg, aloc, sn[j].wC);
+                        if (GM == kGradMse) frame_wrench_mse(tab, ft, 2, cur, sg, aloc, sn[j].wC, loss);
+                        else frame_wrench(tab, ft, 2, cur, sg, aloc, sn[j].wC);
                     } else {
                         const float *px = sg.st + 3 * sg.ns, *py = sg.st + 4 * sg.ns,
                                     *pz = sg.st + 5 * sg.ns;
@@ -711,6 +747,10 @@ __global__ __launch_bounds__(LB) void fa_backward_kernel(
                 }
             }
             wave_lds_sync();
+            if (GM == kGradMse && xyz_out) {
+                lds_to_run(sg, xyz_out, A, L.A0, L.natoms);  // the stage now holds r
+                wave_lds_sync();
+            }
         }
         Wrench S = block_exclusive_suffix<MULTI>(agg, f_end, k.nact, shb[c & 1], rcarry);
         if (!L.active) continue;
@@ -720,6 +760,12 @@ __global__ __launch_bounds__(LB) void fa_backward_kernel(
                 if ((L.lm >> j) & 1u) S = wrench_zero();
                 fa_store_grads(gang, R, L.rs + j, sn[j], S, gchi[j], S);
             }
+        }
+    }
+    if constexpr (GM == kGradMse) {
+        if (loss_part) {
+            const float t = block_sum(loss, loss_tot);
+            if (threadIdx.x == 0) loss_part[blockIdx.x] = t;
         }
     }
 }
@@ -747,14 +793,31 @@ hipError_t fa_fwd_k(const a2c_plan &p, const float *ang, float *xyz, hipStream_t
     return p.multi_chunk ? fa_fwd_km<K, true>(p, ang, xyz, s) : fa_fwd_km<K, false>(p, ang, xyz, s);
 }
 
-template <int K, bool RECOMPUTE, bool MULTI, int LB>
+template <int K, bool RECOMPUTE, bool MULTI, int LB, int GM = kGradLoad>
 void fa_bwd_launch(const a2c_plan &p, const float *ang, const float *xyz, const float *g,
-                   float *gang, hipStream_t s)
+                   float *gang, hipStream_t s, float *xyz_out = nullptr,
+                   float *loss_part = nullptr)
 {
     const size_t lds = (size_t)p.W * (RECOMPUTE ? 3 : 6) * p.fa_stage_atoms * sizeof(float);
-    hipLaunchKernelGGL((fa_backward_kernel<K, RECOMPUTE, MULTI, LB>), dim3(p.n_tiles),
-                       dim3(p.W * kWave), lds, s, ang, xyz, g, gang, p.d_tile_res, p.d_head_bits,
-                       p.d_res_atom_off, p.d_seq, p.d_fa, p.R, p.A, p.bb, p.fa_stage_atoms);
+    hipLaunchKernelGGL((fa_backward_kernel<K, RECOMPUTE, MULTI, LB, GM>), dim3(p.n_tiles),
+                       dim3(p.W * kWave), lds, s, ang, xyz, g, gang, xyz_out, loss_part,
+                       p.d_tile_res, p.d_head_bits, p.d_res_atom_off, p.d_seq, p.d_fa, p.R, p.A,
+                       p.bb, p.fa_stage_atoms);
+}
+
+template <int K>
+hipError_t fa_mse_k(const a2c_plan &p, const float *ang, const float *tgt, float *xyz,
+                    float *loss_part, float *gang, hipStream_t s)
+{
+    const bool small = p.W * kWave <= kLbSmall;
+    if (p.multi_chunk) {
+        if (small) fa_bwd_launch<K, true, true, kLbSmall, kGradMse>(p, ang, nullptr, tgt, gang, s, xyz, loss_part);
+        else fa_bwd_launch<K, true, true, kLbLarge, kGradMse>(p, ang, nullptr, tgt, gang, s, xyz, loss_part);
+    } else {
+        if (small) fa_bwd_launch<K, true, false, kLbSmall, kGradMse>(p, ang, nullptr, tgt, gang, s, xyz, loss_part);
+        else fa_bwd_launch<K, true, false, kLbLarge, kGradMse>(p, ang, nullptr, tgt, gang, s, xyz, loss_part);
+    }
+    return hipGetLastError();
 }
 
 template <int K, bool MULTI, int LB>
@@ -809,6 +872,16 @@ hipError_t launch_fa_backward_scan(const a2c_plan &p, const float *ang, const fl
     }
 }
 
+hipError_t launch_fa_mse_step(const a2c_plan &p, const float *ang, const float *tgt, float *xyz,
+                              float *loss_part, float *gang, hipStream_t s)
+{
+    switch (p.K) {
+    case 1: return fa_mse_k<1>(p, ang, tgt, xyz, loss_part, gang, s);
+    case 2: return fa_mse_k<2>(p, ang, tgt, xyz, loss_part, gang, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 // Dynamic LDS a full-atom launch needs beyond the static tables (forward
 // and recompute backward; the coordinate-mode backward needs twice this and
 // falls back to the recompute form where that does not fit).
@@ -827,6 +900,7 @@ static void allow_lds_km()
     allow_lds(fa_forward_kernel<K, MULTI, LB>);
     allow_lds(fa_backward_kernel<K, false, MULTI, LB>);
     allow_lds(fa_backward_kernel<K, true, MULTI, LB>);
+    allow_lds(fa_backward_kernel<K, true, MULTI, LB, kGradMse>);
 }
 
 void fa_allow_large_lds()

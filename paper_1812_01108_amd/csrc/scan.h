@@ -175,6 +175,26 @@ __device__ __forceinline__ float lane_bcast(float v, int src_lane)
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src_lane));
 }
 
+// Sum of v over the block's lanes in a fixed order (deterministic): quad and
+// row exchanges by DPP, the four row sums by lane reads, then the wave sums
+// in wave order by thread 0.  Every thread calls it (one barrier); the
+// result is meaningful in thread 0.
+__device__ __forceinline__ float block_sum(float v, float (&wave_tot)[kMaxWaves])
+{
+    v += dpp_f<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+    v += dpp_f<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+    v += dpp_f<0x141>(v);   // row_half_mirror
+    v += dpp_f<0x140>(v);   // row_mirror
+    const float w = (lane_bcast(v, 0) + lane_bcast(v, 16)) + (lane_bcast(v, 32) + lane_bcast(v, 48));
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) wave_tot[wave] = w;
+    __syncthreads();
+    float t = 0.f;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += wave_tot[i];
+    return t;
+}
+
 __device__ __forceinline__ Aff aff_bcast(const Aff &a, int l)
 {
     Aff o;
