@@ -226,6 +226,24 @@ a2c_status a2c_backward(a2c_plan *plan, a2c_variant variant, const float *d_angl
                         const float *d_coords, const float *d_grad_coords,
                         float *d_grad_angles, void *d_workspace, void *stream);
 
+/* Inverse map: coordinates [3][A] in the plan's layout -> angles [K][R],
+ * the step before the forward map in a pipeline (targets, initial angles).
+ * The angle of the transform placing atom i is the IUPAC torsion about the
+ * bond into atom i ("Backbone model" section), so
+ *   omega_j = torsion(CA_{j-1}, C_{j-1}, N_j, CA_j),
+ *   phi_j   = torsion(C_{j-1}, N_j, CA_j, C_j),
+ *   psi_j   = torsion(N_j, CA_j, C_j, N_{j+1}),
+ * in (-pi, pi]; at a chain start the start frame's virtual atoms
+ * C_{-1} = origin and CA_{-1} = (-1, 0, 0) stand in (so omega_0 and phi_0
+ * also fix the chain's orientation in that frame); psi of a chain's last
+ * residue moves no atom and is written as 0.  Full-atom plans also write
+ * chi1..chi4 (the torsion carried by each side frame, equal to the IUPAC
+ * chi of the residue table) and 0 in planes a residue lacks.  Forward then
+ * inverse returns the input angles up to float32 rounding (and psi of last
+ * residues).  One kernel on `stream`, no allocation (capturable). */
+a2c_status a2c_coords_to_angles(a2c_plan *plan, const float *d_coords, float *d_angles,
+                                void *stream);
+
 /* Fused training step for the squared-distance loss
  *   L = sum over atoms a of |r_a - t_a|^2
  * (r the map of d_angles, t = d_target [3][A]): one kernel per tile

@@ -197,6 +197,20 @@ class Plan:
         return grad_angles
 
 
+    # -- inverse map ----------------------------------------------------
+    def coords_to_angles(self, coords: torch.Tensor,
+                         out: torch.Tensor | None = None) -> torch.Tensor:
+        """Dihedral angles [K][R] of coordinates [3][A] in the plan's layout."""
+        self._check_tensor(coords, (3, self.n_atoms), "coords")
+        if out is None:
+            out = torch.empty((self.n_planes, self.n_res), dtype=torch.float32,
+                              device=coords.device)
+        self._check_tensor(out, (self.n_planes, self.n_res), "angles")
+        check(_lib.load().a2c_coords_to_angles(
+            self._h, ctypes.c_void_p(coords.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+            _stream_ptr(coords.device)), "a2c_coords_to_angles")
+        return out
+
     # -- fused training step ------------------------------------------
     def mse_step(self, angles: torch.Tensor, target: torch.Tensor,
                  coords: torch.Tensor | None = None, loss: bool = True,

@@ -87,6 +87,7 @@ struct a2c_plan {
     std::vector<int32_t> lr_seg_atom;    // lr_n_seg + 1 first atoms (last = A)
     std::vector<int32_t> lr_seg_chain;   // lr_n_seg chain of each segment
     std::vector<int32_t> lr_chain_seg;   // n_chains + 1 first segment of each chain
+    int8_t *d_chi_slots = nullptr;       // [20][4][4] chi atom slots (full-atom)
     int32_t *d_lr_seg_atom = nullptr;
     int32_t *d_lr_seg_chain = nullptr;
     int32_t *d_lr_chain_seg = nullptr;
@@ -116,6 +117,7 @@ hipError_t launch_fa_backward_scan(const a2c_plan &p, const float *ang, const fl
                                    const float *g, float *gang, hipStream_t s);
 size_t fa_dynamic_lds(const a2c_plan &p);
 void build_lrmsd_segments(a2c_plan &p);
+void build_chi_slots(const FATable &T, int8_t (&out)[A2C_NUM_RESIDUE_TYPES][4][4]);
 size_t lrmsd_workspace_bytes(const a2c_plan &p);
 void fa_allow_large_lds();
 

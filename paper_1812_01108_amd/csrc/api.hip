@@ -214,6 +214,7 @@ void a2c_plan_destroy(a2c_plan *p)
     (void)hipFree(p->d_res_atom_off);
     (void)hipFree(p->d_seq);
     (void)hipFree(p->d_fa);
+    (void)hipFree(p->d_chi_slots);
     (void)hipFree(p->d_lr_seg_atom);
     (void)hipFree(p->d_lr_seg_chain);
     (void)hipFree(p->d_lr_chain_seg);
@@ -315,6 +316,11 @@ a2c_status a2c_plan_create(a2c_plan **out, a2c_model model, int32_t n_chains,
                     p->res_atom_off.size() * sizeof(int32_t), s);
         if (st == A2C_OK) st = upload((void **)&p->d_seq, p->seq.data(), p->seq.size(), s);
         if (st == A2C_OK) st = upload((void **)&p->d_fa, &p->fa_host, sizeof(FATable), s);
+        if (st == A2C_OK) {
+            int8_t chi[A2C_NUM_RESIDUE_TYPES][4][4];
+            build_chi_slots(p->fa_host, chi);
+            st = upload((void **)&p->d_chi_slots, chi, sizeof(chi), s);
+        }
     }
     if (st == A2C_OK) {
         build_lrmsd_segments(*p);
