@@ -172,8 +172,8 @@ a2c_status a2c_plan_workspace_bytes(const a2c_plan *plan, a2c_variant variant,
  * chunk are packed whole, in order, into tiles of at most one chunk; a longer
  * chain gets a tile of its own, which one workgroup walks chunk by chunk
  * (at most 64 chunks), carrying the frame (forward) and the wrench (adjoint)
- * from chunk to chunk.  One workgroup per tile.  Re-packs and re-uploads the
- * tile table (synchronises `stream`).  UNSUPPORTED, leaving the plan's
+ * from chunk to chunk.  One workgroup per tile, longest tiles dispatched
+ * first.  Re-packs and re-uploads the tile table (synchronises `stream`).  UNSUPPORTED, leaving the plan's
  * schedule as it was, if the longest chain needs more than 64 chunks or, for
  * A2C_FULLATOM, if the waves' atoms of one chunk (three float planes each)
  * exceed 136 KiB of LDS per workgroup.  (The full-atom adjoint from

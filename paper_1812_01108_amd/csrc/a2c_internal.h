@@ -74,7 +74,7 @@ struct a2c_plan {
     int32_t fa_stage_atoms = 0;          // per-wave staging (floats per plane)
     bool multi_chunk = false;            // some tile spans several chunks
     // device tables
-    int32_t *d_tile_res = nullptr;       // n_tiles + 1 residue offsets of tiles
+    int32_t *d_tile_res = nullptr;       // n_tiles (first, end) residue pairs, longest first
     uint32_t *d_head_bits = nullptr;     // bit r: residue r starts a chain (bit R set)
     int32_t *d_res_off = nullptr;        // chain residue offsets (plain form)
     int32_t *d_res_atom_off = nullptr;   // R + 1 (full-atom)

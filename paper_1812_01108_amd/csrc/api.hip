@@ -106,7 +106,20 @@ a2c_status apply_schedule(a2c_plan *p, int32_t K, int32_t W, hipStream_t s)
     p->K = K;
     p->W = W;
     p->n_tiles = tiles.empty() ? 0 : (int32_t)tiles.size() - 1;
-    a2c_status st = upload((void **)&p->d_tile_res, tiles.data(), tiles.size() * sizeof(int32_t), s);
+    // (first, end) residue pairs, longest tile first: tiles are independent,
+    // and dispatching the long ones (multi-chunk chains, full tiles) first
+    // keeps them out of the tail of the launch
+    std::vector<int32_t> order(p->n_tiles);
+    for (int32_t t = 0; t < p->n_tiles; ++t) order[t] = t;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        return tiles[a + 1] - tiles[a] > tiles[b + 1] - tiles[b];
+    });
+    std::vector<int32_t> pairs(2 * (size_t)p->n_tiles);
+    for (int32_t t = 0; t < p->n_tiles; ++t) {
+        pairs[2 * t] = tiles[order[t]];
+        pairs[2 * t + 1] = tiles[order[t] + 1];
+    }
+    a2c_status st = upload((void **)&p->d_tile_res, pairs.data(), pairs.size() * sizeof(int32_t), s);
     if (st != A2C_OK) return st;
     hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");

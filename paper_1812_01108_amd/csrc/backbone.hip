@@ -233,7 +233,7 @@ __global__ __launch_bounds__(LB) void bb_forward_scan_kernel(
     __shared__ FwdShared sh[2];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     float *buf = stage_mem + wave * kWave * Stride<3 * K>::value;
-    const int64_t ts = tile_res[blockIdx.x], te = tile_res[blockIdx.x + 1];
+    const int64_t ts = tile_res[2 * blockIdx.x], te = tile_res[2 * blockIdx.x + 1];
     const int64_t A = 3 * R;
     // MULTI = false: every tile is one chunk (straight-line code)
     const int nch = MULTI ? chunks_of<K>(ts, te) : 1;
@@ -287,7 +287,7 @@ __global__ __launch_bounds__(LB) void bb_backward_recompute_kernel(
     float loss = 0.f;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     float *buf = stage_mem + wave * kWave * Stride<3 * K>::value;
-    const int64_t ts = tile_res[blockIdx.x], te = tile_res[blockIdx.x + 1];
+    const int64_t ts = tile_res[2 * blockIdx.x], te = tile_res[2 * blockIdx.x + 1];
     const int64_t A = 3 * R;
     // MULTI = false: every tile is one chunk (straight-line code)
     const int nch = MULTI ? chunks_of<K>(ts, te) : 1;
@@ -388,7 +388,7 @@ __global__ __launch_bounds__(LB) void bb_backward_coords_kernel(
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     float *buf = stage_mem + wave * kWave * Stride<3 * K>::value;
-    const int64_t ts = tile_res[blockIdx.x], te = tile_res[blockIdx.x + 1];
+    const int64_t ts = tile_res[2 * blockIdx.x], te = tile_res[2 * blockIdx.x + 1];
     const int64_t A = 3 * R;
     // MULTI = false: every tile is one chunk (straight-line code)
     const int nch = MULTI ? chunks_of<K>(ts, te) : 1;

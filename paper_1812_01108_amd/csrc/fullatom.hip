@@ -493,7 +493,7 @@ __global__ __launch_bounds__(LB) void fa_forward_kernel(
     load_table(tab, gtab);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const Stage sg{stage_mem + (size_t)wave * 3 * stage_atoms, stage_atoms};
-    const int64_t ts = tile_res[blockIdx.x], te = tile_res[blockIdx.x + 1];
+    const int64_t ts = tile_res[2 * blockIdx.x], te = tile_res[2 * blockIdx.x + 1];
     // MULTI = false: every tile is one chunk (straight-line code)
     const int nch = MULTI ? fa_chunks<K>(ts, te) : 1;
     Aff carry = aff_identity();
@@ -606,7 +606,7 @@ __global__ __launch_bounds__(LB) void fa_backward_kernel(
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int planes = RECOMPUTE ? 3 : 6;
     const Stage sg{stage_mem + (size_t)wave * planes * stage_atoms, stage_atoms};
-    const int64_t ts = tile_res[blockIdx.x], te = tile_res[blockIdx.x + 1];
+    const int64_t ts = tile_res[2 * blockIdx.x], te = tile_res[2 * blockIdx.x + 1];
     // MULTI = false: every tile is one chunk (straight-line code)
     const int nch = MULTI ? fa_chunks<K>(ts, te) : 1;
     if (RECOMPUTE && nch > 1) {
