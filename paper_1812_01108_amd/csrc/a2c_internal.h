@@ -72,6 +72,7 @@ struct a2c_plan {
     // schedule
     int32_t K = 4, W = 4, n_tiles = 0;
     int32_t fa_stage_atoms = 0;          // per-wave staging (floats per plane)
+    bool fa_unstaged = false;            // stage too large for the LDS: direct I/O
     bool multi_chunk = false;            // some tile spans several chunks
     // device tables
     int32_t *d_tile_res = nullptr;       // n_tiles (first, end) residue pairs, longest first

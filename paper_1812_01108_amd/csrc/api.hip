@@ -90,16 +90,20 @@ a2c_status apply_schedule(a2c_plan *p, int32_t K, int32_t W, hipStream_t s)
                 }
             }
         stage_atoms = std::max<int32_t>(stage_atoms, 1);
-        // three planes (forward, recompute adjoint); the coordinate-mode
-        // adjoint stages six and uses the recompute form where they do not fit
-        const size_t lds = (size_t)W * 3 * stage_atoms * sizeof(float);
-        if (lds > (size_t)kMaxDynamicLds)
-            return fail(A2C_ERR_UNSUPPORTED,
-                        "full-atom staging of " + std::to_string(stage_atoms) +
-                            " atoms per wave needs " + std::to_string(lds) +
-                            " bytes of LDS; use fewer waves or residues per lane");
+    }
+    // full-atom atom I/O goes through a per-wave LDS stage of three planes
+    // (forward, recompute adjoint; the coordinate-mode adjoint stages six and
+    // uses the recompute form where they do not fit); where three planes do
+    // not fit either, the kernels read and write the atoms in global memory
+    // directly
+    bool unstaged = false;
+    if (p->model == A2C_FULLATOM &&
+        (size_t)W * 3 * stage_atoms * sizeof(float) > (size_t)kMaxDynamicLds) {
+        unstaged = true;
+        stage_atoms = 0;
     }
     p->fa_stage_atoms = stage_atoms;
+    p->fa_unstaged = unstaged;
     p->multi_chunk = false;
     for (size_t t = 0; t + 1 < tiles.size(); ++t)
         if (tiles[t + 1] - tiles[t] > cap) p->multi_chunk = true;

@@ -221,11 +221,13 @@ __device__ __forceinline__ void aff_rot_x(Aff &m, float c, float s)
     m.r02 = b0; m.r12 = b1; m.r22 = b2;
 }
 
-// Per-wave LDS staging of a wave's atom run [A0, A0 + n): plane p of atom
-// e (relative to A0) lives at st[p * ns + e].
+// A wave's atom run [A0, A0 + n): plane p of atom e (relative to A0) lives
+// at st[p * ns + e] -- in the per-wave LDS stage (ns = the stage's floats per
+// plane), or, for schedules whose stage does not fit the LDS, in global
+// memory itself (st = array + A0, ns = A): the same indexing serves both.
 struct Stage {
     float *st;
-    int ns;   // floats per plane
+    int64_t ns;
 };
 
 // Coalesced copy between a global run (3 planes, plane stride A) and the
@@ -326,8 +328,8 @@ __device__ __forceinline__ void frame_wrench(const FATable &tab, const FAType &f
 // accumulates |r - t|^2, and the staged target is replaced by r (so the
 // stage ends up holding the coordinates).
 __device__ __forceinline__ void frame_wrench_mse(const FATable &tab, const FAType &ft, int k,
-                                                 const Aff &F, const Stage &sg, int aloc,
-                                                 Wrench &w, float &loss)
+                                                 const Aff &F, const Stage &sg, const Stage &so,
+                                                 bool write, int aloc, Wrench &w, float &loss)
 {
     for (int i = 0; i < tab.max_count[k]; ++i) {
         if (i < ft.fcount[k]) {
@@ -338,22 +340,25 @@ __device__ __forceinline__ void frame_wrench_mse(const FATable &tab, const FATyp
             const float dx = x - sg.st[e], dy = y - sg.st[sg.ns + e], dz = z - sg.st[2 * sg.ns + e];
             loss += dx * dx + dy * dy + dz * dz;
             wrench_add_point(w, x, y, z, 2.f * dx, 2.f * dy, 2.f * dz);
-            sg.st[e] = x;
-            sg.st[sg.ns + e] = y;
-            sg.st[2 * sg.ns + e] = z;
+            if (write) {
+                so.st[e] = x;
+                so.st[so.ns + e] = y;
+                so.st[2 * so.ns + e] = z;
+            }
         }
     }
 }
 
-// Wrench of the atoms of frame k with positions staged in planes 3..5 and
-// upstream gradients in planes 0..2.
+// Wrench of the atoms of frame k with positions from sx and upstream
+// gradients from sg.
 __device__ __forceinline__ void frame_wrench_xyz(const FATable &tab, const FAType &ft, int k,
-                                                 const Stage &sg, int aloc, Wrench &w)
+                                                 const Stage &sg, const Stage &sx, int aloc,
+                                                 Wrench &w)
 {
     for (int i = 0; i < tab.max_count[k]; ++i) {
         if (i < ft.fcount[k]) {
             const int e = aloc + ft.slot[ft.fbegin[k] + i];
-            wrench_add_point(w, sg.st[3 * sg.ns + e], sg.st[4 * sg.ns + e], sg.st[5 * sg.ns + e],
+            wrench_add_point(w, sx.st[e], sx.st[sx.ns + e], sx.st[2 * sx.ns + e],
                              sg.st[e], sg.st[sg.ns + e], sg.st[2 * sg.ns + e]);
         }
     }
@@ -480,7 +485,9 @@ __device__ __forceinline__ LaneRun<K> lane_run(const FAChunk &k,
     return L;
 }
 
-template <int K, bool MULTI, int LB>
+// STG: atoms go through the per-wave LDS stage; otherwise straight to
+// global memory (schedules whose stage does not fit the LDS).
+template <int K, bool MULTI, int LB, bool STG = true>
 __global__ __launch_bounds__(LB) void fa_forward_kernel(
     const float *__restrict__ ang, float *__restrict__ xyz, const int32_t *__restrict__ tile_res,
     const uint32_t *__restrict__ head_bits, const int32_t *__restrict__ res_aoff,
@@ -492,7 +499,7 @@ __global__ __launch_bounds__(LB) void fa_forward_kernel(
     __shared__ FwdShared sh[2];
     load_table(tab, gtab);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const Stage sg{stage_mem + (size_t)wave * 3 * stage_atoms, stage_atoms};
+    const Stage lds{stage_mem + (size_t)wave * 3 * stage_atoms, stage_atoms};
     const int64_t ts = tile_res[2 * blockIdx.x], te = tile_res[2 * blockIdx.x + 1];
     // MULTI = false: every tile is one chunk (straight-line code)
     const int nch = MULTI ? fa_chunks<K>(ts, te) : 1;
@@ -506,6 +513,7 @@ __global__ __launch_bounds__(LB) void fa_forward_kernel(
         if (L.active) m = fa_lane_aggregate<K>(ang, R, L.rs, L.cnt, L.hm, P, in, first_head);
         const Aff X = block_exclusive_prefix<MULTI>(m, first_head < K, k.nact, sh[c & 1], carry);
         if (!L.active) continue;
+        const Stage sg = STG ? lds : Stage{xyz + L.A0, A};
         Aff cur = X;
 #pragma unroll
         for (int j = 0; j < K; ++j) {
@@ -533,9 +541,11 @@ __global__ __launch_bounds__(LB) void fa_forward_kernel(
                 emit_frame(tab, ft, 2, cur, sg, aloc);
             }
         }
-        wave_lds_sync();
-        lds_to_run(sg, xyz, A, L.A0, L.natoms);
-        wave_lds_sync();
+        if (STG) {
+            wave_lds_sync();
+            lds_to_run(sg, xyz, A, L.A0, L.natoms);
+            wave_lds_sync();
+        }
     }
 }
 
@@ -584,7 +594,7 @@ __device__ __forceinline__ void fa_store_grads(float *__restrict__ gang, int64_t
 // gradient is 2 (r - t), formed from the recomputed positions (the fused
 // training step); xyz_out (may be NULL) receives the positions, loss_part
 // (may be NULL) the tile's sum of |r - t|^2.
-template <int K, bool RECOMPUTE, bool MULTI, int LB, int GM = kGradLoad>
+template <int K, bool RECOMPUTE, bool MULTI, int LB, int GM = kGradLoad, bool STG = true>
 __global__ __launch_bounds__(LB) void fa_backward_kernel(
     const float *__restrict__ ang, const float *__restrict__ xyz, const float *__restrict__ g,
     float *__restrict__ gang, float *__restrict__ xyz_out, float *__restrict__ loss_part,
@@ -605,7 +615,7 @@ __global__ __launch_bounds__(LB) void fa_backward_kernel(
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int planes = RECOMPUTE ? 3 : 6;
-    const Stage sg{stage_mem + (size_t)wave * planes * stage_atoms, stage_atoms};
+    const Stage lds{stage_mem + (size_t)wave * planes * stage_atoms, stage_atoms};
     const int64_t ts = tile_res[2 * blockIdx.x], te = tile_res[2 * blockIdx.x + 1];
     // MULTI = false: every tile is one chunk (straight-line code)
     const int nch = MULTI ? fa_chunks<K>(ts, te) : 1;
@@ -648,13 +658,21 @@ __global__ __launch_bounds__(LB) void fa_backward_kernel(
         float gchi[K][4];
         Wrench agg = wrench_zero();
         bool f_end = false;
+        // upstream gradient (or target) sg, coordinates sx, positions out sout
+        const Stage sg = STG ? lds : Stage{const_cast<float *>(g) + L.A0, A};
+        const Stage sx = STG ? Stage{lds.st + 3 * lds.ns, lds.ns}
+                             : Stage{const_cast<float *>(xyz) + L.A0, A};
+        const Stage sout = STG ? sg : Stage{xyz_out + L.A0, A};
+        const bool write_so = STG || (GM == kGradMse && xyz_out != nullptr);
         if (L.active) {
-            run_to_lds(sg, 0, g, A, L.A0, L.natoms);
-            if (!RECOMPUTE) run_to_lds(sg, 3, xyz, A, L.A0, L.natoms);
+            if (STG) {
+                run_to_lds(sg, 0, g, A, L.A0, L.natoms);
+                if (!RECOMPUTE) run_to_lds(sg, 3, xyz, A, L.A0, L.natoms);
+            }
             wave_lds_sync();
             if (!RECOMPUTE && lane > 0 && L.cnt > 0 && !(L.hm & 1u)) {
                 const int e = res_aoff[L.rs - 1] + 2 - (int)L.A0;
-                pcx = sg.st[3 * sg.ns + e]; pcy = sg.st[4 * sg.ns + e]; pcz = sg.st[5 * sg.ns + e];
+                pcx = sx.st[e]; pcy = sx.st[sx.ns + e]; pcz = sx.st[2 * sx.ns + e];
             }
             Aff cur = X;
 #pragma unroll
@@ -673,11 +691,11 @@ __global__ __launch_bounds__(LB) void fa_backward_kernel(
                         if (head) cur = aff_identity();
                         aff_apply_transform(cur, P.ct[0], P.st[0], P.d[0], in[j].co, in[j].so);
                         set_ou(sn[j].oN, sn[j].uN, cur);
-                        if (GM == kGradMse) frame_wrench_mse(tab, ft, 0, cur, sg, aloc, sn[j].wN, loss);
+                        if (GM == kGradMse) frame_wrench_mse(tab, ft, 0, cur, sg, sout, write_so, aloc, sn[j].wN, loss);
                         else frame_wrench(tab, ft, 0, cur, sg, aloc, sn[j].wN);
                         aff_apply_transform(cur, P.ct[1], P.st[1], P.d[1], in[j].cp, in[j].sp);
                         set_ou(sn[j].oCA, sn[j].uCA, cur);
-                        if (GM == kGradMse) frame_wrench_mse(tab, ft, 1, cur, sg, aloc, sn[j].wCA, loss);
+                        if (GM == kGradMse) frame_wrench_mse(tab, ft, 1, cur, sg, sout, write_so, aloc, sn[j].wCA, loss);
                         else frame_wrench(tab, ft, 1, cur, sg, aloc, sn[j].wCA);
                         Aff sf = cur;
                         aff_rot_x(sf, ft.pre_c, ft.pre_s);
@@ -688,17 +706,16 @@ __global__ __launch_bounds__(LB) void fa_backward_kernel(
                                 side_step(sf, ft, f, ang[(3 + f) * R + r]);
                                 so[f][0] = sf.t0; so[f][1] = sf.t1; so[f][2] = sf.t2;
                                 su[f][0] = sf.r00; su[f][1] = sf.r10; su[f][2] = sf.r20;
-                                if (GM == kGradMse) frame_wrench_mse(tab, ft, 3 + f, sf, sg, aloc, ws[f], loss);
+                                if (GM == kGradMse) frame_wrench_mse(tab, ft, 3 + f, sf, sg, sout, write_so, aloc, ws[f], loss);
                         else frame_wrench(tab, ft, 3 + f, sf, sg, aloc, ws[f]);
                             }
                         }
                         aff_apply_transform(cur, P.ct[2], P.st[2], P.d[2], in[j].cs, in[j].ss);
                         set_ou(sn[j].oC, sn[j].uC, cur);
-                        if (GM == kGradMse) frame_wrench_mse(tab, ft, 2, cur, sg, aloc, sn[j].wC, loss);
+                        if (GM == kGradMse) frame_wrench_mse(tab, ft, 2, cur, sg, sout, write_so, aloc, sn[j].wC, loss);
                         else frame_wrench(tab, ft, 2, cur, sg, aloc, sn[j].wC);
                     } else {
-                        const float *px = sg.st + 3 * sg.ns, *py = sg.st + 4 * sg.ns,
-                                    *pz = sg.st + 5 * sg.ns;
+                        const float *px = sx.st, *py = sx.st + sx.ns, *pz = sx.st + 2 * sx.ns;
                         const float nx = px[aloc], ny = py[aloc], nz = pz[aloc];
                         const float cax = px[aloc + 1], cay = py[aloc + 1], caz = pz[aloc + 1];
                         const float cx = px[aloc + 2], cy = py[aloc + 2], cz = pz[aloc + 2];
@@ -706,9 +723,9 @@ __global__ __launch_bounds__(LB) void fa_backward_kernel(
                         set_ou_pts(sn[j].oN, sn[j].uN, nx, ny, nz, pcx, pcy, pcz, P.inv_d[0]);
                         set_ou_pts(sn[j].oCA, sn[j].uCA, cax, cay, caz, nx, ny, nz, P.inv_d[1]);
                         set_ou_pts(sn[j].oC, sn[j].uC, cx, cy, cz, cax, cay, caz, P.inv_d[2]);
-                        frame_wrench_xyz(tab, ft, 0, sg, aloc, sn[j].wN);
-                        frame_wrench_xyz(tab, ft, 1, sg, aloc, sn[j].wCA);
-                        frame_wrench_xyz(tab, ft, 2, sg, aloc, sn[j].wC);
+                        frame_wrench_xyz(tab, ft, 0, sg, sx, aloc, sn[j].wN);
+                        frame_wrench_xyz(tab, ft, 1, sg, sx, aloc, sn[j].wCA);
+                        frame_wrench_xyz(tab, ft, 2, sg, sx, aloc, sn[j].wC);
                         float ppx = cax, ppy = cay, ppz = caz;
 #pragma unroll
                         for (int f = 0; f < A2C_MAX_SIDE_FRAMES; ++f) {
@@ -721,7 +738,7 @@ __global__ __launch_bounds__(LB) void fa_backward_kernel(
                                 su[f][1] = (oy - ppy) * ft.inv_d[f];
                                 su[f][2] = (oz - ppz) * ft.inv_d[f];
                                 ppx = ox; ppy = oy; ppz = oz;
-                                frame_wrench_xyz(tab, ft, 3 + f, sg, aloc, ws[f]);
+                                frame_wrench_xyz(tab, ft, 3 + f, sg, sx, aloc, ws[f]);
                             }
                         }
                         pcx = cx; pcy = cy; pcz = cz;
@@ -747,7 +764,7 @@ __global__ __launch_bounds__(LB) void fa_backward_kernel(
                 }
             }
             wave_lds_sync();
-            if (GM == kGradMse && xyz_out) {
+            if (STG && GM == kGradMse && xyz_out) {
                 lds_to_run(sg, xyz_out, A, L.A0, L.natoms);  // the stage now holds r
                 wave_lds_sync();
             }
@@ -770,85 +787,90 @@ __global__ __launch_bounds__(LB) void fa_backward_kernel(
     }
 }
 
-template <int K, bool MULTI, int LB>
+template <int K, bool MULTI, int LB, bool STG>
 hipError_t fa_fwd_kml(const a2c_plan &p, const float *ang, float *xyz, hipStream_t s)
 {
-    const size_t lds = (size_t)p.W * 3 * p.fa_stage_atoms * sizeof(float);
-    hipLaunchKernelGGL((fa_forward_kernel<K, MULTI, LB>), dim3(p.n_tiles), dim3(p.W * kWave),
+    const size_t lds = STG ? (size_t)p.W * 3 * p.fa_stage_atoms * sizeof(float) : 0;
+    hipLaunchKernelGGL((fa_forward_kernel<K, MULTI, LB, STG>), dim3(p.n_tiles), dim3(p.W * kWave),
                        lds, s, ang, xyz, p.d_tile_res, p.d_head_bits, p.d_res_atom_off, p.d_seq,
                        p.d_fa, p.R, p.A, p.bb, p.fa_stage_atoms);
     return hipGetLastError();
 }
 
-template <int K, bool MULTI>
-hipError_t fa_fwd_km(const a2c_plan &p, const float *ang, float *xyz, hipStream_t s)
+template <int K, bool STG>
+hipError_t fa_fwd_ks(const a2c_plan &p, const float *ang, float *xyz, hipStream_t s)
 {
-    return p.W * kWave <= kLbSmall ? fa_fwd_kml<K, MULTI, kLbSmall>(p, ang, xyz, s)
-                                   : fa_fwd_kml<K, MULTI, kLbLarge>(p, ang, xyz, s);
+    const bool small = p.W * kWave <= kLbSmall;
+    if (p.multi_chunk)
+        return small ? fa_fwd_kml<K, true, kLbSmall, STG>(p, ang, xyz, s)
+                     : fa_fwd_kml<K, true, kLbLarge, STG>(p, ang, xyz, s);
+    return small ? fa_fwd_kml<K, false, kLbSmall, STG>(p, ang, xyz, s)
+                 : fa_fwd_kml<K, false, kLbLarge, STG>(p, ang, xyz, s);
 }
 
 template <int K>
 hipError_t fa_fwd_k(const a2c_plan &p, const float *ang, float *xyz, hipStream_t s)
 {
-    return p.multi_chunk ? fa_fwd_km<K, true>(p, ang, xyz, s) : fa_fwd_km<K, false>(p, ang, xyz, s);
+    return p.fa_unstaged ? fa_fwd_ks<K, false>(p, ang, xyz, s) : fa_fwd_ks<K, true>(p, ang, xyz, s);
 }
 
-template <int K, bool RECOMPUTE, bool MULTI, int LB, int GM = kGradLoad>
+template <int K, bool RECOMPUTE, bool MULTI, int LB, int GM, bool STG>
 void fa_bwd_launch(const a2c_plan &p, const float *ang, const float *xyz, const float *g,
-                   float *gang, hipStream_t s, float *xyz_out = nullptr,
-                   float *loss_part = nullptr)
+                   float *gang, hipStream_t s, float *xyz_out, float *loss_part)
 {
-    const size_t lds = (size_t)p.W * (RECOMPUTE ? 3 : 6) * p.fa_stage_atoms * sizeof(float);
-    hipLaunchKernelGGL((fa_backward_kernel<K, RECOMPUTE, MULTI, LB, GM>), dim3(p.n_tiles),
+    const size_t lds =
+        STG ? (size_t)p.W * (RECOMPUTE ? 3 : 6) * p.fa_stage_atoms * sizeof(float) : 0;
+    hipLaunchKernelGGL((fa_backward_kernel<K, RECOMPUTE, MULTI, LB, GM, STG>), dim3(p.n_tiles),
                        dim3(p.W * kWave), lds, s, ang, xyz, g, gang, xyz_out, loss_part,
                        p.d_tile_res, p.d_head_bits, p.d_res_atom_off, p.d_seq, p.d_fa, p.R, p.A,
                        p.bb, p.fa_stage_atoms);
+}
+
+// mode 0: adjoint from coordinates, 1: recompute, 2: fused squared-distance step
+template <int K, int MODE, bool STG>
+void fa_bwd_dispatch(const a2c_plan &p, const float *ang, const float *xyz, const float *g,
+                     float *gang, hipStream_t s, float *xyz_out, float *loss_part)
+{
+    constexpr bool RC = MODE != 0;
+    constexpr int GM = MODE == 2 ? kGradMse : kGradLoad;
+    const bool small = p.W * kWave <= kLbSmall;
+    if (p.multi_chunk) {
+        if (small) fa_bwd_launch<K, RC, true, kLbSmall, GM, STG>(p, ang, xyz, g, gang, s, xyz_out, loss_part);
+        else fa_bwd_launch<K, RC, true, kLbLarge, GM, STG>(p, ang, xyz, g, gang, s, xyz_out, loss_part);
+    } else {
+        if (small) fa_bwd_launch<K, RC, false, kLbSmall, GM, STG>(p, ang, xyz, g, gang, s, xyz_out, loss_part);
+        else fa_bwd_launch<K, RC, false, kLbLarge, GM, STG>(p, ang, xyz, g, gang, s, xyz_out, loss_part);
+    }
+}
+
+template <int K, int MODE>
+hipError_t fa_bwd_mode(const a2c_plan &p, const float *ang, const float *xyz, const float *g,
+                       float *gang, hipStream_t s, float *xyz_out = nullptr,
+                       float *loss_part = nullptr)
+{
+    if (p.fa_unstaged) fa_bwd_dispatch<K, MODE, false>(p, ang, xyz, g, gang, s, xyz_out, loss_part);
+    else fa_bwd_dispatch<K, MODE, true>(p, ang, xyz, g, gang, s, xyz_out, loss_part);
+    return hipGetLastError();
 }
 
 template <int K>
 hipError_t fa_mse_k(const a2c_plan &p, const float *ang, const float *tgt, float *xyz,
                     float *loss_part, float *gang, hipStream_t s)
 {
-    const bool small = p.W * kWave <= kLbSmall;
-    if (p.multi_chunk) {
-        if (small) fa_bwd_launch<K, true, true, kLbSmall, kGradMse>(p, ang, nullptr, tgt, gang, s, xyz, loss_part);
-        else fa_bwd_launch<K, true, true, kLbLarge, kGradMse>(p, ang, nullptr, tgt, gang, s, xyz, loss_part);
-    } else {
-        if (small) fa_bwd_launch<K, true, false, kLbSmall, kGradMse>(p, ang, nullptr, tgt, gang, s, xyz, loss_part);
-        else fa_bwd_launch<K, true, false, kLbLarge, kGradMse>(p, ang, nullptr, tgt, gang, s, xyz, loss_part);
-    }
-    return hipGetLastError();
-}
-
-template <int K, bool MULTI, int LB>
-hipError_t fa_bwd_kml(const a2c_plan &p, const float *ang, const float *xyz, const float *g,
-                      float *gang, hipStream_t s)
-{
-    // the coordinate form stages six planes; where they do not fit, the
-    // recompute form (three planes) computes the same gradient
-    if (xyz && (size_t)p.W * 6 * p.fa_stage_atoms * sizeof(float) > (size_t)kMaxDynamicLds)
-        xyz = nullptr;
-    if (xyz)
-        fa_bwd_launch<K, false, MULTI, LB>(p, ang, xyz, g, gang, s);
-    else
-        fa_bwd_launch<K, true, MULTI, LB>(p, ang, xyz, g, gang, s);
-    return hipGetLastError();
-}
-
-template <int K, bool MULTI>
-hipError_t fa_bwd_km(const a2c_plan &p, const float *ang, const float *xyz, const float *g,
-                     float *gang, hipStream_t s)
-{
-    return p.W * kWave <= kLbSmall ? fa_bwd_kml<K, MULTI, kLbSmall>(p, ang, xyz, g, gang, s)
-                                   : fa_bwd_kml<K, MULTI, kLbLarge>(p, ang, xyz, g, gang, s);
+    return fa_bwd_mode<K, 2>(p, ang, nullptr, tgt, gang, s, xyz, loss_part);
 }
 
 template <int K>
 hipError_t fa_bwd_k(const a2c_plan &p, const float *ang, const float *xyz, const float *g,
                     float *gang, hipStream_t s)
 {
-    return p.multi_chunk ? fa_bwd_km<K, true>(p, ang, xyz, g, gang, s)
-                         : fa_bwd_km<K, false>(p, ang, xyz, g, gang, s);
+    // the staged coordinate form needs six planes; where they do not fit,
+    // the recompute form (three planes) computes the same gradient
+    if (xyz && !p.fa_unstaged &&
+        (size_t)p.W * 6 * p.fa_stage_atoms * sizeof(float) > (size_t)kMaxDynamicLds)
+        xyz = nullptr;
+    return xyz ? fa_bwd_mode<K, 0>(p, ang, xyz, g, gang, s)
+               : fa_bwd_mode<K, 1>(p, ang, xyz, g, gang, s);
 }
 
 }  // namespace
@@ -885,7 +907,10 @@ hipError_t launch_fa_mse_step(const a2c_plan &p, const float *ang, const float *
 // Dynamic LDS a full-atom launch needs beyond the static tables (forward
 // and recompute backward; the coordinate-mode backward needs twice this and
 // falls back to the recompute form where that does not fit).
-size_t fa_dynamic_lds(const a2c_plan &p) { return (size_t)p.W * 3 * p.fa_stage_atoms * sizeof(float); }
+size_t fa_dynamic_lds(const a2c_plan &p)
+{
+    return p.fa_unstaged ? 0 : (size_t)p.W * 3 * p.fa_stage_atoms * sizeof(float);
+}
 
 template <typename F>
 static void allow_lds(F kernel)
@@ -900,7 +925,7 @@ static void allow_lds_km()
     allow_lds(fa_forward_kernel<K, MULTI, LB>);
     allow_lds(fa_backward_kernel<K, false, MULTI, LB>);
     allow_lds(fa_backward_kernel<K, true, MULTI, LB>);
-    allow_lds(fa_backward_kernel<K, true, MULTI, LB, kGradMse>);
+    allow_lds(fa_backward_kernel<K, true, MULTI, LB, kGradMse, true>);
 }
 
 void fa_allow_large_lds()

@@ -71,18 +71,17 @@ def test_max_chunks_per_tile(mode):
     _check(plan, off, seq, ang, mode, coord_tol=4e-3, label="64 chunks")
 
 
-def test_staging_beyond_lds_is_refused():
-    """Sixteen waves of 128 residues each would stage ~1000 atoms per wave in
-    three planes, beyond the LDS a workgroup may use: refused on the host,
-    and the plan keeps its schedule."""
+@pytest.mark.parametrize("mode", ["coords", "recompute"])
+def test_unstaged_schedule(mode):
+    """K = 2, W = 16: sixteen waves of 128 residues would stage ~1000 atoms
+    per wave, beyond the LDS a workgroup may use; the kernels then read and
+    write the atoms in global memory directly.  Chains up to 3000 residues
+    (two 2048-residue chunks) and short ones."""
     a2c = _a2c()
-    off, seq, ang = _batch([3000], 109)
+    off, seq, ang = _batch([3000, 5, 2048, 1, 700, 2049], 109)
     plan = a2c.Plan("fullatom", offsets=off, seq=seq)
-    before = plan.schedule
-    with pytest.raises(a2c.A2CError):
-        plan.set_schedule(2, 16)
-    assert plan.schedule == before
-    _check(plan, off, seq, ang, "coords", coord_tol=4e-3, label="after refusal")
+    plan.set_schedule(2, 16)
+    _check(plan, off, seq, ang, mode, coord_tol=4e-3, label=f"unstaged {mode}")
 
 
 @pytest.mark.parametrize("mode", ["coords", "recompute"])

@@ -85,7 +85,7 @@ def test_backbone_schedules(K, W):
     _run(plan, "backbone", off, seq, ang, t, f"backbone K={K} W={W}")
 
 
-@pytest.mark.parametrize("K,W", [(1, 16), (1, 8), (2, 4), (1, 1), (2, 8)])
+@pytest.mark.parametrize("K,W", [(1, 16), (1, 8), (2, 4), (1, 1), (2, 8), (2, 16)])
 def test_fullatom_schedules(K, W):
     a2c = _a2c()
     off, seq, ang, t = _case("fullatom", [1, 20, 0, 64, 65, 300, 700, 3], 307)
