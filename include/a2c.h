@@ -173,12 +173,13 @@ a2c_status a2c_plan_workspace_bytes(const a2c_plan *plan, a2c_variant variant,
  * chain gets a tile of its own, which one workgroup walks chunk by chunk
  * (at most 64 chunks), carrying the frame (forward) and the wrench (adjoint)
  * from chunk to chunk.  One workgroup per tile, longest tiles dispatched
- * first.  Re-packs and re-uploads the tile table (synchronises `stream`).  UNSUPPORTED, leaving the plan's
- * schedule as it was, if the longest chain needs more than 64 chunks or, for
- * A2C_FULLATOM, if the waves' atoms of one chunk (three float planes each)
- * exceed 136 KiB of LDS per workgroup.  (The full-atom adjoint from
- * coordinates stages six planes; where those do not fit, it recomputes the
- * frames from the angles instead, with the same result.) */
+ * first.  Re-packs and re-uploads the tile table (synchronises `stream`).
+ * UNSUPPORTED, leaving the plan's schedule as it was, if the longest chain
+ * needs more than 64 chunks.  Full-atom atom I/O goes through a per-wave LDS
+ * stage (three float planes; the adjoint from coordinates stages six and
+ * recomputes the frames from the angles instead where those do not fit,
+ * with the same result); where the waves' atoms of one chunk exceed 136 KiB
+ * of LDS, the kernels read and write atoms in global memory directly. */
 a2c_status a2c_plan_set_schedule(a2c_plan *plan, int32_t res_per_lane,
                                  int32_t waves_per_group, void *stream);
 a2c_status a2c_plan_get_schedule(const a2c_plan *plan, int32_t *res_per_lane,
