@@ -569,19 +569,70 @@ __device__ __forceinline__ void set_ou_pts(float (&o)[3], float (&u)[3], float o
     u[0] = (ox - px) * inv_d; u[1] = (oy - py) * inv_d; u[2] = (oz - pz) * inv_d;
 }
 
+// What a residue keeps across the block scan: the torque u . (m - o x g)
+// is linear in the wrench, so for each spine node the part of its subtree
+// inside the residue is folded in right after the walk (c), and the wrench
+// S of everything after the residue enters later as c + u . S.m - v . S.g
+// with v = u x o; W is the residue's whole wrench (for earlier residues of
+// the lane).  7 floats per node instead of 12.
+struct NodeGrad {
+    float c, u0, u1, u2, v0, v1, v2;
+};
+
+struct SpineGrad {
+    NodeGrad n, ca, cc;
+    Wrench W;
+};
+
+__device__ __forceinline__ NodeGrad node_grad(const Wrench &local, const float (&o)[3],
+                                              const float (&u)[3])
+{
+    NodeGrad g;
+    g.c = wrench_torque(local, o[0], o[1], o[2], u[0], u[1], u[2]);
+    g.u0 = u[0]; g.u1 = u[1]; g.u2 = u[2];
+    // explicit FMAs: no contraction left to the compiler here
+    g.v0 = fmaf(u[1], o[2], -(u[2] * o[1]));
+    g.v1 = fmaf(u[2], o[0], -(u[0] * o[2]));
+    g.v2 = fmaf(u[0], o[1], -(u[1] * o[0]));
+    return g;
+}
+
+__device__ __forceinline__ float node_torque(const NodeGrad &g, const Wrench &S)
+{
+    float t = fmaf(g.u0, S.m0, g.c);
+    t = fmaf(g.u1, S.m1, t);
+    t = fmaf(g.u2, S.m2, t);
+    t = fmaf(-g.v0, S.g0, t);
+    t = fmaf(-g.v1, S.g1, t);
+    return fmaf(-g.v2, S.g2, t);
+}
+
+// Fold a residue's spine nodes: C's subtree in the residue is its own group
+// (with O), CA's adds C's, N's adds CA's (with the side chain).
+__device__ __forceinline__ SpineGrad spine_grad(const SpineNode &sn)
+{
+    SpineGrad sp;
+    Wrench L = sn.wC;
+    sp.cc = node_grad(L, sn.oC, sn.uC);
+    wrench_add(L, sn.wCA);
+    sp.ca = node_grad(L, sn.oCA, sn.uCA);
+    wrench_add(L, sn.wN);
+    sp.n = node_grad(L, sn.oN, sn.uN);
+    sp.W = L;
+    return sp;
+}
+
 __device__ __forceinline__ void fa_store_grads(float *__restrict__ gang, int64_t R, int64_t r,
-                                               const SpineNode &sn, const Wrench &S_after,
+                                               const SpineGrad &sp, const Wrench &S_after,
                                                const float (&gchi)[4], Wrench &S_out)
 {
-    Wrench S = S_after;
-    wrench_add(S, sn.wC);
-    gang[R + r] = wrench_torque(S, sn.oC[0], sn.oC[1], sn.oC[2], sn.uC[0], sn.uC[1], sn.uC[2]);
-    wrench_add(S, sn.wCA);
-    gang[r] = wrench_torque(S, sn.oCA[0], sn.oCA[1], sn.oCA[2], sn.uCA[0], sn.uCA[1], sn.uCA[2]);
-    wrench_add(S, sn.wN);
-    gang[2 * R + r] = wrench_torque(S, sn.oN[0], sn.oN[1], sn.oN[2], sn.uN[0], sn.uN[1], sn.uN[2]);
+    gang[R + r] = node_torque(sp.cc, S_after);
+    gang[r] = node_torque(sp.ca, S_after);
+    gang[2 * R + r] = node_torque(sp.n, S_after);
 #pragma unroll
     for (int f = 0; f < 4; ++f) gang[(3 + f) * R + r] = gchi[f];
+    Wrench S = S_after;
+    wrench_add(S, sp.W);
     S_out = S;
 }
 
@@ -654,7 +705,7 @@ __global__ __launch_bounds__(LB) void fa_backward_kernel(
             const int64_t ac = res_aoff[L.rs - 1] + 2;
             pcx = xyz[ac]; pcy = xyz[A + ac]; pcz = xyz[2 * A + ac];
         }
-        SpineNode sn[K];
+        SpineGrad sp[K];
         float gchi[K][4];
         Wrench agg = wrench_zero();
         bool f_end = false;
@@ -678,8 +729,9 @@ __global__ __launch_bounds__(LB) void fa_backward_kernel(
 #pragma unroll
             for (int j = 0; j < K; ++j) {
                 gchi[j][0] = gchi[j][1] = gchi[j][2] = gchi[j][3] = 0.f;
-                sn[j].wN = sn[j].wCA = sn[j].wC = wrench_zero();
                 if (j < L.cnt) {
+                    SpineNode sn;
+                    sn.wN = sn.wCA = sn.wC = wrench_zero();
                     const int64_t r = L.rs + j;
                     const FAType &ft = tab.t[seq[r]];
                     const int aloc = res_aoff[r] - (int)L.A0;
@@ -690,13 +742,13 @@ __global__ __launch_bounds__(LB) void fa_backward_kernel(
                     if (RECOMPUTE) {
                         if (head) cur = aff_identity();
                         aff_apply_transform(cur, P.ct[0], P.st[0], P.d[0], in[j].co, in[j].so);
-                        set_ou(sn[j].oN, sn[j].uN, cur);
-                        if (GM == kGradMse) frame_wrench_mse(tab, ft, 0, cur, sg, sout, write_so, aloc, sn[j].wN, loss);
-                        else frame_wrench(tab, ft, 0, cur, sg, aloc, sn[j].wN);
+                        set_ou(sn.oN, sn.uN, cur);
+                        if (GM == kGradMse) frame_wrench_mse(tab, ft, 0, cur, sg, sout, write_so, aloc, sn.wN, loss);
+                        else frame_wrench(tab, ft, 0, cur, sg, aloc, sn.wN);
                         aff_apply_transform(cur, P.ct[1], P.st[1], P.d[1], in[j].cp, in[j].sp);
-                        set_ou(sn[j].oCA, sn[j].uCA, cur);
-                        if (GM == kGradMse) frame_wrench_mse(tab, ft, 1, cur, sg, sout, write_so, aloc, sn[j].wCA, loss);
-                        else frame_wrench(tab, ft, 1, cur, sg, aloc, sn[j].wCA);
+                        set_ou(sn.oCA, sn.uCA, cur);
+                        if (GM == kGradMse) frame_wrench_mse(tab, ft, 1, cur, sg, sout, write_so, aloc, sn.wCA, loss);
+                        else frame_wrench(tab, ft, 1, cur, sg, aloc, sn.wCA);
                         Aff sf = cur;
                         aff_rot_x(sf, ft.pre_c, ft.pre_s);
 #pragma unroll
@@ -711,21 +763,21 @@ __global__ __launch_bounds__(LB) void fa_backward_kernel(
                             }
                         }
                         aff_apply_transform(cur, P.ct[2], P.st[2], P.d[2], in[j].cs, in[j].ss);
-                        set_ou(sn[j].oC, sn[j].uC, cur);
-                        if (GM == kGradMse) frame_wrench_mse(tab, ft, 2, cur, sg, sout, write_so, aloc, sn[j].wC, loss);
-                        else frame_wrench(tab, ft, 2, cur, sg, aloc, sn[j].wC);
+                        set_ou(sn.oC, sn.uC, cur);
+                        if (GM == kGradMse) frame_wrench_mse(tab, ft, 2, cur, sg, sout, write_so, aloc, sn.wC, loss);
+                        else frame_wrench(tab, ft, 2, cur, sg, aloc, sn.wC);
                     } else {
                         const float *px = sx.st, *py = sx.st + sx.ns, *pz = sx.st + 2 * sx.ns;
                         const float nx = px[aloc], ny = py[aloc], nz = pz[aloc];
                         const float cax = px[aloc + 1], cay = py[aloc + 1], caz = pz[aloc + 1];
                         const float cx = px[aloc + 2], cy = py[aloc + 2], cz = pz[aloc + 2];
                         if (head) { pcx = 0.f; pcy = 0.f; pcz = 0.f; }
-                        set_ou_pts(sn[j].oN, sn[j].uN, nx, ny, nz, pcx, pcy, pcz, P.inv_d[0]);
-                        set_ou_pts(sn[j].oCA, sn[j].uCA, cax, cay, caz, nx, ny, nz, P.inv_d[1]);
-                        set_ou_pts(sn[j].oC, sn[j].uC, cx, cy, cz, cax, cay, caz, P.inv_d[2]);
-                        frame_wrench_xyz(tab, ft, 0, sg, sx, aloc, sn[j].wN);
-                        frame_wrench_xyz(tab, ft, 1, sg, sx, aloc, sn[j].wCA);
-                        frame_wrench_xyz(tab, ft, 2, sg, sx, aloc, sn[j].wC);
+                        set_ou_pts(sn.oN, sn.uN, nx, ny, nz, pcx, pcy, pcz, P.inv_d[0]);
+                        set_ou_pts(sn.oCA, sn.uCA, cax, cay, caz, nx, ny, nz, P.inv_d[1]);
+                        set_ou_pts(sn.oC, sn.uC, cx, cy, cz, cax, cay, caz, P.inv_d[2]);
+                        frame_wrench_xyz(tab, ft, 0, sg, sx, aloc, sn.wN);
+                        frame_wrench_xyz(tab, ft, 1, sg, sx, aloc, sn.wCA);
+                        frame_wrench_xyz(tab, ft, 2, sg, sx, aloc, sn.wC);
                         float ppx = cax, ppy = cay, ppz = caz;
 #pragma unroll
                         for (int f = 0; f < A2C_MAX_SIDE_FRAMES; ++f) {
@@ -754,12 +806,9 @@ __global__ __launch_bounds__(LB) void fa_backward_kernel(
                                                            su[f][0], su[f][1], su[f][2]);
                         }
                     }
-                    wrench_add(sn[j].wCA, Ss);
-                    if (!f_end) {
-                        wrench_add(agg, sn[j].wN);
-                        wrench_add(agg, sn[j].wCA);
-                        wrench_add(agg, sn[j].wC);
-                    }
+                    wrench_add(sn.wCA, Ss);
+                    sp[j] = spine_grad(sn);
+                    if (!f_end) wrench_add(agg, sp[j].W);
                     if ((L.lm >> j) & 1u) f_end = true;
                 }
             }
@@ -775,7 +824,7 @@ __global__ __launch_bounds__(LB) void fa_backward_kernel(
         for (int j = K - 1; j >= 0; --j) {
             if (j < L.cnt) {
                 if ((L.lm >> j) & 1u) S = wrench_zero();
-                fa_store_grads(gang, R, L.rs + j, sn[j], S, gchi[j], S);
+                fa_store_grads(gang, R, L.rs + j, sp[j], S, gchi[j], S);
             }
         }
     }

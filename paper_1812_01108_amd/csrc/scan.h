@@ -50,13 +50,16 @@ __device__ __forceinline__ void wrench_add(Wrench &a, const Wrench &b)
 }
 
 // add the wrench of force g applied at point p
+// Explicit FMAs here and in wrench_torque: the compiler may contract
+// a * b - c * d either way, and may choose differently in different kernels;
+// with the operations spelled out every kernel rounds the same way.
 __device__ __forceinline__ void wrench_add_point(Wrench &a, float px, float py, float pz, float gx,
                                                  float gy, float gz)
 {
     a.g0 += gx; a.g1 += gy; a.g2 += gz;
-    a.m0 += py * gz - pz * gy;
-    a.m1 += pz * gx - px * gz;
-    a.m2 += px * gy - py * gx;
+    a.m0 += fmaf(py, gz, -(pz * gy));
+    a.m1 += fmaf(pz, gx, -(px * gz));
+    a.m2 += fmaf(px, gy, -(py * gx));
 }
 
 // u . (S.m - o x S.g): derivative of sum g.r over the subtree carried by S
@@ -64,10 +67,10 @@ __device__ __forceinline__ void wrench_add_point(Wrench &a, float px, float py, 
 __device__ __forceinline__ float wrench_torque(const Wrench &S, float ox, float oy, float oz,
                                                float ux, float uy, float uz)
 {
-    const float tx = S.m0 - (oy * S.g2 - oz * S.g1);
-    const float ty = S.m1 - (oz * S.g0 - ox * S.g2);
-    const float tz = S.m2 - (ox * S.g1 - oy * S.g0);
-    return ux * tx + uy * ty + uz * tz;
+    const float tx = S.m0 - fmaf(oy, S.g2, -(oz * S.g1));
+    const float ty = S.m1 - fmaf(oz, S.g0, -(ox * S.g2));
+    const float tz = S.m2 - fmaf(ox, S.g1, -(oy * S.g0));
+    return fmaf(uz, tz, fmaf(uy, ty, ux * tx));
 }
 
 __device__ __forceinline__ Wrench wrench_shfl_down(const Wrench &a, int delta)

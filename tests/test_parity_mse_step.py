@@ -4,8 +4,10 @@ L = sum |r - t|^2 and its angle gradient in one kernel, against
 * the FP64 oracle: forward, g = 2 (r - t) in float64, O(N) adjoint;
 * the unfused GPU path on the same schedule: a2c_forward, g = 2 (r - t) in
   float32 by torch, a2c_backward recomputing the frames.  The fused kernel
-  performs exactly the same float32 operations in the same order, so the
-  angle gradient, the coordinates and the gradient agree bit for bit.
+  performs the same float32 operations; the compiler may contract a
+  multiply-add differently in the two kernels, which changes a last bit, and
+  the gradient's moment sums u . (m - o x g) cancel large terms, so the two
+  agree to 1e-5 A and 1e-4 (normwise per chain), not bit for bit.
 
 Loss tolerance: the coordinates carry float32 rounding of up to ~1e-3 A
 against residuals |r - t| of order 1-10 A, and the sum runs in float32 over
@@ -70,8 +72,8 @@ def _run(plan, model, off, seq, ang, t, label, coord_tol=COORD_TOL_A):
     lerr = abs(float(loss) - L) / max(L, 1e-30)
     print(f"{label}: max|dr|={cerr:.3e} A grad_rel={gerr:.3e} loss_rel={lerr:.3e}", flush=True)
     assert cerr <= coord_tol and gerr <= GRAD_TOL_REL and lerr <= LOSS_RTOL
-    assert np.array_equal(xyz, c2.cpu().numpy())
-    assert np.array_equal(gr, g2.cpu().numpy())
+    assert float(np.max(np.abs(xyz - c2.cpu().numpy()))) <= 1e-5
+    assert grad_rel_err(gr, g2.cpu().numpy().astype(np.float64), off) <= 1e-4
 
 
 @pytest.mark.parametrize("K,W", [(1, 16), (2, 8), (4, 4), (1, 1), (2, 3), (4, 16)])
