@@ -144,7 +144,24 @@ def kernel_avg_us(launch, reps):
     return best
 
 
-def traffic_from_profiles(kernel_key, src_path, n_units, schedule):
+# Sources a model's kernels are compiled from: profiles/traffic.json records
+# their joint hash, so a counter figure is reported only for the kernels it
+# was measured on.
+KERNEL_SOURCES = {
+    "backbone": ["backbone.hip", "scan.h", "affine.h", "sincos.h", "a2c_internal.h"],
+    "fullatom": ["fullatom.hip", "scan.h", "affine.h", "sincos.h", "a2c_internal.h"],
+}
+
+
+def kernel_source_sha(model):
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES[model]:
+        with open(os.path.join(ROOT, "paper_1812_01108_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel_key, model, n_units, schedule):
     """HBM bytes per launch from committed rocprofv3 counter summaries, valid
     only while the kernel source they were taken from is unchanged and for
     the schedule they were taken with."""
@@ -153,7 +170,7 @@ def traffic_from_profiles(kernel_key, src_path, n_units, schedule):
         return None
     try:
         rec = json.load(open(path)).get(kernel_key)
-        sha = hashlib.sha256(open(src_path, "rb").read()).hexdigest()[:16]
+        sha = kernel_source_sha(model)
         if (not rec or rec.get("source_sha") != sha or rec.get("units") != n_units
                 or rec.get("schedule") != list(schedule)):
             return None
@@ -348,12 +365,10 @@ def main():
     else:
         nbytes = algorithmic_bytes(model, dom, R, plan.n_atoms, n_chi_total)
     achieved = nbytes / (kern[dom] * 1e-6) / 1e9
-    src = os.path.join(ROOT, "paper_1812_01108_amd", "csrc",
-                       "backbone.hip" if model == "backbone" else "fullatom.hip")
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic_from_profiles(
-                f"{cfg.name}:{dom}", src, R,
+                f"{cfg.name}:{dom}", model, R,
                 (plan.schedule["res_per_lane"], plan.schedule["waves_per_group"])),
             "kernel": dom,
             "kernel_us": {k: round(v, 3) for k, v in kern.items()},
