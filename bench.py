@@ -283,6 +283,8 @@ def main():
     if args.schedule:
         k, w = (int(v) for v in args.schedule.split(","))
         plan.set_schedule(k, w)
+    elif args.fused:
+        plan.autotune(angles, reps=5, mse_target=target)
     else:
         plan.autotune(angles, grad_up, from_coords=mode == "coords", reps=5)
 

@@ -192,8 +192,9 @@ a2c_status a2c_plan_get_schedule(const a2c_plan *plan, int32_t *res_per_lane,
  * it, so near-ties resolve to the smaller schedule).
  *   d_angles, d_coords, d_grad_coords, d_grad_angles: buffers of the plan's
  *     sizes; their contents are overwritten (coords and grad_angles) or read.
- *   backward_from_coords: nonzero times a2c_backward with d_coords (the
- *     forward's output), zero times the recompute form.
+ *   backward_from_coords: 1 times a2c_forward + a2c_backward with d_coords
+ *     (the forward's output), 0 the recompute form, A2C_TUNE_MSE_STEP the
+ *     fused step a2c_mse_step with d_grad_coords as its target.
  *   reps: timed repetitions per candidate (>= 1).
  *   cache_path: text file of earlier choices, keyed by device name, model,
  *     residue count, longest chain, chain count and backward form; NULL for
@@ -201,6 +202,7 @@ a2c_status a2c_plan_get_schedule(const a2c_plan *plan, int32_t *res_per_lane,
  *     unreadable or malformed cache is ignored.
  *   out_res_per_lane, out_waves_per_group (may be NULL): the choice.
  * Synchronises `stream`; not capturable.  Call it before capturing a graph. */
+#define A2C_TUNE_MSE_STEP 2
 a2c_status a2c_plan_autotune(a2c_plan *plan, const float *d_angles, float *d_coords,
                              const float *d_grad_coords, float *d_grad_angles,
                              int32_t backward_from_coords, int32_t reps, const char *cache_path,

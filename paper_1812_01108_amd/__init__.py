@@ -139,21 +139,28 @@ class Plan:
                   "a2c_plan_set_schedule")
 
     def autotune(self, angles: torch.Tensor, grad_coords: torch.Tensor | None = None,
-                 from_coords: bool = True, reps: int = 5, cache_path: str | None = None):
+                 from_coords: bool = True, reps: int = 5, cache_path: str | None = None,
+                 mse_target: torch.Tensor | None = None):
         """Time every valid schedule on these buffers and keep the fastest
-        (synchronises; call before capturing a graph).  Returns the schedule."""
+        (synchronises; call before capturing a graph).  With mse_target, the
+        fused training step (mse_step) is timed instead of forward + adjoint.
+        Returns the schedule."""
         self._check_tensor(angles, (self.n_planes, self.n_res), "angles")
         coords = torch.empty((3, self.n_atoms), dtype=torch.float32, device=angles.device)
         if grad_coords is None:
             grad_coords = torch.ones_like(coords)
         self._check_tensor(grad_coords, (3, self.n_atoms), "grad_coords")
         grad = torch.empty_like(angles)
+        mode = 1 if from_coords else 0
+        if mse_target is not None:
+            self._check_tensor(mse_target, (3, self.n_atoms), "mse_target")
+            grad_coords, mode = mse_target, _lib.A2C_TUNE_MSE_STEP
         k, w = ctypes.c_int32(), ctypes.c_int32()
         with torch.cuda.device(self.device):
             check(_lib.load().a2c_plan_autotune(
                 self._h, ctypes.c_void_p(angles.data_ptr()), ctypes.c_void_p(coords.data_ptr()),
                 ctypes.c_void_p(grad_coords.data_ptr()), ctypes.c_void_p(grad.data_ptr()),
-                1 if from_coords else 0, reps,
+                mode, reps,
                 None if cache_path is None else cache_path.encode(), ctypes.byref(k),
                 ctypes.byref(w), _stream_ptr(self.device)), "a2c_plan_autotune")
         return self.schedule

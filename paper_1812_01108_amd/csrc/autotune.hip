@@ -119,6 +119,12 @@ extern "C" a2c_status a2c_plan_autotune(a2c_plan *p, const float *d_angles, floa
             for (int trial = 0; trial < 3 && st == A2C_OK; ++trial) {
                 (void)hipEventRecord(e0, s);
                 for (int r = 0; r < reps && st == A2C_OK; ++r) {
+                    if (from_coords == A2C_TUNE_MSE_STEP) {
+                        // d_grad_coords serves as the target
+                        st = a2c_mse_step(p, d_angles, d_grad_coords, d_coords, nullptr,
+                                          d_grad_angles, s);
+                        continue;
+                    }
                     st = a2c_forward(p, A2C_SCAN, d_angles, d_coords, nullptr, s);
                     if (st == A2C_OK)
                         st = a2c_backward(p, A2C_SCAN, d_angles, from_coords ? d_coords : nullptr,
