@@ -221,9 +221,13 @@ class Plan:
     # -- fused training step ------------------------------------------
     def mse_step(self, angles: torch.Tensor, target: torch.Tensor,
                  coords: torch.Tensor | None = None, loss: bool = True,
-                 grad_angles: torch.Tensor | None = None):
+                 grad_angles: torch.Tensor | None = None,
+                 loss_tiles: torch.Tensor | None = None):
         """One fused pass for L = sum |r - t|^2: returns (L as a 0-dim tensor
-        or None, dL/dangles); writes r into `coords` when given."""
+        or None, dL/dangles); writes r into `coords` when given.  With
+        `loss_tiles` (float32, at least schedule["n_tiles"] elements) the
+        per-tile partial sums land there and nothing is allocated, so the call
+        can be captured in a graph; L is then their sum, left to the caller."""
         self._check_tensor(angles, (self.n_planes, self.n_res), "angles")
         self._check_tensor(target, (3, self.n_atoms), "target")
         if coords is not None:
@@ -231,8 +235,13 @@ class Plan:
         if grad_angles is None:
             grad_angles = torch.empty_like(angles)
         self._check_tensor(grad_angles, (self.n_planes, self.n_res), "grad_angles")
-        tiles = None
-        if loss:
+        tiles = loss_tiles
+        if tiles is not None:
+            if (tiles.dtype != torch.float32 or not tiles.is_contiguous()
+                    or tiles.device != angles.device or tiles.numel() < self.schedule["n_tiles"]):
+                raise ValueError("loss_tiles: contiguous float32 with >= n_tiles elements "
+                                 "on the plan's device")
+        elif loss:
             tiles = torch.zeros(max(self.schedule["n_tiles"], 1), dtype=torch.float32,
                                 device=angles.device)
         check(_lib.load().a2c_mse_step(
@@ -241,6 +250,8 @@ class Plan:
             None if tiles is None else ctypes.c_void_p(tiles.data_ptr()),
             ctypes.c_void_p(grad_angles.data_ptr()), _stream_ptr(angles.device)),
             "a2c_mse_step")
+        if loss_tiles is not None:
+            return None, grad_angles
         return (tiles.sum() if loss else None), grad_angles
 
     # -- LRMSD loss -------------------------------------------------------

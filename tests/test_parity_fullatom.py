@@ -137,6 +137,31 @@ def test_fullatom_backbone_matches_backbone_model():
 
 
 @pytest.mark.parametrize("mode", ["coords", "recompute"])
+def test_nan_stays_in_its_chain(mode):
+    """A NaN chi1 poisons only its own residue's side chain; a NaN phi poisons
+    its chain from that residue's CA on (CA does not depend on phi, but it is
+    emitted through the residue frame phi rotates, and NaN * 0 is NaN); other
+    chains (packed in the same tile) stay finite, forward and adjoint."""
+    a2c = _a2c()
+    off, seq, ang = _batch([50, 60, 70, 40], 113)
+    info = oracle.load_residue_table()[1]
+    nchi = np.array([info[t]["chi"] for t in range(20)])[seq]
+    j = 50 + int(np.flatnonzero(nchi[50:110] >= 2)[0])        # a residue of chain 1 with chi2
+    ang = ang.copy()
+    ang[3, j] = np.nan
+    ang[0, 110 + 30] = np.nan                                # phi of residue 30 of chain 2
+    plan = a2c.Plan("fullatom", offsets=off, seq=seq)
+    ra = plan.atom_offsets()[1]
+    xyz, gr = run_fullatom(plan, ang, upstream_grad(len(seq), int(ra[-1])), mode)
+    fin = np.all(np.isfinite(xyz), axis=0)
+    assert np.all(fin[: ra[50]]) and np.all(fin[ra[180]:])
+    assert np.all(np.isfinite(gr[:, :50])) and np.all(np.isfinite(gr[:, 180:]))
+    assert np.all(fin[ra[50]: ra[j]]) and np.all(fin[ra[j + 1]: ra[110]])
+    assert np.all(fin[ra[j]: ra[j] + 3]) and not np.all(fin[ra[j]: ra[j + 1]])
+    assert np.all(fin[ra[110]: ra[140] + 1]) and not np.any(fin[ra[141]: ra[180]])
+
+
+@pytest.mark.parametrize("mode", ["coords", "recompute"])
 def test_autograd_fullatom(mode):
     import torch
     a2c = _a2c()
