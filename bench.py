@@ -2,8 +2,10 @@
 
 One step = the whole path over one batch: forward coordinates and the adjoint
 angle gradient for a fixed upstream gradient, through the torch.autograd
-Function, captured in one CUDA (HIP) graph.  Inputs are resident in HBM
-before timing starts.  Prints one JSON line.
+Function.  Steps are captured in HIP graphs, --steps-per-graph complete
+steps per graph (one graph launch costs the host more than one step takes
+on the GPU); every timed step runs the whole path.  Inputs are resident in
+HBM before timing starts.  Prints one JSON line.
 
 Default workload: 256 chains x 700 residues, backbone, Ramachandran-like
 mixture angles, omega = pi, upstream gradient iid N(0,1).
@@ -46,6 +48,8 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=200)
     p.add_argument("--warmup", type=int, default=20)
+    p.add_argument("--steps-per-graph", type=int, default=10,
+                   help="complete steps captured back to back in one graph")
     p.add_argument("--workload", default="backbone_256x700")
     p.add_argument("--mode", default=None, choices=["coords", "recompute"],
                    help="adjoint reads the forward's coordinates, or recomputes the frames "
@@ -88,7 +92,9 @@ def make_step(a2c, plan, angles, grad_up, mode, target=None, loss="mse"):
     return step
 
 
-def capture(step, warm=3):
+def capture(step, warm=3, per_graph=1):
+    """Graphs of `per_graph` back-to-back steps and of one step; returns
+    ((graph_n, n), graph_1, outputs of the last captured step)."""
     import torch
 
     s = torch.cuda.Stream()
@@ -97,21 +103,35 @@ def capture(step, warm=3):
         for _ in range(warm):
             step()
     torch.cuda.current_stream().wait_stream(s)
-    g = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g):
+    g1 = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g1):
         outs = step()
-    return g, outs
+    n = max(1, per_graph)
+    gn = g1
+    if n > 1:
+        gn = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gn):
+            for _ in range(n):
+                outs = step()
+    return (gn, n), g1, outs
 
 
-def time_graph(g, steps, warmup):
+def _run_steps(graphs, k):
+    (gn, n), g1 = graphs
+    for _ in range(k // n):
+        gn.replay()
+    for _ in range(k % n):
+        g1.replay()
+
+
+def time_graph(graphs, steps, warmup):
+    """Exactly `warmup` untimed steps, then wall time of exactly `steps`."""
     import torch
 
-    for _ in range(warmup):
-        g.replay()
+    _run_steps(graphs, warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
-        g.replay()
+    _run_steps(graphs, steps)
     torch.cuda.synchronize()
     return time.perf_counter() - t0
 
@@ -308,8 +328,8 @@ def main():
             return fused_xyz, fused_grad
     else:
         step = make_step(a2c, plan, angles, grad_up, mode, target, loss or "mse")
-    graph, outs = capture(step)
-    dt = time_graph(graph, args.steps, args.warmup)
+    gn, g1, outs = capture(step, per_graph=min(args.steps_per_graph, max(args.steps, 1)))
+    dt = time_graph((gn, g1), args.steps, args.warmup)
     ms = dt * 1000.0 / args.steps
     value = R * args.steps / dt
     gpu_coords = outs[0].detach().cpu().numpy()
@@ -379,9 +399,9 @@ def main():
     plain = None
     if model == "backbone" and not args.no_plain:
         pstep = make_step(a2c, plan, angles, grad_up, "plain")
-        pgraph, _ = capture(pstep, warm=1)
         psteps = max(3, min(args.steps, 20))
-        pdt = time_graph(pgraph, psteps, 2)
+        pgn, pg1, _ = capture(pstep, warm=1, per_graph=min(args.steps_per_graph, psteps))
+        pdt = time_graph((pgn, pg1), psteps, 2)
         plain = {"value": R * psteps / pdt, "ms_per_step": pdt * 1000.0 / psteps,
                  "form": "one workgroup per chain, sequential product storing M_i, "
                          "O(atoms x angles) gradient"}
@@ -408,7 +428,8 @@ def main():
                    "residues": R, "atoms": plan.n_atoms, "angles": cfg.angles,
                    "adjoint": "fused" if args.fused else mode, "loss_in_graph": loss,
                    "res_per_lane": sched["res_per_lane"],
-                   "waves_per_group": sched["waves_per_group"], "tiles": sched["n_tiles"]},
+                   "waves_per_group": sched["waves_per_group"], "tiles": sched["n_tiles"],
+                   "steps_per_graph": gn[1]},
         "roofline": roof,
         "lrmsd": lr_info,
         "plain_gpu": plain,

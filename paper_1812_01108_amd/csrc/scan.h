@@ -10,8 +10,10 @@
 //     (force, moment), reset at chain ends.
 // A workgroup walks its tile in chunks of 64 W K residues and carries the
 // scan state from chunk to chunk.  Inside a chunk each scan is a 6-step DPP
-// scan inside the wave, one workgroup barrier and a short scan of the wave
-// totals that every wave repeats for itself.
+// scan inside the wave, then a scan of the wave totals: for the prefix
+// product wave 0 scans them between two workgroup barriers and every wave
+// reads its prefix from LDS; the suffix sum's totals are scanned by every
+// wave for itself after one barrier.
 #pragma once
 #include "a2c_internal.h"
 #include "affine.h"
@@ -83,8 +85,10 @@ __device__ __forceinline__ Wrench wrench_shfl_down(const Wrench &a, int delta)
 }
 
 struct FwdShared {
-    float tot[kMaxWaves][12];
-    int tot_flag[kMaxWaves];
+    float tot[kMaxWaves][12];   // wave totals
+    int tot_flag[kMaxWaves];    // a chain starts in the wave
+    float pre[kMaxWaves][12];   // inclusive prefixes of the wave totals
+    int pre_flag[kMaxWaves];    // a chain starts in waves 0..w
 };
 
 struct BwdShared {
@@ -231,6 +235,72 @@ __device__ __forceinline__ Aff aff_seg_after(const Aff &carry, const Aff &t, boo
     return aff_select(t_head, t, c);
 }
 
+// Lanes at or below `lane` (bit l set for l <= lane) and strictly below it.
+__device__ __forceinline__ uint64_t lanes_upto(int lane) { return ~0ull >> (63 - lane); }
+__device__ __forceinline__ uint64_t lanes_below(int lane)
+{
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Lane of the last set bit of `heads` at or below `lane` (0 when none).
+__device__ __forceinline__ int last_head_upto(uint64_t heads, int lane)
+{
+    const uint64_t b = heads & lanes_upto(lane);
+    return b ? 63 - __builtin_clzll(b) : 0;
+}
+
+// DPP read with bound_ctrl (a lane without a source reads 0) and full row and
+// bank masks: the compiler may then fold the move into the instructions that
+// consume it.  Callers only use lanes that have a source.
+template <int CTRL>
+__device__ __forceinline__ float dpp_z(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, true));
+}
+
+template <int CTRL>
+__device__ __forceinline__ Aff aff_dpp_z(const Aff &a)
+{
+    Aff o;
+    o.r00 = dpp_z<CTRL>(a.r00); o.r10 = dpp_z<CTRL>(a.r10); o.r20 = dpp_z<CTRL>(a.r20);
+    o.r01 = dpp_z<CTRL>(a.r01); o.r11 = dpp_z<CTRL>(a.r11); o.r21 = dpp_z<CTRL>(a.r21);
+    o.r02 = dpp_z<CTRL>(a.r02); o.r12 = dpp_z<CTRL>(a.r12); o.r22 = dpp_z<CTRL>(a.r22);
+    o.t0 = dpp_z<CTRL>(a.t0); o.t1 = dpp_z<CTRL>(a.t1); o.t2 = dpp_z<CTRL>(a.t2);
+    return o;
+}
+
+// One step of a segmented inclusive affine scan, branch-free: lanes with
+// `take` prepend the value of their source lane.
+template <int CTRL>
+__device__ __forceinline__ void aff_scan_step(Aff &m, bool take)
+{
+    const Aff c = aff_compose(aff_dpp_z<CTRL>(m), m);
+    m = aff_select(take, c, m);
+}
+
+// Segmented inclusive scan of 3x4 affines over the lanes of a wave (or over
+// lanes 0..n-1, n <= 16, when ROW0).  heads: bit l set when lane l starts a
+// segment.  Lane l prepends the value of lane l - d when that lane is in the
+// same segment, i.e. when l - d >= s_l, the last head at or below l; the row
+// steps (d = 1, 2, 4, 8 inside rows of 16 lanes) also need l - d in l's row.
+template <bool ROW0>
+__device__ __forceinline__ void aff_wave_scan(Aff &m, uint64_t heads, int n)
+{
+    const int lane = threadIdx.x & 63;
+    const int s = last_head_upto(heads, lane);
+    const int row = lane & ~15;
+    const int dist = lane - max(s, row);   // lanes of l's segment before l, in its row
+    if (!ROW0 || n > 1) aff_scan_step<kDppRowShr + 1>(m, dist >= 1);
+    if (!ROW0 || n > 2) aff_scan_step<kDppRowShr + 2>(m, dist >= 2);
+    if (!ROW0 || n > 4) aff_scan_step<kDppRowShr + 4>(m, dist >= 4);
+    if (!ROW0 || n > 8) aff_scan_step<kDppRowShr + 8>(m, dist >= 8);
+    if (!ROW0) {
+        // rows 1 and 3 prepend the last lane of rows 0 and 2; rows 2-3 lane 31
+        aff_scan_step<kDppBcast15>(m, (lane & 16) != 0 && s < row);
+        aff_scan_step<kDppBcast31>(m, lane >= 32 && s < 32);
+    }
+}
+
 // Exclusive segmented prefix product over one chunk of a tile.
 //   m, f     lane aggregate (product of the lane's transforms since its last
 //            chain head; identity for an empty lane) and "a chain starts in
@@ -242,9 +312,10 @@ __device__ __forceinline__ Aff aff_seg_after(const Aff &carry, const Aff &t, boo
 //            also in waves idle in this chunk.
 // Returns the frame X preceding the lane's first transform (meaningful for
 // the lane's residues before its first chain head).  Every thread of the
-// block calls this (one barrier); sh must not be reused by the next call
-// (callers alternate two buffers).  MULTI = false: the tile is one chunk and
-// the carry is neither read nor written.
+// block calls this.  Each wave scans its lanes; wave 0 alone then scans the
+// wave totals (two barriers) and every wave reads the prefix it needs.
+// MULTI = false: the tile is one chunk and the carry is neither read nor
+// written.
 template <bool MULTI>
 __device__ __forceinline__ Aff block_exclusive_prefix(Aff m, bool f, int nact, FwdShared &sh,
                                                       Aff &carry)
@@ -252,64 +323,53 @@ __device__ __forceinline__ Aff block_exclusive_prefix(Aff m, bool f, int nact, F
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const bool wave_active = wave < nact;
+    const uint64_t heads = __builtin_amdgcn_ballot_w64(f);
     if (wave_active) {
-        // inclusive scan: four shifts inside rows of 16, then the row totals
-        const int rl = lane & 15;
-        aff_scan_combine(m, f, aff_dpp<kDppRowShr + 1>(m), dpp_i<kDppRowShr + 1>(f), rl >= 1);
-        aff_scan_combine(m, f, aff_dpp<kDppRowShr + 2>(m), dpp_i<kDppRowShr + 2>(f), rl >= 2);
-        aff_scan_combine(m, f, aff_dpp<kDppRowShr + 4>(m), dpp_i<kDppRowShr + 4>(f), rl >= 4);
-        aff_scan_combine(m, f, aff_dpp<kDppRowShr + 8>(m), dpp_i<kDppRowShr + 8>(f), rl >= 8);
-        aff_scan_combine(m, f, aff_dpp<kDppBcast15, 0xa>(m), dpp_i<kDppBcast15, 0xa>(f),
-                         (lane & 16) != 0);
-        aff_scan_combine(m, f, aff_dpp<kDppBcast31, 0xc>(m), dpp_i<kDppBcast31, 0xc>(f),
-                         lane >= 32);
+        aff_wave_scan<false>(m, heads, kWave);
         if (lane == kWave - 1) {
             aff_store(sh.tot[wave], m);
-            sh.tot_flag[wave] = f ? 1 : 0;
+            sh.tot_flag[wave] = heads != 0ull ? 1 : 0;
         }
     }
-    __syncthreads();
-    if (!MULTI && !wave_active) return aff_identity();
-    // inclusive scan of the wave totals in lanes 0..span-1 of row 0: this
-    // wave needs lanes before it; the chunk carry needs all nact of them
-    const int span = MULTI ? nact : wave;
-    Aff t = aff_identity();
-    bool tf = false;
-    if (lane < span) {
-        t = aff_load(sh.tot[lane]);
-        tf = sh.tot_flag[lane] != 0;
+    // the wave totals' inclusive prefixes, by wave 0 (block-uniform branch)
+    if (MULTI || nact > 1) {
+        __syncthreads();
+        if (wave == 0) {
+            Aff t = aff_identity();
+            bool tf = false;
+            if (lane < nact) {
+                t = aff_load(sh.tot[lane]);
+                tf = sh.tot_flag[lane] != 0;
+            }
+            const uint64_t th = __builtin_amdgcn_ballot_w64(tf);
+            aff_wave_scan<true>(t, th, nact);
+            if (lane < nact) {
+                aff_store(sh.pre[lane], t);
+                sh.pre_flag[lane] = (th & lanes_upto(lane)) != 0ull ? 1 : 0;
+            }
+        }
+        __syncthreads();
     }
-    const int rl = lane & 15;
-    if (span > 1)
-        aff_scan_combine(t, tf, aff_dpp<kDppRowShr + 1>(t), dpp_i<kDppRowShr + 1>(tf), rl >= 1);
-    if (span > 2)
-        aff_scan_combine(t, tf, aff_dpp<kDppRowShr + 2>(t), dpp_i<kDppRowShr + 2>(tf), rl >= 2);
-    if (span > 4)
-        aff_scan_combine(t, tf, aff_dpp<kDppRowShr + 4>(t), dpp_i<kDppRowShr + 4>(tf), rl >= 4);
-    if (span > 8)
-        aff_scan_combine(t, tf, aff_dpp<kDppRowShr + 8>(t), dpp_i<kDppRowShr + 8>(tf), rl >= 8);
     // carry-in of this wave (identity for wave 0 of a one-chunk tile)
     Aff cw = aff_identity();
     if (MULTI) cw = carry;
     if (wave_active && wave > 0) {
-        const Aff p = aff_bcast(t, wave - 1);
-        const bool pf = __builtin_amdgcn_readlane((int)tf, wave - 1) != 0;
+        const Aff p = aff_load(sh.pre[wave - 1]);
+        const bool pf = sh.pre_flag[wave - 1] != 0;
         cw = MULTI ? aff_seg_after(carry, p, pf) : p;
     }
     if (MULTI) {  // every wave advances the carry, also one idle in this chunk
-        const Aff p = aff_bcast(t, nact - 1);
-        const bool pf = __builtin_amdgcn_readlane((int)tf, nact - 1) != 0;
+        const Aff p = aff_load(sh.pre[nact - 1]);
+        const bool pf = sh.pre_flag[nact - 1] != 0;
         carry = aff_uniform(aff_seg_after(carry, p, pf));
     }
     if (!wave_active) return aff_identity();
-    Aff e = aff_dpp<kDppWaveShr1>(m);
-    int fe = dpp_i<kDppWaveShr1>(f);
-    if (lane == 0) {
-        e = aff_identity();
-        fe = 0;
-    }
-    const Aff xc = aff_compose(cw, e);
-    return fe ? e : xc;
+    // lane l's prefix inside the wave: the inclusive value of lane l - 1,
+    // complete when a chain starts in lanes before l
+    Aff e = aff_dpp_z<kDppWaveShr1>(m);
+    if (lane == 0) e = aff_identity();
+    const bool fe = (heads & lanes_below(lane)) != 0ull;
+    return fe ? e : aff_compose(cw, e);
 }
 
 // Exclusive segmented suffix sum over one chunk of a tile, chunks visited
