@@ -11,9 +11,8 @@
 // A workgroup walks its tile in chunks of 64 W K residues and carries the
 // scan state from chunk to chunk.  Inside a chunk each scan is a 6-step DPP
 // scan inside the wave, then a scan of the wave totals: for the prefix
-// product wave 0 scans them between two workgroup barriers and every wave
-// reads its prefix from LDS; the suffix sum's totals are scanned by every
-// wave for itself after one barrier.
+// product and the suffix sum alike, wave 0 scans them between two
+// workgroup barriers and every wave reads the value it needs from LDS.
 #pragma once
 #include "a2c_internal.h"
 #include "affine.h"
@@ -75,15 +74,6 @@ __device__ __forceinline__ float wrench_torque(const Wrench &S, float ox, float 
     return fmaf(uz, tz, fmaf(uy, ty, ux * tx));
 }
 
-__device__ __forceinline__ Wrench wrench_shfl_down(const Wrench &a, int delta)
-{
-    Wrench o;
-    o.g0 = __shfl_down(a.g0, delta, 64); o.g1 = __shfl_down(a.g1, delta, 64);
-    o.g2 = __shfl_down(a.g2, delta, 64); o.m0 = __shfl_down(a.m0, delta, 64);
-    o.m1 = __shfl_down(a.m1, delta, 64); o.m2 = __shfl_down(a.m2, delta, 64);
-    return o;
-}
-
 struct FwdShared {
     float tot[kMaxWaves][12];   // wave totals
     int tot_flag[kMaxWaves];    // a chain starts in the wave
@@ -92,8 +82,10 @@ struct FwdShared {
 };
 
 struct BwdShared {
-    float tot[kMaxWaves][6];
-    int tot_flag[kMaxWaves];
+    float tot[kMaxWaves][6];    // wave totals
+    int tot_flag[kMaxWaves];    // a chain ends in the wave
+    float suf[kMaxWaves][6];    // inclusive suffixes of the wave totals
+    int suf_flag[kMaxWaves];    // a chain ends in waves w..nact-1
 };
 
 __device__ __forceinline__ void aff_store(float *dst, const Aff &m)
@@ -129,54 +121,6 @@ __device__ __forceinline__ float dpp_f(float v)
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, false));
 }
 
-template <int CTRL, int ROW_MASK = 0xf>
-__device__ __forceinline__ int dpp_i(int v)
-{
-    return __builtin_amdgcn_update_dpp(0, v, CTRL, ROW_MASK, 0xf, false);
-}
-
-template <int CTRL, int ROW_MASK = 0xf>
-__device__ __forceinline__ Aff aff_dpp(const Aff &a)
-{
-    Aff o;
-    o.r00 = dpp_f<CTRL, ROW_MASK>(a.r00); o.r10 = dpp_f<CTRL, ROW_MASK>(a.r10);
-    o.r20 = dpp_f<CTRL, ROW_MASK>(a.r20); o.r01 = dpp_f<CTRL, ROW_MASK>(a.r01);
-    o.r11 = dpp_f<CTRL, ROW_MASK>(a.r11); o.r21 = dpp_f<CTRL, ROW_MASK>(a.r21);
-    o.r02 = dpp_f<CTRL, ROW_MASK>(a.r02); o.r12 = dpp_f<CTRL, ROW_MASK>(a.r12);
-    o.r22 = dpp_f<CTRL, ROW_MASK>(a.r22); o.t0 = dpp_f<CTRL, ROW_MASK>(a.t0);
-    o.t1 = dpp_f<CTRL, ROW_MASK>(a.t1); o.t2 = dpp_f<CTRL, ROW_MASK>(a.t2);
-    return o;
-}
-
-template <int CTRL>
-__device__ __forceinline__ Wrench wrench_dpp(const Wrench &a)
-{
-    Wrench o;
-    o.g0 = dpp_f<CTRL>(a.g0); o.g1 = dpp_f<CTRL>(a.g1); o.g2 = dpp_f<CTRL>(a.g2);
-    o.m0 = dpp_f<CTRL>(a.m0); o.m1 = dpp_f<CTRL>(a.m1); o.m2 = dpp_f<CTRL>(a.m2);
-    return o;
-}
-
-// one step of the segmented affine scan: lanes with `take` combine with the
-// value o received from earlier lanes
-__device__ __forceinline__ void aff_scan_combine(Aff &m, bool &f, const Aff &o, int fo, bool take)
-{
-    if (take) {
-        const Aff c = aff_compose(o, m);
-        m = aff_select(f, m, c);
-        f = f || (fo != 0);
-    }
-}
-
-__device__ __forceinline__ void wrench_scan_combine(Wrench &w, bool &f, const Wrench &o, int fo,
-                                                    bool take)
-{
-    if (take) {
-        if (!f) wrench_add(w, o);
-        f = f || (fo != 0);
-    }
-}
-
 __device__ __forceinline__ float lane_bcast(float v, int src_lane)
 {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src_lane));
@@ -200,16 +144,6 @@ __device__ __forceinline__ float block_sum(float v, float (&wave_tot)[kMaxWaves]
     if (threadIdx.x == 0)
         for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += wave_tot[i];
     return t;
-}
-
-__device__ __forceinline__ Aff aff_bcast(const Aff &a, int l)
-{
-    Aff o;
-    o.r00 = lane_bcast(a.r00, l); o.r10 = lane_bcast(a.r10, l); o.r20 = lane_bcast(a.r20, l);
-    o.r01 = lane_bcast(a.r01, l); o.r11 = lane_bcast(a.r11, l); o.r21 = lane_bcast(a.r21, l);
-    o.r02 = lane_bcast(a.r02, l); o.r12 = lane_bcast(a.r12, l); o.r22 = lane_bcast(a.r22, l);
-    o.t0 = lane_bcast(a.t0, l); o.t1 = lane_bcast(a.t1, l); o.t2 = lane_bcast(a.t2, l);
-    return o;
 }
 
 __device__ __forceinline__ float uni(float v)
@@ -372,6 +306,75 @@ __device__ __forceinline__ Aff block_exclusive_prefix(Aff m, bool f, int nact, F
     return fe ? e : aff_compose(cw, e);
 }
 
+// Lane of the first set bit of `ends` at or above `lane` (63 when none).
+__device__ __forceinline__ int first_end_from(uint64_t ends, int lane)
+{
+    const uint64_t b = ends & (~0ull << lane);
+    return b ? __builtin_ctzll(b) : kWave - 1;
+}
+
+template <int CTRL>
+__device__ __forceinline__ Wrench wrench_dpp_z(const Wrench &a)
+{
+    Wrench o;
+    o.g0 = dpp_z<CTRL>(a.g0); o.g1 = dpp_z<CTRL>(a.g1); o.g2 = dpp_z<CTRL>(a.g2);
+    o.m0 = dpp_z<CTRL>(a.m0); o.m1 = dpp_z<CTRL>(a.m1); o.m2 = dpp_z<CTRL>(a.m2);
+    return o;
+}
+
+// every lane of each 32-lane half reads lane 16 of its half (ds_swizzle in
+// bit mode: and_mask 0, or_mask 16)
+__device__ __forceinline__ float swz_lane16(float v)
+{
+    return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 16 << 5));
+}
+
+__device__ __forceinline__ void wrench_add_if(Wrench &w, const Wrench &o, bool take)
+{
+    w.g0 = take ? w.g0 + o.g0 : w.g0; w.g1 = take ? w.g1 + o.g1 : w.g1;
+    w.g2 = take ? w.g2 + o.g2 : w.g2; w.m0 = take ? w.m0 + o.m0 : w.m0;
+    w.m1 = take ? w.m1 + o.m1 : w.m1; w.m2 = take ? w.m2 + o.m2 : w.m2;
+}
+
+// Segmented inclusive suffix sum of wrenches over the lanes of a wave (or
+// over lanes 0..n-1, n <= 16, when ROW0).  ends: bit l set when lane l's
+// value closes a segment.  Lane l adds the value of lane l + d when no
+// segment closes in lanes l .. l+d-1, i.e. when l + d <= e_l, the first end
+// at or after l; the row steps also need l + d in l's row.
+template <bool ROW0>
+__device__ __forceinline__ void wrench_wave_rscan(Wrench &w, uint64_t ends, int n)
+{
+    const int lane = threadIdx.x & 63;
+    const int e = first_end_from(ends, lane);
+    const int dist = min(e, lane | 15) - lane;
+    if (!ROW0 || n > 1) wrench_add_if(w, wrench_dpp_z<kDppRowShl + 1>(w), dist >= 1);
+    if (!ROW0 || n > 2) wrench_add_if(w, wrench_dpp_z<kDppRowShl + 2>(w), dist >= 2);
+    if (!ROW0 || n > 4) wrench_add_if(w, wrench_dpp_z<kDppRowShl + 4>(w), dist >= 4);
+    if (!ROW0 || n > 8) wrench_add_if(w, wrench_dpp_z<kDppRowShl + 8>(w), dist >= 8);
+    if (!ROW0) {
+        // rows 0 and 2 add the first lane of rows 1 and 3, then rows 0-1 lane 32
+        Wrench o;
+        o.g0 = swz_lane16(w.g0); o.g1 = swz_lane16(w.g1); o.g2 = swz_lane16(w.g2);
+        o.m0 = swz_lane16(w.m0); o.m1 = swz_lane16(w.m1); o.m2 = swz_lane16(w.m2);
+        wrench_add_if(w, o, (lane & 16) == 0 && e > (lane | 15));
+        o.g0 = lane_bcast(w.g0, 32); o.g1 = lane_bcast(w.g1, 32); o.g2 = lane_bcast(w.g2, 32);
+        o.m0 = lane_bcast(w.m0, 32); o.m1 = lane_bcast(w.m1, 32); o.m2 = lane_bcast(w.m2, 32);
+        wrench_add_if(w, o, lane < 32 && e >= 32);
+    }
+}
+
+__device__ __forceinline__ void wrench_store(float *dst, const Wrench &w)
+{
+    dst[0] = w.g0; dst[1] = w.g1; dst[2] = w.g2; dst[3] = w.m0; dst[4] = w.m1; dst[5] = w.m2;
+}
+
+__device__ __forceinline__ Wrench wrench_load(const float *src)
+{
+    Wrench w;
+    w.g0 = src[0]; w.g1 = src[1]; w.g2 = src[2]; w.m0 = src[3]; w.m1 = src[4]; w.m2 = src[5];
+    return w;
+}
+
 // Exclusive segmented suffix sum over one chunk of a tile, chunks visited
 // last to first.
 //   agg, f   lane aggregate (sum over the lane's atoms up to and including
@@ -383,8 +386,9 @@ __device__ __forceinline__ Aff block_exclusive_prefix(Aff m, bool f, int nact, F
 //            first, may leave waves idle that the earlier chunks use).
 // Returns the wrench of everything after the lane up to the end of the
 // chain the lane's last residue belongs to (callers discard it when that
-// residue ends its chain).  Every thread of the block calls this (one
-// barrier); callers alternate two buffers sh.
+// residue ends its chain).  Every thread of the block calls this.  Each wave
+// scans its lanes; wave 0 alone then scans the wave totals (two barriers)
+// and every wave reads the suffix it needs.
 template <bool MULTI>
 __device__ __forceinline__ Wrench block_exclusive_suffix(Wrench agg, bool f, int nact,
                                                          BwdShared &sh, Wrench &carry)
@@ -392,92 +396,52 @@ __device__ __forceinline__ Wrench block_exclusive_suffix(Wrench agg, bool f, int
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const bool wave_active = wave < nact;
+    const uint64_t ends = __builtin_amdgcn_ballot_w64(f);
     if (wave_active) {
-        // inclusive reverse scan: four shifts inside rows, then the suffix
-        // totals of rows 1 and 3 (lanes 16, 48) and of rows 2-3 (lane 32)
-        const int rl = lane & 15;
-        wrench_scan_combine(agg, f, wrench_dpp<kDppRowShl + 1>(agg), dpp_i<kDppRowShl + 1>(f), rl < 15);
-        wrench_scan_combine(agg, f, wrench_dpp<kDppRowShl + 2>(agg), dpp_i<kDppRowShl + 2>(f), rl < 14);
-        wrench_scan_combine(agg, f, wrench_dpp<kDppRowShl + 4>(agg), dpp_i<kDppRowShl + 4>(f), rl < 12);
-        wrench_scan_combine(agg, f, wrench_dpp<kDppRowShl + 8>(agg), dpp_i<kDppRowShl + 8>(f), rl < 8);
-        {
-            const bool lo = lane < 16;
-            Wrench o;
-            const float a0 = lane_bcast(agg.g0, 16), b0 = lane_bcast(agg.g0, 48);
-            const float a1 = lane_bcast(agg.g1, 16), b1 = lane_bcast(agg.g1, 48);
-            const float a2 = lane_bcast(agg.g2, 16), b2 = lane_bcast(agg.g2, 48);
-            const float a3 = lane_bcast(agg.m0, 16), b3 = lane_bcast(agg.m0, 48);
-            const float a4 = lane_bcast(agg.m1, 16), b4 = lane_bcast(agg.m1, 48);
-            const float a5 = lane_bcast(agg.m2, 16), b5 = lane_bcast(agg.m2, 48);
-            const int fa = __builtin_amdgcn_readlane((int)f, 16);
-            const int fb = __builtin_amdgcn_readlane((int)f, 48);
-            o.g0 = lo ? a0 : b0; o.g1 = lo ? a1 : b1; o.g2 = lo ? a2 : b2;
-            o.m0 = lo ? a3 : b3; o.m1 = lo ? a4 : b4; o.m2 = lo ? a5 : b5;
-            wrench_scan_combine(agg, f, o, lo ? fa : fb, (lane & 16) == 0);
-        }
-        {
-            Wrench o;
-            o.g0 = lane_bcast(agg.g0, 32); o.g1 = lane_bcast(agg.g1, 32);
-            o.g2 = lane_bcast(agg.g2, 32); o.m0 = lane_bcast(agg.m0, 32);
-            o.m1 = lane_bcast(agg.m1, 32); o.m2 = lane_bcast(agg.m2, 32);
-            const int fo = __builtin_amdgcn_readlane((int)f, 32);
-            wrench_scan_combine(agg, f, o, fo, lane < 32);
-        }
+        wrench_wave_rscan<false>(agg, ends, kWave);
         if (lane == 0) {
-            sh.tot[wave][0] = agg.g0; sh.tot[wave][1] = agg.g1; sh.tot[wave][2] = agg.g2;
-            sh.tot[wave][3] = agg.m0; sh.tot[wave][4] = agg.m1; sh.tot[wave][5] = agg.m2;
-            sh.tot_flag[wave] = f ? 1 : 0;
+            wrench_store(sh.tot[wave], agg);
+            sh.tot_flag[wave] = ends != 0ull ? 1 : 0;
         }
     }
-    __syncthreads();
-    if (!MULTI && !wave_active) return wrench_zero();
-    // inclusive reverse scan of the wave totals in lanes 0..nact-1 of row 0,
-    // over as many of them as are needed: lanes wave+1..nact-1 for this
-    // wave, all nact for the chunk carry
-    const int span = MULTI ? nact : nact - 1 - wave;
-    Wrench t = wrench_zero();
-    bool tf = false;
-    if (lane < nact) {
-        t.g0 = sh.tot[lane][0]; t.g1 = sh.tot[lane][1]; t.g2 = sh.tot[lane][2];
-        t.m0 = sh.tot[lane][3]; t.m1 = sh.tot[lane][4]; t.m2 = sh.tot[lane][5];
-        tf = sh.tot_flag[lane] != 0;
+    // the wave totals' inclusive suffixes, by wave 0 (block-uniform branch)
+    if (MULTI || nact > 1) {
+        __syncthreads();
+        if (wave == 0) {
+            Wrench t = wrench_zero();
+            bool tf = false;
+            if (lane < nact) {
+                t = wrench_load(sh.tot[lane]);
+                tf = sh.tot_flag[lane] != 0;
+            }
+            const uint64_t th = __builtin_amdgcn_ballot_w64(tf);
+            wrench_wave_rscan<true>(t, th, nact);
+            if (lane < nact) {
+                wrench_store(sh.suf[lane], t);
+                sh.suf_flag[lane] = (th & (~0ull << lane)) != 0ull ? 1 : 0;
+            }
+        }
+        __syncthreads();
     }
-    const int rl = lane & 15;
-    if (span > 1)
-        wrench_scan_combine(t, tf, wrench_dpp<kDppRowShl + 1>(t), dpp_i<kDppRowShl + 1>(tf), rl < 15);
-    if (span > 2)
-        wrench_scan_combine(t, tf, wrench_dpp<kDppRowShl + 2>(t), dpp_i<kDppRowShl + 2>(tf), rl < 14);
-    if (span > 4)
-        wrench_scan_combine(t, tf, wrench_dpp<kDppRowShl + 4>(t), dpp_i<kDppRowShl + 4>(tf), rl < 12);
-    if (span > 8)
-        wrench_scan_combine(t, tf, wrench_dpp<kDppRowShl + 8>(t), dpp_i<kDppRowShl + 8>(tf), rl < 8);
     // carry into this wave from the waves after it (and, MULTI, later chunks)
     Wrench cw = wrench_zero();
     if (MULTI) cw = carry;
     if (wave_active && wave + 1 < nact) {
-        Wrench p;
-        p.g0 = lane_bcast(t.g0, wave + 1); p.g1 = lane_bcast(t.g1, wave + 1);
-        p.g2 = lane_bcast(t.g2, wave + 1); p.m0 = lane_bcast(t.m0, wave + 1);
-        p.m1 = lane_bcast(t.m1, wave + 1); p.m2 = lane_bcast(t.m2, wave + 1);
-        const bool pf = __builtin_amdgcn_readlane((int)tf, wave + 1) != 0;
-        if (MULTI && !pf) wrench_add(p, carry);
+        Wrench p = wrench_load(sh.suf[wave + 1]);
+        if (MULTI && sh.suf_flag[wave + 1] == 0) wrench_add(p, carry);
         cw = p;
     }
     if (MULTI) {  // every wave advances the carry, also one idle in this chunk
-        Wrench p;
-        p.g0 = lane_bcast(t.g0, 0); p.g1 = lane_bcast(t.g1, 0); p.g2 = lane_bcast(t.g2, 0);
-        p.m0 = lane_bcast(t.m0, 0); p.m1 = lane_bcast(t.m1, 0); p.m2 = lane_bcast(t.m2, 0);
-        const bool pf = __builtin_amdgcn_readlane((int)tf, 0) != 0;
-        if (!pf) wrench_add(p, carry);
+        Wrench p = wrench_load(sh.suf[0]);
+        if (sh.suf_flag[0] == 0) wrench_add(p, carry);
         carry = p;
     }
     if (!wave_active) return wrench_zero();
-    Wrench S = wrench_dpp<kDppWaveShl1>(agg);
-    int fs = dpp_i<kDppWaveShl1>(f);
-    if (lane == kWave - 1) {
-        S = wrench_zero();
-        fs = 0;
-    }
+    // everything after lane l inside the wave: the inclusive value of lane
+    // l + 1, complete when a chain ends in lanes after l
+    Wrench S = wrench_dpp_z<kDppWaveShl1>(agg);
+    if (lane == kWave - 1) S = wrench_zero();
+    const bool fs = lane < kWave - 1 && (ends >> (lane + 1)) != 0ull;
     if (!fs) wrench_add(S, cw);
     return S;
 }
