@@ -39,6 +39,13 @@ struct BBParams {
 // backbone geometry) and 3 + f for side frame f; side frames form a chain
 // CA -> 0 -> 1 -> ... (frame f hangs off f-1), frame 0 through a fixed
 // rotation about CA's x axis.  Atoms are grouped by frame.
+// One atom of a residue type: position in its frame and output slot, packed
+// so that a kernel reads it from LDS in one 16-byte access.
+struct alignas(16) FAAtom {
+    float x, y, z;
+    int32_t slot;
+};
+
 struct FAType {
     int32_t n_atoms;
     int32_t n_side;
@@ -47,8 +54,7 @@ struct FAType {
     float ct[4], st[4], d[4], inv_d[4];
     int32_t fbegin[7], fcount[7];   // atoms of frame k in the sorted lists
     int32_t origin_slot[7];         // residue slot of the atom at frame k's origin
-    int32_t slot[A2C_MAX_RESIDUE_ATOMS];  // output slot of each sorted atom
-    float rx[A2C_MAX_RESIDUE_ATOMS], ry[A2C_MAX_RESIDUE_ATOMS], rz[A2C_MAX_RESIDUE_ATOMS];
+    FAAtom atom[A2C_MAX_RESIDUE_ATOMS];   // sorted by frame
 };
 
 struct FATable {

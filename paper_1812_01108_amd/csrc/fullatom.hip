@@ -139,10 +139,10 @@ a2c_status convert_residue_table(const a2c_residue_table *table, const double sp
             ft.fbegin[k] = n;
             for (int a = 0; a < rd.n_atoms; ++a)
                 if (rd.atoms[a].frame == k) {
-                    ft.slot[n] = a;
-                    ft.rx[n] = (float)local[a].x;
-                    ft.ry[n] = (float)local[a].y;
-                    ft.rz[n] = (float)local[a].z;
+                    ft.atom[n].slot = a;
+                    ft.atom[n].x = (float)local[a].x;
+                    ft.atom[n].y = (float)local[a].y;
+                    ft.atom[n].z = (float)local[a].z;
                     ++n;
                 }
             ft.fcount[k] = n - ft.fbegin[k];
@@ -190,8 +190,8 @@ extern "C" a2c_status a2c_residue_table_info(const a2c_residue_table *table, int
         if (n_atoms) n_atoms[t] = ft.n_atoms;
         if (local_xyz)
             for (int q = 0; q < ft.n_atoms; ++q) {
-                float *o = local_xyz + 3 * (A2C_MAX_RESIDUE_ATOMS * t + ft.slot[q]);
-                o[0] = ft.rx[q]; o[1] = ft.ry[q]; o[2] = ft.rz[q];
+                float *o = local_xyz + 3 * (A2C_MAX_RESIDUE_ATOMS * t + ft.atom[q].slot);
+                o[0] = ft.atom[q].x; o[1] = ft.atom[q].y; o[2] = ft.atom[q].z;
             }
     }
     return A2C_OK;
@@ -203,12 +203,22 @@ namespace a2c {
 
 namespace {
 
+// The constant table into LDS: 16-byte pieces, every load of a thread issued
+// before its first store (one memory latency also for a one-wave group).
 __device__ __forceinline__ void load_table(FATable &tab, const FATable *__restrict__ g)
 {
-    const int32_t *src = reinterpret_cast<const int32_t *>(g);
-    int32_t *dst = reinterpret_cast<int32_t *>(&tab);
-    constexpr int n = sizeof(FATable) / sizeof(int32_t);
-    for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+    static_assert(sizeof(FATable) % 16 == 0, "FATable copies in 16-byte pieces");
+    constexpr int n = sizeof(FATable) / 16;
+    constexpr int per = (n + kWave - 1) / kWave;
+    const int4 *src = reinterpret_cast<const int4 *>(g);
+    int4 *dst = reinterpret_cast<int4 *>(&tab);
+    int4 v[per];
+    // indices past the end are clamped: those threads rewrite the last piece
+    // with the value it already gets (no branches, so the loads batch)
+#pragma unroll
+    for (int u = 0; u < per; ++u) v[u] = src[min((int)(threadIdx.x + u * blockDim.x), n - 1)];
+#pragma unroll
+    for (int u = 0; u < per; ++u) dst[min((int)(threadIdx.x + u * blockDim.x), n - 1)] = v[u];
     __syncthreads();
 }
 
@@ -296,10 +306,10 @@ __device__ __forceinline__ void emit_frame(const FATable &tab, const FAType &ft,
 {
     for (int i = 0; i < tab.max_count[k]; ++i) {
         if (i < ft.fcount[k]) {
-            const int q = ft.fbegin[k] + i;
+            const FAAtom at = ft.atom[ft.fbegin[k] + i];
             float x, y, z;
-            aff_point(F, ft.rx[q], ft.ry[q], ft.rz[q], x, y, z);
-            const int e = aloc + ft.slot[q];
+            aff_point(F, at.x, at.y, at.z, x, y, z);
+            const int e = aloc + at.slot;
             sg.st[e] = x;
             sg.st[sg.ns + e] = y;
             sg.st[2 * sg.ns + e] = z;
@@ -314,10 +324,10 @@ __device__ __forceinline__ void frame_wrench(const FATable &tab, const FAType &f
 {
     for (int i = 0; i < tab.max_count[k]; ++i) {
         if (i < ft.fcount[k]) {
-            const int q = ft.fbegin[k] + i;
+            const FAAtom at = ft.atom[ft.fbegin[k] + i];
             float x, y, z;
-            aff_point(F, ft.rx[q], ft.ry[q], ft.rz[q], x, y, z);
-            const int e = aloc + ft.slot[q];
+            aff_point(F, at.x, at.y, at.z, x, y, z);
+            const int e = aloc + at.slot;
             wrench_add_point(w, x, y, z, sg.st[e], sg.st[sg.ns + e], sg.st[2 * sg.ns + e]);
         }
     }
@@ -333,10 +343,10 @@ __device__ __forceinline__ void frame_wrench_mse(const FATable &tab, const FATyp
 {
     for (int i = 0; i < tab.max_count[k]; ++i) {
         if (i < ft.fcount[k]) {
-            const int q = ft.fbegin[k] + i;
+            const FAAtom at = ft.atom[ft.fbegin[k] + i];
             float x, y, z;
-            aff_point(F, ft.rx[q], ft.ry[q], ft.rz[q], x, y, z);
-            const int e = aloc + ft.slot[q];
+            aff_point(F, at.x, at.y, at.z, x, y, z);
+            const int e = aloc + at.slot;
             const float dx = x - sg.st[e], dy = y - sg.st[sg.ns + e], dz = z - sg.st[2 * sg.ns + e];
             loss += dx * dx + dy * dy + dz * dz;
             wrench_add_point(w, x, y, z, 2.f * dx, 2.f * dy, 2.f * dz);
@@ -357,7 +367,7 @@ __device__ __forceinline__ void frame_wrench_xyz(const FATable &tab, const FATyp
 {
     for (int i = 0; i < tab.max_count[k]; ++i) {
         if (i < ft.fcount[k]) {
-            const int e = aloc + ft.slot[ft.fbegin[k] + i];
+            const int e = aloc + ft.atom[ft.fbegin[k] + i].slot;
             wrench_add_point(w, sx.st[e], sx.st[sx.ns + e], sx.st[2 * sx.ns + e],
                              sg.st[e], sg.st[sg.ns + e], sg.st[2 * sg.ns + e]);
         }
@@ -485,6 +495,64 @@ __device__ __forceinline__ LaneRun<K> lane_run(const FAChunk &k,
     return L;
 }
 
+// Per-residue inputs of a lane, read right after the chunk's bookkeeping so
+// that their latency overlaps the block scan instead of stalling the walk:
+// residue type, first atom and (CHI) the four chi planes (read for every
+// residue; a residue without chi f ignores plane f).
+template <int K, bool CHI>
+struct LaneRes {
+    int type[K];
+    int aoff[K];
+    float chi[CHI ? K : 1][4];
+};
+
+template <int K, bool CHI>
+__device__ __forceinline__ LaneRes<K, CHI> load_lane_res(const LaneRun<K> &L,
+                                                         const uint8_t *__restrict__ seq,
+                                                         const int32_t *__restrict__ res_aoff,
+                                                         const float *__restrict__ ang, int64_t R)
+{
+    LaneRes<K, CHI> lr;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const bool v = j < L.cnt;
+        const int64_t r = v ? L.rs + j : 0;
+        lr.type[j] = v ? seq[r] : 0;
+        lr.aoff[j] = v ? res_aoff[r] : 0;
+        if (CHI) {
+#pragma unroll
+            for (int f = 0; f < 4; ++f) lr.chi[j][f] = v ? ang[(3 + f) * R + r] : 0.f;
+        }
+    }
+    return lr;
+}
+
+// All atoms of one residue from the frame before it (cur, advanced to the
+// residue's C frame): spine transforms omega, phi, psi, and the side chain
+// branching off the CA frame, each frame's atoms written to the stage.
+__device__ __forceinline__ void fa_emit_residue(const FATable &tab, const FAType &ft, Aff &cur,
+                                                const ResidueIn &in, const float (&chi)[4],
+                                                const BBParams &P, const Stage &sg, int aloc)
+{
+    aff_apply_transform(cur, P.ct[0], P.st[0], P.d[0], in.co, in.so);
+    emit_frame(tab, ft, 0, cur, sg, aloc);
+    aff_apply_transform(cur, P.ct[1], P.st[1], P.d[1], in.cp, in.sp);
+    emit_frame(tab, ft, 1, cur, sg, aloc);
+    if (ft.n_side > 0) {
+        Aff sf = cur;
+        aff_rot_x(sf, ft.pre_c, ft.pre_s);
+#pragma unroll
+        for (int f = 0; f < A2C_MAX_SIDE_FRAMES; ++f) {
+            if (f < tab.max_side && f < ft.n_side) {
+                side_step(sf, ft, f, chi[f]);
+                emit_frame(tab, ft, 3 + f, sf, sg, aloc);
+            }
+        }
+    }
+    aff_apply_transform(cur, P.ct[2], P.st[2], P.d[2], in.cs, in.ss);
+    emit_frame(tab, ft, 2, cur, sg, aloc);
+}
+
 // STG: atoms go through the per-wave LDS stage; otherwise straight to
 // global memory (schedules whose stage does not fit the LDS).
 template <int K, bool MULTI, int LB, bool STG = true>
@@ -495,12 +563,12 @@ __global__ __launch_bounds__(LB) void fa_forward_kernel(
     BBParams P, int stage_atoms)
 {
     extern __shared__ float stage_mem[];
-    __shared__ FATable tab;
+    __shared__ __align__(16) FATable tab;
     __shared__ FwdShared sh[2];
+    const int64_t ts = tile_res[2 * blockIdx.x], te = tile_res[2 * blockIdx.x + 1];
     load_table(tab, gtab);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const Stage lds{stage_mem + (size_t)wave * 3 * stage_atoms, stage_atoms};
-    const int64_t ts = tile_res[2 * blockIdx.x], te = tile_res[2 * blockIdx.x + 1];
     // MULTI = false: every tile is one chunk (straight-line code)
     const int nch = MULTI ? fa_chunks<K>(ts, te) : 1;
     Aff carry = aff_identity();
@@ -511,6 +579,8 @@ __global__ __launch_bounds__(LB) void fa_forward_kernel(
         int first_head = K;
         Aff m = aff_identity();
         if (L.active) m = fa_lane_aggregate<K>(ang, R, L.rs, L.cnt, L.hm, P, in, first_head);
+        // issued after the spine angles (whose wait would otherwise cover them)
+        const LaneRes<K, true> lr = load_lane_res<K, true>(L, seq, res_aoff, ang, R);
         const Aff X = block_exclusive_prefix<MULTI>(m, first_head < K, k.nact, sh[c & 1], carry);
         if (!L.active) continue;
         const Stage sg = STG ? lds : Stage{xyz + L.A0, A};
@@ -518,27 +588,9 @@ __global__ __launch_bounds__(LB) void fa_forward_kernel(
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             if (j < L.cnt) {
-                const int64_t r = L.rs + j;
-                const FAType &ft = tab.t[seq[r]];
-                const int aloc = res_aoff[r] - (int)L.A0;
                 if ((L.hm >> j) & 1u) cur = aff_identity();
-                aff_apply_transform(cur, P.ct[0], P.st[0], P.d[0], in[j].co, in[j].so);
-                emit_frame(tab, ft, 0, cur, sg, aloc);
-                aff_apply_transform(cur, P.ct[1], P.st[1], P.d[1], in[j].cp, in[j].sp);
-                emit_frame(tab, ft, 1, cur, sg, aloc);
-                if (ft.n_side > 0) {
-                    Aff sf = cur;
-                    aff_rot_x(sf, ft.pre_c, ft.pre_s);
-#pragma unroll
-                    for (int f = 0; f < A2C_MAX_SIDE_FRAMES; ++f) {
-                        if (f < tab.max_side && f < ft.n_side) {
-                            side_step(sf, ft, f, ang[(3 + f) * R + r]);
-                            emit_frame(tab, ft, 3 + f, sf, sg, aloc);
-                        }
-                    }
-                }
-                aff_apply_transform(cur, P.ct[2], P.st[2], P.d[2], in[j].cs, in[j].ss);
-                emit_frame(tab, ft, 2, cur, sg, aloc);
+                fa_emit_residue(tab, tab.t[lr.type[j]], cur, in[j], lr.chi[j], P, sg,
+                                lr.aoff[j] - (int)L.A0);
             }
         }
         if (STG) {
@@ -656,18 +708,18 @@ __global__ __launch_bounds__(LB) void fa_backward_kernel(
 {
     static_assert(GM == kGradLoad || RECOMPUTE, "the fused step recomputes the frames");
     extern __shared__ float stage_mem[];
-    __shared__ FATable tab;
+    __shared__ __align__(16) FATable tab;
     __shared__ FwdShared shf[2];
     __shared__ BwdShared shb[2];
     __shared__ float fwd_carry[RECOMPUTE ? kMaxChunks : 1][12];
     __shared__ float loss_tot[GM == kGradMse ? kMaxWaves : 1];
     float loss = 0.f;
+    const int64_t ts = tile_res[2 * blockIdx.x], te = tile_res[2 * blockIdx.x + 1];
     load_table(tab, gtab);
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int planes = RECOMPUTE ? 3 : 6;
     const Stage lds{stage_mem + (size_t)wave * planes * stage_atoms, stage_atoms};
-    const int64_t ts = tile_res[2 * blockIdx.x], te = tile_res[2 * blockIdx.x + 1];
     // MULTI = false: every tile is one chunk (straight-line code)
     const int nch = MULTI ? fa_chunks<K>(ts, te) : 1;
     if (RECOMPUTE && nch > 1) {
@@ -689,10 +741,13 @@ __global__ __launch_bounds__(LB) void fa_backward_kernel(
         const LaneRun<K> L = lane_run<K>(k, head_bits, res_aoff);
         Aff X = aff_identity();
         ResidueIn in[K];
+        int first_head = K;
+        Aff m = aff_identity();
+        if (RECOMPUTE && L.active)
+            m = fa_lane_aggregate<K>(ang, R, L.rs, L.cnt, L.hm, P, in, first_head);
+        // issued after the spine angles (whose wait would otherwise cover them)
+        const LaneRes<K, RECOMPUTE> lr = load_lane_res<K, RECOMPUTE>(L, seq, res_aoff, ang, R);
         if (RECOMPUTE) {
-            int first_head = K;
-            Aff m = aff_identity();
-            if (L.active) m = fa_lane_aggregate<K>(ang, R, L.rs, L.cnt, L.hm, P, in, first_head);
             Aff fcarry = aff_identity();
             if (nch > 1) fcarry = aff_load(fwd_carry[c]);
             // buffers alternate with the pass above: its last chunk used shf[(nch-1) & 1]
@@ -721,8 +776,10 @@ __global__ __launch_bounds__(LB) void fa_backward_kernel(
                 if (!RECOMPUTE) run_to_lds(sg, 3, xyz, A, L.A0, L.natoms);
             }
             wave_lds_sync();
+            // first atom of the residue before the lane: the previous lane's last
+            const int prev_aoff = __builtin_amdgcn_mov_dpp(lr.aoff[K - 1], kDppWaveShr1, 0xf, 0xf, true);
             if (!RECOMPUTE && lane > 0 && L.cnt > 0 && !(L.hm & 1u)) {
-                const int e = res_aoff[L.rs - 1] + 2 - (int)L.A0;
+                const int e = prev_aoff + 2 - (int)L.A0;
                 pcx = sx.st[e]; pcy = sx.st[sx.ns + e]; pcz = sx.st[2 * sx.ns + e];
             }
             Aff cur = X;
@@ -732,9 +789,8 @@ __global__ __launch_bounds__(LB) void fa_backward_kernel(
                 if (j < L.cnt) {
                     SpineNode sn;
                     sn.wN = sn.wCA = sn.wC = wrench_zero();
-                    const int64_t r = L.rs + j;
-                    const FAType &ft = tab.t[seq[r]];
-                    const int aloc = res_aoff[r] - (int)L.A0;
+                    const FAType &ft = tab.t[lr.type[j]];
+                    const int aloc = lr.aoff[j] - (int)L.A0;
                     const bool head = (L.hm >> j) & 1u;
                     // side-chain frames: origin/axis per frame and own wrenches
                     Wrench ws[A2C_MAX_SIDE_FRAMES];
@@ -755,7 +811,7 @@ __global__ __launch_bounds__(LB) void fa_backward_kernel(
                         for (int f = 0; f < A2C_MAX_SIDE_FRAMES; ++f) {
                             ws[f] = wrench_zero();
                             if (f < tab.max_side && f < ft.n_side) {
-                                side_step(sf, ft, f, ang[(3 + f) * R + r]);
+                                side_step(sf, ft, f, lr.chi[j][f]);
                                 so[f][0] = sf.t0; so[f][1] = sf.t1; so[f][2] = sf.t2;
                                 su[f][0] = sf.r00; su[f][1] = sf.r10; su[f][2] = sf.r20;
                                 if (GM == kGradMse) frame_wrench_mse(tab, ft, 3 + f, sf, sg, sout, write_so, aloc, ws[f], loss);

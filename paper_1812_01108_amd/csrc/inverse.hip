@@ -42,9 +42,9 @@ void build_chi_slots(const FATable &T, int8_t (&out)[A2C_NUM_RESIDUE_TYPES][4][4
                 const int k = 3 + f;
                 for (int i = 0; i < ft.fcount[k] && d < 0; ++i) {
                     const int s = ft.fbegin[k] + i;
-                    const float x = ft.rx[s], y = ft.ry[s], z = ft.rz[s];
+                    const float x = ft.atom[s].x, y = ft.atom[s].y, z = ft.atom[s].z;
                     const float r = std::sqrt(x * x + y * y + z * z);
-                    if (r > 0.f && std::fabs(y) <= 1e-5f * r && z < -1e-3f * r) d = ft.slot[s];
+                    if (r > 0.f && std::fabs(y) <= 1e-5f * r && z < -1e-3f * r) d = ft.atom[s].slot;
                 }
             }
             if (d < 0) continue;
