@@ -527,6 +527,18 @@ __device__ __forceinline__ LaneRes<K, CHI> load_lane_res(const LaneRun<K> &L,
     return lr;
 }
 
+// The spine constants made opaque to the optimiser at the top of a loop over
+// chunks: products of them (the first transforms of a chain head, say) are
+// then formed where they are used instead of being hoisted out of the loop,
+// where these uniform values would each hold a vector register across it.
+__device__ __forceinline__ BBParams opaque_params(BBParams P)
+{
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+        asm volatile("" : "+s"(P.ct[i]), "+s"(P.st[i]), "+s"(P.d[i]), "+s"(P.inv_d[i]));
+    return P;
+}
+
 // All atoms of one residue from the frame before it (cur, advanced to the
 // residue's C frame): spine transforms omega, phi, psi, and the side chain
 // branching off the CA frame, each frame's atoms written to the stage.
@@ -560,7 +572,7 @@ __global__ __launch_bounds__(LB) void fa_forward_kernel(
     const float *__restrict__ ang, float *__restrict__ xyz, const int32_t *__restrict__ tile_res,
     const uint32_t *__restrict__ head_bits, const int32_t *__restrict__ res_aoff,
     const uint8_t *__restrict__ seq, const FATable *__restrict__ gtab, int64_t R, int64_t A,
-    BBParams P, int stage_atoms)
+    BBParams P0, int stage_atoms)
 {
     extern __shared__ float stage_mem[];
     __shared__ __align__(16) FATable tab;
@@ -573,6 +585,8 @@ __global__ __launch_bounds__(LB) void fa_forward_kernel(
     const int nch = MULTI ? fa_chunks<K>(ts, te) : 1;
     Aff carry = aff_identity();
     for (int c = 0; c < nch; ++c) {
+        // the same arithmetic as the adjoint kernels' recomputation
+        const BBParams P = opaque_params(P0);
         const FAChunk k = fa_chunk<K>(ts, te, c);
         const LaneRun<K> L = lane_run<K>(k, head_bits, res_aoff);
         ResidueIn in[K];
@@ -601,52 +615,41 @@ __global__ __launch_bounds__(LB) void fa_forward_kernel(
     }
 }
 
-// Per-residue group wrenches of the spine nodes and the spine frame data the
-// gradient needs.
-struct SpineNode {
-    Wrench wN, wCA, wC;         // own-group wrench (CA includes the side chain)
-    float oN[3], uN[3], oCA[3], uCA[3], oC[3], uC[3];
-};
-
-__device__ __forceinline__ void set_ou(float (&o)[3], float (&u)[3], const Aff &F)
-{
-    o[0] = F.t0; o[1] = F.t1; o[2] = F.t2;
-    u[0] = F.r00; u[1] = F.r10; u[2] = F.r20;
-}
-
-__device__ __forceinline__ void set_ou_pts(float (&o)[3], float (&u)[3], float ox, float oy,
-                                           float oz, float px, float py, float pz, float inv_d)
-{
-    o[0] = ox; o[1] = oy; o[2] = oz;
-    u[0] = (ox - px) * inv_d; u[1] = (oy - py) * inv_d; u[2] = (oz - pz) * inv_d;
-}
-
-// What a residue keeps across the block scan: the torque u . (m - o x g)
-// is linear in the wrench, so for each spine node the part of its subtree
-// inside the residue is folded in right after the walk (c), and the wrench
-// S of everything after the residue enters later as c + u . S.m - v . S.g
-// with v = u x o; W is the residue's whole wrench (for earlier residues of
-// the lane).  7 floats per node instead of 12.
+// Torque bookkeeping of one rotation axis (a spine node or a side frame):
+// the derivative of sum g.r over the atoms a rotation about the axis u
+// through o moves is u . (m - o x g) = u . m - v . g with v = u x o, summed
+// over the wrenches (g, m) of the atom groups it moves.  It is linear in the
+// wrench, so each group's wrench is folded into c as soon as the walk has it
+// (nothing per group is kept), and the wrench S of everything after the
+// residue enters later as c + u . S.m - v . S.g.  7 floats per axis.
 struct NodeGrad {
     float c, u0, u1, u2, v0, v1, v2;
 };
 
+// What a residue keeps across the block scan: its three spine nodes and W,
+// the residue's whole wrench (for earlier residues of the lane).
 struct SpineGrad {
     NodeGrad n, ca, cc;
     Wrench W;
 };
 
-__device__ __forceinline__ NodeGrad node_grad(const Wrench &local, const float (&o)[3],
-                                              const float (&u)[3])
+__device__ __forceinline__ NodeGrad node_at(float ox, float oy, float oz, float ux, float uy,
+                                            float uz)
 {
     NodeGrad g;
-    g.c = wrench_torque(local, o[0], o[1], o[2], u[0], u[1], u[2]);
-    g.u0 = u[0]; g.u1 = u[1]; g.u2 = u[2];
+    g.c = 0.f;
+    g.u0 = ux; g.u1 = uy; g.u2 = uz;
     // explicit FMAs: no contraction left to the compiler here
-    g.v0 = fmaf(u[1], o[2], -(u[2] * o[1]));
-    g.v1 = fmaf(u[2], o[0], -(u[0] * o[2]));
-    g.v2 = fmaf(u[0], o[1], -(u[1] * o[0]));
+    g.v0 = fmaf(uy, oz, -(uz * oy));
+    g.v1 = fmaf(uz, ox, -(ux * oz));
+    g.v2 = fmaf(ux, oy, -(uy * ox));
     return g;
+}
+
+// the axis of frame F: its x axis through its origin
+__device__ __forceinline__ NodeGrad node_of_frame(const Aff &F)
+{
+    return node_at(F.t0, F.t1, F.t2, F.r00, F.r10, F.r20);
 }
 
 __device__ __forceinline__ float node_torque(const NodeGrad &g, const Wrench &S)
@@ -659,30 +662,15 @@ __device__ __forceinline__ float node_torque(const NodeGrad &g, const Wrench &S)
     return fmaf(-g.v2, S.g2, t);
 }
 
-// Fold a residue's spine nodes: C's subtree in the residue is its own group
-// (with O), CA's adds C's, N's adds CA's (with the side chain).
-__device__ __forceinline__ SpineGrad spine_grad(const SpineNode &sn)
-{
-    SpineGrad sp;
-    Wrench L = sn.wC;
-    sp.cc = node_grad(L, sn.oC, sn.uC);
-    wrench_add(L, sn.wCA);
-    sp.ca = node_grad(L, sn.oCA, sn.uCA);
-    wrench_add(L, sn.wN);
-    sp.n = node_grad(L, sn.oN, sn.uN);
-    sp.W = L;
-    return sp;
-}
+__device__ __forceinline__ void node_fold(NodeGrad &g, const Wrench &w) { g.c = node_torque(g, w); }
 
 __device__ __forceinline__ void fa_store_grads(float *__restrict__ gang, int64_t R, int64_t r,
                                                const SpineGrad &sp, const Wrench &S_after,
-                                               const float (&gchi)[4], Wrench &S_out)
+                                               Wrench &S_out)
 {
     gang[R + r] = node_torque(sp.cc, S_after);
     gang[r] = node_torque(sp.ca, S_after);
     gang[2 * R + r] = node_torque(sp.n, S_after);
-#pragma unroll
-    for (int f = 0; f < 4; ++f) gang[(3 + f) * R + r] = gchi[f];
     Wrench S = S_after;
     wrench_add(S, sp.W);
     S_out = S;
@@ -704,7 +692,7 @@ __global__ __launch_bounds__(LB) void fa_backward_kernel(
     const int32_t *__restrict__ tile_res,
     const uint32_t *__restrict__ head_bits, const int32_t *__restrict__ res_aoff,
     const uint8_t *__restrict__ seq, const FATable *__restrict__ gtab, int64_t R, int64_t A,
-    BBParams P, int stage_atoms)
+    BBParams P0, int stage_atoms)
 {
     static_assert(GM == kGradLoad || RECOMPUTE, "the fused step recomputes the frames");
     extern __shared__ float stage_mem[];
@@ -725,6 +713,7 @@ __global__ __launch_bounds__(LB) void fa_backward_kernel(
     if (RECOMPUTE && nch > 1) {
         Aff carry = aff_identity();
         for (int c = 0; c < nch; ++c) {
+            const BBParams P = opaque_params(P0);
             if (threadIdx.x == 0) aff_store(fwd_carry[c], carry);
             const FAChunk k = fa_chunk<K>(ts, te, c);
             const LaneRun<K> L = lane_run<K>(k, head_bits, res_aoff);
@@ -737,6 +726,7 @@ __global__ __launch_bounds__(LB) void fa_backward_kernel(
     }
     Wrench rcarry = wrench_zero();
     for (int c = nch - 1; c >= 0; --c) {
+        const BBParams P = opaque_params(P0);
         const FAChunk k = fa_chunk<K>(ts, te, c);
         const LaneRun<K> L = lane_run<K>(k, head_bits, res_aoff);
         Aff X = aff_identity();
@@ -761,7 +751,6 @@ __global__ __launch_bounds__(LB) void fa_backward_kernel(
             pcx = xyz[ac]; pcy = xyz[A + ac]; pcz = xyz[2 * A + ac];
         }
         SpineGrad sp[K];
-        float gchi[K][4];
         Wrench agg = wrench_zero();
         bool f_end = false;
         // upstream gradient (or target) sg, coordinates sx, positions out sout
@@ -785,86 +774,110 @@ __global__ __launch_bounds__(LB) void fa_backward_kernel(
             Aff cur = X;
 #pragma unroll
             for (int j = 0; j < K; ++j) {
-                gchi[j][0] = gchi[j][1] = gchi[j][2] = gchi[j][3] = 0.f;
                 if (j < L.cnt) {
-                    SpineNode sn;
-                    sn.wN = sn.wCA = sn.wC = wrench_zero();
                     const FAType &ft = tab.t[lr.type[j]];
                     const int aloc = lr.aoff[j] - (int)L.A0;
                     const bool head = (L.hm >> j) & 1u;
-                    // side-chain frames: origin/axis per frame and own wrenches
-                    Wrench ws[A2C_MAX_SIDE_FRAMES];
-                    float so[A2C_MAX_SIDE_FRAMES][3], su[A2C_MAX_SIDE_FRAMES][3];
+                    // each group's wrench is folded into the axes that move it
+                    // (N: every group; CA: its own, the side chain, C's; C: its
+                    // own; side frame f: frames f and after) and into W
+                    SpineGrad g;
+                    NodeGrad sc[A2C_MAX_SIDE_FRAMES];
+                    Wrench w;
                     if (RECOMPUTE) {
                         if (head) cur = aff_identity();
                         aff_apply_transform(cur, P.ct[0], P.st[0], P.d[0], in[j].co, in[j].so);
-                        set_ou(sn.oN, sn.uN, cur);
-                        if (GM == kGradMse) frame_wrench_mse(tab, ft, 0, cur, sg, sout, write_so, aloc, sn.wN, loss);
-                        else frame_wrench(tab, ft, 0, cur, sg, aloc, sn.wN);
+                        g.n = node_of_frame(cur);
+                        w = wrench_zero();
+                        if (GM == kGradMse) frame_wrench_mse(tab, ft, 0, cur, sg, sout, write_so, aloc, w, loss);
+                        else frame_wrench(tab, ft, 0, cur, sg, aloc, w);
+                        node_fold(g.n, w);
+                        g.W = w;
                         aff_apply_transform(cur, P.ct[1], P.st[1], P.d[1], in[j].cp, in[j].sp);
-                        set_ou(sn.oCA, sn.uCA, cur);
-                        if (GM == kGradMse) frame_wrench_mse(tab, ft, 1, cur, sg, sout, write_so, aloc, sn.wCA, loss);
-                        else frame_wrench(tab, ft, 1, cur, sg, aloc, sn.wCA);
+                        g.ca = node_of_frame(cur);
+                        w = wrench_zero();
+                        if (GM == kGradMse) frame_wrench_mse(tab, ft, 1, cur, sg, sout, write_so, aloc, w, loss);
+                        else frame_wrench(tab, ft, 1, cur, sg, aloc, w);
+                        node_fold(g.n, w);
+                        node_fold(g.ca, w);
+                        wrench_add(g.W, w);
                         Aff sf = cur;
                         aff_rot_x(sf, ft.pre_c, ft.pre_s);
 #pragma unroll
                         for (int f = 0; f < A2C_MAX_SIDE_FRAMES; ++f) {
-                            ws[f] = wrench_zero();
                             if (f < tab.max_side && f < ft.n_side) {
                                 side_step(sf, ft, f, lr.chi[j][f]);
-                                so[f][0] = sf.t0; so[f][1] = sf.t1; so[f][2] = sf.t2;
-                                su[f][0] = sf.r00; su[f][1] = sf.r10; su[f][2] = sf.r20;
-                                if (GM == kGradMse) frame_wrench_mse(tab, ft, 3 + f, sf, sg, sout, write_so, aloc, ws[f], loss);
-                        else frame_wrench(tab, ft, 3 + f, sf, sg, aloc, ws[f]);
+                                sc[f] = node_of_frame(sf);
+                                w = wrench_zero();
+                                if (GM == kGradMse) frame_wrench_mse(tab, ft, 3 + f, sf, sg, sout, write_so, aloc, w, loss);
+                                else frame_wrench(tab, ft, 3 + f, sf, sg, aloc, w);
+#pragma unroll
+                                for (int q = 0; q <= f; ++q) node_fold(sc[q], w);
+                                node_fold(g.n, w);
+                                node_fold(g.ca, w);
+                                wrench_add(g.W, w);
                             }
                         }
                         aff_apply_transform(cur, P.ct[2], P.st[2], P.d[2], in[j].cs, in[j].ss);
-                        set_ou(sn.oC, sn.uC, cur);
-                        if (GM == kGradMse) frame_wrench_mse(tab, ft, 2, cur, sg, sout, write_so, aloc, sn.wC, loss);
-                        else frame_wrench(tab, ft, 2, cur, sg, aloc, sn.wC);
+                        g.cc = node_of_frame(cur);
+                        w = wrench_zero();
+                        if (GM == kGradMse) frame_wrench_mse(tab, ft, 2, cur, sg, sout, write_so, aloc, w, loss);
+                        else frame_wrench(tab, ft, 2, cur, sg, aloc, w);
                     } else {
                         const float *px = sx.st, *py = sx.st + sx.ns, *pz = sx.st + 2 * sx.ns;
                         const float nx = px[aloc], ny = py[aloc], nz = pz[aloc];
                         const float cax = px[aloc + 1], cay = py[aloc + 1], caz = pz[aloc + 1];
                         const float cx = px[aloc + 2], cy = py[aloc + 2], cz = pz[aloc + 2];
                         if (head) { pcx = 0.f; pcy = 0.f; pcz = 0.f; }
-                        set_ou_pts(sn.oN, sn.uN, nx, ny, nz, pcx, pcy, pcz, P.inv_d[0]);
-                        set_ou_pts(sn.oCA, sn.uCA, cax, cay, caz, nx, ny, nz, P.inv_d[1]);
-                        set_ou_pts(sn.oC, sn.uC, cx, cy, cz, cax, cay, caz, P.inv_d[2]);
-                        frame_wrench_xyz(tab, ft, 0, sg, sx, aloc, sn.wN);
-                        frame_wrench_xyz(tab, ft, 1, sg, sx, aloc, sn.wCA);
-                        frame_wrench_xyz(tab, ft, 2, sg, sx, aloc, sn.wC);
+                        g.n = node_at(nx, ny, nz, (nx - pcx) * P.inv_d[0], (ny - pcy) * P.inv_d[0],
+                                      (nz - pcz) * P.inv_d[0]);
+                        g.ca = node_at(cax, cay, caz, (cax - nx) * P.inv_d[1],
+                                       (cay - ny) * P.inv_d[1], (caz - nz) * P.inv_d[1]);
+                        g.cc = node_at(cx, cy, cz, (cx - cax) * P.inv_d[2], (cy - cay) * P.inv_d[2],
+                                       (cz - caz) * P.inv_d[2]);
+                        w = wrench_zero();
+                        frame_wrench_xyz(tab, ft, 0, sg, sx, aloc, w);
+                        node_fold(g.n, w);
+                        g.W = w;
+                        w = wrench_zero();
+                        frame_wrench_xyz(tab, ft, 1, sg, sx, aloc, w);
+                        node_fold(g.n, w);
+                        node_fold(g.ca, w);
+                        wrench_add(g.W, w);
                         float ppx = cax, ppy = cay, ppz = caz;
 #pragma unroll
                         for (int f = 0; f < A2C_MAX_SIDE_FRAMES; ++f) {
-                            ws[f] = wrench_zero();
                             if (f < tab.max_side && f < ft.n_side) {
                                 const int eo = aloc + ft.origin_slot[3 + f];
                                 const float ox = px[eo], oy = py[eo], oz = pz[eo];
-                                so[f][0] = ox; so[f][1] = oy; so[f][2] = oz;
-                                su[f][0] = (ox - ppx) * ft.inv_d[f];
-                                su[f][1] = (oy - ppy) * ft.inv_d[f];
-                                su[f][2] = (oz - ppz) * ft.inv_d[f];
+                                sc[f] = node_at(ox, oy, oz, (ox - ppx) * ft.inv_d[f],
+                                                (oy - ppy) * ft.inv_d[f], (oz - ppz) * ft.inv_d[f]);
                                 ppx = ox; ppy = oy; ppz = oz;
-                                frame_wrench_xyz(tab, ft, 3 + f, sg, sx, aloc, ws[f]);
+                                w = wrench_zero();
+                                frame_wrench_xyz(tab, ft, 3 + f, sg, sx, aloc, w);
+#pragma unroll
+                                for (int q = 0; q <= f; ++q) node_fold(sc[q], w);
+                                node_fold(g.n, w);
+                                node_fold(g.ca, w);
+                                wrench_add(g.W, w);
                             }
                         }
+                        w = wrench_zero();
+                        frame_wrench_xyz(tab, ft, 2, sg, sx, aloc, w);
                         pcx = cx; pcy = cy; pcz = cz;
                     }
-                    // chi gradients: side frames form a chain, subtree = suffix
-                    Wrench Ss = wrench_zero();
+                    // the C group (with O)
+                    node_fold(g.n, w);
+                    node_fold(g.ca, w);
+                    node_fold(g.cc, w);
+                    wrench_add(g.W, w);
+                    // chi gradients are complete here (their subtrees end in the residue)
 #pragma unroll
-                    for (int f = A2C_MAX_SIDE_FRAMES - 1; f >= 0; --f) {
-                        if (f < tab.max_side && f < ft.n_side) {
-                            wrench_add(Ss, ws[f]);
-                            if (ft.side_chi[f])
-                                gchi[j][f] = wrench_torque(Ss, so[f][0], so[f][1], so[f][2],
-                                                           su[f][0], su[f][1], su[f][2]);
-                        }
-                    }
-                    wrench_add(sn.wCA, Ss);
-                    sp[j] = spine_grad(sn);
-                    if (!f_end) wrench_add(agg, sp[j].W);
+                    for (int f = 0; f < A2C_MAX_SIDE_FRAMES; ++f)
+                        gang[(3 + f) * R + L.rs + j] =
+                            (f < tab.max_side && f < ft.n_side && ft.side_chi[f]) ? sc[f].c : 0.f;
+                    sp[j] = g;
+                    if (!f_end) wrench_add(agg, g.W);
                     if ((L.lm >> j) & 1u) f_end = true;
                 }
             }
@@ -880,7 +893,7 @@ __global__ __launch_bounds__(LB) void fa_backward_kernel(
         for (int j = K - 1; j >= 0; --j) {
             if (j < L.cnt) {
                 if ((L.lm >> j) & 1u) S = wrench_zero();
-                fa_store_grads(gang, R, L.rs + j, sp[j], S, gchi[j], S);
+                fa_store_grads(gang, R, L.rs + j, sp[j], S, S);
             }
         }
     }

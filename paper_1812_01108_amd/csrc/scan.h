@@ -169,6 +169,16 @@ __device__ __forceinline__ Aff aff_seg_after(const Aff &carry, const Aff &t, boo
     return aff_select(t_head, t, c);
 }
 
+// The lane index made opaque to the optimiser, so address arithmetic
+// derived from it is recomputed where it is used instead of being hoisted out
+// of the chunk loop and held live in registers across it.
+__device__ __forceinline__ int lane_id()
+{
+    int l = threadIdx.x & 63;
+    asm volatile("" : "+v"(l));
+    return l;
+}
+
 // Lanes at or below `lane` (bit l set for l <= lane) and strictly below it.
 __device__ __forceinline__ uint64_t lanes_upto(int lane) { return ~0ull >> (63 - lane); }
 __device__ __forceinline__ uint64_t lanes_below(int lane)
@@ -220,7 +230,7 @@ __device__ __forceinline__ void aff_scan_step(Aff &m, bool take)
 template <bool ROW0>
 __device__ __forceinline__ void aff_wave_scan(Aff &m, uint64_t heads, int n)
 {
-    const int lane = threadIdx.x & 63;
+    const int lane = lane_id();
     const int s = last_head_upto(heads, lane);
     const int row = lane & ~15;
     const int dist = lane - max(s, row);   // lanes of l's segment before l, in its row
@@ -254,7 +264,7 @@ template <bool MULTI>
 __device__ __forceinline__ Aff block_exclusive_prefix(Aff m, bool f, int nact, FwdShared &sh,
                                                       Aff &carry)
 {
-    const int lane = threadIdx.x & 63;
+    const int lane = lane_id();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const bool wave_active = wave < nact;
     const uint64_t heads = __builtin_amdgcn_ballot_w64(f);
@@ -344,7 +354,7 @@ __device__ __forceinline__ void wrench_add_if(Wrench &w, const Wrench &o, bool t
 template <bool ROW0>
 __device__ __forceinline__ void wrench_wave_rscan(Wrench &w, uint64_t ends, int n)
 {
-    const int lane = threadIdx.x & 63;
+    const int lane = lane_id();
     const int e = first_end_from(ends, lane);
     const int dist = min(e, lane | 15) - lane;
     if (!ROW0 || n > 1) wrench_add_if(w, wrench_dpp_z<kDppRowShl + 1>(w), dist >= 1);
@@ -393,7 +403,7 @@ template <bool MULTI>
 __device__ __forceinline__ Wrench block_exclusive_suffix(Wrench agg, bool f, int nact,
                                                          BwdShared &sh, Wrench &carry)
 {
-    const int lane = threadIdx.x & 63;
+    const int lane = lane_id();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const bool wave_active = wave < nact;
     const uint64_t ends = __builtin_amdgcn_ballot_w64(f);
@@ -456,15 +466,6 @@ struct Stride {
     static constexpr int value = (N & 1) ? N : N + 1;
 };
 
-// The lane index made opaque to the optimiser, so address arithmetic
-// derived from it is recomputed where it is used instead of being hoisted out
-// of the chunk loop and held live in registers across it.
-__device__ __forceinline__ int lane_id()
-{
-    int l = threadIdx.x & 63;
-    asm volatile("" : "+v"(l));
-    return l;
-}
 
 __device__ __forceinline__ void wave_lds_sync()
 {
