@@ -5,7 +5,9 @@ angle gradient for a fixed upstream gradient, through the torch.autograd
 Function.  Steps are captured in HIP graphs, --steps-per-graph complete
 steps per graph (one graph launch costs the host more than one step takes
 on the GPU); every timed step runs the whole path.  Inputs are resident in
-HBM before timing starts.  Prints one JSON line.
+HBM before timing starts.  Prints one JSON line; besides the (warm) timed
+steps it carries "cold", the median step time with a 512 MiB device write
+before each step, so that no input or output is left in the caches.
 
 Default workload: 256 chains x 700 residues, backbone, Ramachandran-like
 mixture angles, omega = pi, upstream gradient iid N(0,1).
@@ -134,6 +136,35 @@ def time_graph(graphs, steps, warmup):
     _run_steps(graphs, steps)
     torch.cuda.synchronize()
     return time.perf_counter() - t0
+
+
+def time_cold(g1, R, reps=20, flush_bytes=512 << 20):
+    """Cold-cache step time: before every step a 512 MiB write (twice the
+    256 MiB Infinity Cache) evicts the step's data; HIP events on the
+    stream bracket the step alone (one step per graph launch).  Median over
+    `reps`; the same protocol without the write is reported beside it."""
+    import torch
+
+    buf = torch.empty(flush_bytes // 4, dtype=torch.float32, device="cuda")
+    st = torch.cuda.current_stream()
+
+    def one(flush, i):
+        if flush:
+            buf.fill_(float(i))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        g1.replay()
+        e1.record(st)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / 1000.0
+
+    cold = [one(True, i) for i in range(reps + 2)][2:]
+    warm = [one(False, i) for i in range(reps + 2)][2:]
+    del buf
+    t, w = float(np.median(cold)), float(np.median(warm))
+    return {"value": R / t, "ms_per_step": t * 1000.0, "reps": reps,
+            "flush": "512 MiB device write before each step",
+            "warm_same_protocol_ms_per_step": w * 1000.0}
 
 
 def kernel_avg_us(launch, reps):
@@ -332,6 +363,7 @@ def main():
     dt = time_graph((gn, g1), args.steps, args.warmup)
     ms = dt * 1000.0 / args.steps
     value = R * args.steps / dt
+    cold = time_cold(g1, R)
     gpu_coords = outs[0].detach().cpu().numpy()
     gpu_grad = outs[1].detach().cpu().numpy()
     lr_info = None
@@ -434,6 +466,7 @@ def main():
         "lrmsd": lr_info,
         "plain_gpu": plain,
         "speedup_vs_plain": (value / plain["value"]) if plain else None,
+        "cold": cold,
         "cpu_baseline": cpu,
         "parity": parity,
     }
