@@ -227,7 +227,7 @@ __device__ __forceinline__ void load_angles(float *buf, const float *__restrict_
 template <int K, bool MULTI, int LB>
 __global__ __launch_bounds__(LB) void bb_forward_scan_kernel(
     const float *__restrict__ ang, float *__restrict__ xyz, const int32_t *__restrict__ tile_res,
-    const uint32_t *__restrict__ head_bits, int64_t R, BBParams P)
+    const uint32_t *__restrict__ head_bits, int64_t R, BBParams P0)
 {
     extern __shared__ float stage_mem[];
     __shared__ FwdShared sh[2];
@@ -239,6 +239,7 @@ __global__ __launch_bounds__(LB) void bb_forward_scan_kernel(
     const int nch = MULTI ? chunks_of<K>(ts, te) : 1;
     Aff carry = aff_identity();
     for (int c = 0; c < nch; ++c) {
+        const BBParams P = MULTI ? opaque_params(P0) : P0;
         const Chunk k = chunk_of<K>(ts, te, c);
         const int64_t rbase = k.cs + (int64_t)wave * kWave * K;
         const bool active = wave < k.nact;
@@ -277,7 +278,7 @@ __global__ __launch_bounds__(LB) void bb_backward_recompute_kernel(
     const float *__restrict__ ang, const float *__restrict__ g, float *__restrict__ gang,
     float *__restrict__ xyz_out, float *__restrict__ loss_part,
     const int32_t *__restrict__ tile_res, const uint32_t *__restrict__ head_bits, int64_t R,
-    BBParams P)
+    BBParams P0)
 {
     extern __shared__ float stage_mem[];
     __shared__ FwdShared shf[2];
@@ -294,6 +295,7 @@ __global__ __launch_bounds__(LB) void bb_backward_recompute_kernel(
     if (nch > 1) {
         Aff carry = aff_identity();
         for (int c = 0; c < nch; ++c) {
+            const BBParams P = MULTI ? opaque_params(P0) : P0;
             if (threadIdx.x == 0) aff_store(fwd_carry[c], carry);
             const Chunk k = chunk_of<K>(ts, te, c);
             const int64_t rbase = k.cs + (int64_t)wave * kWave * K;
@@ -312,6 +314,7 @@ __global__ __launch_bounds__(LB) void bb_backward_recompute_kernel(
     }
     Wrench rcarry = wrench_zero();
     for (int c = nch - 1; c >= 0; --c) {
+        const BBParams P = MULTI ? opaque_params(P0) : P0;
         const Chunk k = chunk_of<K>(ts, te, c);
         const int64_t rbase = k.cs + (int64_t)wave * kWave * K;
         const bool active = wave < k.nact;
@@ -381,7 +384,7 @@ template <int K, bool MULTI, int LB>
 __global__ __launch_bounds__(LB) void bb_backward_coords_kernel(
     const float *__restrict__ xyz, const float *__restrict__ g, float *__restrict__ gang,
     const int32_t *__restrict__ tile_res, const uint32_t *__restrict__ head_bits, int64_t R,
-    BBParams P)
+    BBParams P0)
 {
     extern __shared__ float stage_mem[];
     __shared__ BwdShared shb[2];
@@ -394,6 +397,7 @@ __global__ __launch_bounds__(LB) void bb_backward_coords_kernel(
     const int nch = MULTI ? chunks_of<K>(ts, te) : 1;
     Wrench rcarry = wrench_zero();
     for (int c = nch - 1; c >= 0; --c) {
+        const BBParams P = MULTI ? opaque_params(P0) : P0;
         const Chunk k = chunk_of<K>(ts, te, c);
         const int64_t rbase = k.cs + (int64_t)wave * kWave * K;
         const bool active = wave < k.nact;

@@ -527,18 +527,6 @@ __device__ __forceinline__ LaneRes<K, CHI> load_lane_res(const LaneRun<K> &L,
     return lr;
 }
 
-// The spine constants made opaque to the optimiser at the top of a loop over
-// chunks: products of them (the first transforms of a chain head, say) are
-// then formed where they are used instead of being hoisted out of the loop,
-// where these uniform values would each hold a vector register across it.
-__device__ __forceinline__ BBParams opaque_params(BBParams P)
-{
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-        asm volatile("" : "+s"(P.ct[i]), "+s"(P.st[i]), "+s"(P.d[i]), "+s"(P.inv_d[i]));
-    return P;
-}
-
 // All atoms of one residue from the frame before it (cur, advanced to the
 // residue's C frame): spine transforms omega, phi, psi, and the side chain
 // branching off the CA frame, each frame's atoms written to the stage.
@@ -586,7 +574,7 @@ __global__ __launch_bounds__(LB) void fa_forward_kernel(
     Aff carry = aff_identity();
     for (int c = 0; c < nch; ++c) {
         // the same arithmetic as the adjoint kernels' recomputation
-        const BBParams P = opaque_params(P0);
+        const BBParams P = MULTI ? opaque_params(P0) : P0;
         const FAChunk k = fa_chunk<K>(ts, te, c);
         const LaneRun<K> L = lane_run<K>(k, head_bits, res_aoff);
         ResidueIn in[K];
@@ -713,7 +701,7 @@ __global__ __launch_bounds__(LB) void fa_backward_kernel(
     if (RECOMPUTE && nch > 1) {
         Aff carry = aff_identity();
         for (int c = 0; c < nch; ++c) {
-            const BBParams P = opaque_params(P0);
+            const BBParams P = MULTI ? opaque_params(P0) : P0;
             if (threadIdx.x == 0) aff_store(fwd_carry[c], carry);
             const FAChunk k = fa_chunk<K>(ts, te, c);
             const LaneRun<K> L = lane_run<K>(k, head_bits, res_aoff);
@@ -726,7 +714,7 @@ __global__ __launch_bounds__(LB) void fa_backward_kernel(
     }
     Wrench rcarry = wrench_zero();
     for (int c = nch - 1; c >= 0; --c) {
-        const BBParams P = opaque_params(P0);
+        const BBParams P = MULTI ? opaque_params(P0) : P0;
         const FAChunk k = fa_chunk<K>(ts, te, c);
         const LaneRun<K> L = lane_run<K>(k, head_bits, res_aoff);
         Aff X = aff_identity();

@@ -179,6 +179,18 @@ __device__ __forceinline__ int lane_id()
     return l;
 }
 
+// The backbone constants made opaque to the optimiser at the top of a loop over
+// chunks: products of them (the first transforms of a chain head, say) are
+// then formed where they are used instead of being hoisted out of the loop,
+// where these uniform values would each hold a vector register across it.
+__device__ __forceinline__ BBParams opaque_params(BBParams P)
+{
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+        asm volatile("" : "+s"(P.ct[i]), "+s"(P.st[i]), "+s"(P.d[i]), "+s"(P.inv_d[i]));
+    return P;
+}
+
 // Lanes at or below `lane` (bit l set for l <= lane) and strictly below it.
 __device__ __forceinline__ uint64_t lanes_upto(int lane) { return ~0ull >> (63 - lane); }
 __device__ __forceinline__ uint64_t lanes_below(int lane)
@@ -228,9 +240,8 @@ __device__ __forceinline__ void aff_scan_step(Aff &m, bool take)
 // same segment, i.e. when l - d >= s_l, the last head at or below l; the row
 // steps (d = 1, 2, 4, 8 inside rows of 16 lanes) also need l - d in l's row.
 template <bool ROW0>
-__device__ __forceinline__ void aff_wave_scan(Aff &m, uint64_t heads, int n)
+__device__ __forceinline__ void aff_wave_scan(Aff &m, uint64_t heads, int n, int lane)
 {
-    const int lane = lane_id();
     const int s = last_head_upto(heads, lane);
     const int row = lane & ~15;
     const int dist = lane - max(s, row);   // lanes of l's segment before l, in its row
@@ -264,12 +275,13 @@ template <bool MULTI>
 __device__ __forceinline__ Aff block_exclusive_prefix(Aff m, bool f, int nact, FwdShared &sh,
                                                       Aff &carry)
 {
-    const int lane = lane_id();
+    // opaque inside chunk loops (MULTI), so lane masks are not hoisted out
+    const int lane = MULTI ? lane_id() : (int)(threadIdx.x & 63);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const bool wave_active = wave < nact;
     const uint64_t heads = __builtin_amdgcn_ballot_w64(f);
     if (wave_active) {
-        aff_wave_scan<false>(m, heads, kWave);
+        aff_wave_scan<false>(m, heads, kWave, lane);
         if (lane == kWave - 1) {
             aff_store(sh.tot[wave], m);
             sh.tot_flag[wave] = heads != 0ull ? 1 : 0;
@@ -286,7 +298,7 @@ __device__ __forceinline__ Aff block_exclusive_prefix(Aff m, bool f, int nact, F
                 tf = sh.tot_flag[lane] != 0;
             }
             const uint64_t th = __builtin_amdgcn_ballot_w64(tf);
-            aff_wave_scan<true>(t, th, nact);
+            aff_wave_scan<true>(t, th, nact, lane);
             if (lane < nact) {
                 aff_store(sh.pre[lane], t);
                 sh.pre_flag[lane] = (th & lanes_upto(lane)) != 0ull ? 1 : 0;
@@ -352,9 +364,8 @@ __device__ __forceinline__ void wrench_add_if(Wrench &w, const Wrench &o, bool t
 // segment closes in lanes l .. l+d-1, i.e. when l + d <= e_l, the first end
 // at or after l; the row steps also need l + d in l's row.
 template <bool ROW0>
-__device__ __forceinline__ void wrench_wave_rscan(Wrench &w, uint64_t ends, int n)
+__device__ __forceinline__ void wrench_wave_rscan(Wrench &w, uint64_t ends, int n, int lane)
 {
-    const int lane = lane_id();
     const int e = first_end_from(ends, lane);
     const int dist = min(e, lane | 15) - lane;
     if (!ROW0 || n > 1) wrench_add_if(w, wrench_dpp_z<kDppRowShl + 1>(w), dist >= 1);
@@ -403,12 +414,13 @@ template <bool MULTI>
 __device__ __forceinline__ Wrench block_exclusive_suffix(Wrench agg, bool f, int nact,
                                                          BwdShared &sh, Wrench &carry)
 {
-    const int lane = lane_id();
+    // opaque inside chunk loops (MULTI), so lane masks are not hoisted out
+    const int lane = MULTI ? lane_id() : (int)(threadIdx.x & 63);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const bool wave_active = wave < nact;
     const uint64_t ends = __builtin_amdgcn_ballot_w64(f);
     if (wave_active) {
-        wrench_wave_rscan<false>(agg, ends, kWave);
+        wrench_wave_rscan<false>(agg, ends, kWave, lane);
         if (lane == 0) {
             wrench_store(sh.tot[wave], agg);
             sh.tot_flag[wave] = ends != 0ull ? 1 : 0;
@@ -425,7 +437,7 @@ __device__ __forceinline__ Wrench block_exclusive_suffix(Wrench agg, bool f, int
                 tf = sh.tot_flag[lane] != 0;
             }
             const uint64_t th = __builtin_amdgcn_ballot_w64(tf);
-            wrench_wave_rscan<true>(t, th, nact);
+            wrench_wave_rscan<true>(t, th, nact, lane);
             if (lane < nact) {
                 wrench_store(sh.suf[lane], t);
                 sh.suf_flag[lane] = (th & (~0ull << lane)) != 0ull ? 1 : 0;
