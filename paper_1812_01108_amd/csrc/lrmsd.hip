@@ -243,6 +243,15 @@ __global__ __launch_bounds__(kLrThreads) void lr_solve_kernel(
     const int c = blockIdx.x * (kLrThreads / 64) + (threadIdx.x >> 6);
     if (c >= n_chains) return;  // whole waves leave together
     const int s0 = chain_seg[c], s1 = chain_seg[c + 1];
+    // the chain's first atom and size, read now so that their latency
+    // overlaps the sums below (lane 0 uses them at the end)
+    const int r0 = s1 > s0 ? seg_atom[s0] : 0;
+    const int64_t n_atoms = s1 > s0 ? (int64_t)seg_atom[s1] - r0 : 0;
+    float x0[3] = {0.f, 0.f, 0.f}, y0[3] = {0.f, 0.f, 0.f};
+    if (lane == 0 && n_atoms > 0) {
+        x0[0] = x[r0]; x0[1] = x[A + r0]; x0[2] = x[2 * A + r0];
+        y0[0] = y[r0]; y0[1] = y[A + r0]; y0[2] = y[2 * A + r0];
+    }
     double acc[17];
 #pragma unroll
     for (int k = 0; k < 17; ++k) acc[k] = 0.0;
@@ -254,17 +263,15 @@ __global__ __launch_bounds__(kLrThreads) void lr_solve_kernel(
     for (int k = 0; k < 17; ++k) acc[k] = wave_sum_f64(acc[k]);
     if (lane != 0) return;
     float *st = state + (size_t)c * kLrState;
-    const int64_t n_atoms = s1 > s0 ? (int64_t)seg_atom[s1] - seg_atom[s0] : 0;
     if (n_atoms == 0) {
         for (int k = 0; k < kLrState; ++k) st[k] = 0.f;
         st[0] = st[4] = st[8] = 1.f;
         out[c] = 0.f;
         return;
     }
-    const double N = (double)n_atoms;
-    const int r0 = seg_atom[s0];
-    const double mx[3] = {acc[0] / N, acc[1] / N, acc[2] / N};
-    const double my[3] = {acc[3] / N, acc[4] / N, acc[5] / N};
+    const double N = (double)n_atoms, inv_N = 1.0 / N;
+    const double mx[3] = {acc[0] * inv_N, acc[1] * inv_N, acc[2] * inv_N};
+    const double my[3] = {acc[3] * inv_N, acc[4] * inv_N, acc[5] * inv_N};
     const double gx = acc[6] - N * (mx[0] * mx[0] + mx[1] * mx[1] + mx[2] * mx[2]);
     const double gy = acc[7] - N * (my[0] * my[0] + my[1] * my[1] + my[2] * my[2]);
     double R[3][3];
@@ -296,9 +303,13 @@ __global__ __launch_bounds__(kLrThreads) void lr_solve_kernel(
         tr2 += T2[i][i];
         for (int k = 0; k < 4; ++k) tr3 += T2[i][k] * T[k][i];
     }
-    const double c2 = -0.5 * tr2, c1 = -tr3 / 3.0, c0 = det4(T);
+    const double c2 = -0.5 * tr2, c1 = tr3 * (-1.0 / 3.0), c0 = det4(T);
     const double G = gx + gy;
-    double lam = 0.5 * G;
+    // start above the largest root, where Newton descends monotonically:
+    // lambda_max <= G / 2 (LRMSD^2 >= 0), and for a traceless symmetric 4x4
+    // lambda_max <= sqrt(3/4 tr(T^2)) (the other three eigenvalues sum to
+    // -lambda_max, so their squares sum to at least lambda_max^2 / 3)
+    double lam = fmin(0.5 * G, sqrt(0.75 * tr2));
     for (int it = 0; it < 100; ++it) {
         const double l2 = lam * lam;
         const double P = (l2 + c2) * l2 + c1 * lam + c0;
@@ -345,12 +356,12 @@ __global__ __launch_bounds__(kLrThreads) void lr_solve_kernel(
     st[6] = (float)(2.0 * (q1 * q3 - q0 * q2));
     st[7] = (float)(2.0 * (q2 * q3 + q0 * q1));
     st[8] = (float)(q0 * q0 - q1 * q1 - q2 * q2 + q3 * q3);
-    st[9] = (float)(x[r0] + mx[0]);
-    st[10] = (float)(x[A + r0] + mx[1]);
-    st[11] = (float)(x[2 * A + r0] + mx[2]);
-    st[12] = (float)(y[r0] + my[0]);
-    st[13] = (float)(y[A + r0] + my[1]);
-    st[14] = (float)(y[2 * A + r0] + my[2]);
+    st[9] = (float)(x0[0] + mx[0]);
+    st[10] = (float)(x0[1] + mx[1]);
+    st[11] = (float)(x0[2] + mx[2]);
+    st[12] = (float)(y0[0] + my[0]);
+    st[13] = (float)(y0[1] + my[1]);
+    st[14] = (float)(y0[2] + my[2]);
     const double l = sqrt(fmax(G - 2.0 * lam, 0.0) / N);
     st[15] = l > 0.0 ? (float)(1.0 / (N * l)) : 0.f;
     out[c] = (float)l;
