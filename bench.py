@@ -349,13 +349,8 @@ def main():
         fused_tiles = torch.zeros(max(plan.schedule["n_tiles"], 1), device=dev)
 
         def step():
-            a2c._lib.check(a2c._lib.load().a2c_mse_step(
-                plan._h, a2c.ctypes.c_void_p(angles.data_ptr()),
-                a2c.ctypes.c_void_p(target.data_ptr()),
-                a2c.ctypes.c_void_p(fused_xyz.data_ptr()),
-                a2c.ctypes.c_void_p(fused_tiles.data_ptr()),
-                a2c.ctypes.c_void_p(fused_grad.data_ptr()),
-                a2c._stream_ptr(dev)), "a2c_mse_step")
+            plan.mse_step(angles, target, coords=fused_xyz, grad_angles=fused_grad,
+                          loss_tiles=fused_tiles)
             return fused_xyz, fused_grad
     else:
         step = make_step(a2c, plan, angles, grad_up, mode, target, loss or "mse")

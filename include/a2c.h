@@ -22,10 +22,12 @@
  *     buffer.  The library owns only the plan and the device copies of the
  *     plan's tables, freed by a2c_plan_destroy.
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
- *     a2c_forward and a2c_backward only enqueue kernels on it: they never
- *     allocate, never synchronise and never read device memory on the host,
- *     so they may be captured in a hipGraph.  Plan creation, schedule changes
- *     and autotuning upload tables and synchronise: not capturable.
+ *     a2c_forward, a2c_backward, a2c_mse_step, a2c_lrmsd_forward,
+ *     a2c_lrmsd_backward and a2c_coords_to_angles only enqueue kernels on
+ *     it: they never allocate, never synchronise and never read device
+ *     memory on the host, so they may be captured in a hipGraph (replays
+ *     reproduce the eager results bit for bit).  Plan creation, schedule
+ *     changes and autotuning upload tables and synchronise: not capturable.
  *   - Angles are radians, any range; NaN/Inf propagate unchecked.  Planes:
  *       0 phi, 1 psi, 2 omega, 3 chi1, 4 chi2, 5 chi3, 6 chi4.
  *     Layout [K][R] float32, K = 3 (backbone) or 7 (full-atom), R = total
