@@ -509,6 +509,10 @@ __device__ __forceinline__ void to_blocked(float *buf, const float (&v)[N], int 
 {
     constexpr int S = Stride<N>::value;
     const int lane = lane_id();
+    if constexpr (N == 1) {  // the run is already in lane order
+        out[0] = lane < n ? v[0] : 0.f;
+        return;
+    }
 #pragma unroll
     for (int m = 0; m < N; ++m) {
         const int e = lane + 64 * m;
@@ -528,6 +532,10 @@ __device__ __forceinline__ void stage_store(float *buf, const float (&in)[N], fl
 {
     constexpr int S = Stride<N>::value;
     const int lane = lane_id();
+    if constexpr (N == 1) {  // lane order is already the run's order
+        if (lane < n) base[lane] = in[0];
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < N; ++i) buf[lane * S + i] = in[i];
     wave_lds_sync();
