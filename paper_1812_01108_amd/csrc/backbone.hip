@@ -248,7 +248,7 @@ __global__ __launch_bounds__(LB) void bb_forward_scan_kernel(
         const int cnt = (int)max((int64_t)0, min((int64_t)K, k.ce - rs));
         // chain-head bits before the angle loads: the LDS transposes below
         // are fenced, and a load issued after them would wait for the angles
-        const uint32_t hm = cnt > 0 ? head_mask<K>(head_bits, rs) : 0u;
+        const uint32_t hm = lane_head_mask<K>(head_bits, rs, k.ce, cnt);
         float phi[K], psi[K], om[K];
         if (active) load_angles<K>(buf, ang, R, rbase, nres, phi, psi, om);
         float x[3 * K], y[3 * K], z[3 * K];
@@ -303,7 +303,7 @@ __global__ __launch_bounds__(LB) void bb_backward_recompute_kernel(
             const int nres = active ? (int)min((int64_t)kWave * K, k.ce - rbase) : 0;
             const int64_t rs = k.cs + (int64_t)threadIdx.x * K;
             const int cnt = (int)max((int64_t)0, min((int64_t)K, k.ce - rs));
-            const uint32_t hm = cnt > 0 ? head_mask<K>(head_bits, rs) : 0u;
+            const uint32_t hm = lane_head_mask<K>(head_bits, rs, k.ce, cnt);
             float phi[K], psi[K], om[K];
             if (active) load_angles<K>(buf, ang, R, rbase, nres, phi, psi, om);
             float x[3 * K], y[3 * K], z[3 * K];
@@ -321,8 +321,8 @@ __global__ __launch_bounds__(LB) void bb_backward_recompute_kernel(
         const int nres = active ? (int)min((int64_t)kWave * K, k.ce - rbase) : 0;
         const int64_t rs = k.cs + (int64_t)threadIdx.x * K;
         const int cnt = (int)max((int64_t)0, min((int64_t)K, k.ce - rs));
-        const uint32_t hm = cnt > 0 ? head_mask<K>(head_bits, rs) : 0u;
-        const uint32_t lm = cnt > 0 ? head_mask<K>(head_bits, rs + 1) : 0u;
+        const uint32_t hm = lane_head_mask<K>(head_bits, rs, k.ce, cnt);
+        const uint32_t lm = lane_head_mask<K>(head_bits, rs + 1, k.ce + 1, cnt);
         float phi[K], psi[K], om[K];
         float gx[3 * K], gy[3 * K], gz[3 * K];
         if (active) {
@@ -405,8 +405,8 @@ __global__ __launch_bounds__(LB) void bb_backward_coords_kernel(
         const int64_t rs = k.cs + (int64_t)tid * K;
         const int cnt = (int)max((int64_t)0, min((int64_t)K, k.ce - rs));
         float x[3 * K], y[3 * K], z[3 * K], gx[3 * K], gy[3 * K], gz[3 * K];
-        const uint32_t hm = cnt > 0 ? head_mask<K>(head_bits, rs) : 0u;
-        const uint32_t lm = cnt > 0 ? head_mask<K>(head_bits, rs + 1) : 0u;
+        const uint32_t hm = lane_head_mask<K>(head_bits, rs, k.ce, cnt);
+        const uint32_t lm = lane_head_mask<K>(head_bits, rs + 1, k.ce + 1, cnt);
         // the atom before lane 0 of the wave (read before the fenced transposes)
         float px0 = 0.f, py0 = 0.f, pz0 = 0.f;
         if (lane == 0 && cnt > 0 && !(hm & 1u)) {

@@ -378,25 +378,42 @@ struct ResidueIn {
     float co, so, cp, sp, cs, ss;  // cos/sin of omega, phi, psi
 };
 
+// Spine angles (phi, psi, omega) of a lane's K residues, 0 past the chunk.
+template <int K>
+struct SpineAngles {
+    float phi[K], psi[K], om[K];
+};
+
+template <int K>
+__device__ __forceinline__ SpineAngles<K> load_spine_angles(const float *__restrict__ ang,
+                                                            int64_t R, int64_t rs, int cnt)
+{
+    SpineAngles<K> a;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        a.phi[j] = j < cnt ? ang[rs + j] : 0.f;
+        a.psi[j] = j < cnt ? ang[R + rs + j] : 0.f;
+        a.om[j] = j < cnt ? ang[2 * R + rs + j] : 0.f;
+    }
+    return a;
+}
+
 // Lane-serial spine aggregate of K residues (reset at chain heads), with one
 // polar step; keeps the spine cos/sin per residue for the re-walk.
 template <int K>
-__device__ __forceinline__ Aff fa_lane_aggregate(const float *__restrict__ ang, int64_t R,
-                                                 int64_t rs, int cnt, uint32_t hm,
+__device__ __forceinline__ Aff fa_lane_aggregate(const SpineAngles<K> &a, int cnt, uint32_t hm,
                                                  const BBParams &P, ResidueIn (&in)[K],
                                                  int &first_head)
 {
     Aff m = aff_identity();
     first_head = K;
-    float phi[K], psi[K], om[K];
+    const float(&phi)[K] = a.phi;
+    const float(&psi)[K] = a.psi;
+    const float(&om)[K] = a.om;
     bool ok = true;
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
-        phi[j] = j < cnt ? ang[rs + j] : 0.f;
-        psi[j] = j < cnt ? ang[R + rs + j] : 0.f;
-        om[j] = j < cnt ? ang[2 * R + rs + j] : 0.f;
+    for (int j = 0; j < K; ++j)
         ok = ok && sincos_fast_ok(om[j]) && sincos_fast_ok(phi[j]) && sincos_fast_ok(psi[j]);
-    }
     if (__all(ok)) {
 #pragma unroll
         for (int j = 0; j < K; ++j) {
@@ -426,6 +443,16 @@ __device__ __forceinline__ Aff fa_lane_aggregate(const float *__restrict__ ang, 
     }
     aff_orthonormalise(m);
     return m;
+}
+
+template <int K>
+__device__ __forceinline__ Aff fa_lane_aggregate(const float *__restrict__ ang, int64_t R,
+                                                 int64_t rs, int cnt, uint32_t hm,
+                                                 const BBParams &P, ResidueIn (&in)[K],
+                                                 int &first_head)
+{
+    return fa_lane_aggregate<K>(load_spine_angles<K>(ang, R, rs, cnt), cnt, hm, P, in,
+                                first_head);
 }
 
 __device__ __forceinline__ void side_step(Aff &sf, const FAType &ft, int f, float chi)
@@ -484,8 +511,8 @@ __device__ __forceinline__ LaneRun<K> lane_run(const FAChunk &k,
     L.nres = L.active ? (int)min((int64_t)kWave * K, k.ce - L.rbase) : 0;
     L.rs = k.cs + (int64_t)threadIdx.x * K;
     L.cnt = (int)max((int64_t)0, min((int64_t)K, k.ce - L.rs));
-    L.hm = L.cnt > 0 ? head_mask<K>(head_bits, L.rs) : 0u;
-    L.lm = L.cnt > 0 ? head_mask<K>(head_bits, L.rs + 1) : 0u;
+    L.hm = lane_head_mask<K>(head_bits, L.rs, k.ce, L.cnt);
+    L.lm = lane_head_mask<K>(head_bits, L.rs + 1, k.ce + 1, L.cnt);
     L.A0 = 0;
     L.natoms = 0;
     if (L.active) {
@@ -566,6 +593,18 @@ __global__ __launch_bounds__(LB) void fa_forward_kernel(
     __shared__ __align__(16) FATable tab;
     __shared__ FwdShared sh[2];
     const int64_t ts = tile_res[2 * blockIdx.x], te = tile_res[2 * blockIdx.x + 1];
+    // one-chunk tiles read the chunk's inputs before the table copy, so that
+    // the two latencies overlap (the copy ends in a workgroup barrier)
+    FAChunk k0{};
+    LaneRun<K> L0{};
+    SpineAngles<K> a0{};
+    LaneRes<K, true> lr0{};
+    if (!MULTI) {
+        k0 = fa_chunk<K>(ts, te, 0);
+        L0 = lane_run<K>(k0, head_bits, res_aoff);
+        if (L0.active) a0 = load_spine_angles<K>(ang, R, L0.rs, L0.cnt);
+        lr0 = load_lane_res<K, true>(L0, seq, res_aoff, ang, R);
+    }
     load_table(tab, gtab);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const Stage lds{stage_mem + (size_t)wave * 3 * stage_atoms, stage_atoms};
@@ -575,14 +614,16 @@ __global__ __launch_bounds__(LB) void fa_forward_kernel(
     for (int c = 0; c < nch; ++c) {
         // the same arithmetic as the adjoint kernels' recomputation
         const BBParams P = MULTI ? opaque_params(P0) : P0;
-        const FAChunk k = fa_chunk<K>(ts, te, c);
-        const LaneRun<K> L = lane_run<K>(k, head_bits, res_aoff);
+        const FAChunk k = MULTI ? fa_chunk<K>(ts, te, c) : k0;
+        const LaneRun<K> L = MULTI ? lane_run<K>(k, head_bits, res_aoff) : L0;
         ResidueIn in[K];
         int first_head = K;
         Aff m = aff_identity();
-        if (L.active) m = fa_lane_aggregate<K>(ang, R, L.rs, L.cnt, L.hm, P, in, first_head);
+        if (L.active)
+            m = fa_lane_aggregate<K>(MULTI ? load_spine_angles<K>(ang, R, L.rs, L.cnt) : a0,
+                                     L.cnt, L.hm, P, in, first_head);
         // issued after the spine angles (whose wait would otherwise cover them)
-        const LaneRes<K, true> lr = load_lane_res<K, true>(L, seq, res_aoff, ang, R);
+        const LaneRes<K, true> lr = MULTI ? load_lane_res<K, true>(L, seq, res_aoff, ang, R) : lr0;
         const Aff X = block_exclusive_prefix<MULTI>(m, first_head < K, k.nact, sh[c & 1], carry);
         if (!L.active) continue;
         const Stage sg = STG ? lds : Stage{xyz + L.A0, A};

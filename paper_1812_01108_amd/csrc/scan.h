@@ -21,16 +21,26 @@
 namespace a2c {
 
 // K-bit mask: bit j set when residue rs + j starts a chain.  The bit array is
-// padded so that reading one word past rs + K is in bounds.
+// padded so that reading one word past rs + K is in bounds for rs <= R + 1;
+// both words are read unconditionally (no branch holds the loads back).
 template <int K>
 __device__ __forceinline__ uint32_t head_mask(const uint32_t *__restrict__ bits, int64_t rs)
 {
     const int64_t w = rs >> 5;
     const int sh = (int)(rs & 31);
-    const uint64_t lo = bits[w];
-    const uint64_t hi = (sh + K > 32) ? (uint64_t)bits[w + 1] : 0ull;
-    const uint64_t v = (hi << 32) | lo;
+    const uint64_t v = ((uint64_t)bits[w + 1] << 32) | bits[w];
     return (uint32_t)(v >> sh) & ((1u << K) - 1u);
+}
+
+// head_mask of a lane holding cnt residues from rs in a chunk ending at ce:
+// the index is clamped to ce (<= R), so the read needs no branch; 0 for an
+// empty lane.
+template <int K>
+__device__ __forceinline__ uint32_t lane_head_mask(const uint32_t *__restrict__ bits, int64_t rs,
+                                                   int64_t ce, int cnt)
+{
+    const uint32_t m = head_mask<K>(bits, rs < ce ? rs : ce);
+    return cnt > 0 ? m : 0u;
 }
 
 struct Wrench {
