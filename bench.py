@@ -252,7 +252,7 @@ def cpu_baseline(model, inp, g_np, gpu_coords, gpu_grad, budget_s=12.0):
     R = int(off[-1])
     n, t_total = 0, 0.0
     ref = gref = None
-    while t_total < budget_s and n < 1000:
+    while t_total < budget_s and n < 100000:
         t0 = time.perf_counter()
         if model == "backbone":
             ref = oracle.backbone_forward(off, ang, BACKBONE_GEOMETRY, n_threads=cores)
