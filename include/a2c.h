@@ -187,14 +187,28 @@ a2c_status a2c_plan_set_schedule(a2c_plan *plan, int32_t res_per_lane,
 a2c_status a2c_plan_get_schedule(const a2c_plan *plan, int32_t *res_per_lane,
                                  int32_t *waves_per_group, int32_t *n_tiles);
 
-/* Autotuner: times forward + backward (A2C_SCAN) for every schedule that
- * a2c_plan_set_schedule accepts for the plan, on the caller's buffers, and
- * keeps the fastest on the plan (candidates in order of residues per lane,
+/* A plan holds two schedules with their own tile tables: the forward's
+ * (a2c_forward) and the adjoint's (a2c_backward and a2c_mse_step); the two
+ * kernels favour different shapes (more residues per lane suits the forward
+ * scan, fewer the adjoint's larger per-lane state).  a2c_plan_set_schedule
+ * sets both, a2c_plan_get_schedule reports the forward's, and these set and
+ * report the adjoint's alone (same arguments, checks and synchronisation as
+ * a2c_plan_set_schedule; on failure the adjoint schedule is unchanged).
+ * Results do not depend on the schedules beyond float32 rounding. */
+a2c_status a2c_plan_set_adjoint_schedule(a2c_plan *plan, int32_t res_per_lane,
+                                         int32_t waves_per_group, void *stream);
+a2c_status a2c_plan_get_adjoint_schedule(const a2c_plan *plan, int32_t *res_per_lane,
+                                         int32_t *waves_per_group, int32_t *n_tiles);
+
+/* Autotuner: for every schedule that a2c_plan_set_schedule accepts for the
+ * plan, times the forward and the adjoint (A2C_SCAN) separately on the
+ * caller's buffers, and keeps the fastest forward schedule and the fastest
+ * adjoint schedule on the plan (candidates in order of residues per lane,
  * then waves; a later one must be 3 % faster than the best so far to replace
  * it, so near-ties resolve to the smaller schedule).
  *   d_angles, d_coords, d_grad_coords, d_grad_angles: buffers of the plan's
  *     sizes; their contents are overwritten (coords and grad_angles) or read.
- *   backward_from_coords: 1 times a2c_forward + a2c_backward with d_coords
+ *   backward_from_coords: the adjoint timed: 1 a2c_backward with d_coords
  *     (the forward's output), 0 the recompute form, A2C_TUNE_MSE_STEP the
  *     fused step a2c_mse_step with d_grad_coords as its target.
  *   reps: timed repetitions per candidate (>= 1).
@@ -202,7 +216,8 @@ a2c_status a2c_plan_get_schedule(const a2c_plan *plan, int32_t *res_per_lane,
  *     residue count, longest chain, chain count and backward form; NULL for
  *     none.  A hit skips the timing; a miss appends the new choice.  An
  *     unreadable or malformed cache is ignored.
- *   out_res_per_lane, out_waves_per_group (may be NULL): the choice.
+ *   out_res_per_lane, out_waves_per_group (may be NULL): the forward's
+ *     choice (a2c_plan_get_adjoint_schedule gives the adjoint's).
  * Synchronises `stream`; not capturable.  Call it before capturing a graph. */
 #define A2C_TUNE_MSE_STEP 2
 a2c_status a2c_plan_autotune(a2c_plan *plan, const float *d_angles, float *d_coords,
@@ -257,7 +272,7 @@ a2c_status a2c_coords_to_angles(a2c_plan *plan, const float *d_coords, float *d_
  * make a round trip through memory.  Same result as a2c_forward, then
  * dL/dr = 2 (r - t), then a2c_backward, up to float32 rounding.
  *   d_coords      [3][A] receives r, or NULL (not written);
- *   d_loss_tiles  float[n_tiles] (a2c_plan_get_schedule) receives each
+ *   d_loss_tiles  float[n_tiles] (a2c_plan_get_adjoint_schedule) receives each
  *                 tile's share of L, or NULL; L is their sum (tiles hold
  *                 whole chains or one long chain; shares are deterministic);
  *   d_grad_angles [K][R] receives dL/dalpha.

@@ -132,19 +132,37 @@ class Plan:
                                                 ctypes.byref(t)), "a2c_plan_get_schedule")
         return {"res_per_lane": k.value, "waves_per_group": w.value, "n_tiles": t.value}
 
+    @property
+    def adjoint_schedule(self):
+        """The schedule of the adjoint and the fused step."""
+        k, w, t = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        check(_lib.load().a2c_plan_get_adjoint_schedule(self._h, ctypes.byref(k),
+                                                        ctypes.byref(w), ctypes.byref(t)),
+              "a2c_plan_get_adjoint_schedule")
+        return {"res_per_lane": k.value, "waves_per_group": w.value, "n_tiles": t.value}
+
     def set_schedule(self, res_per_lane: int, waves_per_group: int):
+        """Both schedules (forward, and adjoint / fused step)."""
         with torch.cuda.device(self.device):
             check(_lib.load().a2c_plan_set_schedule(self._h, res_per_lane, waves_per_group,
                                                     _stream_ptr(self.device)),
                   "a2c_plan_set_schedule")
 
+    def set_adjoint_schedule(self, res_per_lane: int, waves_per_group: int):
+        with torch.cuda.device(self.device):
+            check(_lib.load().a2c_plan_set_adjoint_schedule(self._h, res_per_lane,
+                                                            waves_per_group,
+                                                            _stream_ptr(self.device)),
+                  "a2c_plan_set_adjoint_schedule")
+
     def autotune(self, angles: torch.Tensor, grad_coords: torch.Tensor | None = None,
                  from_coords: bool = True, reps: int = 5, cache_path: str | None = None,
                  mse_target: torch.Tensor | None = None):
         """Time every valid schedule on these buffers and keep the fastest
-        (synchronises; call before capturing a graph).  With mse_target, the
-        fused training step (mse_step) is timed instead of forward + adjoint.
-        Returns the schedule."""
+        forward and the fastest adjoint schedule (synchronises; call before
+        capturing a graph).  With mse_target, the fused training step
+        (mse_step) is timed as the adjoint.  Returns (forward, adjoint)
+        schedules."""
         self._check_tensor(angles, (self.n_planes, self.n_res), "angles")
         coords = torch.empty((3, self.n_atoms), dtype=torch.float32, device=angles.device)
         if grad_coords is None:
@@ -163,7 +181,7 @@ class Plan:
                 mode, reps,
                 None if cache_path is None else cache_path.encode(), ctypes.byref(k),
                 ctypes.byref(w), _stream_ptr(self.device)), "a2c_plan_autotune")
-        return self.schedule
+        return self.schedule, self.adjoint_schedule
 
     # -- raw calls (no autograd) ------------------------------------------
     def _check_tensor(self, t, shape, name):
@@ -225,7 +243,7 @@ class Plan:
                  loss_tiles: torch.Tensor | None = None):
         """One fused pass for L = sum |r - t|^2: returns (L as a 0-dim tensor
         or None, dL/dangles); writes r into `coords` when given.  With
-        `loss_tiles` (float32, at least schedule["n_tiles"] elements) the
+        `loss_tiles` (float32, at least adjoint_schedule["n_tiles"] elements) the
         per-tile partial sums land there and nothing is allocated, so the call
         can be captured in a graph; L is then their sum, left to the caller."""
         self._check_tensor(angles, (self.n_planes, self.n_res), "angles")
@@ -238,11 +256,12 @@ class Plan:
         tiles = loss_tiles
         if tiles is not None:
             if (tiles.dtype != torch.float32 or not tiles.is_contiguous()
-                    or tiles.device != angles.device or tiles.numel() < self.schedule["n_tiles"]):
+                    or tiles.device != angles.device
+                    or tiles.numel() < self.adjoint_schedule["n_tiles"]):
                 raise ValueError("loss_tiles: contiguous float32 with >= n_tiles elements "
                                  "on the plan's device")
         elif loss:
-            tiles = torch.zeros(max(self.schedule["n_tiles"], 1), dtype=torch.float32,
+            tiles = torch.zeros(max(self.adjoint_schedule["n_tiles"], 1), dtype=torch.float32,
                                 device=angles.device)
         check(_lib.load().a2c_mse_step(
             self._h, ctypes.c_void_p(angles.data_ptr()), ctypes.c_void_p(target.data_ptr()),

@@ -26,7 +26,7 @@ ATOM_ORIGIN, ATOM_AZIMUTH, ATOM_ZMATRIX = 0, 1, 2
 EXPORTS = (
     "a2c_plan_create", "a2c_plan_destroy", "a2c_plan_sizes", "a2c_plan_atom_offsets",
     "a2c_plan_workspace_bytes", "a2c_plan_set_schedule", "a2c_plan_get_schedule",
-    "a2c_plan_autotune",
+    "a2c_plan_set_adjoint_schedule", "a2c_plan_get_adjoint_schedule", "a2c_plan_autotune",
     "a2c_forward", "a2c_backward", "a2c_residue_table_info", "a2c_status_string",
     "a2c_last_error", "a2c_version", "a2c_lrmsd_workspace_bytes", "a2c_lrmsd_forward",
     "a2c_lrmsd_backward", "a2c_mse_step", "a2c_coords_to_angles",
@@ -86,6 +86,8 @@ def load():
     lib.a2c_plan_workspace_bytes.argtypes = [vp, ctypes.c_int, P(sz)]
     lib.a2c_plan_set_schedule.argtypes = [vp, i32, i32, vp]
     lib.a2c_plan_get_schedule.argtypes = [vp, P(i32), P(i32), P(i32)]
+    lib.a2c_plan_set_adjoint_schedule.argtypes = [vp, i32, i32, vp]
+    lib.a2c_plan_get_adjoint_schedule.argtypes = [vp, P(i32), P(i32), P(i32)]
     lib.a2c_plan_autotune.argtypes = [vp, vp, vp, vp, vp, i32, i32, ctypes.c_char_p, P(i32),
                                       P(i32), vp]
     lib.a2c_plan_autotune.restype = ctypes.c_int
@@ -97,7 +99,8 @@ def load():
     lib.a2c_lrmsd_forward.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.a2c_lrmsd_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     for name in ("a2c_plan_sizes", "a2c_plan_atom_offsets", "a2c_plan_workspace_bytes",
-                 "a2c_plan_set_schedule", "a2c_plan_get_schedule", "a2c_forward",
+                 "a2c_plan_set_schedule", "a2c_plan_get_schedule",
+                 "a2c_plan_set_adjoint_schedule", "a2c_plan_get_adjoint_schedule", "a2c_forward",
                  "a2c_backward", "a2c_lrmsd_workspace_bytes", "a2c_lrmsd_forward",
                  "a2c_lrmsd_backward", "a2c_mse_step", "a2c_coords_to_angles"):
         getattr(lib, name).restype = ctypes.c_int

@@ -63,6 +63,17 @@ struct FATable {
     int32_t max_side;
 };
 
+// One scan schedule: K residues per lane, W waves per workgroup, and the
+// tile table packed for them (chains of at most one chunk of 64 W K residues
+// packed whole into tiles of at most one chunk; a longer chain alone).
+struct Sched {
+    int32_t K = 4, W = 4, n_tiles = 0;
+    int32_t fa_stage_atoms = 0;          // per-wave staging (floats per plane)
+    bool fa_unstaged = false;            // stage too large for the LDS: direct I/O
+    bool multi_chunk = false;            // some tile spans several chunks
+    int32_t *d_tile_res = nullptr;       // n_tiles (first, end) residue pairs, longest first
+};
+
 }  // namespace a2c
 
 struct a2c_plan {
@@ -75,13 +86,9 @@ struct a2c_plan {
     std::vector<int32_t> chain_atom_off; // n_chains + 1
     std::vector<int32_t> res_atom_off;   // R + 1
     std::vector<uint8_t> seq;
-    // schedule
-    int32_t K = 4, W = 4, n_tiles = 0;
-    int32_t fa_stage_atoms = 0;          // per-wave staging (floats per plane)
-    bool fa_unstaged = false;            // stage too large for the LDS: direct I/O
-    bool multi_chunk = false;            // some tile spans several chunks
+    // schedules: fs for the forward, bs for the adjoint and the fused step
+    a2c::Sched fs, bs;
     // device tables
-    int32_t *d_tile_res = nullptr;       // n_tiles (first, end) residue pairs, longest first
     uint32_t *d_head_bits = nullptr;     // bit r: residue r starts a chain (bit R set)
     int32_t *d_res_off = nullptr;        // chain residue offsets (plain form)
     int32_t *d_res_atom_off = nullptr;   // R + 1 (full-atom)
@@ -122,7 +129,6 @@ hipError_t launch_fa_mse_step(const a2c_plan &p, const float *ang, const float *
 hipError_t launch_fa_forward_scan(const a2c_plan &p, const float *ang, float *xyz, hipStream_t s);
 hipError_t launch_fa_backward_scan(const a2c_plan &p, const float *ang, const float *xyz,
                                    const float *g, float *gang, hipStream_t s);
-size_t fa_dynamic_lds(const a2c_plan &p);
 void build_lrmsd_segments(a2c_plan &p);
 void build_chi_slots(const FATable &T, int8_t (&out)[A2C_NUM_RESIDUE_TYPES][4][4]);
 size_t lrmsd_workspace_bytes(const a2c_plan &p);

@@ -67,7 +67,9 @@ std::vector<int32_t> pack_tiles(const std::vector<int32_t> &off, int64_t cap)
     return tiles;
 }
 
-a2c_status apply_schedule(a2c_plan *p, int32_t K, int32_t W, hipStream_t s)
+// Pack the tiles of schedule (K, W) and upload its tile table into out
+// (whose own table, if any, the caller frees).
+a2c_status build_sched(const a2c_plan *p, int32_t K, int32_t W, Sched &out, hipStream_t s)
 {
     const int64_t cap = (int64_t)kWave * W * K;  // residues per chunk
     if (p->max_len > cap * kMaxChunks)
@@ -102,31 +104,67 @@ a2c_status apply_schedule(a2c_plan *p, int32_t K, int32_t W, hipStream_t s)
         unstaged = true;
         stage_atoms = 0;
     }
-    p->fa_stage_atoms = stage_atoms;
-    p->fa_unstaged = unstaged;
-    p->multi_chunk = false;
+    Sched S;
+    S.fa_stage_atoms = stage_atoms;
+    S.fa_unstaged = unstaged;
+    S.multi_chunk = false;
     for (size_t t = 0; t + 1 < tiles.size(); ++t)
-        if (tiles[t + 1] - tiles[t] > cap) p->multi_chunk = true;
-    p->K = K;
-    p->W = W;
-    p->n_tiles = tiles.empty() ? 0 : (int32_t)tiles.size() - 1;
+        if (tiles[t + 1] - tiles[t] > cap) S.multi_chunk = true;
+    S.K = K;
+    S.W = W;
+    S.n_tiles = tiles.empty() ? 0 : (int32_t)tiles.size() - 1;
     // (first, end) residue pairs, longest tile first: tiles are independent,
     // and dispatching the long ones (multi-chunk chains, full tiles) first
     // keeps them out of the tail of the launch
-    std::vector<int32_t> order(p->n_tiles);
-    for (int32_t t = 0; t < p->n_tiles; ++t) order[t] = t;
+    std::vector<int32_t> order(S.n_tiles);
+    for (int32_t t = 0; t < S.n_tiles; ++t) order[t] = t;
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
         return tiles[a + 1] - tiles[a] > tiles[b + 1] - tiles[b];
     });
-    std::vector<int32_t> pairs(2 * (size_t)p->n_tiles);
-    for (int32_t t = 0; t < p->n_tiles; ++t) {
+    std::vector<int32_t> pairs(2 * (size_t)S.n_tiles);
+    for (int32_t t = 0; t < S.n_tiles; ++t) {
         pairs[2 * t] = tiles[order[t]];
         pairs[2 * t + 1] = tiles[order[t] + 1];
     }
-    a2c_status st = upload((void **)&p->d_tile_res, pairs.data(), pairs.size() * sizeof(int32_t), s);
+    a2c_status st = upload((void **)&S.d_tile_res, pairs.data(), pairs.size() * sizeof(int32_t), s);
+    if (st == A2C_OK) {
+        const hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) st = hip_fail(e, "hipStreamSynchronize");
+    }
+    if (st != A2C_OK) {
+        (void)hipFree(S.d_tile_res);
+        return st;
+    }
+    out = S;
+    return A2C_OK;
+}
+
+// Replace one of the plan's schedules; on failure it stays as it was.
+a2c_status set_sched(a2c_plan *p, Sched &dst, int32_t K, int32_t W, hipStream_t s)
+{
+    Sched S;
+    const a2c_status st = build_sched(p, K, W, S, s);
     if (st != A2C_OK) return st;
-    hipError_t e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    (void)hipFree(dst.d_tile_res);
+    dst = S;
+    return A2C_OK;
+}
+
+// Both schedules (forward, and adjoint / fused step) to (K, W).
+a2c_status apply_schedule(a2c_plan *p, int32_t K, int32_t W, hipStream_t s)
+{
+    Sched f, b;
+    a2c_status st = build_sched(p, K, W, f, s);
+    if (st != A2C_OK) return st;
+    st = build_sched(p, K, W, b, s);
+    if (st != A2C_OK) {
+        (void)hipFree(f.d_tile_res);
+        return st;
+    }
+    (void)hipFree(p->fs.d_tile_res);
+    (void)hipFree(p->bs.d_tile_res);
+    p->fs = f;
+    p->bs = b;
     return A2C_OK;
 }
 
@@ -199,6 +237,16 @@ a2c_status plan_apply_schedule(a2c_plan *p, int32_t K, int32_t W, hipStream_t s)
     return apply_schedule(p, K, W, s);
 }
 
+a2c_status plan_apply_adjoint_schedule(a2c_plan *p, int32_t K, int32_t W, hipStream_t s)
+{
+    return set_sched(p, p->bs, K, W, s);
+}
+
+a2c_status plan_apply_forward_schedule(a2c_plan *p, int32_t K, int32_t W, hipStream_t s)
+{
+    return set_sched(p, p->fs, K, W, s);
+}
+
 }  // namespace a2c
 
 using namespace a2c;
@@ -225,7 +273,8 @@ const char *a2c_last_error(void) { return g_last_error.c_str(); }
 void a2c_plan_destroy(a2c_plan *p)
 {
     if (!p) return;
-    (void)hipFree(p->d_tile_res);
+    (void)hipFree(p->fs.d_tile_res);
+    (void)hipFree(p->bs.d_tile_res);
     (void)hipFree(p->d_head_bits);
     (void)hipFree(p->d_res_off);
     (void)hipFree(p->d_res_atom_off);
@@ -410,12 +459,34 @@ a2c_status a2c_plan_set_schedule(a2c_plan *p, int32_t K, int32_t W, void *stream
     return apply_schedule(p, K, W, (hipStream_t)stream);
 }
 
+a2c_status a2c_plan_set_adjoint_schedule(a2c_plan *p, int32_t K, int32_t W, void *stream)
+{
+    if (!p) return fail(A2C_ERR_INVALID_ARG, "plan is NULL");
+    if (!(K == 1 || K == 2 || K == 4))
+        return fail(A2C_ERR_INVALID_ARG, "res_per_lane must be 1, 2 or 4");
+    if (p->model == A2C_FULLATOM && K == 4)
+        return fail(A2C_ERR_INVALID_ARG, "the full-atom kernels take res_per_lane 1 or 2");
+    if (W < 1 || W > kMaxWaves) return fail(A2C_ERR_INVALID_ARG, "waves_per_group must be 1..16");
+    if (!check_device(p)) return fail(A2C_ERR_STATE, "current device is not the plan's device");
+    return set_sched(p, p->bs, K, W, (hipStream_t)stream);
+}
+
 a2c_status a2c_plan_get_schedule(const a2c_plan *p, int32_t *K, int32_t *W, int32_t *n_tiles)
 {
     if (!p) return fail(A2C_ERR_INVALID_ARG, "plan is NULL");
-    if (K) *K = p->K;
-    if (W) *W = p->W;
-    if (n_tiles) *n_tiles = p->n_tiles;
+    if (K) *K = p->fs.K;
+    if (W) *W = p->fs.W;
+    if (n_tiles) *n_tiles = p->fs.n_tiles;
+    return A2C_OK;
+}
+
+a2c_status a2c_plan_get_adjoint_schedule(const a2c_plan *p, int32_t *K, int32_t *W,
+                                         int32_t *n_tiles)
+{
+    if (!p) return fail(A2C_ERR_INVALID_ARG, "plan is NULL");
+    if (K) *K = p->bs.K;
+    if (W) *W = p->bs.W;
+    if (n_tiles) *n_tiles = p->bs.n_tiles;
     return A2C_OK;
 }
 

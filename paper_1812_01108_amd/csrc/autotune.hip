@@ -1,6 +1,7 @@
-// Schedule autotuner: times forward + backward for every valid (residues per
-// lane, waves per workgroup) with HIP events and keeps the fastest; choices
-// can be kept in a small text cache.
+// Schedule autotuner: for every valid (residues per lane, waves per
+// workgroup) times the forward and the adjoint (or the fused step) separately
+// with HIP events, and keeps the fastest of each as the plan's forward and
+// adjoint schedules; choices can be kept in a small text cache.
 #include <cstdio>
 #include <cstring>
 #include <fstream>
@@ -12,6 +13,8 @@
 
 namespace a2c {
 a2c_status plan_apply_schedule(a2c_plan *p, int32_t K, int32_t W, hipStream_t s);
+a2c_status plan_apply_forward_schedule(a2c_plan *p, int32_t K, int32_t W, hipStream_t s);
+a2c_status plan_apply_adjoint_schedule(a2c_plan *p, int32_t K, int32_t W, hipStream_t s);
 }
 
 using namespace a2c;
@@ -31,7 +34,10 @@ std::string cache_key(const a2c_plan *p, int from_coords)
     return k.str();
 }
 
-bool cache_lookup(const char *path, const std::string &key, int32_t &K, int32_t &W)
+// A cache line is "<key> K W [bK bW]": forward, then adjoint schedule (a line
+// with two numbers gives both).
+bool cache_lookup(const char *path, const std::string &key, int32_t &K, int32_t &W, int32_t &bK,
+                  int32_t &bW)
 {
     if (!path) return false;
     std::ifstream f(path);
@@ -42,21 +48,34 @@ bool cache_lookup(const char *path, const std::string &key, int32_t &K, int32_t 
         if (line.compare(0, key.size(), key) != 0 || line.size() <= key.size() ||
             line[key.size()] != ' ')
             continue;
-        int k = 0, w = 0;
-        if (std::sscanf(line.c_str() + key.size(), " %d %d", &k, &w) == 2) {
+        int k = 0, w = 0, bk = 0, bw = 0;
+        const int n = std::sscanf(line.c_str() + key.size(), " %d %d %d %d", &k, &w, &bk, &bw);
+        if (n == 2 || n == 4) {
             K = k;
             W = w;
+            bK = n == 4 ? bk : k;
+            bW = n == 4 ? bw : w;
             found = true;  // the last matching line wins
         }
     }
     return found;
 }
 
-void cache_store(const char *path, const std::string &key, int32_t K, int32_t W)
+void cache_store(const char *path, const std::string &key, int32_t K, int32_t W, int32_t bK,
+                 int32_t bW)
 {
     if (!path) return;
     std::ofstream f(path, std::ios::app);
-    if (f) f << key << ' ' << K << ' ' << W << '\n';
+    if (f) f << key << ' ' << K << ' ' << W << ' ' << bK << ' ' << bW << '\n';
+}
+
+// The forward, then the adjoint schedule (each setter leaves its schedule
+// unchanged when it fails).
+a2c_status apply_pair(a2c_plan *p, int32_t K, int32_t W, int32_t bK, int32_t bW, hipStream_t s)
+{
+    a2c_status st = plan_apply_forward_schedule(p, K, W, s);
+    if (st == A2C_OK) st = plan_apply_adjoint_schedule(p, bK, bW, s);
+    return st;
 }
 
 }  // namespace
@@ -76,8 +95,8 @@ extern "C" a2c_status a2c_plan_autotune(a2c_plan *p, const float *d_angles, floa
     }
     hipStream_t s = (hipStream_t)stream;
     if (p->R == 0) {
-        if (out_K) *out_K = p->K;
-        if (out_W) *out_W = p->W;
+        if (out_K) *out_K = p->fs.K;
+        if (out_W) *out_W = p->fs.W;
         return A2C_OK;
     }
     if (!d_angles || !d_coords || !d_grad_coords || !d_grad_angles) {
@@ -90,9 +109,9 @@ extern "C" a2c_status a2c_plan_autotune(a2c_plan *p, const float *d_angles, floa
         return A2C_ERR_STATE;
     }
     const std::string key = cache_key(p, from_coords);
-    int32_t K = 0, W = 0;
-    if (cache_lookup(cache_path, key, K, W)) {
-        if (plan_apply_schedule(p, K, W, s) == A2C_OK) {
+    int32_t K = 0, W = 0, cK = 0, cW = 0;
+    if (cache_lookup(cache_path, key, K, W, cK, cW)) {
+        if (apply_pair(p, K, W, cK, cW, s) == A2C_OK) {
             if (out_K) *out_K = K;
             if (out_W) *out_W = W;
             return A2C_OK;
@@ -103,8 +122,8 @@ extern "C" a2c_status a2c_plan_autotune(a2c_plan *p, const float *d_angles, floa
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return hip_fail(hipGetLastError(), "hipEventCreate");
-    float best = 1e30f;
-    int32_t bK = p->K, bW = p->W;
+    float best_f = 1e30f, best_b = 1e30f;
+    int32_t fK = p->fs.K, fW = p->fs.W, bK = p->bs.K, bW = p->bs.W;
     a2c_status st = A2C_OK;
     for (int k : Ks) {
         if (p->model == A2C_FULLATOM && k == 4) continue;
@@ -115,36 +134,43 @@ extern "C" a2c_status a2c_plan_autotune(a2c_plan *p, const float *d_angles, floa
                 continue;
             }
             if (st != A2C_OK) break;
-            float cand = 1e30f;
-            for (int trial = 0; trial < 3 && st == A2C_OK; ++trial) {
-                (void)hipEventRecord(e0, s);
-                for (int r = 0; r < reps && st == A2C_OK; ++r) {
-                    if (from_coords == A2C_TUNE_MSE_STEP) {
-                        // d_grad_coords serves as the target
-                        st = a2c_mse_step(p, d_angles, d_grad_coords, d_coords, nullptr,
-                                          d_grad_angles, s);
-                        continue;
+            // the forward alone, then the adjoint (or the fused step) alone;
+            // the forward's output feeds the coordinate-mode adjoint
+            float cand[2] = {1e30f, 1e30f};
+            for (int part = 0; part < 2 && st == A2C_OK; ++part)
+                for (int trial = 0; trial < 3 && st == A2C_OK; ++trial) {
+                    (void)hipEventRecord(e0, s);
+                    for (int r = 0; r < reps && st == A2C_OK; ++r) {
+                        if (part == 0)
+                            st = a2c_forward(p, A2C_SCAN, d_angles, d_coords, nullptr, s);
+                        else if (from_coords == A2C_TUNE_MSE_STEP)  // d_grad_coords: the target
+                            st = a2c_mse_step(p, d_angles, d_grad_coords, d_coords, nullptr,
+                                              d_grad_angles, s);
+                        else
+                            st = a2c_backward(p, A2C_SCAN, d_angles,
+                                              from_coords ? d_coords : nullptr, d_grad_coords,
+                                              d_grad_angles, nullptr, s);
                     }
-                    st = a2c_forward(p, A2C_SCAN, d_angles, d_coords, nullptr, s);
-                    if (st == A2C_OK)
-                        st = a2c_backward(p, A2C_SCAN, d_angles, from_coords ? d_coords : nullptr,
-                                          d_grad_coords, d_grad_angles, nullptr, s);
+                    (void)hipEventRecord(e1, s);
+                    if (hipEventSynchronize(e1) != hipSuccess) {
+                        st = hip_fail(hipGetLastError(), "hipEventSynchronize");
+                        break;
+                    }
+                    float ms = 0.f;
+                    (void)hipEventElapsedTime(&ms, e0, e1);
+                    if (trial > 0) cand[part] = std::min(cand[part], ms);  // first trial warms up
                 }
-                (void)hipEventRecord(e1, s);
-                if (hipEventSynchronize(e1) != hipSuccess) {
-                    st = hip_fail(hipGetLastError(), "hipEventSynchronize");
-                    break;
-                }
-                float ms = 0.f;
-                (void)hipEventElapsedTime(&ms, e0, e1);
-                if (trial > 0) cand = std::min(cand, ms);  // first trial warms up
-            }
             if (st != A2C_OK) break;
             // a later candidate (more residues per lane or waves) must be
             // 3 % faster to win: near-ties keep the smaller schedule, so the
             // choice does not flip with timing noise
-            if (cand < 0.97f * best) {
-                best = cand;
+            if (cand[0] < 0.97f * best_f) {
+                best_f = cand[0];
+                fK = k;
+                fW = w;
+            }
+            if (cand[1] < 0.97f * best_b) {
+                best_b = cand[1];
                 bK = k;
                 bW = w;
             }
@@ -154,10 +180,10 @@ extern "C" a2c_status a2c_plan_autotune(a2c_plan *p, const float *d_angles, floa
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st != A2C_OK) return st;
-    st = plan_apply_schedule(p, bK, bW, s);
+    st = apply_pair(p, fK, fW, bK, bW, s);
     if (st != A2C_OK) return st;
-    cache_store(cache_path, key, bK, bW);
-    if (out_K) *out_K = bK;
-    if (out_W) *out_W = bW;
+    cache_store(cache_path, key, fK, fW, bK, bW);
+    if (out_K) *out_K = fK;
+    if (out_W) *out_W = fW;
     return A2C_OK;
 }

@@ -557,17 +557,17 @@ __global__ __launch_bounds__(kPlainBlock) void bb_backward_plain_kernel(
 template <int K, bool MULTI, int LB>
 hipError_t fwd_kml(const a2c_plan &p, const float *ang, float *xyz, hipStream_t s)
 {
-    const dim3 grid(p.n_tiles), block(p.W * kWave);
-    hipLaunchKernelGGL((bb_forward_scan_kernel<K, MULTI, LB>), grid, block, stage_bytes<K>(p.W),
-                       s, ang, xyz, p.d_tile_res, p.d_head_bits, p.R, p.bb);
+    const dim3 grid(p.fs.n_tiles), block(p.fs.W * kWave);
+    hipLaunchKernelGGL((bb_forward_scan_kernel<K, MULTI, LB>), grid, block, stage_bytes<K>(p.fs.W),
+                       s, ang, xyz, p.fs.d_tile_res, p.d_head_bits, p.R, p.bb);
     return hipGetLastError();
 }
 
 template <int K>
 hipError_t fwd_k(const a2c_plan &p, const float *ang, float *xyz, hipStream_t s)
 {
-    const bool small = p.W * kWave <= kLbSmall;
-    if (p.multi_chunk)
+    const bool small = p.fs.W * kWave <= kLbSmall;
+    if (p.fs.multi_chunk)
         return small ? fwd_kml<K, true, kLbSmall>(p, ang, xyz, s)
                      : fwd_kml<K, true, kLbLarge>(p, ang, xyz, s);
     return small ? fwd_kml<K, false, kLbSmall>(p, ang, xyz, s)
@@ -578,14 +578,14 @@ template <int K, bool MULTI, int LB>
 hipError_t bwd_kml(const a2c_plan &p, const float *ang, const float *xyz, const float *g,
                    float *gang, hipStream_t s)
 {
-    const dim3 grid(p.n_tiles), block(p.W * kWave);
-    const size_t lds = stage_bytes<K>(p.W);
+    const dim3 grid(p.bs.n_tiles), block(p.bs.W * kWave);
+    const size_t lds = stage_bytes<K>(p.bs.W);
     if (xyz)
         hipLaunchKernelGGL((bb_backward_coords_kernel<K, MULTI, LB>), grid, block, lds, s, xyz,
-                           g, gang, p.d_tile_res, p.d_head_bits, p.R, p.bb);
+                           g, gang, p.bs.d_tile_res, p.d_head_bits, p.R, p.bb);
     else
         hipLaunchKernelGGL((bb_backward_recompute_kernel<K, MULTI, LB, kGradLoad>), grid, block,
-                           lds, s, ang, g, gang, nullptr, nullptr, p.d_tile_res, p.d_head_bits,
+                           lds, s, ang, g, gang, nullptr, nullptr, p.bs.d_tile_res, p.d_head_bits,
                            p.R, p.bb);
     return hipGetLastError();
 }
@@ -594,9 +594,9 @@ template <int K, bool MULTI, int LB>
 hipError_t mse_kml(const a2c_plan &p, const float *ang, const float *tgt, float *xyz,
                    float *loss_part, float *gang, hipStream_t s)
 {
-    hipLaunchKernelGGL((bb_backward_recompute_kernel<K, MULTI, LB, kGradMse>), dim3(p.n_tiles),
-                       dim3(p.W * kWave), stage_bytes<K>(p.W), s, ang, tgt, gang, xyz, loss_part,
-                       p.d_tile_res, p.d_head_bits, p.R, p.bb);
+    hipLaunchKernelGGL((bb_backward_recompute_kernel<K, MULTI, LB, kGradMse>), dim3(p.bs.n_tiles),
+                       dim3(p.bs.W * kWave), stage_bytes<K>(p.bs.W), s, ang, tgt, gang, xyz, loss_part,
+                       p.bs.d_tile_res, p.d_head_bits, p.R, p.bb);
     return hipGetLastError();
 }
 
@@ -604,8 +604,8 @@ template <int K>
 hipError_t mse_k(const a2c_plan &p, const float *ang, const float *tgt, float *xyz,
                  float *loss_part, float *gang, hipStream_t s)
 {
-    const bool small = p.W * kWave <= kLbSmall;
-    if (p.multi_chunk)
+    const bool small = p.bs.W * kWave <= kLbSmall;
+    if (p.bs.multi_chunk)
         return small ? mse_kml<K, true, kLbSmall>(p, ang, tgt, xyz, loss_part, gang, s)
                      : mse_kml<K, true, kLbLarge>(p, ang, tgt, xyz, loss_part, gang, s);
     return small ? mse_kml<K, false, kLbSmall>(p, ang, tgt, xyz, loss_part, gang, s)
@@ -616,8 +616,8 @@ template <int K>
 hipError_t bwd_k(const a2c_plan &p, const float *ang, const float *xyz, const float *g,
                  float *gang, hipStream_t s)
 {
-    const bool small = p.W * kWave <= kLbSmall;
-    if (p.multi_chunk)
+    const bool small = p.bs.W * kWave <= kLbSmall;
+    if (p.bs.multi_chunk)
         return small ? bwd_kml<K, true, kLbSmall>(p, ang, xyz, g, gang, s)
                      : bwd_kml<K, true, kLbLarge>(p, ang, xyz, g, gang, s);
     return small ? bwd_kml<K, false, kLbSmall>(p, ang, xyz, g, gang, s)
@@ -628,7 +628,7 @@ hipError_t bwd_k(const a2c_plan &p, const float *ang, const float *xyz, const fl
 
 hipError_t launch_bb_forward_scan(const a2c_plan &p, const float *ang, float *xyz, hipStream_t s)
 {
-    switch (p.K) {
+    switch (p.fs.K) {
     case 1: return fwd_k<1>(p, ang, xyz, s);
     case 2: return fwd_k<2>(p, ang, xyz, s);
     case 4: return fwd_k<4>(p, ang, xyz, s);
@@ -639,7 +639,7 @@ hipError_t launch_bb_forward_scan(const a2c_plan &p, const float *ang, float *xy
 hipError_t launch_bb_backward_scan(const a2c_plan &p, const float *ang, const float *xyz,
                                    const float *g, float *gang, hipStream_t s)
 {
-    switch (p.K) {
+    switch (p.bs.K) {
     case 1: return bwd_k<1>(p, ang, xyz, g, gang, s);
     case 2: return bwd_k<2>(p, ang, xyz, g, gang, s);
     case 4: return bwd_k<4>(p, ang, xyz, g, gang, s);
@@ -650,7 +650,7 @@ hipError_t launch_bb_backward_scan(const a2c_plan &p, const float *ang, const fl
 hipError_t launch_bb_mse_step(const a2c_plan &p, const float *ang, const float *tgt, float *xyz,
                               float *loss_part, float *gang, hipStream_t s)
 {
-    switch (p.K) {
+    switch (p.bs.K) {
     case 1: return mse_k<1>(p, ang, tgt, xyz, loss_part, gang, s);
     case 2: return mse_k<2>(p, ang, tgt, xyz, loss_part, gang, s);
     case 4: return mse_k<4>(p, ang, tgt, xyz, loss_part, gang, s);

@@ -937,18 +937,18 @@ __global__ __launch_bounds__(LB) void fa_backward_kernel(
 template <int K, bool MULTI, int LB, bool STG>
 hipError_t fa_fwd_kml(const a2c_plan &p, const float *ang, float *xyz, hipStream_t s)
 {
-    const size_t lds = STG ? (size_t)p.W * 3 * p.fa_stage_atoms * sizeof(float) : 0;
-    hipLaunchKernelGGL((fa_forward_kernel<K, MULTI, LB, STG>), dim3(p.n_tiles), dim3(p.W * kWave),
-                       lds, s, ang, xyz, p.d_tile_res, p.d_head_bits, p.d_res_atom_off, p.d_seq,
-                       p.d_fa, p.R, p.A, p.bb, p.fa_stage_atoms);
+    const size_t lds = STG ? (size_t)p.fs.W * 3 * p.fs.fa_stage_atoms * sizeof(float) : 0;
+    hipLaunchKernelGGL((fa_forward_kernel<K, MULTI, LB, STG>), dim3(p.fs.n_tiles), dim3(p.fs.W * kWave),
+                       lds, s, ang, xyz, p.fs.d_tile_res, p.d_head_bits, p.d_res_atom_off, p.d_seq,
+                       p.d_fa, p.R, p.A, p.bb, p.fs.fa_stage_atoms);
     return hipGetLastError();
 }
 
 template <int K, bool STG>
 hipError_t fa_fwd_ks(const a2c_plan &p, const float *ang, float *xyz, hipStream_t s)
 {
-    const bool small = p.W * kWave <= kLbSmall;
-    if (p.multi_chunk)
+    const bool small = p.fs.W * kWave <= kLbSmall;
+    if (p.fs.multi_chunk)
         return small ? fa_fwd_kml<K, true, kLbSmall, STG>(p, ang, xyz, s)
                      : fa_fwd_kml<K, true, kLbLarge, STG>(p, ang, xyz, s);
     return small ? fa_fwd_kml<K, false, kLbSmall, STG>(p, ang, xyz, s)
@@ -958,7 +958,7 @@ hipError_t fa_fwd_ks(const a2c_plan &p, const float *ang, float *xyz, hipStream_
 template <int K>
 hipError_t fa_fwd_k(const a2c_plan &p, const float *ang, float *xyz, hipStream_t s)
 {
-    return p.fa_unstaged ? fa_fwd_ks<K, false>(p, ang, xyz, s) : fa_fwd_ks<K, true>(p, ang, xyz, s);
+    return p.fs.fa_unstaged ? fa_fwd_ks<K, false>(p, ang, xyz, s) : fa_fwd_ks<K, true>(p, ang, xyz, s);
 }
 
 template <int K, bool RECOMPUTE, bool MULTI, int LB, int GM, bool STG>
@@ -966,11 +966,11 @@ void fa_bwd_launch(const a2c_plan &p, const float *ang, const float *xyz, const 
                    float *gang, hipStream_t s, float *xyz_out, float *loss_part)
 {
     const size_t lds =
-        STG ? (size_t)p.W * (RECOMPUTE ? 3 : 6) * p.fa_stage_atoms * sizeof(float) : 0;
-    hipLaunchKernelGGL((fa_backward_kernel<K, RECOMPUTE, MULTI, LB, GM, STG>), dim3(p.n_tiles),
-                       dim3(p.W * kWave), lds, s, ang, xyz, g, gang, xyz_out, loss_part,
-                       p.d_tile_res, p.d_head_bits, p.d_res_atom_off, p.d_seq, p.d_fa, p.R, p.A,
-                       p.bb, p.fa_stage_atoms);
+        STG ? (size_t)p.bs.W * (RECOMPUTE ? 3 : 6) * p.bs.fa_stage_atoms * sizeof(float) : 0;
+    hipLaunchKernelGGL((fa_backward_kernel<K, RECOMPUTE, MULTI, LB, GM, STG>), dim3(p.bs.n_tiles),
+                       dim3(p.bs.W * kWave), lds, s, ang, xyz, g, gang, xyz_out, loss_part,
+                       p.bs.d_tile_res, p.d_head_bits, p.d_res_atom_off, p.d_seq, p.d_fa, p.R, p.A,
+                       p.bb, p.bs.fa_stage_atoms);
 }
 
 // mode 0: adjoint from coordinates, 1: recompute, 2: fused squared-distance step
@@ -980,8 +980,8 @@ void fa_bwd_dispatch(const a2c_plan &p, const float *ang, const float *xyz, cons
 {
     constexpr bool RC = MODE != 0;
     constexpr int GM = MODE == 2 ? kGradMse : kGradLoad;
-    const bool small = p.W * kWave <= kLbSmall;
-    if (p.multi_chunk) {
+    const bool small = p.bs.W * kWave <= kLbSmall;
+    if (p.bs.multi_chunk) {
         if (small) fa_bwd_launch<K, RC, true, kLbSmall, GM, STG>(p, ang, xyz, g, gang, s, xyz_out, loss_part);
         else fa_bwd_launch<K, RC, true, kLbLarge, GM, STG>(p, ang, xyz, g, gang, s, xyz_out, loss_part);
     } else {
@@ -995,7 +995,7 @@ hipError_t fa_bwd_mode(const a2c_plan &p, const float *ang, const float *xyz, co
                        float *gang, hipStream_t s, float *xyz_out = nullptr,
                        float *loss_part = nullptr)
 {
-    if (p.fa_unstaged) fa_bwd_dispatch<K, MODE, false>(p, ang, xyz, g, gang, s, xyz_out, loss_part);
+    if (p.bs.fa_unstaged) fa_bwd_dispatch<K, MODE, false>(p, ang, xyz, g, gang, s, xyz_out, loss_part);
     else fa_bwd_dispatch<K, MODE, true>(p, ang, xyz, g, gang, s, xyz_out, loss_part);
     return hipGetLastError();
 }
@@ -1013,8 +1013,8 @@ hipError_t fa_bwd_k(const a2c_plan &p, const float *ang, const float *xyz, const
 {
     // the staged coordinate form needs six planes; where they do not fit,
     // the recompute form (three planes) computes the same gradient
-    if (xyz && !p.fa_unstaged &&
-        (size_t)p.W * 6 * p.fa_stage_atoms * sizeof(float) > (size_t)kMaxDynamicLds)
+    if (xyz && !p.bs.fa_unstaged &&
+        (size_t)p.bs.W * 6 * p.bs.fa_stage_atoms * sizeof(float) > (size_t)kMaxDynamicLds)
         xyz = nullptr;
     return xyz ? fa_bwd_mode<K, 0>(p, ang, xyz, g, gang, s)
                : fa_bwd_mode<K, 1>(p, ang, xyz, g, gang, s);
@@ -1024,7 +1024,7 @@ hipError_t fa_bwd_k(const a2c_plan &p, const float *ang, const float *xyz, const
 
 hipError_t launch_fa_forward_scan(const a2c_plan &p, const float *ang, float *xyz, hipStream_t s)
 {
-    switch (p.K) {
+    switch (p.fs.K) {
     case 1: return fa_fwd_k<1>(p, ang, xyz, s);
     case 2: return fa_fwd_k<2>(p, ang, xyz, s);
     default: return hipErrorInvalidValue;
@@ -1034,7 +1034,7 @@ hipError_t launch_fa_forward_scan(const a2c_plan &p, const float *ang, float *xy
 hipError_t launch_fa_backward_scan(const a2c_plan &p, const float *ang, const float *xyz,
                                    const float *g, float *gang, hipStream_t s)
 {
-    switch (p.K) {
+    switch (p.bs.K) {
     case 1: return fa_bwd_k<1>(p, ang, xyz, g, gang, s);
     case 2: return fa_bwd_k<2>(p, ang, xyz, g, gang, s);
     default: return hipErrorInvalidValue;
@@ -1044,19 +1044,11 @@ hipError_t launch_fa_backward_scan(const a2c_plan &p, const float *ang, const fl
 hipError_t launch_fa_mse_step(const a2c_plan &p, const float *ang, const float *tgt, float *xyz,
                               float *loss_part, float *gang, hipStream_t s)
 {
-    switch (p.K) {
+    switch (p.bs.K) {
     case 1: return fa_mse_k<1>(p, ang, tgt, xyz, loss_part, gang, s);
     case 2: return fa_mse_k<2>(p, ang, tgt, xyz, loss_part, gang, s);
     default: return hipErrorInvalidValue;
     }
-}
-
-// Dynamic LDS a full-atom launch needs beyond the static tables (forward
-// and recompute backward; the coordinate-mode backward needs twice this and
-// falls back to the recompute form where that does not fit).
-size_t fa_dynamic_lds(const a2c_plan &p)
-{
-    return p.fa_unstaged ? 0 : (size_t)p.W * 3 * p.fa_stage_atoms * sizeof(float);
 }
 
 template <typename F>

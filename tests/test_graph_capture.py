@@ -93,7 +93,7 @@ def test_fused_step(model):
     a, td = to_dev(ang), to_dev(t)
     coords = torch.empty((3, plan.n_atoms), device="cuda")
     grad = torch.empty_like(a)
-    tiles = torch.empty(plan.schedule["n_tiles"], device="cuda")
+    tiles = torch.empty(plan.adjoint_schedule["n_tiles"], device="cuda")
 
     def run():
         plan.mse_step(a, td, coords=coords, grad_angles=grad, loss_tiles=tiles)

@@ -56,6 +56,22 @@ def test_schedules_ragged_edges(K, W, mode):
     _check(plan, off, ang, g, mode=mode, label=f"K={K} W={W}")
 
 
+@pytest.mark.parametrize("fwd,adj", [((4, 4), (1, 8)), ((1, 1), (4, 2)), ((2, 16), (2, 3))])
+@pytest.mark.parametrize("mode", ["coords", "recompute"])
+def test_separate_forward_and_adjoint_schedules(fwd, adj, mode):
+    """Forward and adjoint each on their own schedule and tile table (one of
+    them multi-chunk where the other is not)."""
+    a2c = _a2c()
+    off, ang, g = _batch(EDGE_LENGTHS, 19)
+    plan = a2c.Plan("backbone", offsets=off)
+    plan.set_schedule(*fwd)
+    plan.set_adjoint_schedule(*adj)
+    assert (plan.schedule["res_per_lane"], plan.schedule["waves_per_group"]) == fwd
+    assert (plan.adjoint_schedule["res_per_lane"],
+            plan.adjoint_schedule["waves_per_group"]) == adj
+    _check(plan, off, ang, g, mode=mode, label=f"fwd={fwd} adj={adj}")
+
+
 def test_default_schedule_small_config_and_plain():
     a2c = _a2c()
     inp = make_inputs("backbone_16x64")

@@ -61,6 +61,19 @@ def test_schedules_all_types(K, W, mode):
     _check(plan, off, seq, ang, mode, label=f"K={K} W={W}")
 
 
+@pytest.mark.parametrize("fwd,adj", [((1, 16), (2, 16)), ((2, 4), (1, 1))])
+@pytest.mark.parametrize("mode", ["coords", "recompute"])
+def test_separate_forward_and_adjoint_schedules(fwd, adj, mode):
+    """Forward and adjoint on their own schedules (staged and unstaged,
+    one- and multi-chunk tiles mixed)."""
+    a2c = _a2c()
+    off, seq, ang = _batch([1, 2, 20, 63, 64, 65, 0, 130, 7, 200, 1000], 103)
+    plan = a2c.Plan("fullatom", offsets=off, seq=seq)
+    plan.set_schedule(*fwd)
+    plan.set_adjoint_schedule(*adj)
+    _check(plan, off, seq, ang, mode, label=f"fwd={fwd} adj={adj}")
+
+
 @pytest.mark.parametrize("mode", ["coords", "recompute"])
 def test_max_chunks_per_tile(mode):
     """K = 1, W = 1: a 4096-residue chain is exactly 64 chunks of 64 residues."""
