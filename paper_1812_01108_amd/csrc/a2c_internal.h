@@ -100,10 +100,12 @@ struct a2c_plan {
     int32_t lr_n_seg = 0;
     std::vector<int32_t> lr_seg_atom;    // lr_n_seg + 1 first atoms (last = A)
     std::vector<int32_t> lr_seg_chain;   // lr_n_seg chain of each segment
+    std::vector<int32_t> lr_seg_origin;  // lr_n_seg first atom of each segment's chain
     std::vector<int32_t> lr_chain_seg;   // n_chains + 1 first segment of each chain
     int8_t *d_chi_slots = nullptr;       // [20][4][4] chi atom slots (full-atom)
     int32_t *d_lr_seg_atom = nullptr;
     int32_t *d_lr_seg_chain = nullptr;
+    int32_t *d_lr_seg_origin = nullptr;
     int32_t *d_lr_chain_seg = nullptr;
 };
 

@@ -283,6 +283,7 @@ void a2c_plan_destroy(a2c_plan *p)
     (void)hipFree(p->d_chi_slots);
     (void)hipFree(p->d_lr_seg_atom);
     (void)hipFree(p->d_lr_seg_chain);
+    (void)hipFree(p->d_lr_seg_origin);
     (void)hipFree(p->d_lr_chain_seg);
     delete p;
 }
@@ -395,6 +396,9 @@ a2c_status a2c_plan_create(a2c_plan **out, a2c_model model, int32_t n_chains,
         if (st == A2C_OK)
             st = upload((void **)&p->d_lr_seg_chain, p->lr_seg_chain.data(),
                         p->lr_seg_chain.size() * sizeof(int32_t), s);
+        if (st == A2C_OK)
+            st = upload((void **)&p->d_lr_seg_origin, p->lr_seg_origin.data(),
+                        p->lr_seg_origin.size() * sizeof(int32_t), s);
         if (st == A2C_OK)
             st = upload((void **)&p->d_lr_chain_seg, p->lr_chain_seg.data(),
                         p->lr_chain_seg.size() * sizeof(int32_t), s);

@@ -20,7 +20,7 @@
 //               shifted by the chain's first atom, accumulated in float64
 //               (the shift keeps the centring well conditioned; float64
 //               makes the sums exact to far below float32 rounding);
-//   lr_solve    one wave per chain: folds the chain's segment sums, centres
+//   lr_solve    one lane per chain: folds the chain's segment sums, centres
 //               them, finds lambda by Newton's method on the characteristic
 //               polynomial of T from above (monotone: lambda <= the bound
 //               (sum |x~|^2 + sum |y~|^2) / 2 it starts from), q from the
@@ -37,6 +37,7 @@ namespace a2c {
 namespace {
 
 constexpr int kLrThreads = 256;
+constexpr int kLrSolveThreads = 64;  // one lane per chain
 constexpr int kLrPart = 18;  // doubles per segment record (17 used)
 constexpr int kLrState = 16; // floats per chain: U (9), x mean (3), y mean (3), 1/(N LRMSD)
 
@@ -97,14 +98,12 @@ __device__ __forceinline__ double wave_sum_f64(double v)
 
 __global__ __launch_bounds__(kLrThreads) void lr_partial_kernel(
     const float *__restrict__ y, const float *__restrict__ x, const int32_t *__restrict__ seg_atom,
-    const int32_t *__restrict__ seg_chain, const int32_t *__restrict__ chain_seg, int64_t A,
-    double *__restrict__ part)
+    const int32_t *__restrict__ seg_origin, int64_t A, double *__restrict__ part)
 {
     __shared__ double red[17][kLrThreads + 1];
     const int s = blockIdx.x;
     const int a0 = seg_atom[s], a1 = seg_atom[s + 1];
-    const int c = seg_chain[s];
-    const int r0 = seg_atom[chain_seg[c]];
+    const int r0 = seg_origin[s];  // the chain's first atom
     const double x0 = x[r0], x1 = x[A + r0], x2 = x[2 * A + r0];
     const double y0 = y[r0], y1 = y[A + r0], y2 = y[2 * A + r0];
     double acc[17];
@@ -234,40 +233,34 @@ __device__ void jacobi_top_vector(const double (&t)[4][4], double (&q)[4])
         }
 }
 
-__global__ __launch_bounds__(kLrThreads) void lr_solve_kernel(
+__global__ __launch_bounds__(kLrSolveThreads) void lr_solve_kernel(
     const float *__restrict__ y, const float *__restrict__ x, const int32_t *__restrict__ seg_atom,
     const int32_t *__restrict__ chain_seg, int32_t n_chains, int64_t A,
     const double *__restrict__ part, float *__restrict__ state, float *__restrict__ out)
 {
-    const int lane = threadIdx.x & 63;
-    const int c = blockIdx.x * (kLrThreads / 64) + (threadIdx.x >> 6);
-    if (c >= n_chains) return;  // whole waves leave together
+    const int c = blockIdx.x * kLrSolveThreads + (int)threadIdx.x;
+    if (c >= n_chains) return;
     const int s0 = chain_seg[c], s1 = chain_seg[c + 1];
-    // the chain's first atom and size, read now so that their latency
-    // overlaps the sums below (lane 0 uses them at the end)
     const int r0 = s1 > s0 ? seg_atom[s0] : 0;
     const int64_t n_atoms = s1 > s0 ? (int64_t)seg_atom[s1] - r0 : 0;
-    float x0[3] = {0.f, 0.f, 0.f}, y0[3] = {0.f, 0.f, 0.f};
-    if (lane == 0 && n_atoms > 0) {
-        x0[0] = x[r0]; x0[1] = x[A + r0]; x0[2] = x[2 * A + r0];
-        y0[0] = y[r0]; y0[1] = y[A + r0]; y0[2] = y[2 * A + r0];
-    }
-    double acc[17];
-#pragma unroll
-    for (int k = 0; k < 17; ++k) acc[k] = 0.0;
-    for (int s = s0 + lane; s < s1; s += 64) {
-#pragma unroll
-        for (int k = 0; k < 17; ++k) acc[k] += part[(size_t)s * kLrPart + k];
-    }
-#pragma unroll
-    for (int k = 0; k < 17; ++k) acc[k] = wave_sum_f64(acc[k]);
-    if (lane != 0) return;
     float *st = state + (size_t)c * kLrState;
     if (n_atoms == 0) {
         for (int k = 0; k < kLrState; ++k) st[k] = 0.f;
         st[0] = st[4] = st[8] = 1.f;
         out[c] = 0.f;
         return;
+    }
+    // the chain's first atom (the shift of the segment sums), loaded ahead of
+    // the sums so that the two latencies overlap
+    const float x0[3] = {x[r0], x[A + r0], x[2 * A + r0]};
+    const float y0[3] = {y[r0], y[A + r0], y[2 * A + r0]};
+    // the chain's segment records, folded in segment order
+    double acc[17];
+#pragma unroll
+    for (int k = 0; k < 17; ++k) acc[k] = part[(size_t)s0 * kLrPart + k];
+    for (int s = s0 + 1; s < s1; ++s) {
+#pragma unroll
+        for (int k = 0; k < 17; ++k) acc[k] += part[(size_t)s * kLrPart + k];
     }
     const double N = (double)n_atoms, inv_N = 1.0 / N;
     const double mx[3] = {acc[0] * inv_N, acc[1] * inv_N, acc[2] * inv_N};
@@ -398,7 +391,8 @@ __global__ __launch_bounds__(kLrThreads) void lr_grad_kernel(
 
 bool lr_ready(const a2c_plan *p)
 {
-    return p->n_chains == 0 || (p->d_lr_chain_seg && (p->lr_n_seg == 0 || p->d_lr_seg_atom));
+    return p->n_chains == 0 ||
+           (p->d_lr_chain_seg && (p->lr_n_seg == 0 || (p->d_lr_seg_atom && p->d_lr_seg_origin)));
 }
 
 }  // namespace
@@ -414,12 +408,14 @@ void build_lrmsd_segments(a2c_plan &p)
 {
     p.lr_seg_atom.clear();
     p.lr_seg_chain.clear();
+    p.lr_seg_origin.clear();
     p.lr_chain_seg.assign(p.n_chains + 1, 0);
     for (int32_t c = 0; c < p.n_chains; ++c) {
         p.lr_chain_seg[c] = (int32_t)p.lr_seg_chain.size();
         for (int64_t a = p.chain_atom_off[c]; a < p.chain_atom_off[c + 1]; a += kLrSegAtoms) {
             p.lr_seg_atom.push_back((int32_t)a);
             p.lr_seg_chain.push_back(c);
+            p.lr_seg_origin.push_back(p.chain_atom_off[c]);
         }
     }
     p.lr_chain_seg[p.n_chains] = (int32_t)p.lr_seg_chain.size();
@@ -480,11 +476,10 @@ a2c_status a2c_lrmsd_forward(a2c_plan *p, const float *d_coords, const float *d_
     float *state = (float *)((char *)d_workspace + (size_t)p->lr_n_seg * kLrPart * sizeof(double));
     if (p->lr_n_seg > 0)
         hipLaunchKernelGGL(lr_partial_kernel, dim3(p->lr_n_seg), dim3(kLrThreads), 0, s, d_coords,
-                           d_target, p->d_lr_seg_atom, p->d_lr_seg_chain, p->d_lr_chain_seg, p->A,
-                           part);
-    const int per_block = kLrThreads / 64;
-    hipLaunchKernelGGL(lr_solve_kernel, dim3((p->n_chains + per_block - 1) / per_block),
-                       dim3(kLrThreads), 0, s, d_coords, d_target, p->d_lr_seg_atom,
+                           d_target, p->d_lr_seg_atom, p->d_lr_seg_origin, p->A, part);
+    hipLaunchKernelGGL(lr_solve_kernel,
+                       dim3((p->n_chains + kLrSolveThreads - 1) / kLrSolveThreads),
+                       dim3(kLrSolveThreads), 0, s, d_coords, d_target, p->d_lr_seg_atom,
                        p->d_lr_chain_seg, p->n_chains, p->A, part, state, d_lrmsd);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? A2C_OK : hip_fail(e, "lrmsd forward launch");
