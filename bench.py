@@ -32,12 +32,18 @@ HBM_PEAK_GBS = 8000.0
 # Backbone, per residue: angles 12 B, coordinates 36 B, upstream gradient
 # 36 B, angle gradient 12 B.  Full-atom, per residue: angles 4 (3 + n_chi) B,
 # residue code 1 B, residue atom offset 4 B, 12 B per atom for coordinates
-# and for their gradient, 28 B of angle gradient (seven planes).
-def algorithmic_bytes(model, kernel, R, A=None, n_chi_total=None):
+# and for their gradient, 28 B of angle gradient (seven planes).  The inverse
+# map reads the three backbone atoms of every residue (neighbours' are the
+# same bytes) and, full-atom, the side atoms its chi torsions use (n_chi + 1
+# for a residue with any chi: the first side frame's origin and one atom per
+# chi), plus the residue code and atom offset; it writes every angle plane.
+def algorithmic_bytes(model, kernel, R, A=None, n_chi_total=None, n_side_used=None):
     if model == "backbone":
         per = {"forward": 12 + 36, "backward_coords": 36 + 36 + 12,
-               "backward_recompute": 12 + 36 + 12}[kernel]
+               "backward_recompute": 12 + 36 + 12, "inverse": 36 + 12}[kernel]
         return per * R
+    if kernel == "inverse":
+        return 36 * R + 12 * n_side_used + 5 * R + 28 * R
     ang = 4 * (3 * R + n_chi_total)
     meta = 5 * R
     return {"forward": ang + meta + 12 * A,
@@ -407,10 +413,12 @@ def main():
     if args.fused:
         kern = {"fused_step": kernel_avg_us(step, args.kernel_reps)}
     dom = max(kern, key=kern.get)
-    n_chi_total = None
+    n_chi_total = n_side_used = None
     if model == "fullatom":
         from paper_1812_01108_amd.residues import default_table
-        n_chi_total = int(np.sum(np.array(default_table().n_chi)[inp["seq"]]))
+        chi_of = np.array(default_table().n_chi)[inp["seq"]]
+        n_chi_total = int(np.sum(chi_of))
+        n_side_used = int(np.sum(chi_of + (chi_of > 0)))
     if args.fused:
         # angles, codes and offsets, the target (12 B per atom), the
         # coordinates written (12 B per atom) and the angle gradient
@@ -429,6 +437,15 @@ def main():
             "kernel": dom,
             "kernel_us": {k: round(v, 3) for k, v in kern.items()},
             "bytes_per_launch": nbytes}
+
+    # the inverse map (coordinates -> angles) on the forward's coordinates
+    back = torch.empty_like(angles)
+    plan.coords_to_angles(coords_buf, out=back)
+    inv_us = kernel_avg_us(lambda: plan.coords_to_angles(coords_buf, out=back), args.kernel_reps)
+    inv_bytes = algorithmic_bytes(model, "inverse", R, plan.n_atoms, n_chi_total, n_side_used)
+    inv_gbs = inv_bytes / (inv_us * 1e-6) / 1e9
+    inverse = {"us": round(inv_us, 3), "bytes_per_launch": inv_bytes,
+               "GBs": round(inv_gbs, 1), "frac": round(inv_gbs / HBM_PEAK_GBS, 4)}
 
     plain = None
     if model == "backbone" and not args.no_plain:
@@ -468,6 +485,7 @@ def main():
                    "adjoint_tiles": asched["n_tiles"], "steps_per_graph": gn[1]},
         "roofline": roof,
         "lrmsd": lr_info,
+        "inverse_map": inverse,
         "plain_gpu": plain,
         "speedup_vs_plain": (value / plain["value"]) if plain else None,
         "cold": cold,

@@ -309,8 +309,12 @@ __global__ __launch_bounds__(kLrSolveThreads) void lr_solve_kernel(
         const double dP = (4.0 * l2 + 2.0 * c2) * lam + c1;
         if (!(dP > 0.0)) break;
         const double step = P / dP;
+        // every exact step from above is positive: a step that is not has
+        // reached the rounding noise of P (which, with a close second
+        // eigenvalue, stays above the relative test below)
+        if (!(step > 0.0)) break;
         lam -= step;
-        if (!(fabs(step) > 1e-15 * fabs(lam))) break;
+        if (!(step > 1e-15 * fabs(lam))) break;
     }
     // eigenvector: the largest column of adj(T - lambda I)
     double M[4][4];

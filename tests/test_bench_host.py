@@ -50,6 +50,21 @@ def test_algorithmic_bytes_per_residue():
             == meta + 24 * A + 28 * R)
 
 
+def test_inverse_map_bytes():
+    """Backbone: three atoms in, three angles out per residue.  Full-atom: a
+    residue with n chi angles reads n + 1 side atoms (none without chi)."""
+    import numpy as np
+    from paper_1812_01108_amd.residues import default_table
+    assert bench.algorithmic_bytes("backbone", "inverse", 10) == 480
+    n_chi = np.array(default_table().n_chi)
+    seq = np.arange(20)
+    used = int(np.sum(n_chi[seq] + (n_chi[seq] > 0)))
+    # glycine and alanine have no chi, so 18 residue types read side atoms
+    assert used == int(n_chi.sum()) + 18
+    assert (bench.algorithmic_bytes("fullatom", "inverse", 20, n_side_used=used)
+            == 20 * (36 + 5 + 28) + 12 * used)
+
+
 def test_traffic_only_for_the_profiled_sources_and_schedule():
     rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
     key, r = next(iter(rec.items()))
