@@ -3,8 +3,9 @@ oracle on the same float32 coordinates, and the round trip through the
 forward map.
 
 Tolerance: each torsion is formed in float32 from coordinate differences
-(bond vectors of ~1.5 A, rounded relative ~1e-7) and atan2f: ~1e-6 rad on
-protein geometry (bond angles near 110-120 degrees); 2e-5 rad is used.  The
+(bond vectors of ~1.5 A, rounded relative ~1e-7) and the library's
+polynomial arctangent (<= 5.3e-7 rad): ~1e-6 rad on protein geometry (bond
+angles near 110-120 degrees); 2e-5 rad is used.  The
 round trip also carries the forward map's coordinate error (<= 1e-3 A at
 L <= 1000, i.e. ~1e-3 rad on a 1.5 A bond), checked at 2e-3 rad."""
 import numpy as np
@@ -113,3 +114,53 @@ def test_empty_plan():
     out = plan.coords_to_angles(e)
     torch.cuda.synchronize()
     assert out.shape == (3, 0)
+
+
+@pytest.mark.parametrize("model", ["backbone", "fullatom"])
+def test_chain_ends_on_workgroup_edges(model):
+    """Each workgroup of 256 residues stages its atoms with one residue on
+    either side; chains here start and end exactly on those edges (and one
+    residue either side of them), against the oracle."""
+    a2c = _a2c()
+    off = offsets_from_lengths([256, 1, 255, 256, 257, 0, 511, 2, 254])
+    R = int(off[-1])
+    rng = np.random.Generator(np.random.PCG64(419))
+    if model == "backbone":
+        ang = make_angles(rng, R, "mixture", 3)
+        xyz = oracle.backbone_forward(off, ang, GEOM).astype(np.float32)
+        plan = a2c.Plan("backbone", offsets=off)
+        ref = inv.backbone_angles(off, xyz.astype(np.float64))
+    else:
+        tab, info = oracle.load_residue_table()
+        seq = random_sequence(rng, R)
+        ang = make_angles(rng, R, "mixture", 7)
+        xyz, aoff = oracle.fullatom_forward(off, seq, ang, GEOM)
+        xyz = xyz.astype(np.float32)
+        plan = a2c.Plan("fullatom", offsets=off, seq=seq)
+        ref = inv.fullatom_angles(off, seq, xyz.astype(np.float64), aoff,
+                                  [i["name"] for i in info], [i["atoms"] for i in info])
+    got = _gpu(plan, xyz)
+    err = float(np.max(np.abs(wrapped(got - ref))))
+    print(f"{model} inverse at workgroup edges: max|dangle|={err:.3e} rad", flush=True)
+    assert err <= TORSION_TOL
+
+
+def test_nan_coordinates_stay_local():
+    """A NaN coordinate gives NaN only in torsions that use that atom: the
+    residue's own angles and its neighbours'; every other angle equals the
+    clean result bit for bit."""
+    a2c = _a2c()
+    off = offsets_from_lengths([300, 400])
+    rng = np.random.Generator(np.random.PCG64(421))
+    ang = make_angles(rng, int(off[-1]), "mixture", 3)
+    xyz = oracle.backbone_forward(off, ang, GEOM).astype(np.float32)
+    plan = a2c.Plan("backbone", offsets=off)
+    clean = _gpu(plan, xyz)
+    j = 450
+    bad = xyz.copy()
+    bad[1, 3 * j + 1] = np.nan  # y of CA_j
+    got = _gpu(plan, bad)
+    assert np.isnan(got[0, j]) and np.isnan(got[1, j]) and np.isnan(got[2, j])
+    far = np.ones(got.shape[1], dtype=bool)
+    far[j - 1:j + 2] = False
+    assert np.array_equal(got[:, far], clean[:, far])
