@@ -237,6 +237,33 @@ def traffic_from_profiles(kernel_key, model, n_units, schedule):
         return None
 
 
+# VALU issue: one wave64 instruction occupies a 16-lane SIMD for 4 cycles
+# (unpacked float32); 256 CUs x 4 SIMDs at 2.4 GHz.
+SIMDS, CLOCK_MHZ, CYCLES_PER_VALU = 1024, 2400.0, 4
+
+
+def valu_issue_from_profiles(kernel_key, model, schedule, kernel_us):
+    """Fraction of the chip's VALU issue rate the kernel used: committed SQ
+    counters (VALU instructions per wave, waves per dispatch) over the
+    kernel's measured duration; valid only for the sources and schedule the
+    counters were taken with."""
+    path = os.path.join(ROOT, "profiles", "valu.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path)).get(kernel_key)
+        if (not rec or rec.get("source_sha") != kernel_source_sha(model)
+                or rec.get("schedule") != list(schedule)):
+            return None
+        issue_us = (rec["waves"] * rec["valu_per_wave"] * CYCLES_PER_VALU
+                    / (SIMDS * CLOCK_MHZ))
+        return {"valu_per_wave": rec["valu_per_wave"], "waves": rec["waves"],
+                "issue_us": round(issue_us, 3), "frac": round(issue_us / kernel_us, 4),
+                "profile": rec["profile"]}
+    except Exception:
+        return None
+
+
 def chain_grad_rel(gpu, ref, off):
     worst = 0.0
     for c in range(len(off) - 1):
@@ -436,7 +463,10 @@ def main():
                 (dom_sched["res_per_lane"], dom_sched["waves_per_group"])),
             "kernel": dom,
             "kernel_us": {k: round(v, 3) for k, v in kern.items()},
-            "bytes_per_launch": nbytes}
+            "bytes_per_launch": nbytes,
+            "valu_issue": valu_issue_from_profiles(
+                f"{cfg.name}:{dom}", model,
+                (dom_sched["res_per_lane"], dom_sched["waves_per_group"]), kern[dom])}
 
     # the inverse map (coordinates -> angles) on the forward's coordinates
     back = torch.empty_like(angles)

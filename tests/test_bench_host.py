@@ -78,3 +78,18 @@ def test_traffic_only_for_the_profiled_sources_and_schedule():
     assert bench.traffic_from_profiles(key, model, r["units"], (K, W + 1)) is None
     assert bench.traffic_from_profiles(key, model, r["units"] + 1, (K, W)) is None
     assert bench.traffic_from_profiles("no_such_workload:forward", model, 1, (K, W)) is None
+
+
+def test_valu_issue_only_for_the_profiled_sources_and_schedule():
+    rec = json.load(open(os.path.join(ROOT, "profiles", "valu.json")))
+    key, r = next(iter(rec.items()))
+    got = bench.valu_issue_from_profiles(key, "backbone", tuple(r["schedule"]), 10.0)
+    if r["source_sha"] == bench.kernel_source_sha("backbone"):
+        issue_us = r["waves"] * r["valu_per_wave"] * 4 / (1024 * 2400.0)
+        assert got["issue_us"] == round(issue_us, 3)
+        assert got["frac"] == round(issue_us / 10.0, 4)
+    else:
+        assert got is None
+    K, W = r["schedule"]
+    assert bench.valu_issue_from_profiles(key, "backbone", (K, W + 1), 10.0) is None
+    assert bench.valu_issue_from_profiles("no_such_workload:forward", "backbone", (K, W), 10.0) is None
