@@ -133,7 +133,7 @@ __global__ __launch_bounds__(kInvThreads) void inverse_kernel(
     const int64_t r0 = (int64_t)blockIdx.x * kInvThreads;
     const int64_t rlo = r0 > 0 ? r0 - 1 : 0;
     const int64_t rhi = r0 + kInvThreads + 1 < R ? r0 + kInvThreads + 1 : R;
-    // atom indices fit in int32 (the plan's atom offsets are int32)
+    // atom indices fit in int32: a plan holds at most INT32_MAX / 16 residues
     const int lo = FA ? res_aoff[rlo] : (int)(3 * rlo);
     const int hi = FA ? res_aoff[rhi] : (int)(3 * rhi);
     const float *__restrict__ px = xyz + lo;
