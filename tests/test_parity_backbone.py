@@ -139,6 +139,14 @@ def test_full_size_workloads(name):
     plan = a2c.Plan("backbone", offsets=off)
     for mode in ("coords", "recompute"):
         _check(plan, off, ang, g, mode=mode, label=name)
+    # the launch configuration bench.py times: the autotuner's forward and
+    # adjoint schedules for this batch (bench.py tunes the same way)
+    a, gd = to_dev(ang), to_dev(g)
+    for mode in ("coords", "recompute"):
+        fs, bs = plan.autotune(a, gd, from_coords=mode == "coords", reps=3)
+        tag = (f"{name} autotuned ({fs['res_per_lane']},{fs['waves_per_group']})/"
+               f"({bs['res_per_lane']},{bs['waves_per_group']})")
+        _check(plan, off, ang, g, mode=mode, label=tag)
 
 
 def test_deterministic_bits():
