@@ -17,8 +17,8 @@ import pytest
 import oracle
 from oracle import lrmsd as olr
 from tests.gpu_util import GRAD_TOL_REL, grad_rel_err, to_dev
-from workloads import (BACKBONE_GEOMETRY, make_angles, offsets_from_lengths, random_sequence,
-                       target_perturbation)
+from workloads import (BACKBONE_GEOMETRY, make_angles, make_inputs, offsets_from_lengths,
+                       random_sequence, target_perturbation)
 
 pytestmark = pytest.mark.gpu
 GEOM = BACKBONE_GEOMETRY
@@ -210,3 +210,24 @@ def test_empty_plan_and_all_empty_chains():
     g = plan.lrmsd_backward(e, e, torch.ones(2, device="cuda:0"), ws)
     torch.cuda.synchronize()
     assert val.cpu().numpy().tolist() == [0.0, 0.0] and g.numel() == 0
+
+
+def test_training_workload_full_size():
+    """The 512-chain full-atom training batch (2.36 M atoms; chains of up to
+    ~17 k atoms, up to five segments each) with the targets of the training
+    step: the layer on perturbed angles, moved by a random rigid motion per
+    chain; values of every chain and gradients against the oracle."""
+    inp = make_inputs("ragged_fullatom_512")
+    off, seq, ang = inp["offsets"], inp["seq"], inp["angles"]
+    seed = inp["config"].seed
+    pert, quat, trans = target_perturbation(seed, ang, inp["n_chains"])
+    y, aoff = oracle.fullatom_forward(off, seq, ang, GEOM)
+    t, _ = oracle.fullatom_forward(off, seq, pert, GEOM)
+    ca = np.asarray(aoff)[off].astype(np.int64)
+    rot = _rotations(quat)
+    x = np.empty_like(t)
+    for c in range(len(ca) - 1):
+        a0, a1 = ca[c], ca[c + 1]
+        x[:, a0:a1] = rot[c] @ t[:, a0:a1] + trans[c][:, None]
+    plan = _plan("fullatom", off, seq)
+    _check(plan, y.astype(np.float32), x.astype(np.float32), ca, seed, "training batch")
