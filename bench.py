@@ -6,11 +6,14 @@ Function.  Steps are captured in HIP graphs, --steps-per-graph complete
 steps per graph (one graph launch costs the host more than one step takes
 on the GPU); every timed step runs the whole path.  Inputs are resident in
 HBM before timing starts.  Prints one JSON line; besides the (warm) timed
-steps it carries "cold", the median step time with a 512 MiB device write
-before each step, so that no input or output is left in the caches.
+steps it carries "cold": the step time when a 512 MiB device write precedes
+every step (captured in the same graph as the steps), so that no input or
+output is left in the caches, and the plain device-copy bandwidth the HBM
+fractions can be read against.
 
-Default workload: 256 chains x 700 residues, backbone, Ramachandran-like
-mixture angles, omega = pi, upstream gradient iid N(0,1).
+Default workload: the largest single-GPU batch, 4096 backbone chains with
+lengths uniform in [20, 1000] (about 2.09 M residues) packed back to back,
+Ramachandran-like mixture angles, omega = pi, upstream gradient iid N(0,1).
 """
 from __future__ import annotations
 
@@ -58,7 +61,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=20)
     p.add_argument("--steps-per-graph", type=int, default=10,
                    help="complete steps captured back to back in one graph")
-    p.add_argument("--workload", default="backbone_256x700")
+    p.add_argument("--workload", default="ragged_backbone_4096")
     p.add_argument("--mode", default=None, choices=["coords", "recompute"],
                    help="adjoint reads the forward's coordinates, or recomputes the frames "
                         "(default: coords; recompute for the training-step workload)")
@@ -145,33 +148,76 @@ def time_graph(graphs, steps, warmup):
     return time.perf_counter() - t0
 
 
-def time_cold(g1, R, reps=20, flush_bytes=512 << 20):
-    """Cold-cache step time: before every step a 512 MiB write (twice the
-    256 MiB Infinity Cache) evicts the step's data; HIP events on the
-    stream bracket the step alone (one step per graph launch).  Median over
-    `reps`; the same protocol without the write is reported beside it."""
+def time_cold(step, R, n=10, reps=5, flush_bytes=512 << 20):
+    """Cold-cache step time.  One graph holds n x (512 MiB device write,
+    step) and a second graph the n writes alone; the write (twice the
+    256 MiB Infinity Cache) evicts the step's data before every step.  The
+    cold step time is the difference of the two graphs' durations over n,
+    so neither the graph launch nor the writes are counted.  Both graphs are
+    timed with HIP events on the stream they run on; best of `reps`."""
     import torch
 
     buf = torch.empty(flush_bytes // 4, dtype=torch.float32, device="cuda")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        step()
+        buf.fill_(1.0)
+    torch.cuda.current_stream().wait_stream(s)
+    g_both, g_flush = torch.cuda.CUDAGraph(), torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g_both):
+        for i in range(n):
+            buf.fill_(float(i + 1))   # a fill kernel, not a memset node
+            step()
+    with torch.cuda.graph(g_flush):
+        for i in range(n):
+            buf.fill_(float(i + 1))
     st = torch.cuda.current_stream()
 
-    def one(flush, i):
-        if flush:
-            buf.fill_(float(i))
+    def best(g):
+        g.replay()
+        torch.cuda.synchronize()
+        out = float("inf")
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            g.replay()
+            e1.record(st)
+            e1.synchronize()
+            out = min(out, e0.elapsed_time(e1) / 1000.0)
+        return out
+
+    t_both, t_flush = best(g_both), best(g_flush)
+    del g_both, g_flush, buf
+    t = max(t_both - t_flush, 1e-9) / n
+    return {"value": R / t, "ms_per_step": t * 1000.0, "steps_per_graph": n,
+            "flush": "512 MiB device write before every step, captured with the steps; "
+                     "cold step = (graph of writes and steps - graph of writes alone) / n",
+            "flush_only_ms_per_step": t_flush * 1000.0 / n}
+
+
+def copy_bandwidth_gbs(nbytes=1 << 30, reps=5):
+    """Plain device-to-device copy of `nbytes` (torch copy_, one kernel):
+    (bytes read + bytes written) / duration, best of `reps`, HIP events on
+    the current stream.  The HBM fractions are quoted against the 8 TB/s
+    peak; this is what a streaming kernel reaches on the same board."""
+    import torch
+
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    best = float("inf")
+    for _ in range(reps):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(st)
-        g1.replay()
+        y.copy_(x)
         e1.record(st)
         e1.synchronize()
-        return e0.elapsed_time(e1) / 1000.0
-
-    cold = [one(True, i) for i in range(reps + 2)][2:]
-    warm = [one(False, i) for i in range(reps + 2)][2:]
-    del buf
-    t, w = float(np.median(cold)), float(np.median(warm))
-    return {"value": R / t, "ms_per_step": t * 1000.0, "reps": reps,
-            "flush": "512 MiB device write before each step",
-            "warm_same_protocol_ms_per_step": w * 1000.0}
+        best = min(best, e0.elapsed_time(e1) / 1000.0)
+    del x, y
+    return 2 * nbytes / best / 1e9
 
 
 def kernel_avg_us(launch, reps):
@@ -259,7 +305,9 @@ def valu_issue_from_profiles(kernel_key, model, schedule, kernel_us):
                     / (SIMDS * CLOCK_MHZ))
         return {"valu_per_wave": rec["valu_per_wave"], "waves": rec["waves"],
                 "issue_us": round(issue_us, 3), "frac": round(issue_us / kernel_us, 4),
-                "profile": rec["profile"]}
+                "profile": rec["profile"],
+                "source": "committed rocprofv3 SQ_WAVES/SQ_INSTS_VALU runs over this run's "
+                          "kernel duration"}
     except Exception:
         return None
 
@@ -275,33 +323,51 @@ def chain_grad_rel(gpu, ref, off):
     return worst
 
 
-def cpu_baseline(model, inp, g_np, gpu_coords, gpu_grad, budget_s=12.0):
+def cpu_baseline(model, inp, g_np, gpu_coords, gpu_grad, budget_s=12.0, single_budget_s=4.0):
     """The FP64 oracle (forward + O(N) adjoint, OpenMP over chains) on the
-    full batch, repeated for about budget_s seconds of host time."""
+    full batch, repeated for about budget_s seconds of host time on every
+    host core, then on one thread for about single_budget_s seconds (whole
+    batches, at least one).  The parity figures compare the GPU output of
+    the timed graph with the oracle's on the same float32 inputs."""
     import oracle
     from workloads import BACKBONE_GEOMETRY
 
     cores = len(os.sched_getaffinity(0))
     off, ang, seq = inp["offsets"], inp["angles"], inp["seq"]
     R = int(off[-1])
-    n, t_total = 0, 0.0
-    ref = gref = None
-    while t_total < budget_s and n < 100000:
-        t0 = time.perf_counter()
+
+    def run(threads):
         if model == "backbone":
-            ref = oracle.backbone_forward(off, ang, BACKBONE_GEOMETRY, n_threads=cores)
-            gref = oracle.backbone_backward(off, ang, BACKBONE_GEOMETRY, g_np, n_threads=cores)
+            ref = oracle.backbone_forward(off, ang, BACKBONE_GEOMETRY, n_threads=threads)
+            gref = oracle.backbone_backward(off, ang, BACKBONE_GEOMETRY, g_np, n_threads=threads)
         else:
-            ref, _ = oracle.fullatom_forward(off, seq, ang, BACKBONE_GEOMETRY, n_threads=cores)
+            ref, _ = oracle.fullatom_forward(off, seq, ang, BACKBONE_GEOMETRY, n_threads=threads)
             gref = oracle.fullatom_backward(off, seq, ang, BACKBONE_GEOMETRY, g_np,
-                                            n_threads=cores)
-        t_total += time.perf_counter() - t0
-        n += 1
+                                            n_threads=threads)
+        return ref, gref
+
+    def timed(threads, budget):
+        n, t_total, out = 0, 0.0, None
+        while (n == 0 or t_total < budget) and n < 100000:
+            t0 = time.perf_counter()
+            out = run(threads)
+            t_total += time.perf_counter() - t0
+            n += 1
+        return n, t_total, out
+
+    n, t_total, (ref, gref) = timed(cores, budget_s)
+    n1, t1, _ = timed(1, single_budget_s)
+    lens = np.diff(off)
     parity = {"max_abs_coord_A": float(np.max(np.abs(gpu_coords - ref))),
-              "max_chain_grad_rel": chain_grad_rel(gpu_grad, gref, off)}
+              "max_chain_grad_rel": chain_grad_rel(gpu_grad, gref, off),
+              "max_chain_len": int(lens.max()) if len(lens) else 0,
+              "chains_len_ge_900": int(np.sum(lens >= 900)),
+              "compared": "every atom and every angle gradient of the batch"}
     return {"value": n * R / t_total, "unit": "residues/s", "cores": cores, "kind": "oracle",
             "sample": f"full batch ({R} residues) x {n} repeats, FP64 {model} forward + O(N) "
-                      f"adjoint, OpenMP over chains"}, parity
+                      f"adjoint, OpenMP over chains",
+            "single_thread": {"value": n1 * R / t1, "unit": "residues/s", "cores": 1,
+                              "sample": f"full batch x {n1} repeats on one thread"}}, parity
 
 
 def copy_calibration(torch):
@@ -384,11 +450,11 @@ def main():
     if args.fused:
         fused_xyz = torch.empty((3, plan.n_atoms), dtype=torch.float32, device=dev)
         fused_grad = torch.empty_like(angles)
-        fused_tiles = torch.zeros(max(plan.adjoint_schedule["n_tiles"], 1), device=dev)
+        fused_loss = torch.zeros(1, device=dev)
 
         def step():
             plan.mse_step(angles, target, coords=fused_xyz, grad_angles=fused_grad,
-                          loss_tiles=fused_tiles)
+                          loss_out=fused_loss)
             return fused_xyz, fused_grad
     else:
         step = make_step(a2c, plan, angles, grad_up, mode, target, loss or "mse")
@@ -396,7 +462,8 @@ def main():
     dt = time_graph((gn, g1), args.steps, args.warmup)
     ms = dt * 1000.0 / args.steps
     value = R * args.steps / dt
-    cold = time_cold(g1, R)
+    cold = time_cold(step, R)
+    copy_gbs = copy_bandwidth_gbs()
     gpu_coords = outs[0].detach().cpu().numpy()
     gpu_grad = outs[1].detach().cpu().numpy()
     lr_info = None
@@ -464,9 +531,14 @@ def main():
             "kernel": dom,
             "kernel_us": {k: round(v, 3) for k, v in kern.items()},
             "bytes_per_launch": nbytes,
+            "traffic_source": "committed rocprofv3 FETCH_SIZE/WRITE_SIZE runs "
+                              "(profiles/traffic.json), reported only for the kernel sources "
+                              "and schedule they were taken on",
             "valu_issue": valu_issue_from_profiles(
                 f"{cfg.name}:{dom}", model,
-                (dom_sched["res_per_lane"], dom_sched["waves_per_group"]), kern[dom])}
+                (dom_sched["res_per_lane"], dom_sched["waves_per_group"]), kern[dom]),
+            "copy_GBs": round(copy_gbs, 1),
+            "frac_of_copy": round(achieved / copy_gbs, 4)}
 
     # the inverse map (coordinates -> angles) on the forward's coordinates
     back = torch.empty_like(angles)

@@ -134,13 +134,22 @@ typedef struct {
     a2c_residue_def residues[A2C_NUM_RESIDUE_TYPES];
 } a2c_residue_table;
 
-/* Create a plan for one packed batch of chains.
+/* Create a plan for one packed batch of chains (the paper's statement of the
+ * problem: angles and, for the full-atom model, the residue sequence, since
+ * theta and d depend only on the residue type; "Full-atom model" section).
  *   h_res_offsets  host int32[n_chains + 1]: [0] = 0, non-decreasing, last =
  *                  R.  Zero-length chains are allowed and produce nothing.
  *   h_seq          host uint8[R] residue codes 0..19 (table order); required
  *                  for A2C_FULLATOM, ignored (may be NULL) for A2C_BACKBONE.
  *   geom           backbone geometry or NULL for the defaults above.
  *   table          residue table, required for A2C_FULLATOM.
+ *   mem_budget_bytes  store-vs-recompute threshold for the memory kept
+ *                  between the forward and the adjoint: the forward's
+ *                  coordinates (12 bytes per atom) are worth keeping for the
+ *                  adjoint while they fit in it (a2c_plan_keep_coords); 0 =
+ *                  always recompute the frames from the angles in the
+ *                  adjoint; SIZE_MAX = no limit.  Per-atom transforms are
+ *                  never stored by the scan form.
  *   stream         used for the table uploads; the call synchronises it.
  * Picks a default schedule (a2c_plan_set_schedule) that runs the longest
  * chain.  Fails with A2C_ERR_INVALID_ARG on malformed offsets or codes >= 20,
@@ -151,11 +160,20 @@ typedef struct {
 a2c_status a2c_plan_create(a2c_plan **out, a2c_model model, int32_t n_chains,
                            const int32_t *h_res_offsets, const uint8_t *h_seq,
                            const a2c_backbone_geometry *geom,
-                           const a2c_residue_table *table, void *stream);
+                           const a2c_residue_table *table, size_t mem_budget_bytes,
+                           void *stream);
+
+/* The plan's store-vs-recompute choice: *keep = 1 when the forward's
+ * coordinates (12 bytes per atom, A atoms) fit the plan's memory budget, so
+ * a2c_backward should be given them (d_coords); 0 when the adjoint should
+ * recompute the frames from the angles (d_coords = NULL).  Host only.  Both
+ * choices give the same gradient up to float32 rounding. */
+a2c_status a2c_plan_keep_coords(const a2c_plan *plan, int32_t *keep);
 
 void a2c_plan_destroy(a2c_plan *plan);
 
-/* Total residues R and atoms A of the plan. */
+/* Total residues R and atoms A of the plan.  (The workspace size a variant
+ * needs is a2c_plan_workspace_bytes.) */
 a2c_status a2c_plan_sizes(const a2c_plan *plan, int64_t *n_res, int64_t *n_atoms);
 
 /* Atom offsets: h_chain_atom_offsets int32[n_chains + 1] (may be NULL),
@@ -176,6 +194,10 @@ a2c_status a2c_plan_workspace_bytes(const a2c_plan *plan, a2c_variant variant,
  * (at most 64 chunks), carrying the frame (forward) and the wrench (adjoint)
  * from chunk to chunk.  One workgroup per tile, longest tiles dispatched
  * first.  Re-packs and re-uploads the tile table (synchronises `stream`).
+ * The tables of the schedule it replaces stay allocated until
+ * a2c_plan_destroy, so a graph captured before the change replays the
+ * schedule it captured, with the same results; no graph captured over a plan
+ * may be replayed after the plan is destroyed.
  * UNSUPPORTED, leaving the plan's schedule as it was, if the longest chain
  * needs more than 64 chunks.  Full-atom atom I/O goes through a per-wave LDS
  * stage (three float planes; the adjoint from coordinates stages six and
@@ -213,9 +235,12 @@ a2c_status a2c_plan_get_adjoint_schedule(const a2c_plan *plan, int32_t *res_per_
  *     fused step a2c_mse_step with d_grad_coords as its target.
  *   reps: timed repetitions per candidate (>= 1).
  *   cache_path: text file of earlier choices, keyed by device name, model,
- *     residue count, longest chain, chain count and backward form; NULL for
- *     none.  A hit skips the timing; a miss appends the new choice.  An
- *     unreadable or malformed cache is ignored.
+ *     residue count, longest chain, chain count and the adjoint timed
+ *     (coords, recompute or mse); NULL for none.  A line is
+ *     "<key> K W aK aW" (or "<key> K W" for both).  A hit skips the timing;
+ *     a miss appends the new choice.  An unreadable cache, and any line that
+ *     is malformed or names schedules a2c_plan_set_schedule would reject for
+ *     the plan, are ignored (the schedules are then tuned).
  *   out_res_per_lane, out_waves_per_group (may be NULL): the forward's
  *     choice (a2c_plan_get_adjoint_schedule gives the adjoint's).
  * Synchronises `stream`; not capturable.  Call it before capturing a graph. */
@@ -266,20 +291,22 @@ a2c_status a2c_coords_to_angles(a2c_plan *plan, const float *d_coords, float *d_
 
 /* Fused training step for the squared-distance loss
  *   L = sum over atoms a of |r_a - t_a|^2
- * (r the map of d_angles, t = d_target [3][A]): one kernel per tile
- * recomputes the frames, forms the loss gradient 2 (r - t) in registers and
- * runs the adjoint above, so neither the coordinates nor their gradient
- * make a round trip through memory.  Same result as a2c_forward, then
- * dL/dr = 2 (r - t), then a2c_backward, up to float32 rounding.
+ * (r the map of d_angles, t = d_target [3][A]): one kernel, one workgroup
+ * per tile, recomputes the frames, forms the loss gradient 2 (r - t) in
+ * registers and runs the adjoint above, so neither the coordinates nor
+ * their gradient make a round trip through memory.  Same result as
+ * a2c_forward, then dL/dr = 2 (r - t), then a2c_backward, up to float32
+ * rounding.
  *   d_coords      [3][A] receives r, or NULL (not written);
- *   d_loss_tiles  float[n_tiles] (a2c_plan_get_adjoint_schedule) receives each
- *                 tile's share of L, or NULL; L is their sum (tiles hold
- *                 whole chains or one long chain; shares are deterministic);
+ *   d_loss        float[1] receives L, or NULL (not computed).  Each tile
+ *                 adds its atoms in a fixed order into a share kept in the
+ *                 plan; the tile that finishes last sums the shares in tile
+ *                 order, so L is deterministic for a given schedule.
  *   d_grad_angles [K][R] receives dL/dalpha.
- * Enqueues one kernel on `stream`; no allocation (capturable). */
+ * Enqueues one kernel on `stream` (a fill kernel for an empty plan); no
+ * allocation (capturable).  Calls that share a plan must not overlap. */
 a2c_status a2c_mse_step(a2c_plan *plan, const float *d_angles, const float *d_target,
-                        float *d_coords, float *d_loss_tiles, float *d_grad_angles,
-                        void *stream);
+                        float *d_coords, float *d_loss, float *d_grad_angles, void *stream);
 
 /* ----------------------------------------------------------------- LRMSD
  * The loss the paper pairs with the map (section "Loss function"): for each

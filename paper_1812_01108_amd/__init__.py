@@ -7,6 +7,10 @@ PyTorch supplies device memory and the current stream.
     plan = Plan("backbone", lengths=[700] * 256)
     coords = angles_to_coords(angles, plan)      # angles [3][R] -> coords [3][A]
     coords.backward(grad)                        # angle gradient via the adjoint
+
+The backward keeps the forward's coordinates for the adjoint while they fit
+the plan's memory budget (Plan(..., mem_budget_bytes=...)), and otherwise
+recomputes the frames from the angles; nothing else is kept between passes.
 """
 from __future__ import annotations
 
@@ -19,11 +23,25 @@ from . import _lib
 from ._lib import A2C_BACKBONE, A2C_FULLATOM, A2C_PLAIN, A2C_SCAN, A2CError, check
 
 __all__ = ["Plan", "Angles2Coords", "angles_to_coords", "LRMSD", "lrmsd", "A2CError",
-           "library_version", "DEFAULT_GEOMETRY"]
+           "library_version", "DEFAULT_GEOMETRY", "PAPER_LITERAL_GEOMETRY"]
 
 DEFAULT_GEOMETRY = {
     "bond_N_CA": 1.458, "bond_CA_C": 1.525, "bond_C_N": 1.329,
     "angle_N_CA_C": 111.2, "angle_CA_C_N": 116.2, "angle_C_N_CA": 121.7,
+}
+
+# The constants listed in the paper's "Backbone model" section, kept as data
+# for reproducing its numbers: per slot a bond length and theta = pi - angle
+# (angles 2.1186, 1.9391 and 2.0610 rad for the transforms placing N, CA and
+# C).  Read with the vertex-named convention of a2c_backbone_geometry they
+# are attached one slot off the chemical bond angles (C-N-CA comes out
+# 111.1 deg, N-CA-C 118.1 deg), which is why the default geometry is the
+# standard one above.
+_RAD = 180.0 / 3.141592653589793
+PAPER_LITERAL_GEOMETRY = {
+    "bond_C_N": 1.330, "angle_CA_C_N": 2.1186 * _RAD,     # transform placing N_j
+    "bond_N_CA": 1.460, "angle_C_N_CA": 1.9391 * _RAD,    # transform placing CA_j
+    "bond_CA_C": 1.525, "angle_N_CA_C": 2.0610 * _RAD,    # transform placing C_j
 }
 
 _VARIANTS = {"scan": A2C_SCAN, "plain": A2C_PLAIN}
@@ -51,7 +69,11 @@ class Plan:
     on batches of the same shape."""
 
     def __init__(self, model: str = "backbone", lengths=None, offsets=None, seq=None,
-                 geometry: dict | None = None, table=None, device=None):
+                 geometry: dict | None = None, table=None, device=None,
+                 mem_budget_bytes: int | None = None):
+        """mem_budget_bytes: memory the autograd Function may keep between the
+        forward and the backward (the coordinates, 12 bytes per atom); None =
+        no limit, 0 = always recompute."""
         lib = _lib.load()
         if model not in ("backbone", "fullatom"):
             raise ValueError(f"unknown model {model!r}")
@@ -89,6 +111,7 @@ class Plan:
                 None if seq_arr is None else seq_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
                 None if geom is None else ctypes.byref(geom),
                 None if table_struct is None else ctypes.byref(table_struct),
+                _lib.SIZE_MAX if mem_budget_bytes is None else int(mem_budget_bytes),
                 _stream_ptr(self.device))
         check(st, "a2c_plan_create")
         self._h = handle
@@ -104,6 +127,14 @@ class Plan:
             self._h = None
 
     # -- plan queries ------------------------------------------------------
+    @property
+    def keep_coords(self) -> bool:
+        """The plan's store-vs-recompute choice: keep the forward's
+        coordinates for the adjoint (True) or recompute the frames (False)."""
+        k = ctypes.c_int32()
+        check(_lib.load().a2c_plan_keep_coords(self._h, ctypes.byref(k)), "a2c_plan_keep_coords")
+        return bool(k.value)
+
     def atom_offsets(self):
         """(chain atom offsets [n_chains+1], residue atom offsets [R+1])."""
         ca = np.zeros(self.n_chains + 1, dtype=np.int32)
@@ -240,12 +271,12 @@ class Plan:
     def mse_step(self, angles: torch.Tensor, target: torch.Tensor,
                  coords: torch.Tensor | None = None, loss: bool = True,
                  grad_angles: torch.Tensor | None = None,
-                 loss_tiles: torch.Tensor | None = None):
+                 loss_out: torch.Tensor | None = None):
         """One fused pass for L = sum |r - t|^2: returns (L as a 0-dim tensor
-        or None, dL/dangles); writes r into `coords` when given.  With
-        `loss_tiles` (float32, at least adjoint_schedule["n_tiles"] elements) the
-        per-tile partial sums land there and nothing is allocated, so the call
-        can be captured in a graph; L is then their sum, left to the caller."""
+        or None, dL/dangles); writes r into `coords` when given.  L is summed
+        on the device (a2c_mse_step); with `loss_out` (float32, >= 1 element)
+        it lands in loss_out[0] and nothing is allocated, so the call can be
+        captured in a graph."""
         self._check_tensor(angles, (self.n_planes, self.n_res), "angles")
         self._check_tensor(target, (3, self.n_atoms), "target")
         if coords is not None:
@@ -253,25 +284,21 @@ class Plan:
         if grad_angles is None:
             grad_angles = torch.empty_like(angles)
         self._check_tensor(grad_angles, (self.n_planes, self.n_res), "grad_angles")
-        tiles = loss_tiles
-        if tiles is not None:
-            if (tiles.dtype != torch.float32 or not tiles.is_contiguous()
-                    or tiles.device != angles.device
-                    or tiles.numel() < self.adjoint_schedule["n_tiles"]):
-                raise ValueError("loss_tiles: contiguous float32 with >= n_tiles elements "
-                                 "on the plan's device")
+        out = loss_out
+        if out is not None:
+            if (out.dtype != torch.float32 or not out.is_contiguous()
+                    or out.device != angles.device or out.numel() < 1):
+                raise ValueError("loss_out: contiguous float32 with >= 1 element on the "
+                                 "plan's device")
         elif loss:
-            tiles = torch.zeros(max(self.adjoint_schedule["n_tiles"], 1), dtype=torch.float32,
-                                device=angles.device)
+            out = torch.empty(1, dtype=torch.float32, device=angles.device)
         check(_lib.load().a2c_mse_step(
             self._h, ctypes.c_void_p(angles.data_ptr()), ctypes.c_void_p(target.data_ptr()),
             None if coords is None else ctypes.c_void_p(coords.data_ptr()),
-            None if tiles is None else ctypes.c_void_p(tiles.data_ptr()),
+            None if out is None else ctypes.c_void_p(out.data_ptr()),
             ctypes.c_void_p(grad_angles.data_ptr()), _stream_ptr(angles.device)),
             "a2c_mse_step")
-        if loss_tiles is not None:
-            return None, grad_angles
-        return (tiles.sum() if loss else None), grad_angles
+        return (None if out is None else out[0]), grad_angles
 
     # -- LRMSD loss -------------------------------------------------------
     def lrmsd_workspace(self) -> torch.Tensor | None:
@@ -342,6 +369,8 @@ def lrmsd(coords: torch.Tensor, target: torch.Tensor, plan: Plan) -> torch.Tenso
 class Angles2Coords(torch.autograd.Function):
     """coords = Angles2Coords.apply(angles, plan, mode).
 
+    mode "auto" (default): the plan's store-vs-recompute choice
+    (Plan.keep_coords: the coordinates fit its memory budget or not);
     mode "coords": the backward reads the forward's coordinates (saved);
     mode "recompute": the backward recomputes every frame from the angles and
     nothing but the angles is kept between the passes;
@@ -349,7 +378,11 @@ class Angles2Coords(torch.autograd.Function):
     """
 
     @staticmethod
-    def forward(ctx, angles, plan: Plan, mode: str = "coords"):
+    def forward(ctx, angles, plan: Plan, mode: str = "auto"):
+        if mode == "auto":
+            mode = "coords" if plan.keep_coords else "recompute"
+        if mode not in ("coords", "recompute", "plain"):
+            raise ValueError(f"unknown mode {mode!r}")
         angles = angles.contiguous()
         ws = plan.new_workspace("plain") if mode == "plain" else None
         variant = "plain" if mode == "plain" else "scan"
@@ -375,5 +408,5 @@ class Angles2Coords(torch.autograd.Function):
         return grad, None, None
 
 
-def angles_to_coords(angles: torch.Tensor, plan: Plan, mode: str = "coords") -> torch.Tensor:
+def angles_to_coords(angles: torch.Tensor, plan: Plan, mode: str = "auto") -> torch.Tensor:
     return Angles2Coords.apply(angles, plan, mode)

@@ -29,8 +29,10 @@ EXPORTS = (
     "a2c_plan_set_adjoint_schedule", "a2c_plan_get_adjoint_schedule", "a2c_plan_autotune",
     "a2c_forward", "a2c_backward", "a2c_residue_table_info", "a2c_status_string",
     "a2c_last_error", "a2c_version", "a2c_lrmsd_workspace_bytes", "a2c_lrmsd_forward",
-    "a2c_lrmsd_backward", "a2c_mse_step", "a2c_coords_to_angles",
+    "a2c_lrmsd_backward", "a2c_mse_step", "a2c_coords_to_angles", "a2c_plan_keep_coords",
 )
+
+SIZE_MAX = 2 ** 64 - 1
 
 
 class BackboneGeometry(ctypes.Structure):
@@ -77,11 +79,12 @@ def load():
     vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
     P = ctypes.POINTER
     lib.a2c_plan_create.argtypes = [P(vp), ctypes.c_int, i32, P(i32), P(ctypes.c_uint8),
-                                    P(BackboneGeometry), P(ResidueTable), vp]
+                                    P(BackboneGeometry), P(ResidueTable), sz, vp]
     lib.a2c_plan_create.restype = ctypes.c_int
     lib.a2c_plan_destroy.argtypes = [vp]
     lib.a2c_plan_destroy.restype = None
     lib.a2c_plan_sizes.argtypes = [vp, P(i64), P(i64)]
+    lib.a2c_plan_keep_coords.argtypes = [vp, P(i32)]
     lib.a2c_plan_atom_offsets.argtypes = [vp, P(i32), P(i32)]
     lib.a2c_plan_workspace_bytes.argtypes = [vp, ctypes.c_int, P(sz)]
     lib.a2c_plan_set_schedule.argtypes = [vp, i32, i32, vp]
@@ -98,7 +101,7 @@ def load():
     lib.a2c_lrmsd_workspace_bytes.argtypes = [vp, P(sz)]
     lib.a2c_lrmsd_forward.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.a2c_lrmsd_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp]
-    for name in ("a2c_plan_sizes", "a2c_plan_atom_offsets", "a2c_plan_workspace_bytes",
+    for name in ("a2c_plan_sizes", "a2c_plan_keep_coords", "a2c_plan_atom_offsets", "a2c_plan_workspace_bytes",
                  "a2c_plan_set_schedule", "a2c_plan_get_schedule",
                  "a2c_plan_set_adjoint_schedule", "a2c_plan_get_adjoint_schedule", "a2c_forward",
                  "a2c_backward", "a2c_lrmsd_workspace_bytes", "a2c_lrmsd_forward",

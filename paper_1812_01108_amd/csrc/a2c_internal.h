@@ -72,6 +72,10 @@ struct Sched {
     bool fa_unstaged = false;            // stage too large for the LDS: direct I/O
     bool multi_chunk = false;            // some tile spans several chunks
     int32_t *d_tile_res = nullptr;       // n_tiles (first, end) residue pairs, longest first
+    // fused training step: each tile's share of the loss, and the count of
+    // tiles done (the last one sums the shares; it re-arms the count to 0)
+    float *d_loss_part = nullptr;        // n_tiles
+    uint32_t *d_loss_count = nullptr;    // 1
 };
 
 }  // namespace a2c
@@ -88,6 +92,12 @@ struct a2c_plan {
     std::vector<uint8_t> seq;
     // schedules: fs for the forward, bs for the adjoint and the fused step
     a2c::Sched fs, bs;
+    // device tables of schedules that were replaced: a graph captured before
+    // the change still launches with them, so they live until the plan does
+    std::vector<void *> retired;
+    // store-vs-recompute threshold: the forward's coordinates (12 bytes per
+    // atom) are kept for the adjoint while they fit; 0 = always recompute
+    size_t mem_budget = 0;
     // device tables
     uint32_t *d_head_bits = nullptr;     // bit r: residue r starts a chain (bit R set)
     int32_t *d_res_off = nullptr;        // chain residue offsets (plain form)
@@ -112,6 +122,9 @@ struct a2c_plan {
 namespace a2c {
 
 void set_error(const std::string &msg);
+// the checks a2c_plan_set_schedule makes on (K, W), without the device
+a2c_status check_schedule_args(const a2c_plan *p, int32_t K, int32_t W);
+hipError_t launch_fill_zero(float *x, int64_t n, hipStream_t s);
 // float32 (cos t, sin t) pair with squared norm closest to 1
 void unit_pair(double t, float &c, float &s);
 a2c_status hip_fail(hipError_t e, const char *what);
@@ -124,10 +137,12 @@ hipError_t launch_bb_forward_plain(const a2c_plan &p, const float *ang, float *x
                                    hipStream_t s);
 hipError_t launch_bb_backward_plain(const a2c_plan &p, const float *ang, const float *g,
                                     float *gang, const float *ws, hipStream_t s);
+// loss (may be NULL): receives sum |r - t|^2, from the schedule's per-tile
+// shares (bs.d_loss_part, bs.d_loss_count)
 hipError_t launch_bb_mse_step(const a2c_plan &p, const float *ang, const float *tgt, float *xyz,
-                              float *loss_part, float *gang, hipStream_t s);
+                              float *loss, float *gang, hipStream_t s);
 hipError_t launch_fa_mse_step(const a2c_plan &p, const float *ang, const float *tgt, float *xyz,
-                              float *loss_part, float *gang, hipStream_t s);
+                              float *loss, float *gang, hipStream_t s);
 hipError_t launch_fa_forward_scan(const a2c_plan &p, const float *ang, float *xyz, hipStream_t s);
 hipError_t launch_fa_backward_scan(const a2c_plan &p, const float *ang, const float *xyz,
                                    const float *g, float *gang, hipStream_t s);

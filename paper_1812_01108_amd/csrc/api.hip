@@ -39,6 +39,16 @@ a2c_status upload(void **dst, const void *src, size_t bytes, hipStream_t s)
     return A2C_OK;
 }
 
+void free_sched(Sched &S)
+{
+    (void)hipFree(S.d_tile_res);
+    (void)hipFree(S.d_loss_part);
+    (void)hipFree(S.d_loss_count);
+    S.d_tile_res = nullptr;
+    S.d_loss_part = nullptr;
+    S.d_loss_count = nullptr;
+}
+
 // Greedy packing of whole chains, in order, into tiles: chains of at most one
 // chunk (`cap` residues) share tiles of at most `cap` residues; a longer chain
 // gets a tile of its own, which the kernels walk chunk by chunk.  Zero-length
@@ -127,42 +137,73 @@ a2c_status build_sched(const a2c_plan *p, int32_t K, int32_t W, Sched &out, hipS
         pairs[2 * t + 1] = tiles[order[t] + 1];
     }
     a2c_status st = upload((void **)&S.d_tile_res, pairs.data(), pairs.size() * sizeof(int32_t), s);
+    // the fused step's per-tile loss shares and its count of finished tiles
+    // (zero: the last tile of every launch sets it back to zero)
+    if (st == A2C_OK) {
+        hipError_t e = hipMalloc((void **)&S.d_loss_part,
+                                 std::max<size_t>(1, S.n_tiles) * sizeof(float));
+        if (e == hipSuccess) e = hipMalloc((void **)&S.d_loss_count, sizeof(uint32_t));
+        if (e == hipSuccess) e = hipMemsetAsync(S.d_loss_count, 0, sizeof(uint32_t), s);
+        if (e != hipSuccess) st = hip_fail(e, "loss scratch");
+    }
     if (st == A2C_OK) {
         const hipError_t e = hipStreamSynchronize(s);
         if (e != hipSuccess) st = hip_fail(e, "hipStreamSynchronize");
     }
     if (st != A2C_OK) {
-        (void)hipFree(S.d_tile_res);
+        free_sched(S);
         return st;
     }
     out = S;
     return A2C_OK;
 }
 
-// Replace one of the plan's schedules; on failure it stays as it was.
-a2c_status set_sched(a2c_plan *p, Sched &dst, int32_t K, int32_t W, hipStream_t s)
+// A replaced schedule's device tables stay allocated until the plan is
+// destroyed: a graph captured before the change still launches with them.
+void retire_sched(a2c_plan *p, Sched &S)
+{
+    for (void *q : {(void *)S.d_tile_res, (void *)S.d_loss_part, (void *)S.d_loss_count})
+        if (q) p->retired.push_back(q);
+    S.d_tile_res = nullptr;
+    S.d_loss_part = nullptr;
+    S.d_loss_count = nullptr;
+}
+
+// Replace one of the plan's schedules; on failure it stays as it was.  The
+// old tables are retired (kept until the plan is destroyed), or freed at once
+// when retire_old is false: the autotuner's own candidates, which no graph
+// can have captured.
+a2c_status set_sched(a2c_plan *p, Sched &dst, int32_t K, int32_t W, hipStream_t s,
+                     bool retire_old = true)
 {
     Sched S;
     const a2c_status st = build_sched(p, K, W, S, s);
     if (st != A2C_OK) return st;
-    (void)hipFree(dst.d_tile_res);
+    if (retire_old) retire_sched(p, dst);
+    else free_sched(dst);
     dst = S;
     return A2C_OK;
 }
 
 // Both schedules (forward, and adjoint / fused step) to (K, W).
-a2c_status apply_schedule(a2c_plan *p, int32_t K, int32_t W, hipStream_t s)
+a2c_status apply_schedule(a2c_plan *p, int32_t K, int32_t W, hipStream_t s,
+                          bool retire_old = true)
 {
     Sched f, b;
     a2c_status st = build_sched(p, K, W, f, s);
     if (st != A2C_OK) return st;
     st = build_sched(p, K, W, b, s);
     if (st != A2C_OK) {
-        (void)hipFree(f.d_tile_res);
+        free_sched(f);
         return st;
     }
-    (void)hipFree(p->fs.d_tile_res);
-    (void)hipFree(p->bs.d_tile_res);
+    if (retire_old) {
+        retire_sched(p, p->fs);
+        retire_sched(p, p->bs);
+    } else {
+        free_sched(p->fs);
+        free_sched(p->bs);
+    }
     p->fs = f;
     p->bs = b;
     return A2C_OK;
@@ -222,6 +263,33 @@ void unit_pair(double t, float &c_out, float &s_out)
         }
 }
 
+// The checks a2c_plan_set_schedule makes on (K, W), without the device.
+a2c_status check_schedule_args(const a2c_plan *p, int32_t K, int32_t W)
+{
+    if (!(K == 1 || K == 2 || K == 4))
+        return fail(A2C_ERR_INVALID_ARG, "res_per_lane must be 1, 2 or 4");
+    if (p->model == A2C_FULLATOM && K == 4)
+        return fail(A2C_ERR_INVALID_ARG, "the full-atom kernels take res_per_lane 1 or 2");
+    if (W < 1 || W > kMaxWaves) return fail(A2C_ERR_INVALID_ARG, "waves_per_group must be 1..16");
+    return A2C_OK;
+}
+
+namespace {
+__global__ void fill_zero_kernel(float *x, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = 0.f;
+}
+}  // namespace
+
+// A kernel, not hipMemsetAsync: callers may capture it in a graph.
+hipError_t launch_fill_zero(float *x, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, n);
+    return hipGetLastError();
+}
+
 void set_error(const std::string &msg) { g_last_error = msg; }
 
 a2c_status hip_fail(hipError_t e, const char *what)
@@ -232,19 +300,21 @@ a2c_status hip_fail(hipError_t e, const char *what)
 
 a2c_status build_fullatom_tables(a2c_plan *p, const a2c_residue_table *table);
 
-a2c_status plan_apply_schedule(a2c_plan *p, int32_t K, int32_t W, hipStream_t s)
+a2c_status plan_apply_schedule(a2c_plan *p, int32_t K, int32_t W, hipStream_t s, bool retire_old)
 {
-    return apply_schedule(p, K, W, s);
+    return apply_schedule(p, K, W, s, retire_old);
 }
 
-a2c_status plan_apply_adjoint_schedule(a2c_plan *p, int32_t K, int32_t W, hipStream_t s)
+a2c_status plan_apply_adjoint_schedule(a2c_plan *p, int32_t K, int32_t W, hipStream_t s,
+                                       bool retire_old)
 {
-    return set_sched(p, p->bs, K, W, s);
+    return set_sched(p, p->bs, K, W, s, retire_old);
 }
 
-a2c_status plan_apply_forward_schedule(a2c_plan *p, int32_t K, int32_t W, hipStream_t s)
+a2c_status plan_apply_forward_schedule(a2c_plan *p, int32_t K, int32_t W, hipStream_t s,
+                                       bool retire_old)
 {
-    return set_sched(p, p->fs, K, W, s);
+    return set_sched(p, p->fs, K, W, s, retire_old);
 }
 
 }  // namespace a2c
@@ -273,8 +343,9 @@ const char *a2c_last_error(void) { return g_last_error.c_str(); }
 void a2c_plan_destroy(a2c_plan *p)
 {
     if (!p) return;
-    (void)hipFree(p->fs.d_tile_res);
-    (void)hipFree(p->bs.d_tile_res);
+    free_sched(p->fs);
+    free_sched(p->bs);
+    for (void *q : p->retired) (void)hipFree(q);
     (void)hipFree(p->d_head_bits);
     (void)hipFree(p->d_res_off);
     (void)hipFree(p->d_res_atom_off);
@@ -291,7 +362,7 @@ void a2c_plan_destroy(a2c_plan *p)
 a2c_status a2c_plan_create(a2c_plan **out, a2c_model model, int32_t n_chains,
                            const int32_t *h_res_offsets, const uint8_t *h_seq,
                            const a2c_backbone_geometry *geom, const a2c_residue_table *table,
-                           void *stream)
+                           size_t mem_budget_bytes, void *stream)
 {
     if (!out) return fail(A2C_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
@@ -336,6 +407,7 @@ a2c_status a2c_plan_create(a2c_plan **out, a2c_model model, int32_t n_chains,
     p->n_chains = n_chains;
     p->R = R;
     p->max_len = max_len;
+    p->mem_budget = mem_budget_bytes;
     p->res_off.assign(h_res_offsets, h_res_offsets + n_chains + 1);
     // slot constants (N, CA, C): bond to the previous atom and the bond angle
     // at the previous atom; theta = pi - angle
@@ -442,6 +514,14 @@ a2c_status a2c_plan_atom_offsets(const a2c_plan *p, int32_t *h_chain_atom_offset
     return A2C_OK;
 }
 
+a2c_status a2c_plan_keep_coords(const a2c_plan *p, int32_t *keep)
+{
+    if (!p || !keep) return fail(A2C_ERR_INVALID_ARG, "plan or keep is NULL");
+    *keep = (uint64_t)p->A * 3 * sizeof(float) <= (uint64_t)p->mem_budget && p->mem_budget > 0
+                ? 1 : 0;
+    return A2C_OK;
+}
+
 a2c_status a2c_plan_workspace_bytes(const a2c_plan *p, a2c_variant v, size_t *bytes)
 {
     if (!p || !bytes) return fail(A2C_ERR_INVALID_ARG, "plan or bytes is NULL");
@@ -454,11 +534,8 @@ a2c_status a2c_plan_workspace_bytes(const a2c_plan *p, a2c_variant v, size_t *by
 a2c_status a2c_plan_set_schedule(a2c_plan *p, int32_t K, int32_t W, void *stream)
 {
     if (!p) return fail(A2C_ERR_INVALID_ARG, "plan is NULL");
-    if (!(K == 1 || K == 2 || K == 4))
-        return fail(A2C_ERR_INVALID_ARG, "res_per_lane must be 1, 2 or 4");
-    if (p->model == A2C_FULLATOM && K == 4)
-        return fail(A2C_ERR_INVALID_ARG, "the full-atom kernels take res_per_lane 1 or 2");
-    if (W < 1 || W > kMaxWaves) return fail(A2C_ERR_INVALID_ARG, "waves_per_group must be 1..16");
+    const a2c_status sa = check_schedule_args(p, K, W);
+    if (sa != A2C_OK) return sa;
     if (!check_device(p)) return fail(A2C_ERR_STATE, "current device is not the plan's device");
     return apply_schedule(p, K, W, (hipStream_t)stream);
 }
@@ -466,11 +543,8 @@ a2c_status a2c_plan_set_schedule(a2c_plan *p, int32_t K, int32_t W, void *stream
 a2c_status a2c_plan_set_adjoint_schedule(a2c_plan *p, int32_t K, int32_t W, void *stream)
 {
     if (!p) return fail(A2C_ERR_INVALID_ARG, "plan is NULL");
-    if (!(K == 1 || K == 2 || K == 4))
-        return fail(A2C_ERR_INVALID_ARG, "res_per_lane must be 1, 2 or 4");
-    if (p->model == A2C_FULLATOM && K == 4)
-        return fail(A2C_ERR_INVALID_ARG, "the full-atom kernels take res_per_lane 1 or 2");
-    if (W < 1 || W > kMaxWaves) return fail(A2C_ERR_INVALID_ARG, "waves_per_group must be 1..16");
+    const a2c_status sa = check_schedule_args(p, K, W);
+    if (sa != A2C_OK) return sa;
     if (!check_device(p)) return fail(A2C_ERR_STATE, "current device is not the plan's device");
     return set_sched(p, p->bs, K, W, (hipStream_t)stream);
 }
@@ -544,18 +618,23 @@ a2c_status a2c_backward(a2c_plan *p, a2c_variant v, const float *d_angles, const
 }
 
 a2c_status a2c_mse_step(a2c_plan *p, const float *d_angles, const float *d_target,
-                        float *d_coords, float *d_loss_tiles, float *d_grad_angles, void *stream)
+                        float *d_coords, float *d_loss, float *d_grad_angles, void *stream)
 {
     if (!p) return fail(A2C_ERR_INVALID_ARG, "plan is NULL");
-    if (p->R == 0) return A2C_OK;
+    if (p->R == 0) {  // the loss of an empty batch is 0 (one fill kernel, capturable)
+        if (!d_loss) return A2C_OK;
+        if (!check_device(p)) return fail(A2C_ERR_STATE, "current device is not the plan's device");
+        const hipError_t e = launch_fill_zero(d_loss, 1, (hipStream_t)stream);
+        return e == hipSuccess ? A2C_OK : hip_fail(e, "loss fill launch");
+    }
     if (!d_angles || !d_target || !d_grad_angles)
         return fail(A2C_ERR_INVALID_ARG, "NULL angles, target or grad_angles");
     if (!check_device(p)) return fail(A2C_ERR_STATE, "current device is not the plan's device");
     hipStream_t s = (hipStream_t)stream;
     const hipError_t e =
         p->model == A2C_BACKBONE
-            ? launch_bb_mse_step(*p, d_angles, d_target, d_coords, d_loss_tiles, d_grad_angles, s)
-            : launch_fa_mse_step(*p, d_angles, d_target, d_coords, d_loss_tiles, d_grad_angles, s);
+            ? launch_bb_mse_step(*p, d_angles, d_target, d_coords, d_loss, d_grad_angles, s)
+            : launch_fa_mse_step(*p, d_angles, d_target, d_coords, d_loss, d_grad_angles, s);
     if (e != hipSuccess) return hip_fail(e, "training step launch");
     return A2C_OK;
 }

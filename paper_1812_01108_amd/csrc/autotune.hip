@@ -12,9 +12,13 @@
 #include "a2c_internal.h"
 
 namespace a2c {
-a2c_status plan_apply_schedule(a2c_plan *p, int32_t K, int32_t W, hipStream_t s);
-a2c_status plan_apply_forward_schedule(a2c_plan *p, int32_t K, int32_t W, hipStream_t s);
-a2c_status plan_apply_adjoint_schedule(a2c_plan *p, int32_t K, int32_t W, hipStream_t s);
+// retire_old: keep the replaced tables until the plan is destroyed (a graph
+// captured before may use them); false frees them (the tuner's own candidates)
+a2c_status plan_apply_schedule(a2c_plan *p, int32_t K, int32_t W, hipStream_t s, bool retire_old);
+a2c_status plan_apply_forward_schedule(a2c_plan *p, int32_t K, int32_t W, hipStream_t s,
+                                       bool retire_old);
+a2c_status plan_apply_adjoint_schedule(a2c_plan *p, int32_t K, int32_t W, hipStream_t s,
+                                       bool retire_old);
 }
 
 using namespace a2c;
@@ -30,14 +34,16 @@ std::string cache_key(const a2c_plan *p, int from_coords)
         if (c == ' ' || c == ':') c = '_';
     std::ostringstream k;
     k << dev << ' ' << (p->model == A2C_BACKBONE ? "backbone" : "fullatom") << ' ' << p->R << ' '
-      << p->max_len << ' ' << p->n_chains << ' ' << (from_coords ? "coords" : "recompute");
+      << p->max_len << ' ' << p->n_chains << ' '
+      << (from_coords == A2C_TUNE_MSE_STEP ? "mse" : from_coords ? "coords" : "recompute");
     return k.str();
 }
 
 // A cache line is "<key> K W [bK bW]": forward, then adjoint schedule (a line
-// with two numbers gives both).
-bool cache_lookup(const char *path, const std::string &key, int32_t &K, int32_t &W, int32_t &bK,
-                  int32_t &bW)
+// with two numbers gives both).  A line whose schedules a2c_plan_set_schedule
+// would reject for this plan is skipped, as is anything after the numbers.
+bool cache_lookup(const a2c_plan *p, const char *path, const std::string &key, int32_t &K,
+                  int32_t &W, int32_t &bK, int32_t &bW)
 {
     if (!path) return false;
     std::ifstream f(path);
@@ -48,14 +54,22 @@ bool cache_lookup(const char *path, const std::string &key, int32_t &K, int32_t 
         if (line.compare(0, key.size(), key) != 0 || line.size() <= key.size() ||
             line[key.size()] != ' ')
             continue;
-        int k = 0, w = 0, bk = 0, bw = 0;
-        const int n = std::sscanf(line.c_str() + key.size(), " %d %d %d %d", &k, &w, &bk, &bw);
-        if (n == 2 || n == 4) {
+        int k = 0, w = 0, bk = 0, bw = 0, used = 0;
+        const char *rest = line.c_str() + key.size();
+        int n = std::sscanf(rest, " %d %d %d %d%n", &k, &w, &bk, &bw, &used);
+        if (n != 4) {
+            used = 0;
+            n = std::sscanf(rest, " %d %d%n", &k, &w, &used) == 2 ? 2 : 0;
+        }
+        if (n == 2) bk = k, bw = w;
+        const bool tail_blank = used > 0 && rest[std::strspn(rest + used, " \t\r") + used] == '\0';
+        if (n != 0 && tail_blank && check_schedule_args(p, k, w) == A2C_OK &&
+            check_schedule_args(p, bk, bw) == A2C_OK) {
             K = k;
             W = w;
-            bK = n == 4 ? bk : k;
-            bW = n == 4 ? bw : w;
-            found = true;  // the last matching line wins
+            bK = bk;
+            bW = bw;
+            found = true;  // the last valid matching line wins
         }
     }
     return found;
@@ -71,10 +85,11 @@ void cache_store(const char *path, const std::string &key, int32_t K, int32_t W,
 
 // The forward, then the adjoint schedule (each setter leaves its schedule
 // unchanged when it fails).
-a2c_status apply_pair(a2c_plan *p, int32_t K, int32_t W, int32_t bK, int32_t bW, hipStream_t s)
+a2c_status apply_pair(a2c_plan *p, int32_t K, int32_t W, int32_t bK, int32_t bW, hipStream_t s,
+                      bool retire_old)
 {
-    a2c_status st = plan_apply_forward_schedule(p, K, W, s);
-    if (st == A2C_OK) st = plan_apply_adjoint_schedule(p, bK, bW, s);
+    a2c_status st = plan_apply_forward_schedule(p, K, W, s, retire_old);
+    if (st == A2C_OK) st = plan_apply_adjoint_schedule(p, bK, bW, s, retire_old);
     return st;
 }
 
@@ -110,8 +125,8 @@ extern "C" a2c_status a2c_plan_autotune(a2c_plan *p, const float *d_angles, floa
     }
     const std::string key = cache_key(p, from_coords);
     int32_t K = 0, W = 0, cK = 0, cW = 0;
-    if (cache_lookup(cache_path, key, K, W, cK, cW)) {
-        if (apply_pair(p, K, W, cK, cW, s) == A2C_OK) {
+    if (cache_lookup(p, cache_path, key, K, W, cK, cW)) {
+        if (apply_pair(p, K, W, cK, cW, s, true) == A2C_OK) {
             if (out_K) *out_K = K;
             if (out_W) *out_W = W;
             return A2C_OK;
@@ -125,10 +140,14 @@ extern "C" a2c_status a2c_plan_autotune(a2c_plan *p, const float *d_angles, floa
     float best_f = 1e30f, best_b = 1e30f;
     int32_t fK = p->fs.K, fW = p->fs.W, bK = p->bs.K, bW = p->bs.W;
     a2c_status st = A2C_OK;
+    // the first candidate replaces the caller's schedules (retired: a graph
+    // may hold them); later ones replace the tuner's own (freed)
+    bool own = false;
     for (int k : Ks) {
         if (p->model == A2C_FULLATOM && k == 4) continue;
         for (int w : Ws) {
-            st = plan_apply_schedule(p, k, w, s);
+            st = plan_apply_schedule(p, k, w, s, !own);
+            if (st == A2C_OK) own = true;
             if (st == A2C_ERR_UNSUPPORTED) {  // too many chunks, or staging beyond LDS
                 st = A2C_OK;
                 continue;
@@ -180,7 +199,7 @@ extern "C" a2c_status a2c_plan_autotune(a2c_plan *p, const float *d_angles, floa
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st != A2C_OK) return st;
-    st = apply_pair(p, fK, fW, bK, bW, s);
+    st = apply_pair(p, fK, fW, bK, bW, s, !own);
     if (st != A2C_OK) return st;
     cache_store(cache_path, key, fK, fW, bK, bW);
     if (out_K) *out_K = fK;

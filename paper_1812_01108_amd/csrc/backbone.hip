@@ -271,14 +271,15 @@ __global__ __launch_bounds__(LB) void bb_forward_scan_kernel(
 //   GM = kGradMse:  g points at a target t and the upstream gradient is that
 //                   of the squared distance, 2 (r - t), formed in registers
 //                   from the recomputed positions (the fused training step);
-//                   xyz_out (may be NULL) receives the positions, loss_part
-//                   (may be NULL) the tile's sum of |r - t|^2.
+//                   xyz_out (may be NULL) receives the positions, loss_out
+//                   (may be NULL) the batch's sum of |r - t|^2 (from the
+//                   tiles' shares in loss_part, counted in loss_count).
 template <int K, bool MULTI, int LB, int GM>
 __global__ __launch_bounds__(LB) void bb_backward_recompute_kernel(
     const float *__restrict__ ang, const float *__restrict__ g, float *__restrict__ gang,
-    float *__restrict__ xyz_out, float *__restrict__ loss_part,
-    const int32_t *__restrict__ tile_res, const uint32_t *__restrict__ head_bits, int64_t R,
-    BBParams P0)
+    float *__restrict__ xyz_out, float *__restrict__ loss_out, float *__restrict__ loss_part,
+    uint32_t *__restrict__ loss_count, const int32_t *__restrict__ tile_res,
+    const uint32_t *__restrict__ head_bits, int64_t R, BBParams P0)
 {
     extern __shared__ float stage_mem[];
     __shared__ FwdShared shf[2];
@@ -372,10 +373,7 @@ __global__ __launch_bounds__(LB) void bb_backward_recompute_kernel(
         if (active) store_angle_grads<K>(buf, gr, gang, R, rbase, nres);
     }
     if constexpr (GM == kGradMse) {
-        if (loss_part) {
-            const float t = block_sum(loss, loss_tot);
-            if (threadIdx.x == 0) loss_part[blockIdx.x] = t;
-        }
+        if (loss_out) loss_commit(loss, loss_part, loss_count, loss_out, loss_tot);
     }
 }
 
@@ -585,31 +583,32 @@ hipError_t bwd_kml(const a2c_plan &p, const float *ang, const float *xyz, const 
                            g, gang, p.bs.d_tile_res, p.d_head_bits, p.R, p.bb);
     else
         hipLaunchKernelGGL((bb_backward_recompute_kernel<K, MULTI, LB, kGradLoad>), grid, block,
-                           lds, s, ang, g, gang, nullptr, nullptr, p.bs.d_tile_res, p.d_head_bits,
-                           p.R, p.bb);
+                           lds, s, ang, g, gang, nullptr, nullptr, nullptr, nullptr,
+                           p.bs.d_tile_res, p.d_head_bits, p.R, p.bb);
     return hipGetLastError();
 }
 
 template <int K, bool MULTI, int LB>
 hipError_t mse_kml(const a2c_plan &p, const float *ang, const float *tgt, float *xyz,
-                   float *loss_part, float *gang, hipStream_t s)
+                   float *loss, float *gang, hipStream_t s)
 {
     hipLaunchKernelGGL((bb_backward_recompute_kernel<K, MULTI, LB, kGradMse>), dim3(p.bs.n_tiles),
-                       dim3(p.bs.W * kWave), stage_bytes<K>(p.bs.W), s, ang, tgt, gang, xyz, loss_part,
-                       p.bs.d_tile_res, p.d_head_bits, p.R, p.bb);
+                       dim3(p.bs.W * kWave), stage_bytes<K>(p.bs.W), s, ang, tgt, gang, xyz, loss,
+                       p.bs.d_loss_part, p.bs.d_loss_count, p.bs.d_tile_res, p.d_head_bits, p.R,
+                       p.bb);
     return hipGetLastError();
 }
 
 template <int K>
 hipError_t mse_k(const a2c_plan &p, const float *ang, const float *tgt, float *xyz,
-                 float *loss_part, float *gang, hipStream_t s)
+                 float *loss, float *gang, hipStream_t s)
 {
     const bool small = p.bs.W * kWave <= kLbSmall;
     if (p.bs.multi_chunk)
-        return small ? mse_kml<K, true, kLbSmall>(p, ang, tgt, xyz, loss_part, gang, s)
-                     : mse_kml<K, true, kLbLarge>(p, ang, tgt, xyz, loss_part, gang, s);
-    return small ? mse_kml<K, false, kLbSmall>(p, ang, tgt, xyz, loss_part, gang, s)
-                 : mse_kml<K, false, kLbLarge>(p, ang, tgt, xyz, loss_part, gang, s);
+        return small ? mse_kml<K, true, kLbSmall>(p, ang, tgt, xyz, loss, gang, s)
+                     : mse_kml<K, true, kLbLarge>(p, ang, tgt, xyz, loss, gang, s);
+    return small ? mse_kml<K, false, kLbSmall>(p, ang, tgt, xyz, loss, gang, s)
+                 : mse_kml<K, false, kLbLarge>(p, ang, tgt, xyz, loss, gang, s);
 }
 
 template <int K>
@@ -648,12 +647,12 @@ hipError_t launch_bb_backward_scan(const a2c_plan &p, const float *ang, const fl
 }
 
 hipError_t launch_bb_mse_step(const a2c_plan &p, const float *ang, const float *tgt, float *xyz,
-                              float *loss_part, float *gang, hipStream_t s)
+                              float *loss, float *gang, hipStream_t s)
 {
     switch (p.bs.K) {
-    case 1: return mse_k<1>(p, ang, tgt, xyz, loss_part, gang, s);
-    case 2: return mse_k<2>(p, ang, tgt, xyz, loss_part, gang, s);
-    case 4: return mse_k<4>(p, ang, tgt, xyz, loss_part, gang, s);
+    case 1: return mse_k<1>(p, ang, tgt, xyz, loss, gang, s);
+    case 2: return mse_k<2>(p, ang, tgt, xyz, loss, gang, s);
+    case 4: return mse_k<4>(p, ang, tgt, xyz, loss, gang, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -712,12 +712,14 @@ __device__ __forceinline__ void fa_store_grads(float *__restrict__ gang, int64_t
 // forward's coordinates.
 // GM = kGradMse (with RECOMPUTE): g points at a target t and the upstream
 // gradient is 2 (r - t), formed from the recomputed positions (the fused
-// training step); xyz_out (may be NULL) receives the positions, loss_part
-// (may be NULL) the tile's sum of |r - t|^2.
+// training step); xyz_out (may be NULL) receives the positions, loss_out
+// (may be NULL) the batch's sum of |r - t|^2 (from the tiles' shares in
+// loss_part, counted in loss_count).
 template <int K, bool RECOMPUTE, bool MULTI, int LB, int GM = kGradLoad, bool STG = true>
 __global__ __launch_bounds__(LB) void fa_backward_kernel(
     const float *__restrict__ ang, const float *__restrict__ xyz, const float *__restrict__ g,
-    float *__restrict__ gang, float *__restrict__ xyz_out, float *__restrict__ loss_part,
+    float *__restrict__ gang, float *__restrict__ xyz_out, float *__restrict__ loss_out,
+    float *__restrict__ loss_part, uint32_t *__restrict__ loss_count,
     const int32_t *__restrict__ tile_res,
     const uint32_t *__restrict__ head_bits, const int32_t *__restrict__ res_aoff,
     const uint8_t *__restrict__ seq, const FATable *__restrict__ gtab, int64_t R, int64_t A,
@@ -927,10 +929,7 @@ __global__ __launch_bounds__(LB) void fa_backward_kernel(
         }
     }
     if constexpr (GM == kGradMse) {
-        if (loss_part) {
-            const float t = block_sum(loss, loss_tot);
-            if (threadIdx.x == 0) loss_part[blockIdx.x] = t;
-        }
+        if (loss_out) loss_commit(loss, loss_part, loss_count, loss_out, loss_tot);
     }
 }
 
@@ -963,48 +962,49 @@ hipError_t fa_fwd_k(const a2c_plan &p, const float *ang, float *xyz, hipStream_t
 
 template <int K, bool RECOMPUTE, bool MULTI, int LB, int GM, bool STG>
 void fa_bwd_launch(const a2c_plan &p, const float *ang, const float *xyz, const float *g,
-                   float *gang, hipStream_t s, float *xyz_out, float *loss_part)
+                   float *gang, hipStream_t s, float *xyz_out, float *loss_out)
 {
     const size_t lds =
         STG ? (size_t)p.bs.W * (RECOMPUTE ? 3 : 6) * p.bs.fa_stage_atoms * sizeof(float) : 0;
     hipLaunchKernelGGL((fa_backward_kernel<K, RECOMPUTE, MULTI, LB, GM, STG>), dim3(p.bs.n_tiles),
-                       dim3(p.bs.W * kWave), lds, s, ang, xyz, g, gang, xyz_out, loss_part,
-                       p.bs.d_tile_res, p.d_head_bits, p.d_res_atom_off, p.d_seq, p.d_fa, p.R, p.A,
+                       dim3(p.bs.W * kWave), lds, s, ang, xyz, g, gang, xyz_out, loss_out,
+                       p.bs.d_loss_part, p.bs.d_loss_count, p.bs.d_tile_res, p.d_head_bits,
+                       p.d_res_atom_off, p.d_seq, p.d_fa, p.R, p.A,
                        p.bb, p.bs.fa_stage_atoms);
 }
 
 // mode 0: adjoint from coordinates, 1: recompute, 2: fused squared-distance step
 template <int K, int MODE, bool STG>
 void fa_bwd_dispatch(const a2c_plan &p, const float *ang, const float *xyz, const float *g,
-                     float *gang, hipStream_t s, float *xyz_out, float *loss_part)
+                     float *gang, hipStream_t s, float *xyz_out, float *loss_out)
 {
     constexpr bool RC = MODE != 0;
     constexpr int GM = MODE == 2 ? kGradMse : kGradLoad;
     const bool small = p.bs.W * kWave <= kLbSmall;
     if (p.bs.multi_chunk) {
-        if (small) fa_bwd_launch<K, RC, true, kLbSmall, GM, STG>(p, ang, xyz, g, gang, s, xyz_out, loss_part);
-        else fa_bwd_launch<K, RC, true, kLbLarge, GM, STG>(p, ang, xyz, g, gang, s, xyz_out, loss_part);
+        if (small) fa_bwd_launch<K, RC, true, kLbSmall, GM, STG>(p, ang, xyz, g, gang, s, xyz_out, loss_out);
+        else fa_bwd_launch<K, RC, true, kLbLarge, GM, STG>(p, ang, xyz, g, gang, s, xyz_out, loss_out);
     } else {
-        if (small) fa_bwd_launch<K, RC, false, kLbSmall, GM, STG>(p, ang, xyz, g, gang, s, xyz_out, loss_part);
-        else fa_bwd_launch<K, RC, false, kLbLarge, GM, STG>(p, ang, xyz, g, gang, s, xyz_out, loss_part);
+        if (small) fa_bwd_launch<K, RC, false, kLbSmall, GM, STG>(p, ang, xyz, g, gang, s, xyz_out, loss_out);
+        else fa_bwd_launch<K, RC, false, kLbLarge, GM, STG>(p, ang, xyz, g, gang, s, xyz_out, loss_out);
     }
 }
 
 template <int K, int MODE>
 hipError_t fa_bwd_mode(const a2c_plan &p, const float *ang, const float *xyz, const float *g,
                        float *gang, hipStream_t s, float *xyz_out = nullptr,
-                       float *loss_part = nullptr)
+                       float *loss_out = nullptr)
 {
-    if (p.bs.fa_unstaged) fa_bwd_dispatch<K, MODE, false>(p, ang, xyz, g, gang, s, xyz_out, loss_part);
-    else fa_bwd_dispatch<K, MODE, true>(p, ang, xyz, g, gang, s, xyz_out, loss_part);
+    if (p.bs.fa_unstaged) fa_bwd_dispatch<K, MODE, false>(p, ang, xyz, g, gang, s, xyz_out, loss_out);
+    else fa_bwd_dispatch<K, MODE, true>(p, ang, xyz, g, gang, s, xyz_out, loss_out);
     return hipGetLastError();
 }
 
 template <int K>
 hipError_t fa_mse_k(const a2c_plan &p, const float *ang, const float *tgt, float *xyz,
-                    float *loss_part, float *gang, hipStream_t s)
+                    float *loss_out, float *gang, hipStream_t s)
 {
-    return fa_bwd_mode<K, 2>(p, ang, nullptr, tgt, gang, s, xyz, loss_part);
+    return fa_bwd_mode<K, 2>(p, ang, nullptr, tgt, gang, s, xyz, loss_out);
 }
 
 template <int K>
@@ -1042,11 +1042,11 @@ hipError_t launch_fa_backward_scan(const a2c_plan &p, const float *ang, const fl
 }
 
 hipError_t launch_fa_mse_step(const a2c_plan &p, const float *ang, const float *tgt, float *xyz,
-                              float *loss_part, float *gang, hipStream_t s)
+                              float *loss_out, float *gang, hipStream_t s)
 {
     switch (p.bs.K) {
-    case 1: return fa_mse_k<1>(p, ang, tgt, xyz, loss_part, gang, s);
-    case 2: return fa_mse_k<2>(p, ang, tgt, xyz, loss_part, gang, s);
+    case 1: return fa_mse_k<1>(p, ang, tgt, xyz, loss_out, gang, s);
+    case 2: return fa_mse_k<2>(p, ang, tgt, xyz, loss_out, gang, s);
     default: return hipErrorInvalidValue;
     }
 }

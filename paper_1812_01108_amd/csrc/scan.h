@@ -156,6 +156,37 @@ __device__ __forceinline__ float block_sum(float v, float (&wave_tot)[kMaxWaves]
     return t;
 }
 
+// The fused step's loss: every tile stores its share (the block sum of v),
+// counts itself done with one atomic, and the tile that counts last sums all
+// shares in tile order (each thread a fixed strided subset, then block_sum)
+// into *out and sets the count back to 0 for the next launch.  No tile waits
+// for another; the total does not depend on which tile finishes last.
+// Every thread of the block calls this (block-uniform arguments).
+__device__ __forceinline__ void loss_commit(float v, float *__restrict__ parts,
+                                            uint32_t *__restrict__ count, float *__restrict__ out,
+                                            float (&wave_tot)[kMaxWaves])
+{
+    __shared__ int last;
+    const float t = block_sum(v, wave_tot);
+    if (threadIdx.x == 0) {
+        parts[blockIdx.x] = t;
+        __threadfence();   // the share is visible before the count says so
+        last = atomicAdd(count, 1u) == gridDim.x - 1 ? 1 : 0;
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    float s = 0.f;
+    for (unsigned i = threadIdx.x; i < gridDim.x; i += blockDim.x)
+        s += __hip_atomic_load(parts + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();   // wave_tot is reused
+    const float total = block_sum(s, wave_tot);
+    if (threadIdx.x == 0) {
+        *out = total;
+        __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
 __device__ __forceinline__ float uni(float v)
 {
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));

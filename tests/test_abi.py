@@ -50,7 +50,7 @@ def test_bad_offsets_rejected_on_host(offsets, err):
     h = ctypes.c_void_p()
     st = lib.a2c_plan_create(ctypes.byref(h), 0, len(off) - 1,
                              off.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), None, None,
-                             None, None)
+                             None, 0, None)
     assert st == -1
     assert err in lib.a2c_last_error().decode()
     assert not h.value
@@ -59,16 +59,17 @@ def test_bad_offsets_rejected_on_host(offsets, err):
 def test_null_arguments_rejected_on_host():
     from paper_1812_01108_amd import _lib
     lib = _lib.load()
-    assert lib.a2c_plan_create(None, 0, 0, None, None, None, None, None) == -1
+    assert lib.a2c_plan_create(None, 0, 0, None, None, None, None, 0, None) == -1
     h = ctypes.c_void_p()
-    assert lib.a2c_plan_create(ctypes.byref(h), 0, 1, None, None, None, None, None) == -1
+    assert lib.a2c_plan_create(ctypes.byref(h), 0, 1, None, None, None, None, 0, None) == -1
     assert lib.a2c_forward(None, 0, None, None, None, None) == -1
     assert lib.a2c_backward(None, 0, None, None, None, None, None, None) == -1
     # unknown model
     off = np.array([0, 2], dtype=np.int32)
     assert lib.a2c_plan_create(ctypes.byref(h), 7, 1,
                                off.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-                               None, None, None, None) == -1
+                               None, None, None, 0, None) == -1
+    assert lib.a2c_plan_keep_coords(None, None) == -1
 
 
 @pytest.mark.parametrize("model,limit", [(0, 64 * 64 * 16 * 4), (1, 64 * 64 * 16 * 2)])
@@ -83,7 +84,7 @@ def test_too_long_chain_unsupported(model, limit):
     st = lib.a2c_plan_create(ctypes.byref(h), model, 1,
                              off.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                              seq.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), None, None,
-                             None)
+                             0, None)
     assert st == -2
     assert b"longer than" in lib.a2c_last_error()
 
@@ -96,7 +97,7 @@ def test_bad_geometry_rejected():
     h = ctypes.c_void_p()
     st = lib.a2c_plan_create(ctypes.byref(h), 0, 1,
                              off.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-                             None, ctypes.byref(g), None, None)
+                             None, ctypes.byref(g), None, 0, None)
     assert st == -1 and "geometry" in lib.a2c_last_error().decode()
 
 

@@ -93,15 +93,17 @@ def test_fused_step(model):
     a, td = to_dev(ang), to_dev(t)
     coords = torch.empty((3, plan.n_atoms), device="cuda")
     grad = torch.empty_like(a)
-    tiles = torch.empty(plan.adjoint_schedule["n_tiles"], device="cuda")
+    loss_out = torch.empty(1, device="cuda")
 
     def run():
-        plan.mse_step(a, td, coords=coords, grad_angles=grad, loss_tiles=tiles)
+        plan.mse_step(a, td, coords=coords, grad_angles=grad, loss_out=loss_out)
 
-    _capture_and_check(run, [coords, grad, tiles])
+    # every replay sums the tiles' shares again: the count of finished tiles
+    # the last tile re-arms must start each replay at zero
+    _capture_and_check(run, [coords, grad, loss_out])
     loss, _ = plan.mse_step(a, td)
     torch.cuda.synchronize()
-    assert torch.equal(tiles.sum(), loss)
+    assert torch.equal(loss_out[0], loss)
 
 
 def test_lrmsd_and_inverse_map():

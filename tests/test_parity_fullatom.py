@@ -125,8 +125,8 @@ def test_full_size_workloads(name):
     off, seq, ang = inp["offsets"], inp["seq"], inp["angles"]
     plan = a2c.Plan("fullatom", offsets=off, seq=seq)
     # chains of the ragged batch reach 2000 residues; the stated 1e-3 A bound
-    # is at L = 1000
-    tol = COORD_TOL_A if name == "fullatom_64x300" else 2e-3
+    # is at L = 1000, and 9.5e-4 A is what the kernels reach on this batch
+    tol = COORD_TOL_A if name == "fullatom_64x300" else 1.2e-3
     for mode in ("coords", "recompute"):
         _check(plan, off, seq, ang, mode, label=name, coord_tol=tol)
     # the launch configuration bench.py times: the autotuner's schedules for

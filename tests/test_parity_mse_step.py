@@ -120,9 +120,10 @@ def test_training_workload_full_size():
     pert, _, _ = target_perturbation(inp["config"].seed, ang, inp["n_chains"])
     t, _ = oracle.fullatom_forward(off, seq, pert, GEOM)
     plan = a2c.Plan("fullatom", offsets=off, seq=seq)
-    # chains reach 2000 residues; the stated 1e-3 A bound is at L = 1000
+    # chains reach 2000 residues; the stated 1e-3 A bound is at L = 1000, and
+    # 9.5e-4 A is what the kernels reach on this batch
     _run(plan, "fullatom", off, seq, ang, t.astype(np.float32), "ragged_fullatom_512",
-         coord_tol=2e-3)
+         coord_tol=1.2e-3)
 
 
 def test_optional_outputs_and_empty_plan():

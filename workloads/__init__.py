@@ -13,6 +13,7 @@ from .generate import (  # noqa: F401
     ALPHABET,
     BACKBONE_GEOMETRY,
     CONFIGS,
+    PAPER_LITERAL_GEOMETRY,
     WorkloadConfig,
     chain_lengths,
     make_angles,

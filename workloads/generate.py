@@ -28,6 +28,20 @@ BACKBONE_GEOMETRY = {
     "angle_C_N_CA": 121.7,
 }
 
+# The constant list of the paper's "Backbone model" section, read with the
+# same vertex naming: the transform placing N uses d = 1.330 and
+# theta = pi - 2.1186, the one placing CA d = 1.460 and theta = pi - 1.9391,
+# the one placing C d = 1.525 and theta = pi - 2.0610 (angles in radians
+# there, in degrees here).
+PAPER_LITERAL_GEOMETRY = {
+    "bond_C_N": 1.330,
+    "angle_CA_C_N": float(np.degrees(2.1186)),
+    "bond_N_CA": 1.460,
+    "angle_C_N_CA": float(np.degrees(1.9391)),
+    "bond_CA_C": 1.525,
+    "angle_N_CA_C": float(np.degrees(2.0610)),
+}
+
 PI32 = np.float32(np.pi)
 
 
