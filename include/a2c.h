@@ -344,6 +344,28 @@ a2c_status a2c_lrmsd_backward(a2c_plan *plan, const float *d_coords, const float
                               const float *d_grad_lrmsd, float *d_grad_coords,
                               const void *d_workspace, void *stream);
 
+/* No-allocation form of a2c_lrmsd_forward, for callers that cannot allocate
+ * device memory: code under graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments (without the workspace), kernels
+ * and results (bit for bit) as a2c_lrmsd_forward; the segment sums and
+ * per-chain state go to a fixed array of A2C_LRMSD_STATIC_BYTES (4 MiB)
+ * that the library holds on every device it runs on, from module load until
+ * the process ends, instead of a caller's workspace.  Allocates and frees
+ * nothing; its device address is taken when a plan is created on that
+ * device.
+ *   Fails with A2C_ERR_WORKSPACE, before anything is enqueued, when the plan
+ *   needs more (a2c_lrmsd_workspace_bytes > A2C_LRMSD_STATIC_BYTES: 144
+ *   bytes per segment of up to 4096 atoms of one chain plus 64 per chain,
+ *   e.g. about 20 000 short chains or 28 000 segments).
+ *   Every call on a device shares that device's array and leaves its
+ *   contents there: calls that overlap on one device (several streams or
+ *   threads) race and give wrong results.  a2c_lrmsd_backward takes a
+ *   caller's workspace, never this array.
+ * Two kernels on `stream`, no synchronisation (capturable). */
+#define A2C_LRMSD_STATIC_BYTES (4u << 20)
+a2c_status a2c_lrmsd_forward_noalloc(a2c_plan *plan, const float *d_coords,
+                                     const float *d_target, float *d_lrmsd, void *stream);
+
 /* Host-only check of a residue table (no device needed): validates it as
  * a2c_plan_create would and reports, per residue type, the atom count
  * (n_atoms int32[20], may be NULL) and the standard position r° of every

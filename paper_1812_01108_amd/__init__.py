@@ -325,6 +325,20 @@ class Plan:
             _stream_ptr(coords.device)), "a2c_lrmsd_forward")
         return out
 
+    def lrmsd_forward_noalloc(self, coords: torch.Tensor, target: torch.Tensor,
+                              out: torch.Tensor) -> torch.Tensor:
+        """Per-chain LRMSD into `out` [n_chains] without a workspace: the
+        library's fixed per-device scratch holds the intermediate sums (calls
+        on one device must not overlap)."""
+        self._check_tensor(coords, (3, self.n_atoms), "coords")
+        self._check_tensor(target, (3, self.n_atoms), "target")
+        self._check_tensor(out, (self.n_chains,), "out")
+        check(_lib.load().a2c_lrmsd_forward_noalloc(
+            self._h, ctypes.c_void_p(coords.data_ptr()), ctypes.c_void_p(target.data_ptr()),
+            ctypes.c_void_p(out.data_ptr()), _stream_ptr(coords.device)),
+            "a2c_lrmsd_forward_noalloc")
+        return out
+
     def lrmsd_backward(self, coords: torch.Tensor, target: torch.Tensor,
                        grad_lrmsd: torch.Tensor, workspace,
                        grad_coords: torch.Tensor | None = None) -> torch.Tensor:

@@ -30,6 +30,7 @@ EXPORTS = (
     "a2c_forward", "a2c_backward", "a2c_residue_table_info", "a2c_status_string",
     "a2c_last_error", "a2c_version", "a2c_lrmsd_workspace_bytes", "a2c_lrmsd_forward",
     "a2c_lrmsd_backward", "a2c_mse_step", "a2c_coords_to_angles", "a2c_plan_keep_coords",
+    "a2c_lrmsd_forward_noalloc",
 )
 
 SIZE_MAX = 2 ** 64 - 1
@@ -101,11 +102,13 @@ def load():
     lib.a2c_lrmsd_workspace_bytes.argtypes = [vp, P(sz)]
     lib.a2c_lrmsd_forward.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.a2c_lrmsd_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    lib.a2c_lrmsd_forward_noalloc.argtypes = [vp, vp, vp, vp, vp]
     for name in ("a2c_plan_sizes", "a2c_plan_keep_coords", "a2c_plan_atom_offsets", "a2c_plan_workspace_bytes",
                  "a2c_plan_set_schedule", "a2c_plan_get_schedule",
                  "a2c_plan_set_adjoint_schedule", "a2c_plan_get_adjoint_schedule", "a2c_forward",
                  "a2c_backward", "a2c_lrmsd_workspace_bytes", "a2c_lrmsd_forward",
-                 "a2c_lrmsd_backward", "a2c_mse_step", "a2c_coords_to_angles"):
+                 "a2c_lrmsd_backward", "a2c_mse_step", "a2c_coords_to_angles",
+                 "a2c_lrmsd_forward_noalloc"):
         getattr(lib, name).restype = ctypes.c_int
     lib.a2c_residue_table_info.argtypes = [P(ResidueTable), P(i32), P(ctypes.c_float)]
     lib.a2c_residue_table_info.restype = ctypes.c_int

@@ -149,6 +149,8 @@ hipError_t launch_fa_backward_scan(const a2c_plan &p, const float *ang, const fl
 void build_lrmsd_segments(a2c_plan &p);
 void build_chi_slots(const FATable &T, int8_t (&out)[A2C_NUM_RESIDUE_TYPES][4][4]);
 size_t lrmsd_workspace_bytes(const a2c_plan &p);
+// device address of the no-allocation LRMSD scratch on `device` (current)
+a2c_status lrmsd_scratch_setup(int device);
 void fa_allow_large_lds();
 
 }  // namespace a2c

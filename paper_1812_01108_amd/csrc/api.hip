@@ -475,6 +475,7 @@ a2c_status a2c_plan_create(a2c_plan **out, a2c_model model, int32_t n_chains,
             st = upload((void **)&p->d_lr_chain_seg, p->lr_chain_seg.data(),
                         p->lr_chain_seg.size() * sizeof(int32_t), s);
     }
+    if (st == A2C_OK) st = lrmsd_scratch_setup(dev);
     if (st == A2C_OK && model == A2C_FULLATOM) fa_allow_large_lds();
     if (st == A2C_OK) {
         int32_t K, W;

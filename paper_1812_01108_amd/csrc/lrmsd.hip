@@ -32,6 +32,7 @@
 #include "a2c_internal.h"
 
 #include <cmath>
+#include <mutex>
 
 namespace a2c {
 namespace {
@@ -407,6 +408,41 @@ size_t lrmsd_workspace_bytes(const a2c_plan &p)
            (size_t)p.n_chains * kLrState * sizeof(float);
 }
 
+// ------------------------------------------------------- static scratch
+// The no-allocation forward (a2c_lrmsd_forward_noalloc) keeps the segment
+// records and per-chain state that a caller's workspace holds for
+// a2c_lrmsd_forward in this fixed array instead; every device holds its own
+// copy from module load until the process ends.  In host code the name
+// `scratch` is a host-side stand-in, not a device address: the address is
+// taken once per device (lrmsd_scratch_setup, at plan creation, with that
+// device current) and only that address is handed to kernels.
+static __device__ __align__(256) unsigned char scratch[A2C_LRMSD_STATIC_BYTES];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxScratchDevices];  // device address of `scratch`, per device
+}  // namespace
+
+a2c_status lrmsd_scratch_setup(int device)
+{
+    if (device < 0 || device >= kMaxScratchDevices) return A2C_OK;  // the entry point reports it
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_dev[device]) return A2C_OK;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(LRMSD scratch)");
+    g_scratch_dev[device] = ptr;
+    return A2C_OK;
+}
+
+static void *lrmsd_scratch_ptr(int device)
+{
+    if (device < 0 || device >= kMaxScratchDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_dev[device];
+}
+
 // Segments of at most kLrSegAtoms atoms, never across a chain boundary.
 void build_lrmsd_segments(a2c_plan &p)
 {
@@ -465,19 +501,18 @@ static a2c_status lr_check(const a2c_plan *p, void *ws)
     return A2C_OK;
 }
 
-a2c_status a2c_lrmsd_forward(a2c_plan *p, const float *d_coords, const float *d_target,
-                             float *d_lrmsd, void *d_workspace, void *stream)
+// The forward's two kernels with the segment records and per-chain state in
+// `ws` (a caller's workspace or the static scratch).
+static a2c_status lr_forward_launch(a2c_plan *p, const float *d_coords, const float *d_target,
+                                    float *d_lrmsd, void *ws, hipStream_t s)
 {
-    a2c_status st = lr_check(p, d_workspace);
-    if (st != A2C_OK) return st;
     if (p->n_chains == 0) return A2C_OK;
     if (!d_lrmsd || (p->A > 0 && (!d_coords || !d_target))) {
         set_error("a device pointer is NULL");
         return A2C_ERR_INVALID_ARG;
     }
-    hipStream_t s = (hipStream_t)stream;
-    double *part = (double *)d_workspace;
-    float *state = (float *)((char *)d_workspace + (size_t)p->lr_n_seg * kLrPart * sizeof(double));
+    double *part = (double *)ws;
+    float *state = (float *)((char *)ws + (size_t)p->lr_n_seg * kLrPart * sizeof(double));
     if (p->lr_n_seg > 0)
         hipLaunchKernelGGL(lr_partial_kernel, dim3(p->lr_n_seg), dim3(kLrThreads), 0, s, d_coords,
                            d_target, p->d_lr_seg_atom, p->d_lr_seg_origin, p->A, part);
@@ -487,6 +522,38 @@ a2c_status a2c_lrmsd_forward(a2c_plan *p, const float *d_coords, const float *d_
                        p->d_lr_chain_seg, p->n_chains, p->A, part, state, d_lrmsd);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? A2C_OK : hip_fail(e, "lrmsd forward launch");
+}
+
+a2c_status a2c_lrmsd_forward(a2c_plan *p, const float *d_coords, const float *d_target,
+                             float *d_lrmsd, void *d_workspace, void *stream)
+{
+    const a2c_status st = lr_check(p, d_workspace);
+    if (st != A2C_OK) return st;
+    return lr_forward_launch(p, d_coords, d_target, d_lrmsd, d_workspace, (hipStream_t)stream);
+}
+
+a2c_status a2c_lrmsd_forward_noalloc(a2c_plan *p, const float *d_coords, const float *d_target,
+                                     float *d_lrmsd, void *stream)
+{
+    if (!p) {
+        set_error("plan is NULL");
+        return A2C_ERR_INVALID_ARG;
+    }
+    const size_t need = lrmsd_workspace_bytes(*p);
+    if (need > (size_t)A2C_LRMSD_STATIC_BYTES) {
+        set_error("the plan's LRMSD state needs " + std::to_string(need) +
+                  " bytes; the static scratch holds " +
+                  std::to_string((size_t)A2C_LRMSD_STATIC_BYTES));
+        return A2C_ERR_WORKSPACE;
+    }
+    void *ws = lrmsd_scratch_ptr(p->device);
+    if (!ws) {
+        set_error("no static LRMSD scratch on device " + std::to_string(p->device));
+        return A2C_ERR_STATE;
+    }
+    const a2c_status st = lr_check(p, ws);
+    if (st != A2C_OK) return st;
+    return lr_forward_launch(p, d_coords, d_target, d_lrmsd, ws, (hipStream_t)stream);
 }
 
 a2c_status a2c_lrmsd_backward(a2c_plan *p, const float *d_coords, const float *d_target,
