@@ -188,12 +188,21 @@ a2c_status a2c_plan_workspace_bytes(const a2c_plan *plan, a2c_variant variant,
 
 /* Scan schedule: residues per lane (1, 2 or 4 for A2C_BACKBONE; 1 or 2 for
  * A2C_FULLATOM) and waves of 64 lanes per workgroup (1..16).  A chunk is
- * 64 * waves * res_per_lane consecutive residues.  Chains of at most one
- * chunk are packed whole, in order, into tiles of at most one chunk; a longer
- * chain gets a tile of its own, which one workgroup walks chunk by chunk
- * (at most 64 chunks), carrying the frame (forward) and the wrench (adjoint)
- * from chunk to chunk.  One workgroup per tile, longest tiles dispatched
- * first.  Re-packs and re-uploads the tile table (synchronises `stream`).
+ * 64 * waves * res_per_lane consecutive residues.
+ *   - The backbone forward (a2c_forward, A2C_SCAN) runs on fixed windows:
+ *     workgroup t takes residues [t C, t C + C) of the packed batch, C one
+ *     chunk, whatever the chain boundaries.  A chain entering a window from
+ *     earlier ones gets its frame from those windows' aggregates, which every
+ *     workgroup publishes in plan-owned device memory before it reads any
+ *     (window look-back); a workgroup only waits on workgroups of lower
+ *     index.  Consequently two forward calls on one plan must not run at the
+ *     same time (on different streams), and every launch runs all windows.
+ *   - Every other kernel packs chains of at most one chunk whole, in order,
+ *     into tiles of at most one chunk; a longer chain gets a tile of its own,
+ *     which one workgroup walks chunk by chunk (at most 64 chunks), carrying
+ *     the frame (forward) and the wrench (adjoint) from chunk to chunk.  One
+ *     workgroup per tile, longest tiles dispatched first.
+ * Re-packs and re-uploads the tables (synchronises `stream`).
  * The tables of the schedule it replaces stay allocated until
  * a2c_plan_destroy, so a graph captured before the change replays the
  * schedule it captured, with the same results; no graph captured over a plan
@@ -209,25 +218,28 @@ a2c_status a2c_plan_set_schedule(a2c_plan *plan, int32_t res_per_lane,
 a2c_status a2c_plan_get_schedule(const a2c_plan *plan, int32_t *res_per_lane,
                                  int32_t *waves_per_group, int32_t *n_tiles);
 
-/* A plan holds two schedules with their own tile tables: the forward's
+/* A plan holds two schedules with their own tables: the forward's
  * (a2c_forward) and the adjoint's (a2c_backward and a2c_mse_step); the two
  * kernels favour different shapes (more residues per lane suits the forward
  * scan, fewer the adjoint's larger per-lane state).  a2c_plan_set_schedule
- * sets both, a2c_plan_get_schedule reports the forward's, and these set and
- * report the adjoint's alone (same arguments, checks and synchronisation as
- * a2c_plan_set_schedule; on failure the adjoint schedule is unchanged).
- * Results do not depend on the schedules beyond float32 rounding. */
+ * sets both and a2c_plan_get_schedule reports the forward's; the calls below
+ * set or report one of them alone (same arguments, checks and
+ * synchronisation as a2c_plan_set_schedule; on failure that schedule is
+ * unchanged), except that the backbone forward also takes 8 residues per
+ * lane.  Results do not depend on the schedules beyond float32 rounding. */
+a2c_status a2c_plan_set_forward_schedule(a2c_plan *plan, int32_t res_per_lane,
+                                         int32_t waves_per_group, void *stream);
 a2c_status a2c_plan_set_adjoint_schedule(a2c_plan *plan, int32_t res_per_lane,
                                          int32_t waves_per_group, void *stream);
 a2c_status a2c_plan_get_adjoint_schedule(const a2c_plan *plan, int32_t *res_per_lane,
                                          int32_t *waves_per_group, int32_t *n_tiles);
 
-/* Autotuner: for every schedule that a2c_plan_set_schedule accepts for the
- * plan, times the forward and the adjoint (A2C_SCAN) separately on the
- * caller's buffers, and keeps the fastest forward schedule and the fastest
- * adjoint schedule on the plan (candidates in order of residues per lane,
- * then waves; a later one must be 3 % faster than the best so far to replace
- * it, so near-ties resolve to the smaller schedule).
+/* Autotuner: times the forward (A2C_SCAN) under every schedule
+ * a2c_plan_set_forward_schedule accepts for the plan and keeps the fastest,
+ * then the adjoint under every schedule a2c_plan_set_adjoint_schedule
+ * accepts, on the caller's buffers (candidates in order of residues per
+ * lane, then waves; a later one must be 3 % faster than the best so far to
+ * replace it, so near-ties resolve to the smaller schedule).
  *   d_angles, d_coords, d_grad_coords, d_grad_angles: buffers of the plan's
  *     sizes; their contents are overwritten (coords and grad_angles) or read.
  *   backward_from_coords: the adjoint timed: 1 a2c_backward with d_coords
@@ -239,8 +251,8 @@ a2c_status a2c_plan_get_adjoint_schedule(const a2c_plan *plan, int32_t *res_per_
  *     (coords, recompute or mse); NULL for none.  A line is
  *     "<key> K W aK aW" (or "<key> K W" for both).  A hit skips the timing;
  *     a miss appends the new choice.  An unreadable cache, and any line that
- *     is malformed or names schedules a2c_plan_set_schedule would reject for
- *     the plan, are ignored (the schedules are then tuned).
+ *     is malformed or names schedules the forward or adjoint setter would
+ *     reject for the plan, are ignored (the schedules are then tuned).
  *   out_res_per_lane, out_waves_per_group (may be NULL): the forward's
  *     choice (a2c_plan_get_adjoint_schedule gives the adjoint's).
  * Synchronises `stream`; not capturable.  Call it before capturing a graph. */

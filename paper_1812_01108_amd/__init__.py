@@ -179,6 +179,15 @@ class Plan:
                                                     _stream_ptr(self.device)),
                   "a2c_plan_set_schedule")
 
+    def set_forward_schedule(self, res_per_lane: int, waves_per_group: int):
+        """The forward's schedule alone (the backbone forward also takes 8
+        residues per lane)."""
+        with torch.cuda.device(self.device):
+            check(_lib.load().a2c_plan_set_forward_schedule(self._h, res_per_lane,
+                                                            waves_per_group,
+                                                            _stream_ptr(self.device)),
+                  "a2c_plan_set_forward_schedule")
+
     def set_adjoint_schedule(self, res_per_lane: int, waves_per_group: int):
         with torch.cuda.device(self.device):
             check(_lib.load().a2c_plan_set_adjoint_schedule(self._h, res_per_lane,

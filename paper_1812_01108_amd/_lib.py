@@ -30,7 +30,7 @@ EXPORTS = (
     "a2c_forward", "a2c_backward", "a2c_residue_table_info", "a2c_status_string",
     "a2c_last_error", "a2c_version", "a2c_lrmsd_workspace_bytes", "a2c_lrmsd_forward",
     "a2c_lrmsd_backward", "a2c_mse_step", "a2c_coords_to_angles", "a2c_plan_keep_coords",
-    "a2c_lrmsd_forward_noalloc",
+    "a2c_lrmsd_forward_noalloc", "a2c_plan_set_forward_schedule",
 )
 
 SIZE_MAX = 2 ** 64 - 1
@@ -91,6 +91,7 @@ def load():
     lib.a2c_plan_set_schedule.argtypes = [vp, i32, i32, vp]
     lib.a2c_plan_get_schedule.argtypes = [vp, P(i32), P(i32), P(i32)]
     lib.a2c_plan_set_adjoint_schedule.argtypes = [vp, i32, i32, vp]
+    lib.a2c_plan_set_forward_schedule.argtypes = [vp, i32, i32, vp]
     lib.a2c_plan_get_adjoint_schedule.argtypes = [vp, P(i32), P(i32), P(i32)]
     lib.a2c_plan_autotune.argtypes = [vp, vp, vp, vp, vp, i32, i32, ctypes.c_char_p, P(i32),
                                       P(i32), vp]
@@ -108,7 +109,7 @@ def load():
                  "a2c_plan_set_adjoint_schedule", "a2c_plan_get_adjoint_schedule", "a2c_forward",
                  "a2c_backward", "a2c_lrmsd_workspace_bytes", "a2c_lrmsd_forward",
                  "a2c_lrmsd_backward", "a2c_mse_step", "a2c_coords_to_angles",
-                 "a2c_lrmsd_forward_noalloc"):
+                 "a2c_lrmsd_forward_noalloc", "a2c_plan_set_forward_schedule"):
         getattr(lib, name).restype = ctypes.c_int
     lib.a2c_residue_table_info.argtypes = [P(ResidueTable), P(i32), P(ctypes.c_float)]
     lib.a2c_residue_table_info.restype = ctypes.c_int

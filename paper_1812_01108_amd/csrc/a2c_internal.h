@@ -24,6 +24,8 @@ constexpr int kLbSmall = 512, kLbLarge = 1024;
 // from memory, or 2 (r - t) of the squared distance to a target (the fused
 // training step).
 constexpr int kGradLoad = 0, kGradMse = 1;
+// Window look-back: tagged 64-bit words per tile aggregate (a 3x4 affine)
+constexpr int kLbWords = 12;
 // LRMSD: atoms per segment (one workgroup of 256 lanes, 16 atoms per lane)
 constexpr int kLrSegAtoms = 4096;
 
@@ -65,9 +67,15 @@ struct FATable {
 
 // One scan schedule: K residues per lane, W waves per workgroup, and the
 // tile table packed for them (chains of at most one chunk of 64 W K residues
-// packed whole into tiles of at most one chunk; a longer chain alone).
+// packed whole into tiles of at most one chunk; a longer chain alone), or,
+// for the backbone forward, fixed windows of one chunk with a look-back
+// table (flat).
 struct Sched {
     int32_t K = 4, W = 4, n_tiles = 0;
+    bool flat = false;                   // fixed windows [t C, t C + C), C = 64 W K
+    int32_t *d_look_first = nullptr;     // flat: n_tiles, first tile whose aggregate
+                                         // tile t composes (t: none)
+    uint64_t *d_status = nullptr;        // flat: n_tiles x 12 tagged aggregate words
     int32_t fa_stage_atoms = 0;          // per-wave staging (floats per plane)
     bool fa_unstaged = false;            // stage too large for the LDS: direct I/O
     bool multi_chunk = false;            // some tile spans several chunks
@@ -122,8 +130,10 @@ struct a2c_plan {
 namespace a2c {
 
 void set_error(const std::string &msg);
-// the checks a2c_plan_set_schedule makes on (K, W), without the device
+// the checks a2c_plan_set_schedule (and the adjoint setter) makes on (K, W),
+// without the device; the forward setter's checks (K = 8 too for the backbone)
 a2c_status check_schedule_args(const a2c_plan *p, int32_t K, int32_t W);
+a2c_status check_forward_schedule_args(const a2c_plan *p, int32_t K, int32_t W);
 hipError_t launch_fill_zero(float *x, int64_t n, hipStream_t s);
 // float32 (cos t, sin t) pair with squared norm closest to 1
 void unit_pair(double t, float &c, float &s);
@@ -152,5 +162,6 @@ size_t lrmsd_workspace_bytes(const a2c_plan &p);
 // device address of the no-allocation LRMSD scratch on `device` (current)
 a2c_status lrmsd_scratch_setup(int device);
 void fa_allow_large_lds();
+void bb_allow_large_lds();
 
 }  // namespace a2c

@@ -52,6 +52,20 @@ __device__ __forceinline__ void aff_apply_transform(Aff &m, float ct, float st, 
     m.r02 = e0; m.r12 = e1; m.r22 = e2;
 }
 
+// The identity followed by R(alpha, theta, d): the first transform of a walk,
+// without the products with 0 and 1 (the same values as applying it to the
+// identity with aff_apply_transform, up to the sign of zeros).
+__device__ __forceinline__ Aff aff_first_transform(float ct, float st, float d, float ca,
+                                                   float sa)
+{
+    Aff m;
+    m.r00 = ct; m.r10 = 0.f; m.r20 = -st;
+    m.r01 = sa * st; m.r11 = ca; m.r21 = sa * ct;
+    m.r02 = ca * st; m.r12 = -sa; m.r22 = ca * ct;
+    m.t0 = d * ct; m.t1 = 0.f; m.t2 = -(d * st);
+    return m;
+}
+
 // a * b (a applied after b): rotation a.R b.R, translation a.R b.t + a.t
 __device__ __forceinline__ Aff aff_compose(const Aff &a, const Aff &b)
 {

@@ -44,9 +44,38 @@ void free_sched(Sched &S)
     (void)hipFree(S.d_tile_res);
     (void)hipFree(S.d_loss_part);
     (void)hipFree(S.d_loss_count);
+    (void)hipFree(S.d_look_first);
+    (void)hipFree(S.d_status);
     S.d_tile_res = nullptr;
     S.d_loss_part = nullptr;
     S.d_loss_count = nullptr;
+    S.d_look_first = nullptr;
+    S.d_status = nullptr;
+}
+
+// Fixed windows of `cap` residues for the backbone forward: for each window
+// t, the first window whose aggregate its carry-in needs, i.e. the window
+// holding the head of the chain that residue t * cap belongs to (t itself
+// when a chain starts there).  The tagged aggregate words start at tag 0.
+a2c_status build_flat(const a2c_plan *p, int64_t cap, Sched &S, hipStream_t s)
+{
+    const int64_t n = (p->R + cap - 1) / cap;
+    std::vector<int32_t> first((size_t)n);
+    size_t c = 0;  // chain holding residue ts (non-empty: res_off[c] <= ts < res_off[c + 1])
+    for (int64_t t = 0; t < n; ++t) {
+        const int64_t ts = t * cap;
+        while (p->res_off[c + 1] <= ts) ++c;
+        first[(size_t)t] = (int32_t)(p->res_off[c] / cap);
+    }
+    S.n_tiles = (int32_t)n;
+    S.flat = true;
+    a2c_status st = upload((void **)&S.d_look_first, first.data(), first.size() * sizeof(int32_t), s);
+    if (st != A2C_OK) return st;
+    const size_t words = (size_t)std::max<int64_t>(1, n) * kLbWords * sizeof(uint64_t);
+    hipError_t e = hipMalloc((void **)&S.d_status, words);
+    if (e == hipSuccess) e = hipMemsetAsync(S.d_status, 0, words, s);
+    if (e != hipSuccess) return hip_fail(e, "look-back words");
+    return A2C_OK;
 }
 
 // Greedy packing of whole chains, in order, into tiles: chains of at most one
@@ -79,7 +108,8 @@ std::vector<int32_t> pack_tiles(const std::vector<int32_t> &off, int64_t cap)
 
 // Pack the tiles of schedule (K, W) and upload its tile table into out
 // (whose own table, if any, the caller frees).
-a2c_status build_sched(const a2c_plan *p, int32_t K, int32_t W, Sched &out, hipStream_t s)
+a2c_status build_sched(const a2c_plan *p, int32_t K, int32_t W, Sched &out, hipStream_t s,
+                       bool flat)
 {
     const int64_t cap = (int64_t)kWave * W * K;  // residues per chunk
     if (p->max_len > cap * kMaxChunks)
@@ -87,6 +117,22 @@ a2c_status build_sched(const a2c_plan *p, int32_t K, int32_t W, Sched &out, hipS
                                              " residues needs more than " +
                                              std::to_string(kMaxChunks) + " chunks of " +
                                              std::to_string(cap) + " residues");
+    if (flat) {
+        Sched S;
+        S.K = K;
+        S.W = W;
+        a2c_status st = build_flat(p, cap, S, s);
+        if (st == A2C_OK) {
+            const hipError_t e = hipStreamSynchronize(s);
+            if (e != hipSuccess) st = hip_fail(e, "hipStreamSynchronize");
+        }
+        if (st != A2C_OK) {
+            free_sched(S);
+            return st;
+        }
+        out = S;
+        return A2C_OK;
+    }
     std::vector<int32_t> tiles = pack_tiles(p->res_off, cap);
     int32_t stage_atoms = 0;
     if (p->model == A2C_FULLATOM) {
@@ -162,12 +208,19 @@ a2c_status build_sched(const a2c_plan *p, int32_t K, int32_t W, Sched &out, hipS
 // destroyed: a graph captured before the change still launches with them.
 void retire_sched(a2c_plan *p, Sched &S)
 {
-    for (void *q : {(void *)S.d_tile_res, (void *)S.d_loss_part, (void *)S.d_loss_count})
+    for (void *q : {(void *)S.d_tile_res, (void *)S.d_loss_part, (void *)S.d_loss_count,
+                    (void *)S.d_look_first, (void *)S.d_status})
         if (q) p->retired.push_back(q);
     S.d_tile_res = nullptr;
     S.d_loss_part = nullptr;
     S.d_loss_count = nullptr;
+    S.d_look_first = nullptr;
+    S.d_status = nullptr;
 }
+
+// The backbone forward runs on fixed windows; everything else on tiles of
+// whole chains.
+bool forward_is_flat(const a2c_plan *p) { return p->model == A2C_BACKBONE; }
 
 // Replace one of the plan's schedules; on failure it stays as it was.  The
 // old tables are retired (kept until the plan is destroyed), or freed at once
@@ -177,7 +230,7 @@ a2c_status set_sched(a2c_plan *p, Sched &dst, int32_t K, int32_t W, hipStream_t 
                      bool retire_old = true)
 {
     Sched S;
-    const a2c_status st = build_sched(p, K, W, S, s);
+    const a2c_status st = build_sched(p, K, W, S, s, &dst == &p->fs && forward_is_flat(p));
     if (st != A2C_OK) return st;
     if (retire_old) retire_sched(p, dst);
     else free_sched(dst);
@@ -190,9 +243,9 @@ a2c_status apply_schedule(a2c_plan *p, int32_t K, int32_t W, hipStream_t s,
                           bool retire_old = true)
 {
     Sched f, b;
-    a2c_status st = build_sched(p, K, W, f, s);
+    a2c_status st = build_sched(p, K, W, f, s, forward_is_flat(p));
     if (st != A2C_OK) return st;
-    st = build_sched(p, K, W, b, s);
+    st = build_sched(p, K, W, b, s, false);
     if (st != A2C_OK) {
         free_sched(f);
         return st;
@@ -263,6 +316,16 @@ void unit_pair(double t, float &c_out, float &s_out)
         }
 }
 
+// The forward setter's checks: the backbone forward also takes K = 8.
+a2c_status check_forward_schedule_args(const a2c_plan *p, int32_t K, int32_t W)
+{
+    if (p->model == A2C_BACKBONE && K == 8) {
+        if (W < 1 || W > kMaxWaves) return fail(A2C_ERR_INVALID_ARG, "waves_per_group must be 1..16");
+        return A2C_OK;
+    }
+    return check_schedule_args(p, K, W);
+}
+
 // The checks a2c_plan_set_schedule makes on (K, W), without the device.
 a2c_status check_schedule_args(const a2c_plan *p, int32_t K, int32_t W)
 {
@@ -299,11 +362,6 @@ a2c_status hip_fail(hipError_t e, const char *what)
 }
 
 a2c_status build_fullatom_tables(a2c_plan *p, const a2c_residue_table *table);
-
-a2c_status plan_apply_schedule(a2c_plan *p, int32_t K, int32_t W, hipStream_t s, bool retire_old)
-{
-    return apply_schedule(p, K, W, s, retire_old);
-}
 
 a2c_status plan_apply_adjoint_schedule(a2c_plan *p, int32_t K, int32_t W, hipStream_t s,
                                        bool retire_old)
@@ -476,7 +534,10 @@ a2c_status a2c_plan_create(a2c_plan **out, a2c_model model, int32_t n_chains,
                         p->lr_chain_seg.size() * sizeof(int32_t), s);
     }
     if (st == A2C_OK) st = lrmsd_scratch_setup(dev);
-    if (st == A2C_OK && model == A2C_FULLATOM) fa_allow_large_lds();
+    if (st == A2C_OK) {
+        if (model == A2C_FULLATOM) fa_allow_large_lds();
+        else bb_allow_large_lds();
+    }
     if (st == A2C_OK) {
         int32_t K, W;
         default_schedule(*p, K, W);
@@ -548,6 +609,15 @@ a2c_status a2c_plan_set_adjoint_schedule(a2c_plan *p, int32_t K, int32_t W, void
     if (sa != A2C_OK) return sa;
     if (!check_device(p)) return fail(A2C_ERR_STATE, "current device is not the plan's device");
     return set_sched(p, p->bs, K, W, (hipStream_t)stream);
+}
+
+a2c_status a2c_plan_set_forward_schedule(a2c_plan *p, int32_t K, int32_t W, void *stream)
+{
+    if (!p) return fail(A2C_ERR_INVALID_ARG, "plan is NULL");
+    const a2c_status sa = check_forward_schedule_args(p, K, W);
+    if (sa != A2C_OK) return sa;
+    if (!check_device(p)) return fail(A2C_ERR_STATE, "current device is not the plan's device");
+    return set_sched(p, p->fs, K, W, (hipStream_t)stream);
 }
 
 a2c_status a2c_plan_get_schedule(const a2c_plan *p, int32_t *K, int32_t *W, int32_t *n_tiles)

@@ -2,6 +2,7 @@
 // workgroup) times the forward and the adjoint (or the fused step) separately
 // with HIP events, and keeps the fastest of each as the plan's forward and
 // adjoint schedules; choices can be kept in a small text cache.
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
 #include <fstream>
@@ -14,7 +15,6 @@
 namespace a2c {
 // retire_old: keep the replaced tables until the plan is destroyed (a graph
 // captured before may use them); false frees them (the tuner's own candidates)
-a2c_status plan_apply_schedule(a2c_plan *p, int32_t K, int32_t W, hipStream_t s, bool retire_old);
 a2c_status plan_apply_forward_schedule(a2c_plan *p, int32_t K, int32_t W, hipStream_t s,
                                        bool retire_old);
 a2c_status plan_apply_adjoint_schedule(a2c_plan *p, int32_t K, int32_t W, hipStream_t s,
@@ -63,7 +63,7 @@ bool cache_lookup(const a2c_plan *p, const char *path, const std::string &key, i
         }
         if (n == 2) bk = k, bw = w;
         const bool tail_blank = used > 0 && rest[std::strspn(rest + used, " \t\r") + used] == '\0';
-        if (n != 0 && tail_blank && check_schedule_args(p, k, w) == A2C_OK &&
+        if (n != 0 && tail_blank && check_forward_schedule_args(p, k, w) == A2C_OK &&
             check_schedule_args(p, bk, bw) == A2C_OK) {
             K = k;
             W = w;
@@ -132,74 +132,86 @@ extern "C" a2c_status a2c_plan_autotune(a2c_plan *p, const float *d_angles, floa
             return A2C_OK;
         }
     }
-    const int Ks[3] = {1, 2, 4};
+    const int Ks[4] = {1, 2, 4, 8};
     const int Ws[8] = {1, 2, 3, 4, 6, 8, 12, 16};
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return hip_fail(hipGetLastError(), "hipEventCreate");
+    // best of three timed trials (after one warm-up) of reps calls of part
+    // 0 (forward) or 1 (adjoint / fused step)
+    auto time_part = [&](int part, float &best) -> a2c_status {
+        best = 1e30f;
+        a2c_status rs = A2C_OK;
+        for (int trial = 0; trial < 4 && rs == A2C_OK; ++trial) {
+            (void)hipEventRecord(e0, s);
+            for (int r = 0; r < reps && rs == A2C_OK; ++r) {
+                if (part == 0)
+                    rs = a2c_forward(p, A2C_SCAN, d_angles, d_coords, nullptr, s);
+                else if (from_coords == A2C_TUNE_MSE_STEP)  // d_grad_coords: the target
+                    rs = a2c_mse_step(p, d_angles, d_grad_coords, d_coords, nullptr,
+                                      d_grad_angles, s);
+                else
+                    rs = a2c_backward(p, A2C_SCAN, d_angles, from_coords ? d_coords : nullptr,
+                                      d_grad_coords, d_grad_angles, nullptr, s);
+            }
+            (void)hipEventRecord(e1, s);
+            if (hipEventSynchronize(e1) != hipSuccess)
+                return hip_fail(hipGetLastError(), "hipEventSynchronize");
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (trial > 0) best = std::min(best, ms);  // the first trial warms up
+        }
+        return rs;
+    };
     float best_f = 1e30f, best_b = 1e30f;
     int32_t fK = p->fs.K, fW = p->fs.W, bK = p->bs.K, bW = p->bs.W;
     a2c_status st = A2C_OK;
-    // the first candidate replaces the caller's schedules (retired: a graph
-    // may hold them); later ones replace the tuner's own (freed)
-    bool own = false;
-    for (int k : Ks) {
-        if (p->model == A2C_FULLATOM && k == 4) continue;
-        for (int w : Ws) {
-            st = plan_apply_schedule(p, k, w, s, !own);
-            if (st == A2C_OK) own = true;
-            if (st == A2C_ERR_UNSUPPORTED) {  // too many chunks, or staging beyond LDS
-                st = A2C_OK;
-                continue;
-            }
-            if (st != A2C_OK) break;
-            // the forward alone, then the adjoint (or the fused step) alone;
-            // the forward's output feeds the coordinate-mode adjoint
-            float cand[2] = {1e30f, 1e30f};
-            for (int part = 0; part < 2 && st == A2C_OK; ++part)
-                for (int trial = 0; trial < 3 && st == A2C_OK; ++trial) {
-                    (void)hipEventRecord(e0, s);
-                    for (int r = 0; r < reps && st == A2C_OK; ++r) {
-                        if (part == 0)
-                            st = a2c_forward(p, A2C_SCAN, d_angles, d_coords, nullptr, s);
-                        else if (from_coords == A2C_TUNE_MSE_STEP)  // d_grad_coords: the target
-                            st = a2c_mse_step(p, d_angles, d_grad_coords, d_coords, nullptr,
-                                              d_grad_angles, s);
-                        else
-                            st = a2c_backward(p, A2C_SCAN, d_angles,
-                                              from_coords ? d_coords : nullptr, d_grad_coords,
-                                              d_grad_angles, nullptr, s);
-                    }
-                    (void)hipEventRecord(e1, s);
-                    if (hipEventSynchronize(e1) != hipSuccess) {
-                        st = hip_fail(hipGetLastError(), "hipEventSynchronize");
-                        break;
-                    }
-                    float ms = 0.f;
-                    (void)hipEventElapsedTime(&ms, e0, e1);
-                    if (trial > 0) cand[part] = std::min(cand[part], ms);  // first trial warms up
+    // The forward schedules, then the adjoint ones with the fastest forward in
+    // place (its output feeds the coordinate-mode adjoint).  The first
+    // candidate of each replaces the caller's schedule (retired: a graph may
+    // hold it); later ones replace the tuner's own (freed).
+    bool own_f = false, own_b = false;
+    for (int part = 0; part < 2 && st == A2C_OK; ++part) {
+        for (int k : Ks) {
+            for (int w : Ws) {
+                st = part == 0 ? check_forward_schedule_args(p, k, w)
+                               : check_schedule_args(p, k, w);
+                if (st == A2C_ERR_INVALID_ARG) {  // not a schedule of this kernel
+                    st = A2C_OK;
+                    continue;
                 }
+                st = part == 0 ? plan_apply_forward_schedule(p, k, w, s, !own_f)
+                               : plan_apply_adjoint_schedule(p, k, w, s, !own_b);
+                if (st == A2C_ERR_UNSUPPORTED) {  // too many chunks, or staging beyond LDS
+                    st = A2C_OK;
+                    continue;
+                }
+                if (st != A2C_OK) break;
+                (part == 0 ? own_f : own_b) = true;
+                float t = 0.f;
+                st = time_part(part, t);
+                if (st != A2C_OK) break;
+                // a later candidate (more residues per lane or waves) must be
+                // 3 % faster to win: near-ties keep the smaller schedule, so
+                // the choice does not flip with timing noise
+                float &best = part == 0 ? best_f : best_b;
+                if (t < 0.97f * best) {
+                    best = t;
+                    (part == 0 ? fK : bK) = k;
+                    (part == 0 ? fW : bW) = w;
+                }
+            }
             if (st != A2C_OK) break;
-            // a later candidate (more residues per lane or waves) must be
-            // 3 % faster to win: near-ties keep the smaller schedule, so the
-            // choice does not flip with timing noise
-            if (cand[0] < 0.97f * best_f) {
-                best_f = cand[0];
-                fK = k;
-                fW = w;
-            }
-            if (cand[1] < 0.97f * best_b) {
-                best_b = cand[1];
-                bK = k;
-                bW = w;
-            }
         }
-        if (st != A2C_OK) break;
+        if (st == A2C_OK && part == 0) {
+            st = plan_apply_forward_schedule(p, fK, fW, s, !own_f);
+            if (st == A2C_OK) st = a2c_forward(p, A2C_SCAN, d_angles, d_coords, nullptr, s);
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st != A2C_OK) return st;
-    st = apply_pair(p, fK, fW, bK, bW, s, !own);
+    st = plan_apply_adjoint_schedule(p, bK, bW, s, !own_b);
     if (st != A2C_OK) return st;
     cache_store(cache_path, key, fK, fW, bK, bW);
     if (out_K) *out_K = fK;

@@ -224,44 +224,166 @@ __device__ __forceinline__ void load_angles(float *buf, const float *__restrict_
     to_blocked<K>(buf, v2, nres, om);
 }
 
-template <int K, bool MULTI, int LB>
-__global__ __launch_bounds__(LB) void bb_forward_scan_kernel(
-    const float *__restrict__ ang, float *__restrict__ xyz, const int32_t *__restrict__ tile_res,
-    const uint32_t *__restrict__ head_bits, int64_t R, BBParams P0)
+// Forward over fixed windows of the packed batch: tile t covers residues
+// [t C, t C + C), C = 64 W K, whatever the chains; lane l of wave w owns K
+// consecutive residues.  A chain that enters the tile from an earlier one
+// gets its frame from those tiles' published aggregates (window look-back);
+// every lane holds K residues except in the batch's last wave.
+//   1. angles: coalesced loads of the three planes, LDS transpose to lanes;
+//   2. per lane: sincos, walk from the identity over its 3K transforms
+//      (restarting at chain heads), local positions, one polar step;
+//   3. segmented scan of the lane aggregates across each wave, then of the
+//      wave totals by wave 0, which publishes the tile's aggregate and then
+//      composes the aggregates of the earlier tiles its first chain spans;
+//   4. each lane maps the positions before its first chain head through its
+//      exclusive prefix frame; LDS transpose, coalesced stores of x, y, z.
+template <int K, int LB>
+__global__ __launch_bounds__(LB, 4) void bb_forward_flat_kernel(
+    const float *__restrict__ ang, float *__restrict__ xyz, const uint32_t *__restrict__ head_bits,
+    const int32_t *__restrict__ look_first, uint64_t *__restrict__ status, int64_t R, BBParams P)
 {
     extern __shared__ float stage_mem[];
-    __shared__ FwdShared sh[2];
+    __shared__ FwdShared sh;
+    __shared__ float carry_sh[12];
+    constexpr int RUN = kWave * K;  // residues per wave
+    const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nw = blockDim.x >> 6;
+    const int64_t t = blockIdx.x;
+    const int64_t ts = t * RUN * nw, te = min(ts + (int64_t)RUN * nw, R);
+    const int nact = (int)((te - ts + RUN - 1) / RUN);
+    const int64_t rbase = ts + (int64_t)wave * RUN;
+    const int nres = (int)max((int64_t)0, min((int64_t)RUN, te - rbase));
+    const bool active = nres > 0, full = nres == RUN;
+    const int64_t rs = rbase + lane * K;
     float *buf = stage_mem + wave * kWave * Stride<3 * K>::value;
-    const int64_t ts = tile_res[2 * blockIdx.x], te = tile_res[2 * blockIdx.x + 1];
     const int64_t A = 3 * R;
-    // MULTI = false: every tile is one chunk (straight-line code)
-    const int nch = MULTI ? chunks_of<K>(ts, te) : 1;
-    Aff carry = aff_identity();
-    for (int c = 0; c < nch; ++c) {
-        const BBParams P = MULTI ? opaque_params(P0) : P0;
-        const Chunk k = chunk_of<K>(ts, te, c);
-        const int64_t rbase = k.cs + (int64_t)wave * kWave * K;
-        const bool active = wave < k.nact;
-        const int nres = active ? (int)min((int64_t)kWave * K, k.ce - rbase) : 0;
-        const int64_t rs = k.cs + (int64_t)threadIdx.x * K;
-        const int cnt = (int)max((int64_t)0, min((int64_t)K, k.ce - rs));
-        // chain-head bits before the angle loads: the LDS transposes below
-        // are fenced, and a load issued after them would wait for the angles
-        const uint32_t hm = lane_head_mask<K>(head_bits, rs, k.ce, cnt);
-        float phi[K], psi[K], om[K];
-        if (active) load_angles<K>(buf, ang, R, rbase, nres, phi, psi, om);
-        float x[3 * K], y[3 * K], z[3 * K];
-        float px, py, pz;
-        bb_lane_positions<K, MULTI>(phi, psi, om, P, k.nact, sh[c & 1], carry, x, y, z, px, py, pz,
-                             cnt, hm);
-        if (active) {
-            float *out = xyz + 3 * rbase;
-            stage_store<3 * K>(buf, x, out, 3 * nres);
-            stage_store<3 * K>(buf, y, out + A, 3 * nres);
-            stage_store<3 * K>(buf, z, out + 2 * A, 3 * nres);
+    // own words of the previous launch (the tag) and the look-back range,
+    // read ahead of the angles so that their latency overlaps
+    uint64_t prev = 0;
+    int64_t first = t;
+    if (wave == 0) {
+        prev = lb_load(status + t * kLbWords);
+        first = look_first[t];
+    }
+    const uint32_t hm = head_mask<K>(head_bits, rs < te ? rs : te);
+    float phi[K], psi[K], om[K];
+    if (active) {
+        float v0[K], v1[K], v2[K];
+        run_load<K>(ang + rbase, nres, full, v0);
+        run_load<K>(ang + R + rbase, nres, full, v1);
+        run_load<K>(ang + 2 * R + rbase, nres, full, v2);
+        run_to_lanes<K>(buf, v0, phi);
+        run_to_lanes<K>(buf, v1, psi);
+        run_to_lanes<K>(buf, v2, om);
+    }
+    float x[3 * K], y[3 * K], z[3 * K];
+    Aff m = aff_identity();
+    int first_head = K;  // residues before it need the frame entering the lane
+    if (active) {
+        // one wave-uniform choice between the branch-free sincos and the
+        // library (huge or non-finite arguments anywhere in the wave)
+        bool ok = true;
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            ok = ok && sincos_fast_ok(om[j]) && sincos_fast_ok(phi[j]) && sincos_fast_ok(psi[j]);
+        const bool fast = __all(ok);
+        // Residues past the batch end (last wave only) are walked too: their
+        // positions are never stored and nothing after them reads the frame.
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            float so, co, sp, cp, ss, cs;
+            if (fast) {
+                sincos_fast(om[j], so, co);
+                sincos_fast(phi[j], sp, cp);
+                sincos_fast(psi[j], ss, cs);
+            } else {
+                sincos_accurate(om[j], so, co);
+                sincos_accurate(phi[j], sp, cp);
+                sincos_accurate(psi[j], ss, cs);
+            }
+            // the lane's walk starts from the identity, and so does a chain
+            // that starts here (a wave-uniform test keeps the rare restart
+            // out of the common path)
+            const bool h = (hm >> j) & 1u;
+            if (j == 0) {
+                m = aff_first_transform(P.ct[0], P.st[0], P.d[0], co, so);
+                first_head = h ? 0 : first_head;
+            } else if (__builtin_amdgcn_ballot_w64(h) != 0ull) {
+                const Aff f = aff_first_transform(P.ct[0], P.st[0], P.d[0], co, so);
+                aff_apply_transform(m, P.ct[0], P.st[0], P.d[0], co, so);
+                m = aff_select(h, f, m);
+                first_head = (h && first_head == K) ? j : first_head;
+            } else {
+                aff_apply_transform(m, P.ct[0], P.st[0], P.d[0], co, so);
+            }
+            x[3 * j] = m.t0; y[3 * j] = m.t1; z[3 * j] = m.t2;
+            aff_apply_transform(m, P.ct[1], P.st[1], P.d[1], cp, sp);
+            x[3 * j + 1] = m.t0; y[3 * j + 1] = m.t1; z[3 * j + 1] = m.t2;
+            aff_apply_transform(m, P.ct[2], P.st[2], P.d[2], cs, ss);
+            x[3 * j + 2] = m.t0; y[3 * j + 2] = m.t1; z[3 * j + 2] = m.t2;
+        }
+        // the fixed rotations repeat every residue, so their float32 rounding
+        // drifts the scale of long products coherently; one polar step per
+        // lane aggregate removes that drift
+        aff_orthonormalise(m);
+    }
+    // segmented scan: inside each wave, then the wave totals by wave 0
+    const uint64_t heads = __builtin_amdgcn_ballot_w64(first_head < K);
+    if (active) {
+        aff_wave_scan<false>(m, heads, kWave, lane);
+        if (lane == kWave - 1) {
+            aff_store(sh.tot[wave], m);
+            sh.tot_flag[wave] = heads != 0ull ? 1 : 0;
         }
     }
+    __syncthreads();
+    if (wave == 0) {
+        Aff tw = aff_identity();
+        bool tf = false;
+        if (lane < nact) {
+            tw = aff_load(sh.tot[lane]);
+            tf = sh.tot_flag[lane] != 0;
+        }
+        const uint64_t th = __builtin_amdgcn_ballot_w64(tf);
+        aff_wave_scan<true>(tw, th, nact, lane);
+        if (lane < nact) {
+            aff_store(sh.pre[lane], tw);
+            sh.pre_flag[lane] = (th & lanes_upto(lane)) != 0ull ? 1 : 0;
+        }
+        wave_lds_sync();
+        // publish this tile's aggregate, then read the earlier tiles' ones
+        const uint32_t tag = (uint32_t)(__builtin_amdgcn_readfirstlane((uint32_t)(prev >> 32))) + 1u;
+        if (lane < kLbWords) lb_store(status + t * kLbWords + lane, tag, sh.pre[nact - 1][lane]);
+        const int64_t f = (int64_t)__builtin_amdgcn_readfirstlane((int)first);
+        const Aff carry = lb_carry_in(status, f, t, tag);
+        if (lane == 0) aff_store(carry_sh, carry);
+    }
+    __syncthreads();
+    if (!active) return;
+    // frame entering the wave, then entering each lane
+    const Aff carry = aff_load(carry_sh);
+    Aff cw = carry;
+    if (wave > 0) cw = aff_seg_after(carry, aff_load(sh.pre[wave - 1]), sh.pre_flag[wave - 1] != 0);
+    Aff e = aff_dpp_z<kDppWaveShr1>(m);
+    if (lane == 0) e = aff_identity();
+    const bool fe = (heads & lanes_below(lane)) != 0ull;
+    const Aff X = fe ? e : aff_compose(cw, e);
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        if (j < first_head) {
+#pragma unroll
+            for (int s = 0; s < 3; ++s) {
+                float gx, gy, gz;
+                aff_point(X, x[3 * j + s], y[3 * j + s], z[3 * j + s], gx, gy, gz);
+                x[3 * j + s] = gx; y[3 * j + s] = gy; z[3 * j + s] = gz;
+            }
+        }
+    }
+    float *out = xyz + 3 * rbase;
+    lanes_to_run<3 * K>(buf, x, out, 3 * nres, full);
+    lanes_to_run<3 * K>(buf, y, out + A, 3 * nres, full);
+    lanes_to_run<3 * K>(buf, z, out + 2 * A, 3 * nres, full);
 }
 
 // Backward that recomputes the frames from the angles (no stored state).
@@ -552,24 +674,22 @@ __global__ __launch_bounds__(kPlainBlock) void bb_backward_plain_kernel(
     if (active) gang[(int64_t)slot_plane((int)(i % 3)) * R + r0 + i / 3] = acc;
 }
 
-template <int K, bool MULTI, int LB>
-hipError_t fwd_kml(const a2c_plan &p, const float *ang, float *xyz, hipStream_t s)
+template <int K, int LB>
+hipError_t fwd_kl(const a2c_plan &p, const float *ang, float *xyz, hipStream_t s)
 {
     const dim3 grid(p.fs.n_tiles), block(p.fs.W * kWave);
-    hipLaunchKernelGGL((bb_forward_scan_kernel<K, MULTI, LB>), grid, block, stage_bytes<K>(p.fs.W),
-                       s, ang, xyz, p.fs.d_tile_res, p.d_head_bits, p.R, p.bb);
+    hipLaunchKernelGGL((bb_forward_flat_kernel<K, LB>), grid, block, stage_bytes<K>(p.fs.W), s, ang,
+                       xyz, p.d_head_bits, p.fs.d_look_first, p.fs.d_status, p.R, p.bb);
     return hipGetLastError();
 }
 
 template <int K>
 hipError_t fwd_k(const a2c_plan &p, const float *ang, float *xyz, hipStream_t s)
 {
-    const bool small = p.fs.W * kWave <= kLbSmall;
-    if (p.fs.multi_chunk)
-        return small ? fwd_kml<K, true, kLbSmall>(p, ang, xyz, s)
-                     : fwd_kml<K, true, kLbLarge>(p, ang, xyz, s);
-    return small ? fwd_kml<K, false, kLbSmall>(p, ang, xyz, s)
-                 : fwd_kml<K, false, kLbLarge>(p, ang, xyz, s);
+    const int threads = p.fs.W * kWave;
+    if (threads <= 256) return fwd_kl<K, 256>(p, ang, xyz, s);
+    if (threads <= kLbSmall) return fwd_kl<K, kLbSmall>(p, ang, xyz, s);
+    return fwd_kl<K, kLbLarge>(p, ang, xyz, s);
 }
 
 template <int K, bool MULTI, int LB>
@@ -625,12 +745,26 @@ hipError_t bwd_k(const a2c_plan &p, const float *ang, const float *xyz, const fl
 
 }  // namespace
 
+// The 8-residue forward with more than 10 waves stages more than 64 KiB.
+void bb_allow_large_lds()
+{
+    static bool done = false;
+    if (done) return;
+    for (const void *k : {(const void *)bb_forward_flat_kernel<8, kLbSmall>,
+                          (const void *)bb_forward_flat_kernel<8, kLbLarge>})
+        (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)stage_bytes<8>(kMaxWaves));
+    done = true;
+}
+
 hipError_t launch_bb_forward_scan(const a2c_plan &p, const float *ang, float *xyz, hipStream_t s)
 {
+    if (!p.fs.flat) return hipErrorInvalidValue;
     switch (p.fs.K) {
     case 1: return fwd_k<1>(p, ang, xyz, s);
     case 2: return fwd_k<2>(p, ang, xyz, s);
     case 4: return fwd_k<4>(p, ang, xyz, s);
+    case 8: return fwd_k<8>(p, ang, xyz, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -588,4 +588,174 @@ __device__ __forceinline__ void stage_store(float *buf, const float (&in)[N], fl
     wave_lds_sync();
 }
 
+
+// ------------------------------------------------- staging for fixed windows
+// Same transposes as above for wave runs that start at a multiple of the run
+// length (fixed windows), with every LDS and global address formed from a
+// per-lane base and compile-time offsets.  `full` (wave-uniform): all 64 N
+// elements are valid; otherwise only the first n are (the batch's last wave).
+
+constexpr int cgcd(int a, int b) { return b == 0 ? a : cgcd(b, a % b); }
+
+// Coalesced loads of run[0 .. 64N): element lane + 64 m goes to v[m] (0 past n).
+template <int N>
+__device__ __forceinline__ void run_load(const float *__restrict__ run, int n, bool full,
+                                         float (&v)[N])
+{
+    const int lane = threadIdx.x & 63;
+    if (full) {
+#pragma unroll
+        for (int m = 0; m < N; ++m) v[m] = run[lane + 64 * m];
+    } else {
+#pragma unroll
+        for (int m = 0; m < N; ++m) {
+            const int e = lane + 64 * m;
+            v[m] = e < n ? run[e] : 0.f;
+        }
+    }
+}
+
+// Coalesced run (from run_load) -> lane l holds elements l N .. l N + N - 1;
+// N a power of two.  Element e = lane + 64 m sits at row e / N, column e % N
+// of a row stride N + 1, i.e. at LDS index e + e / N = lane + lane / N +
+// m (64 + 64 / N).
+template <int N>
+__device__ __forceinline__ void run_to_lanes(float *buf, const float (&v)[N], float (&out)[N])
+{
+    static_assert((N & (N - 1)) == 0 && N <= 64, "N must be a power of two");
+    if constexpr (N == 1) {
+        out[0] = v[0];
+    } else {
+        const int lane = threadIdx.x & 63;
+        float *w = buf + lane + lane / N;
+#pragma unroll
+        for (int m = 0; m < N; ++m) w[m * (64 + 64 / N)] = v[m];
+        wave_lds_sync();
+#pragma unroll
+        for (int i = 0; i < N; ++i) out[i] = buf[lane * (N + 1) + i];
+        wave_lds_sync();
+    }
+}
+
+// run[l N + i] = in[i] of lane l for indices below n, written with 64
+// consecutive floats per instruction.  Rows of N + (N even) floats in LDS;
+// the read address of element e = lane + 64 m repeats with period
+// P = N / gcd(N, 64) in m up to a constant step, so P per-lane bases serve
+// all N reads.
+template <int N>
+__device__ __forceinline__ void lanes_to_run(float *buf, const float (&in)[N],
+                                             float *__restrict__ run, int n, bool full)
+{
+    const int lane = threadIdx.x & 63;
+    if constexpr (N == 1) {
+        if (full || lane < n) run[lane] = in[0];
+    } else {
+        constexpr int S = (N & 1) ? N : N + 1;
+        constexpr int P = N / cgcd(N, 64);
+        constexpr int STEP = 64 * P + (64 * P / N) * (S - N);
+#pragma unroll
+        for (int i = 0; i < N; ++i) buf[lane * S + i] = in[i];
+        wave_lds_sync();
+        int base[P];
+#pragma unroll
+        for (int m0 = 0; m0 < P; ++m0) {
+            const unsigned e = (unsigned)(lane + 64 * m0);
+            base[m0] = (int)(e + (e / N) * (S - N));
+        }
+        if (full) {
+#pragma unroll
+            for (int m = 0; m < N; ++m) run[lane + 64 * m] = buf[base[m % P] + (m / P) * STEP];
+        } else {
+#pragma unroll
+            for (int m = 0; m < N; ++m) {
+                const int e = lane + 64 * m;
+                if (e < n) run[e] = buf[base[m % P] + (m / P) * STEP];
+            }
+        }
+        wave_lds_sync();
+    }
+}
+
+// ------------------------------------------------------ window look-back
+// Fixed windows (tiles) of a packed batch hand the scan state across window
+// edges through device memory.  Every tile publishes its aggregate (the
+// product of its transforms from its last chain head, or from its start if it
+// has none, to its end) as kLbWords tagged 64-bit words: high half the launch
+// tag, low half one float.  A tile whose first chain started in an earlier
+// tile reads the aggregates of the tiles back to the one holding that head
+// (a host table) and composes them in order.  Each tile publishes before it
+// reads, so no wait depends on another wait; a tile only waits on tiles of
+// lower index, which start no later than it does.  Words are written and
+// read with relaxed device-scope atomics (each word carries its own tag, so
+// no ordering between words is needed).  The tag of a launch is one more than
+// the one a tile finds in its own words (all tiles start from 0 and every
+// launch runs every tile once, so they agree).  A wait gives up after
+// kLbSpinLimit polls and takes NaN for the missing aggregate, so every wave
+// ends even if a tile it needs never publishes.
+constexpr int kLbSpinLimit = 1 << 18;
+
+__device__ __forceinline__ uint64_t lb_load(const uint64_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void lb_store(uint64_t *p, uint32_t tag, float v)
+{
+    __hip_atomic_store(p, ((uint64_t)tag << 32) | (uint64_t)__float_as_uint(v), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait (one lane) for all kLbWords words of one tile to carry `tag`; returns
+// the aggregate (NaN when the spin limit is reached first).
+__device__ __forceinline__ Aff lb_wait_aff(const uint64_t *w, uint32_t tag)
+{
+    float v[kLbWords];
+    for (int spins = 0;; ++spins) {
+        bool ok = true;
+#pragma unroll
+        for (int k = 0; k < kLbWords; ++k) {
+            const uint64_t x = lb_load(w + k);
+            ok = ok && (uint32_t)(x >> 32) == tag;
+            v[k] = __uint_as_float((uint32_t)x);
+        }
+        if (ok) break;
+        if (spins >= kLbSpinLimit) {
+#pragma unroll
+            for (int k = 0; k < kLbWords; ++k) v[k] = __builtin_nanf("");
+            break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+    return aff_load(v);
+}
+
+__device__ __forceinline__ Aff aff_readlane(const Aff &a, int l)
+{
+    Aff o;
+    o.r00 = lane_bcast(a.r00, l); o.r10 = lane_bcast(a.r10, l); o.r20 = lane_bcast(a.r20, l);
+    o.r01 = lane_bcast(a.r01, l); o.r11 = lane_bcast(a.r11, l); o.r21 = lane_bcast(a.r21, l);
+    o.r02 = lane_bcast(a.r02, l); o.r12 = lane_bcast(a.r12, l); o.r22 = lane_bcast(a.r22, l);
+    o.t0 = lane_bcast(a.t0, l); o.t1 = lane_bcast(a.t1, l); o.t2 = lane_bcast(a.t2, l);
+    return o;
+}
+
+// The frame entering tile t: the ordered product of the aggregates of tiles
+// first .. t-1 (identity when first == t).  Called by one whole wave; lanes
+// wait on up to 64 tiles at a time, then an inclusive scan across the lanes
+// forms their product.  The result is wave-uniform.
+__device__ __forceinline__ Aff lb_carry_in(const uint64_t *status, int64_t first, int64_t t,
+                                           uint32_t tag)
+{
+    const int lane = threadIdx.x & 63;
+    Aff carry = aff_identity();
+    for (int64_t b = first; b < t; b += kWave) {
+        const int n = (int)min((int64_t)kWave, t - b);
+        Aff a = aff_identity();
+        if (lane < n) a = lb_wait_aff(status + (b + lane) * kLbWords, tag);
+        if (n > 1) aff_wave_scan<false>(a, 1ull, kWave, lane);
+        carry = aff_compose(carry, aff_readlane(a, n - 1));
+    }
+    return carry;
+}
+
 }  // namespace a2c

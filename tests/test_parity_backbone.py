@@ -72,6 +72,49 @@ def test_separate_forward_and_adjoint_schedules(fwd, adj, mode):
     _check(plan, off, ang, g, mode=mode, label=f"fwd={fwd} adj={adj}")
 
 
+@pytest.mark.parametrize("fwd,adj", [((8, 1), (4, 4)), ((8, 4), (2, 8)), ((8, 16), (1, 16)),
+                                     ((8, 3), (4, 1))])
+@pytest.mark.parametrize("mode", ["coords", "recompute"])
+def test_forward_eight_residues_per_lane(fwd, adj, mode):
+    """The forward-only 8-residue schedule: windows of 512 W residues cut
+    through chains of every edge length, chains span several windows."""
+    a2c = _a2c()
+    off, ang, g = _batch(EDGE_LENGTHS + [1500, 3, 2049], 43)
+    plan = a2c.Plan("backbone", offsets=off)
+    plan.set_forward_schedule(*fwd)
+    plan.set_adjoint_schedule(*adj)
+    assert (plan.schedule["res_per_lane"], plan.schedule["waves_per_group"]) == fwd
+    assert plan.schedule["n_tiles"] == -(-int(off[-1]) // (64 * fwd[0] * fwd[1]))
+    # chains beyond L = 1000 (where the 1e-3 A bound is stated) get the
+    # long-chain bound of the other tests
+    _check(plan, off, ang, g, mode=mode, coord_tol=4e-3, label=f"fwd={fwd} adj={adj}")
+    with pytest.raises(a2c.A2CError):
+        plan.set_schedule(8, 4)   # 8 residues per lane is a forward-only schedule
+
+
+@pytest.mark.parametrize("K,W", [(1, 1), (4, 2), (8, 4)])
+def test_forward_windows_repeat_bitwise(K, W):
+    """Each launch hands its window aggregates on with a new tag: repeated
+    launches (and the same angles after other angles) give identical bits."""
+    import torch
+    a2c = _a2c()
+    off, ang, _ = _batch([700, 1, 1000, 64, 999, 5], 47)
+    _, ang2, _ = _batch([700, 1, 1000, 64, 999, 5], 48)
+    plan = a2c.Plan("backbone", offsets=off)
+    plan.set_forward_schedule(K, W)
+    a, a2 = to_dev(ang), to_dev(ang2)
+    first = plan.forward(a).clone()
+    for _ in range(3):
+        plan.forward(a2)
+        again = plan.forward(a)
+        torch.cuda.synchronize()
+        assert torch.equal(first, again)
+    ref = oracle.backbone_forward(off, ang, GEOM)
+    err = float(np.max(np.abs(first.cpu().numpy() - ref)))
+    print(f"K={K} W={W}: repeat bitwise, max|dr|={err:.2e} A", flush=True)
+    assert err <= COORD_TOL_A
+
+
 def test_default_schedule_small_config_and_plain():
     a2c = _a2c()
     inp = make_inputs("backbone_16x64")

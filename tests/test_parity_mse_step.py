@@ -7,7 +7,9 @@ L = sum |r - t|^2 and its angle gradient in one kernel, against
   performs the same float32 operations; the compiler may contract a
   multiply-add differently in the two kernels, which changes a last bit, and
   the gradient's moment sums u . (m - o x g) cancel large terms, so the two
-  agree to 1e-5 A and 1e-4 (normwise per chain), not bit for bit.
+  agree to 1e-5 A and 1e-4 (normwise per chain), not bit for bit, where they
+  share tiles (full-atom); the backbone forward runs on fixed windows, so
+  there both are held to the oracle bounds only.
 
 Loss tolerance: the coordinates carry float32 rounding of up to ~1e-3 A
 against residuals |r - t| of order 1-10 A, and the sum runs in float32 over
@@ -72,7 +74,11 @@ def _run(plan, model, off, seq, ang, t, label, coord_tol=COORD_TOL_A, same_sched
     lerr = abs(float(loss) - L) / max(L, 1e-30)
     print(f"{label}: max|dr|={cerr:.3e} A grad_rel={gerr:.3e} loss_rel={lerr:.3e}", flush=True)
     assert cerr <= coord_tol and gerr <= GRAD_TOL_REL and lerr <= LOSS_RTOL
-    if same_schedule:  # otherwise the two scans associate differently
+    # The same association (bitwise-close results) needs the same tiles: the
+    # full-atom forward and fused step share the schedule's tiles, while the
+    # backbone forward always runs on fixed windows and the fused step on
+    # tiles of whole chains, so there only the oracle bounds above apply.
+    if same_schedule and model == "fullatom":
         assert float(np.max(np.abs(xyz - c2.cpu().numpy()))) <= 1e-5
         assert grad_rel_err(gr, g2.cpu().numpy().astype(np.float64), off) <= 1e-4
 
