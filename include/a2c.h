@@ -189,14 +189,17 @@ a2c_status a2c_plan_workspace_bytes(const a2c_plan *plan, a2c_variant variant,
 /* Scan schedule: residues per lane (1, 2 or 4 for A2C_BACKBONE; 1 or 2 for
  * A2C_FULLATOM) and waves of 64 lanes per workgroup (1..16).  A chunk is
  * 64 * waves * res_per_lane consecutive residues.
- *   - The backbone forward (a2c_forward, A2C_SCAN) runs on fixed windows:
+ *   - The backbone forward (a2c_forward, A2C_SCAN) and the backbone adjoint
+ *     from coordinates (a2c_backward with d_coords) run on fixed windows:
  *     workgroup t takes residues [t C, t C + C) of the packed batch, C one
  *     chunk, whatever the chain boundaries.  A chain entering a window from
- *     earlier ones gets its frame from those windows' aggregates, which every
- *     workgroup publishes in plan-owned device memory before it reads any
- *     (window look-back); a workgroup only waits on workgroups of lower
- *     index.  Consequently two forward calls on one plan must not run at the
- *     same time (on different streams), and every launch runs all windows.
+ *     earlier ones gets its frame from those windows' aggregates (forward),
+ *     and a chain running on into later windows gets their wrench sums
+ *     (adjoint); every workgroup publishes its own in plan-owned device
+ *     memory before it reads any (window look-back), and only waits on
+ *     workgroups that were started before it (the adjoint takes the windows
+ *     last to first).  Consequently two such calls on one plan must not run
+ *     at the same time (on different streams).
  *   - Every other kernel packs chains of at most one chunk whole, in order,
  *     into tiles of at most one chunk; a longer chain gets a tile of its own,
  *     which one workgroup walks chunk by chunk (at most 64 chunks), carrying

@@ -66,16 +66,19 @@ struct FATable {
 };
 
 // One scan schedule: K residues per lane, W waves per workgroup, and the
-// tile table packed for them (chains of at most one chunk of 64 W K residues
-// packed whole into tiles of at most one chunk; a longer chain alone), or,
-// for the backbone forward, fixed windows of one chunk with a look-back
-// table (flat).
+// layouts built for them: tiles (chains of at most one chunk of 64 W K
+// residues packed whole into tiles of at most one chunk; a longer chain
+// alone) and/or fixed windows [t C, t C + C) of one chunk C with a look-back
+// table (backbone forward: windows only; backbone adjoint: both, windows for
+// the adjoint from coordinates).  n_tiles counts the layout the schedule
+// reports: windows for the backbone forward, tiles otherwise.
 struct Sched {
     int32_t K = 4, W = 4, n_tiles = 0;
-    bool flat = false;                   // fixed windows [t C, t C + C), C = 64 W K
-    int32_t *d_look_first = nullptr;     // flat: n_tiles, first tile whose aggregate
-                                         // tile t composes (t: none)
-    uint64_t *d_status = nullptr;        // flat: n_tiles x 12 tagged aggregate words
+    int32_t n_win = 0;                   // fixed windows (0: none)
+    int32_t *d_look = nullptr;           // n_win: forward, the first window whose
+                                         // aggregate window t composes; adjoint, the
+                                         // last window whose wrench it adds (t: none)
+    uint64_t *d_status = nullptr;        // n_win x kLbWords tagged words
     int32_t fa_stage_atoms = 0;          // per-wave staging (floats per plane)
     bool fa_unstaged = false;            // stage too large for the LDS: direct I/O
     bool multi_chunk = false;            // some tile spans several chunks

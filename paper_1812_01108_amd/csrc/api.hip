@@ -44,32 +44,33 @@ void free_sched(Sched &S)
     (void)hipFree(S.d_tile_res);
     (void)hipFree(S.d_loss_part);
     (void)hipFree(S.d_loss_count);
-    (void)hipFree(S.d_look_first);
+    (void)hipFree(S.d_look);
     (void)hipFree(S.d_status);
     S.d_tile_res = nullptr;
     S.d_loss_part = nullptr;
     S.d_loss_count = nullptr;
-    S.d_look_first = nullptr;
+    S.d_look = nullptr;
     S.d_status = nullptr;
 }
 
-// Fixed windows of `cap` residues for the backbone forward: for each window
-// t, the first window whose aggregate its carry-in needs, i.e. the window
+// Fixed windows of `cap` residues.  Forward (look_back): for each window t
+// the first window whose aggregate its carry-in needs, i.e. the window
 // holding the head of the chain that residue t * cap belongs to (t itself
-// when a chain starts there).  The tagged aggregate words start at tag 0.
-a2c_status build_flat(const a2c_plan *p, int64_t cap, Sched &S, hipStream_t s)
+// when a chain starts there).  Adjoint: the last window whose wrench it adds,
+// i.e. the window holding the end of the chain of its last residue (t itself
+// when a chain ends there).  The tagged words start at tag 0.
+a2c_status build_windows(const a2c_plan *p, int64_t cap, bool look_back, Sched &S, hipStream_t s)
 {
     const int64_t n = (p->R + cap - 1) / cap;
-    std::vector<int32_t> first((size_t)n);
-    size_t c = 0;  // chain holding residue ts (non-empty: res_off[c] <= ts < res_off[c + 1])
+    std::vector<int32_t> look((size_t)n);
+    size_t c = 0;  // non-empty chain holding the residue: res_off[c] <= r < res_off[c + 1]
     for (int64_t t = 0; t < n; ++t) {
-        const int64_t ts = t * cap;
-        while (p->res_off[c + 1] <= ts) ++c;
-        first[(size_t)t] = (int32_t)(p->res_off[c] / cap);
+        const int64_t r = look_back ? t * cap : std::min<int64_t>(t * cap + cap, p->R) - 1;
+        while (p->res_off[c + 1] <= r) ++c;
+        look[(size_t)t] = (int32_t)(look_back ? p->res_off[c] / cap : (p->res_off[c + 1] - 1) / cap);
     }
-    S.n_tiles = (int32_t)n;
-    S.flat = true;
-    a2c_status st = upload((void **)&S.d_look_first, first.data(), first.size() * sizeof(int32_t), s);
+    S.n_win = (int32_t)n;
+    a2c_status st = upload((void **)&S.d_look, look.data(), look.size() * sizeof(int32_t), s);
     if (st != A2C_OK) return st;
     const size_t words = (size_t)std::max<int64_t>(1, n) * kLbWords * sizeof(uint64_t);
     hipError_t e = hipMalloc((void **)&S.d_status, words);
@@ -78,6 +79,8 @@ a2c_status build_flat(const a2c_plan *p, int64_t cap, Sched &S, hipStream_t s)
     return A2C_OK;
 }
 
+// Pack the tiles of schedule (K, W) and upload its tile table into out
+// (whose own table, if any, the caller frees).
 // Greedy packing of whole chains, in order, into tiles: chains of at most one
 // chunk (`cap` residues) share tiles of at most `cap` residues; a longer chain
 // gets a tile of its own, which the kernels walk chunk by chunk.  Zero-length
@@ -106,11 +109,14 @@ std::vector<int32_t> pack_tiles(const std::vector<int32_t> &off, int64_t cap)
     return tiles;
 }
 
-// Pack the tiles of schedule (K, W) and upload its tile table into out
-// (whose own table, if any, the caller frees).
+// Layouts of a schedule (see Sched).
+enum SchedRole { kRoleForward, kRoleAdjoint };
+
 a2c_status build_sched(const a2c_plan *p, int32_t K, int32_t W, Sched &out, hipStream_t s,
-                       bool flat)
+                       SchedRole role)
 {
+    const bool windows = p->model == A2C_BACKBONE;
+    const bool flat = windows && role == kRoleForward;  // windows only
     const int64_t cap = (int64_t)kWave * W * K;  // residues per chunk
     if (p->max_len > cap * kMaxChunks)
         return fail(A2C_ERR_UNSUPPORTED, "a chain of " + std::to_string(p->max_len) +
@@ -121,7 +127,8 @@ a2c_status build_sched(const a2c_plan *p, int32_t K, int32_t W, Sched &out, hipS
         Sched S;
         S.K = K;
         S.W = W;
-        a2c_status st = build_flat(p, cap, S, s);
+        a2c_status st = build_windows(p, cap, true, S, s);
+        S.n_tiles = S.n_win;
         if (st == A2C_OK) {
             const hipError_t e = hipStreamSynchronize(s);
             if (e != hipSuccess) st = hip_fail(e, "hipStreamSynchronize");
@@ -183,6 +190,7 @@ a2c_status build_sched(const a2c_plan *p, int32_t K, int32_t W, Sched &out, hipS
         pairs[2 * t + 1] = tiles[order[t] + 1];
     }
     a2c_status st = upload((void **)&S.d_tile_res, pairs.data(), pairs.size() * sizeof(int32_t), s);
+    if (st == A2C_OK && windows) st = build_windows(p, cap, false, S, s);
     // the fused step's per-tile loss shares and its count of finished tiles
     // (zero: the last tile of every launch sets it back to zero)
     if (st == A2C_OK) {
@@ -209,18 +217,14 @@ a2c_status build_sched(const a2c_plan *p, int32_t K, int32_t W, Sched &out, hipS
 void retire_sched(a2c_plan *p, Sched &S)
 {
     for (void *q : {(void *)S.d_tile_res, (void *)S.d_loss_part, (void *)S.d_loss_count,
-                    (void *)S.d_look_first, (void *)S.d_status})
+                    (void *)S.d_look, (void *)S.d_status})
         if (q) p->retired.push_back(q);
     S.d_tile_res = nullptr;
     S.d_loss_part = nullptr;
     S.d_loss_count = nullptr;
-    S.d_look_first = nullptr;
+    S.d_look = nullptr;
     S.d_status = nullptr;
 }
-
-// The backbone forward runs on fixed windows; everything else on tiles of
-// whole chains.
-bool forward_is_flat(const a2c_plan *p) { return p->model == A2C_BACKBONE; }
 
 // Replace one of the plan's schedules; on failure it stays as it was.  The
 // old tables are retired (kept until the plan is destroyed), or freed at once
@@ -230,7 +234,7 @@ a2c_status set_sched(a2c_plan *p, Sched &dst, int32_t K, int32_t W, hipStream_t 
                      bool retire_old = true)
 {
     Sched S;
-    const a2c_status st = build_sched(p, K, W, S, s, &dst == &p->fs && forward_is_flat(p));
+    const a2c_status st = build_sched(p, K, W, S, s, &dst == &p->fs ? kRoleForward : kRoleAdjoint);
     if (st != A2C_OK) return st;
     if (retire_old) retire_sched(p, dst);
     else free_sched(dst);
@@ -243,9 +247,9 @@ a2c_status apply_schedule(a2c_plan *p, int32_t K, int32_t W, hipStream_t s,
                           bool retire_old = true)
 {
     Sched f, b;
-    a2c_status st = build_sched(p, K, W, f, s, forward_is_flat(p));
+    a2c_status st = build_sched(p, K, W, f, s, kRoleForward);
     if (st != A2C_OK) return st;
-    st = build_sched(p, K, W, b, s, false);
+    st = build_sched(p, K, W, b, s, kRoleAdjoint);
     if (st != A2C_OK) {
         free_sched(f);
         return st;

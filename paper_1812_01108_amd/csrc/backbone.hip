@@ -499,77 +499,170 @@ __global__ __launch_bounds__(LB) void bb_backward_recompute_kernel(
     }
 }
 
-// Backward from the coordinates the forward produced (chunks last to first).
-template <int K, bool MULTI, int LB>
-__global__ __launch_bounds__(LB) void bb_backward_coords_kernel(
+// Adjoint from the coordinates the forward produced, over fixed windows of
+// the packed batch (as the forward), last window first.  A window publishes
+// the wrench sum from its start up to its first chain end, then adds those of
+// the later windows its last chain runs into (window look-back; a window only
+// waits on later windows, which start no later than it does).
+//   1. coordinates and upstream gradients: coalesced loads, LDS transpose;
+//   2. per lane: wrench sum of its atoms up to and including its first chain
+//      end; segmented suffix scan across the wave, then of the wave totals by
+//      wave 0, which publishes and reads the window wrenches;
+//   3. per lane, last atom first: dL/dalpha = u . (S_rg - r x S_g) with S the
+//      wrench of everything after the atom in its chain, then add the atom;
+//   4. LDS transpose, coalesced stores of the phi, psi, omega planes.
+template <int K, int LB>
+__global__ __launch_bounds__(LB) void bb_backward_coords_flat_kernel(
     const float *__restrict__ xyz, const float *__restrict__ g, float *__restrict__ gang,
-    const int32_t *__restrict__ tile_res, const uint32_t *__restrict__ head_bits, int64_t R,
-    BBParams P0)
+    const uint32_t *__restrict__ head_bits, const int32_t *__restrict__ look_last,
+    uint64_t *__restrict__ status, int64_t R, BBParams P)
 {
     extern __shared__ float stage_mem[];
-    __shared__ BwdShared shb[2];
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    __shared__ BwdShared sh;
+    __shared__ float carry_sh[6];
+    constexpr int RUN = kWave * K;  // residues per wave
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nw = blockDim.x >> 6;
+    const int64_t t = (int64_t)gridDim.x - 1 - blockIdx.x;  // last window first
+    const int64_t ts = t * RUN * nw, te = min(ts + (int64_t)RUN * nw, R);
+    const int nact = (int)((te - ts + RUN - 1) / RUN);
+    const int64_t rbase = ts + (int64_t)wave * RUN;
+    const int nres = (int)max((int64_t)0, min((int64_t)RUN, te - rbase));
+    const bool active = nres > 0, full = nres == RUN;
+    const int64_t rs = rbase + lane * K;
     float *buf = stage_mem + wave * kWave * Stride<3 * K>::value;
-    const int64_t ts = tile_res[2 * blockIdx.x], te = tile_res[2 * blockIdx.x + 1];
     const int64_t A = 3 * R;
-    // MULTI = false: every tile is one chunk (straight-line code)
-    const int nch = MULTI ? chunks_of<K>(ts, te) : 1;
-    Wrench rcarry = wrench_zero();
-    for (int c = nch - 1; c >= 0; --c) {
-        const BBParams P = MULTI ? opaque_params(P0) : P0;
-        const Chunk k = chunk_of<K>(ts, te, c);
-        const int64_t rbase = k.cs + (int64_t)wave * kWave * K;
-        const bool active = wave < k.nact;
-        const int nres = active ? (int)min((int64_t)kWave * K, k.ce - rbase) : 0;
-        const int64_t rs = k.cs + (int64_t)tid * K;
-        const int cnt = (int)max((int64_t)0, min((int64_t)K, k.ce - rs));
-        float x[3 * K], y[3 * K], z[3 * K], gx[3 * K], gy[3 * K], gz[3 * K];
-        const uint32_t hm = lane_head_mask<K>(head_bits, rs, k.ce, cnt);
-        const uint32_t lm = lane_head_mask<K>(head_bits, rs + 1, k.ce + 1, cnt);
-        // the atom before lane 0 of the wave (read before the fenced transposes)
+    uint64_t prev = 0;
+    int64_t last = t;
+    if (wave == 0) {
+        prev = lb_load(status + t * kLbWords);
+        last = look_last[t];
+    }
+    // heads (hm) and chain ends (lm: residue j ends a chain when j + 1 starts
+    // one; bit R is set) of the lane's residues.  Lanes past the batch end
+    // hold zero gradients, so whatever bits they read add nothing.
+    const uint32_t hm = head_mask<K>(head_bits, rs < te ? rs : te);
+    const uint32_t lm = head_mask<K>(head_bits, rs < te ? rs + 1 : te + 1);
+    float x[3 * K], y[3 * K], z[3 * K], gx[3 * K], gy[3 * K], gz[3 * K];
+    float px = 0.f, py = 0.f, pz = 0.f;  // the atom before the lane's first
+    if (active) {
+        // the atom before lane 0 of the wave (read ahead of the fenced transposes)
         float px0 = 0.f, py0 = 0.f, pz0 = 0.f;
-        if (lane == 0 && cnt > 0 && !(hm & 1u)) {
+        if (lane == 0 && !(hm & 1u)) {
             const float *xb = xyz + 3 * rs;
             px0 = xb[-1]; py0 = xb[A - 1]; pz0 = xb[2 * A - 1];
         }
-        float px = 0.f, py = 0.f, pz = 0.f;
-        if (active) {
-            const float *xb = xyz + 3 * rbase;
-            const float *gb = g + 3 * rbase;
-            {
-                float w0[3 * K], w1[3 * K], w2[3 * K];
-                gload<3 * K>(xb, 3 * nres, w0);
-                gload<3 * K>(xb + A, 3 * nres, w1);
-                gload<3 * K>(xb + 2 * A, 3 * nres, w2);
-                to_blocked<3 * K>(buf, w0, 3 * nres, x);
-                to_blocked<3 * K>(buf, w1, 3 * nres, y);
-                to_blocked<3 * K>(buf, w2, 3 * nres, z);
-            }
-            {
-                float w0[3 * K], w1[3 * K], w2[3 * K];
-                gload<3 * K>(gb, 3 * nres, w0);
-                gload<3 * K>(gb + A, 3 * nres, w1);
-                gload<3 * K>(gb + 2 * A, 3 * nres, w2);
-                to_blocked<3 * K>(buf, w0, 3 * nres, gx);
-                to_blocked<3 * K>(buf, w1, 3 * nres, gy);
-                to_blocked<3 * K>(buf, w2, 3 * nres, gz);
-            }
-            // the atom before the lane: last atom of the previous lane, or of
-            // the previous run for lane 0 (the origin when a chain starts here)
-            const float lx = dpp_f<kDppWaveShr1>(x[3 * K - 1]);
-            const float ly = dpp_f<kDppWaveShr1>(y[3 * K - 1]);
-            const float lz = dpp_f<kDppWaveShr1>(z[3 * K - 1]);
-            if (cnt > 0 && !(hm & 1u)) {
-                if (lane > 0) { px = lx; py = ly; pz = lz; }
-                else { px = px0; py = py0; pz = pz0; }
+        float w0[3 * K], w1[3 * K], w2[3 * K], w3[3 * K], w4[3 * K], w5[3 * K];
+        const float *xb = xyz + 3 * rbase, *gb = g + 3 * rbase;
+        run_load<3 * K>(xb, 3 * nres, full, w0);
+        run_load<3 * K>(xb + A, 3 * nres, full, w1);
+        run_load<3 * K>(xb + 2 * A, 3 * nres, full, w2);
+        run_load<3 * K>(gb, 3 * nres, full, w3);
+        run_load<3 * K>(gb + A, 3 * nres, full, w4);
+        run_load<3 * K>(gb + 2 * A, 3 * nres, full, w5);
+        run_to_lanes<3 * K>(buf, w0, x);
+        run_to_lanes<3 * K>(buf, w1, y);
+        run_to_lanes<3 * K>(buf, w2, z);
+        run_to_lanes<3 * K>(buf, w3, gx);
+        run_to_lanes<3 * K>(buf, w4, gy);
+        run_to_lanes<3 * K>(buf, w5, gz);
+        const float lx = dpp_f<kDppWaveShr1>(x[3 * K - 1]);
+        const float ly = dpp_f<kDppWaveShr1>(y[3 * K - 1]);
+        const float lz = dpp_f<kDppWaveShr1>(z[3 * K - 1]);
+        if (!(hm & 1u)) {
+            px = lane > 0 ? lx : px0;
+            py = lane > 0 ? ly : py0;
+            pz = lane > 0 ? lz : pz0;
+        }
+    }
+    // wrench of the lane's atoms up to and including its first chain end
+    Wrench agg = wrench_zero();
+    bool f = false;
+    if (active) {
+        if (__builtin_amdgcn_ballot_w64(lm != 0u) == 0ull) {  // no chain ends in the wave
+#pragma unroll
+            for (int i = 0; i < 3 * K; ++i) wrench_add_point(agg, x[i], y[i], z[i], gx[i], gy[i], gz[i]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+#pragma unroll
+                for (int s = 0; s < 3; ++s) {
+                    const int i = 3 * j + s;
+                    if (!f) wrench_add_point(agg, x[i], y[i], z[i], gx[i], gy[i], gz[i]);
+                }
+                if ((lm >> j) & 1u) f = true;
             }
         }
-        float gr[3][K];
-        bb_lane_adjoint<K, MULTI>(P, k.nact, shb[c & 1], rcarry, x, y, z, gx, gy, gz, px, py, pz, cnt,
-                           hm, lm, gr);
-        if (active) store_angle_grads<K>(buf, gr, gang, R, rbase, nres);
     }
+    // segmented suffix scan: inside each wave, then the wave totals by wave 0
+    const uint64_t ends = __builtin_amdgcn_ballot_w64(f);
+    if (active) {
+        wrench_wave_rscan<false>(agg, ends, kWave, lane);
+        if (lane == 0) {
+            wrench_store(sh.tot[wave], agg);
+            sh.tot_flag[wave] = ends != 0ull ? 1 : 0;
+        }
+    }
+    __syncthreads();
+    if (wave == 0) {
+        Wrench tw = wrench_zero();
+        bool tf = false;
+        if (lane < nact) {
+            tw = wrench_load(sh.tot[lane]);
+            tf = sh.tot_flag[lane] != 0;
+        }
+        const uint64_t th = __builtin_amdgcn_ballot_w64(tf);
+        wrench_wave_rscan<true>(tw, th, nact, lane);
+        if (lane < nact) {
+            wrench_store(sh.suf[lane], tw);
+            sh.suf_flag[lane] = (th & (~0ull << lane)) != 0ull ? 1 : 0;
+        }
+        wave_lds_sync();
+        // publish this window's wrench, then read the later windows' ones
+        const uint32_t tag = (uint32_t)(__builtin_amdgcn_readfirstlane((uint32_t)(prev >> 32))) + 1u;
+        if (lane < kLbWrenchWords) lb_store(status + t * kLbWords + lane, tag, sh.suf[0][lane]);
+        const int64_t l = (int64_t)__builtin_amdgcn_readfirstlane((int)last);
+        const Wrench carry = lb_carry_after(status, t, l, tag);
+        if (lane == 0) wrench_store(carry_sh, carry);
+    }
+    __syncthreads();
+    if (!active) return;
+    // everything after the wave up to the end of its last chain
+    const Wrench carry = wrench_load(carry_sh);
+    Wrench cw = carry;
+    if (wave + 1 < nact) {
+        cw = wrench_load(sh.suf[wave + 1]);
+        if (sh.suf_flag[wave + 1] == 0) wrench_add(cw, carry);
+    }
+    // everything after lane l inside the wave: the inclusive value of lane
+    // l + 1, complete when a chain ends in lanes after l
+    Wrench S = wrench_dpp_z<kDppWaveShl1>(agg);
+    if (lane == kWave - 1) S = wrench_zero();
+    if (!(lane < kWave - 1 && (ends >> (lane + 1)) != 0ull)) wrench_add(S, cw);
+    float gr[3][K];
+#pragma unroll
+    for (int j = K - 1; j >= 0; --j) {
+        if ((lm >> j) & 1u) S = wrench_zero();
+        const bool head = (hm >> j) & 1u;
+#pragma unroll
+        for (int s = 2; s >= 0; --s) {
+            const int i = 3 * j + s;
+            float qx, qy, qz;  // atom before i
+            if (s > 0) { qx = x[i - 1]; qy = y[i - 1]; qz = z[i - 1]; }
+            else if (head) { qx = 0.f; qy = 0.f; qz = 0.f; }
+            else if (j > 0) { qx = x[i - 1]; qy = y[i - 1]; qz = z[i - 1]; }
+            else { qx = px; qy = py; qz = pz; }
+            const float ux = (x[i] - qx) * P.inv_d[s];
+            const float uy = (y[i] - qy) * P.inv_d[s];
+            const float uz = (z[i] - qz) * P.inv_d[s];
+            gr[s][j] = wrench_torque(S, x[i], y[i], z[i], ux, uy, uz);
+            wrench_add_point(S, x[i], y[i], z[i], gx[i], gy[i], gz[i]);
+        }
+    }
+    lanes_to_run<K>(buf, gr[1], gang + rbase, nres, full);           // phi  (slot CA)
+    lanes_to_run<K>(buf, gr[2], gang + R + rbase, nres, full);       // psi  (slot C)
+    lanes_to_run<K>(buf, gr[0], gang + 2 * R + rbase, nres, full);   // omega (slot N)
 }
 
 // ---------------------------------------------------------------- plain form
@@ -677,9 +770,9 @@ __global__ __launch_bounds__(kPlainBlock) void bb_backward_plain_kernel(
 template <int K, int LB>
 hipError_t fwd_kl(const a2c_plan &p, const float *ang, float *xyz, hipStream_t s)
 {
-    const dim3 grid(p.fs.n_tiles), block(p.fs.W * kWave);
+    const dim3 grid(p.fs.n_win), block(p.fs.W * kWave);
     hipLaunchKernelGGL((bb_forward_flat_kernel<K, LB>), grid, block, stage_bytes<K>(p.fs.W), s, ang,
-                       xyz, p.d_head_bits, p.fs.d_look_first, p.fs.d_status, p.R, p.bb);
+                       xyz, p.d_head_bits, p.fs.d_look, p.fs.d_status, p.R, p.bb);
     return hipGetLastError();
 }
 
@@ -699,8 +792,8 @@ hipError_t bwd_kml(const a2c_plan &p, const float *ang, const float *xyz, const 
     const dim3 grid(p.bs.n_tiles), block(p.bs.W * kWave);
     const size_t lds = stage_bytes<K>(p.bs.W);
     if (xyz)
-        hipLaunchKernelGGL((bb_backward_coords_kernel<K, MULTI, LB>), grid, block, lds, s, xyz,
-                           g, gang, p.bs.d_tile_res, p.d_head_bits, p.R, p.bb);
+        hipLaunchKernelGGL((bb_backward_coords_flat_kernel<K, LB>), dim3(p.bs.n_win), block, lds, s,
+                           xyz, g, gang, p.d_head_bits, p.bs.d_look, p.bs.d_status, p.R, p.bb);
     else
         hipLaunchKernelGGL((bb_backward_recompute_kernel<K, MULTI, LB, kGradLoad>), grid, block,
                            lds, s, ang, g, gang, nullptr, nullptr, nullptr, nullptr,
@@ -759,7 +852,7 @@ void bb_allow_large_lds()
 
 hipError_t launch_bb_forward_scan(const a2c_plan &p, const float *ang, float *xyz, hipStream_t s)
 {
-    if (!p.fs.flat) return hipErrorInvalidValue;
+    if (p.fs.n_win != p.fs.n_tiles || !p.fs.d_look) return hipErrorInvalidValue;
     switch (p.fs.K) {
     case 1: return fwd_k<1>(p, ang, xyz, s);
     case 2: return fwd_k<2>(p, ang, xyz, s);

@@ -615,24 +615,32 @@ __device__ __forceinline__ void run_load(const float *__restrict__ run, int n, b
     }
 }
 
-// Coalesced run (from run_load) -> lane l holds elements l N .. l N + N - 1;
-// N a power of two.  Element e = lane + 64 m sits at row e / N, column e % N
-// of a row stride N + 1, i.e. at LDS index e + e / N = lane + lane / N +
-// m (64 + 64 / N).
+// Coalesced run (from run_load) -> lane l holds elements l N .. l N + N - 1.
+// Rows of S = N + (N even) floats in LDS: element e = lane + 64 m sits at
+// index e + (e / N)(S - N), which repeats with period P = N / gcd(N, 64) in m
+// up to a constant step, so P per-lane bases serve all N writes; each lane
+// then reads its own row.
 template <int N>
 __device__ __forceinline__ void run_to_lanes(float *buf, const float (&v)[N], float (&out)[N])
 {
-    static_assert((N & (N - 1)) == 0 && N <= 64, "N must be a power of two");
     if constexpr (N == 1) {
         out[0] = v[0];
     } else {
         const int lane = threadIdx.x & 63;
-        float *w = buf + lane + lane / N;
+        constexpr int S = (N & 1) ? N : N + 1;
+        constexpr int P = N / cgcd(N, 64);
+        constexpr int STEP = 64 * P + (64 * P / N) * (S - N);
+        int base[P];
 #pragma unroll
-        for (int m = 0; m < N; ++m) w[m * (64 + 64 / N)] = v[m];
+        for (int m0 = 0; m0 < P; ++m0) {
+            const unsigned e = (unsigned)(lane + 64 * m0);
+            base[m0] = (int)(e + (e / N) * (S - N));
+        }
+#pragma unroll
+        for (int m = 0; m < N; ++m) buf[base[m % P] + (m / P) * STEP] = v[m];
         wave_lds_sync();
 #pragma unroll
-        for (int i = 0; i < N; ++i) out[i] = buf[lane * (N + 1) + i];
+        for (int i = 0; i < N; ++i) out[i] = buf[lane * S + i];
         wave_lds_sync();
     }
 }
@@ -754,6 +762,64 @@ __device__ __forceinline__ Aff lb_carry_in(const uint64_t *status, int64_t first
         if (lane < n) a = lb_wait_aff(status + (b + lane) * kLbWords, tag);
         if (n > 1) aff_wave_scan<false>(a, 1ull, kWave, lane);
         carry = aff_compose(carry, aff_readlane(a, n - 1));
+    }
+    return carry;
+}
+
+
+// Sum of v over the 64 lanes of a wave in a fixed order (deterministic);
+// wave-uniform result.
+__device__ __forceinline__ float wave_sum_fixed(float v)
+{
+    v += dpp_f<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+    v += dpp_f<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+    v += dpp_f<0x141>(v);   // row_half_mirror
+    v += dpp_f<0x140>(v);   // row_mirror
+    return (lane_bcast(v, 0) + lane_bcast(v, 16)) + (lane_bcast(v, 32) + lane_bcast(v, 48));
+}
+
+// The adjoint's windows publish wrenches (kLbWrenchWords of a tile's
+// kLbWords slots): the sum over the window from its start up to and
+// including its first chain end (all of it when no chain ends there).
+constexpr int kLbWrenchWords = 6;
+
+__device__ __forceinline__ Wrench lb_wait_wrench(const uint64_t *w, uint32_t tag)
+{
+    float v[kLbWrenchWords];
+    for (int spins = 0;; ++spins) {
+        bool ok = true;
+#pragma unroll
+        for (int k = 0; k < kLbWrenchWords; ++k) {
+            const uint64_t x = lb_load(w + k);
+            ok = ok && (uint32_t)(x >> 32) == tag;
+            v[k] = __uint_as_float((uint32_t)x);
+        }
+        if (ok) break;
+        if (spins >= kLbSpinLimit) {
+#pragma unroll
+            for (int k = 0; k < kLbWrenchWords; ++k) v[k] = __builtin_nanf("");
+            break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+    return wrench_load(v);
+}
+
+// The wrench entering window t from the windows after it: the sum of the
+// published wrenches of windows t + 1 .. last (zero when last == t), in a
+// fixed order.  Called by one whole wave; wave-uniform result.
+__device__ __forceinline__ Wrench lb_carry_after(const uint64_t *status, int64_t t, int64_t last,
+                                                 uint32_t tag)
+{
+    const int lane = threadIdx.x & 63;
+    Wrench carry = wrench_zero();
+    for (int64_t b = t + 1; b <= last; b += kWave) {
+        const int n = (int)min((int64_t)kWave, last + 1 - b);
+        Wrench w = wrench_zero();
+        if (lane < n) w = lb_wait_wrench(status + (b + lane) * kLbWords, tag);
+        carry.g0 += wave_sum_fixed(w.g0); carry.g1 += wave_sum_fixed(w.g1);
+        carry.g2 += wave_sum_fixed(w.g2); carry.m0 += wave_sum_fixed(w.m0);
+        carry.m1 += wave_sum_fixed(w.m1); carry.m2 += wave_sum_fixed(w.m2);
     }
     return carry;
 }

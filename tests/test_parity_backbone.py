@@ -92,27 +92,36 @@ def test_forward_eight_residues_per_lane(fwd, adj, mode):
         plan.set_schedule(8, 4)   # 8 residues per lane is a forward-only schedule
 
 
-@pytest.mark.parametrize("K,W", [(1, 1), (4, 2), (8, 4)])
-def test_forward_windows_repeat_bitwise(K, W):
-    """Each launch hands its window aggregates on with a new tag: repeated
-    launches (and the same angles after other angles) give identical bits."""
+@pytest.mark.parametrize("K,W,aK,aW", [(1, 1, 1, 1), (4, 2, 2, 3), (8, 4, 4, 4)])
+def test_windows_repeat_bitwise(K, W, aK, aW):
+    """Each launch hands its window aggregates (forward) and wrenches
+    (adjoint from coordinates) on with a new tag: repeated launches, and the
+    same inputs after other inputs, give identical bits."""
     import torch
     a2c = _a2c()
-    off, ang, _ = _batch([700, 1, 1000, 64, 999, 5], 47)
-    _, ang2, _ = _batch([700, 1, 1000, 64, 999, 5], 48)
+    lengths = [700, 1, 1000, 64, 999, 5]
+    off, ang, g = _batch(lengths, 47)
+    _, ang2, g2 = _batch(lengths, 48)
     plan = a2c.Plan("backbone", offsets=off)
     plan.set_forward_schedule(K, W)
-    a, a2 = to_dev(ang), to_dev(ang2)
+    plan.set_adjoint_schedule(aK, aW)
+    a, a2, gd, gd2 = to_dev(ang), to_dev(ang2), to_dev(g), to_dev(g2)
     first = plan.forward(a).clone()
+    gfirst = plan.backward(a, gd, coords=first).clone()
     for _ in range(3):
-        plan.forward(a2)
+        other = plan.forward(a2)
+        plan.backward(a2, gd2, coords=other)
         again = plan.forward(a)
+        gagain = plan.backward(a, gd, coords=again)
         torch.cuda.synchronize()
-        assert torch.equal(first, again)
+        assert torch.equal(first, again) and torch.equal(gfirst, gagain)
     ref = oracle.backbone_forward(off, ang, GEOM)
+    gref = oracle.backbone_backward(off, ang, GEOM, g)
     err = float(np.max(np.abs(first.cpu().numpy() - ref)))
-    print(f"K={K} W={W}: repeat bitwise, max|dr|={err:.2e} A", flush=True)
-    assert err <= COORD_TOL_A
+    gerr = grad_rel_err(gfirst.cpu().numpy(), gref, off)
+    print(f"K={K} W={W} adj=({aK},{aW}): repeat bitwise, max|dr|={err:.2e} A "
+          f"grad_rel={gerr:.2e}", flush=True)
+    assert err <= COORD_TOL_A and gerr <= GRAD_TOL_REL
 
 
 def test_default_schedule_small_config_and_plain():
