@@ -62,6 +62,10 @@ typedef enum {
     A2C_ERR_STATE = -5         /* call out of order (e.g. no device)         */
 } a2c_status;
 
+/* Selector arguments (model, variant, a status to describe) are passed as
+ * int32_t holding one of these values, so that any other value is refused
+ * with A2C_ERR_INVALID_ARG (or described as unknown) rather than being an
+ * out-of-range enumeration value. */
 typedef enum { A2C_BACKBONE = 0, A2C_FULLATOM = 1 } a2c_model;
 
 /* A2C_SCAN: the library's form -- segmented scans over 3x4 affine transforms
@@ -157,7 +161,7 @@ typedef struct {
  * than 64 chunks of the widest schedule (262144 residues for A2C_BACKBONE,
  * 131072 for A2C_FULLATOM), or if the full-atom default schedule cannot stage
  * its atoms in LDS.  *out is NULL on failure.                             */
-a2c_status a2c_plan_create(a2c_plan **out, a2c_model model, int32_t n_chains,
+a2c_status a2c_plan_create(a2c_plan **out, int32_t model, int32_t n_chains,
                            const int32_t *h_res_offsets, const uint8_t *h_seq,
                            const a2c_backbone_geometry *geom,
                            const a2c_residue_table *table, size_t mem_budget_bytes,
@@ -183,7 +187,7 @@ a2c_status a2c_plan_atom_offsets(const a2c_plan *plan, int32_t *h_chain_atom_off
 
 /* Device workspace a variant needs (0 for A2C_SCAN; 48 bytes per atom for
  * A2C_PLAIN, which stores M_i for every atom as the paper's forward does). */
-a2c_status a2c_plan_workspace_bytes(const a2c_plan *plan, a2c_variant variant,
+a2c_status a2c_plan_workspace_bytes(const a2c_plan *plan, int32_t variant,
                                     size_t *bytes);
 
 /* Scan schedule: residues per lane (1, 2 or 4 for A2C_BACKBONE; 1 or 2 for
@@ -269,7 +273,7 @@ a2c_status a2c_plan_autotune(a2c_plan *plan, const float *d_angles, float *d_coo
 /* Forward map: d_angles [K][R] -> d_coords [3][A].
  * d_workspace: NULL for A2C_SCAN; for A2C_PLAIN a buffer of
  * a2c_plan_workspace_bytes that a2c_backward(A2C_PLAIN) reads later. */
-a2c_status a2c_forward(a2c_plan *plan, a2c_variant variant, const float *d_angles,
+a2c_status a2c_forward(a2c_plan *plan, int32_t variant, const float *d_angles,
                        float *d_coords, void *d_workspace, void *stream);
 
 /* Adjoint: given d_grad_coords = dL/dr [3][A], writes dL/dalpha [K][R]
@@ -282,7 +286,7 @@ a2c_status a2c_forward(a2c_plan *plan, a2c_variant variant, const float *d_angle
  *   dL/dalpha_i = u_i . sum_{k in subtree(i)} (r_k - r_i) x dL/dr_k,
  * u_i the unit bond vector the node rotates about, which equals the sums of
  * Eq. BackboneGradOutput / Eq. FAMBackward. */
-a2c_status a2c_backward(a2c_plan *plan, a2c_variant variant, const float *d_angles,
+a2c_status a2c_backward(a2c_plan *plan, int32_t variant, const float *d_angles,
                         const float *d_coords, const float *d_grad_coords,
                         float *d_grad_angles, void *d_workspace, void *stream);
 
@@ -395,7 +399,7 @@ a2c_status a2c_lrmsd_forward_noalloc(a2c_plan *plan, const float *d_coords,
 a2c_status a2c_residue_table_info(const a2c_residue_table *table, int32_t *n_atoms,
                                   float *local_xyz);
 
-const char *a2c_status_string(a2c_status status);
+const char *a2c_status_string(int32_t status);
 const char *a2c_last_error(void);
 
 /* Library version string, e.g. "a2c 0.1 gfx950". */

@@ -23,9 +23,10 @@ _U8 = ctypes.POINTER(ctypes.c_uint8)
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB):
+        path = os.environ.get("A2C_ORACLE_LIB", LIB)  # e.g. the sanitizer build
+        if path == LIB and not os.path.exists(LIB):
             build()
-        lib = ctypes.CDLL(LIB)
+        lib = ctypes.CDLL(path)
         lib.oracle_transform.argtypes = [ctypes.c_double] * 3 + [_D]
         for name in ("oracle_backbone_forward",):
             getattr(lib, name).argtypes = [ctypes.c_int32, _I32, _D, _D, _D, ctypes.c_int]

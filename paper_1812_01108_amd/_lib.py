@@ -9,7 +9,8 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libangles2coords.so")
+# A2C_LIB selects another build of the library (the host-sanitizer one)
+LIB_PATH = os.environ.get("A2C_LIB", os.path.join(HERE, "libangles2coords.so"))
 
 A2C_OK = 0
 STATUS = {0: "A2C_OK", -1: "A2C_ERR_INVALID_ARG", -2: "A2C_ERR_UNSUPPORTED",

@@ -14,6 +14,13 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libangles2coords.so")
+# host code under AddressSanitizer + UndefinedBehaviorSanitizer (clang's
+# runtimes; the process must preload libclang_rt.asan), for checking the
+# host-side validation and plan building on a machine without a GPU; the
+# device code is compiled as usual
+LIB_SAN = os.path.join(HERE, "libangles2coords_san.so")
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-g"]
 INCLUDE = os.path.join(HERE, "..", "include")
 SOURCES = ["api.hip", "backbone.hip", "fullatom.hip", "autotune.hip", "lrmsd.hip",
            "inverse.hip"]
@@ -31,7 +38,10 @@ def _jobs() -> int:
     return max(1, min(len(SOURCES), int(n) if n and n.isdigit() else (os.cpu_count() or 1)))
 
 
-def build(verbose: bool = False, extra=()) -> str:
+def build(verbose: bool = False, extra=(), sanitize: bool = False) -> str:
+    if sanitize:
+        extra = (*extra, *SAN_FLAGS)
+    out = LIB_SAN if sanitize else LIB
     tmpdir = tempfile.mkdtemp(prefix="a2c_build_")
     try:
         def compile_one(src):
@@ -45,16 +55,16 @@ def build(verbose: bool = False, extra=()) -> str:
 
         with ThreadPoolExecutor(_jobs()) as pool:
             objs = list(pool.map(compile_one, SOURCES))
-        tmp = LIB + ".tmp"
+        tmp = out + ".tmp"
         cmd = ["hipcc", *ARCH, "-shared", "-fPIC", *objs, "-o", tmp]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
-        os.replace(tmp, LIB)
+        os.replace(tmp, out)
     finally:
         shutil.rmtree(tmpdir, ignore_errors=True)
-    return LIB
+    return out
 
 
 if __name__ == "__main__":
-    build(verbose="-v" in sys.argv)
+    build(verbose="-v" in sys.argv, sanitize="--sanitize" in sys.argv)

@@ -115,8 +115,8 @@ enum SchedRole { kRoleForward, kRoleAdjoint };
 a2c_status build_sched(const a2c_plan *p, int32_t K, int32_t W, Sched &out, hipStream_t s,
                        SchedRole role)
 {
-    const bool windows = p->model == A2C_BACKBONE;
-    const bool flat = windows && role == kRoleForward;  // windows only
+    const bool windows = p->model == A2C_BACKBONE || role == kRoleForward;
+    const bool flat = role == kRoleForward;  // windows only
     const int64_t cap = (int64_t)kWave * W * K;  // residues per chunk
     if (p->max_len > cap * kMaxChunks)
         return fail(A2C_ERR_UNSUPPORTED, "a chain of " + std::to_string(p->max_len) +
@@ -127,6 +127,19 @@ a2c_status build_sched(const a2c_plan *p, int32_t K, int32_t W, Sched &out, hipS
         Sched S;
         S.K = K;
         S.W = W;
+        if (p->model == A2C_FULLATOM) {
+            // per-wave LDS stage of three planes: the most atoms of one
+            // wave's run of 64 K residues
+            int64_t most = 1;
+            for (int64_t rb = 0; rb < p->R; rb += (int64_t)kWave * K) {
+                const int64_t re = std::min<int64_t>(rb + (int64_t)kWave * K, p->R);
+                most = std::max<int64_t>(most, p->res_atom_off[re] - p->res_atom_off[rb]);
+            }
+            if ((size_t)W * 3 * most * sizeof(float) > (size_t)kMaxDynamicLds)
+                S.fa_unstaged = true;  // atoms straight to global memory
+            else
+                S.fa_stage_atoms = (int32_t)most;
+        }
         a2c_status st = build_windows(p, cap, true, S, s);
         S.n_tiles = S.n_win;
         if (st == A2C_OK) {
@@ -387,7 +400,7 @@ extern "C" {
 
 const char *a2c_version(void) { return "a2c 0.1 gfx950"; }
 
-const char *a2c_status_string(a2c_status st)
+const char *a2c_status_string(int32_t st)
 {
     switch (st) {
     case A2C_OK: return "ok";
@@ -421,15 +434,16 @@ void a2c_plan_destroy(a2c_plan *p)
     delete p;
 }
 
-a2c_status a2c_plan_create(a2c_plan **out, a2c_model model, int32_t n_chains,
+a2c_status a2c_plan_create(a2c_plan **out, int32_t model_id, int32_t n_chains,
                            const int32_t *h_res_offsets, const uint8_t *h_seq,
                            const a2c_backbone_geometry *geom, const a2c_residue_table *table,
                            size_t mem_budget_bytes, void *stream)
 {
     if (!out) return fail(A2C_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
-    if (model != A2C_BACKBONE && model != A2C_FULLATOM)
+    if (model_id != A2C_BACKBONE && model_id != A2C_FULLATOM)
         return fail(A2C_ERR_INVALID_ARG, "unknown model");
+    const a2c_model model = (a2c_model)model_id;
     if (n_chains < 0) return fail(A2C_ERR_INVALID_ARG, "n_chains < 0");
     if (!h_res_offsets) return fail(A2C_ERR_INVALID_ARG, "h_res_offsets is NULL");
     if (h_res_offsets[0] != 0) return fail(A2C_ERR_INVALID_ARG, "h_res_offsets[0] != 0");
@@ -588,7 +602,7 @@ a2c_status a2c_plan_keep_coords(const a2c_plan *p, int32_t *keep)
     return A2C_OK;
 }
 
-a2c_status a2c_plan_workspace_bytes(const a2c_plan *p, a2c_variant v, size_t *bytes)
+a2c_status a2c_plan_workspace_bytes(const a2c_plan *p, int32_t v, size_t *bytes)
 {
     if (!p || !bytes) return fail(A2C_ERR_INVALID_ARG, "plan or bytes is NULL");
     if (v == A2C_SCAN) *bytes = 0;
@@ -643,7 +657,7 @@ a2c_status a2c_plan_get_adjoint_schedule(const a2c_plan *p, int32_t *K, int32_t 
     return A2C_OK;
 }
 
-a2c_status a2c_forward(a2c_plan *p, a2c_variant v, const float *d_angles, float *d_coords,
+a2c_status a2c_forward(a2c_plan *p, int32_t v, const float *d_angles, float *d_coords,
                        void *d_workspace, void *stream)
 {
     if (!p) return fail(A2C_ERR_INVALID_ARG, "plan is NULL");
@@ -664,7 +678,7 @@ a2c_status a2c_forward(a2c_plan *p, a2c_variant v, const float *d_angles, float 
     return A2C_OK;
 }
 
-a2c_status a2c_backward(a2c_plan *p, a2c_variant v, const float *d_angles, const float *d_coords,
+a2c_status a2c_backward(a2c_plan *p, int32_t v, const float *d_angles, const float *d_coords,
                         const float *d_grad_coords, float *d_grad_angles, void *d_workspace,
                         void *stream)
 {

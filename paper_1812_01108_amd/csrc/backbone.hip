@@ -328,47 +328,9 @@ __global__ __launch_bounds__(LB, 4) void bb_forward_flat_kernel(
         // lane aggregate removes that drift
         aff_orthonormalise(m);
     }
-    // segmented scan: inside each wave, then the wave totals by wave 0
     const uint64_t heads = __builtin_amdgcn_ballot_w64(first_head < K);
-    if (active) {
-        aff_wave_scan<false>(m, heads, kWave, lane);
-        if (lane == kWave - 1) {
-            aff_store(sh.tot[wave], m);
-            sh.tot_flag[wave] = heads != 0ull ? 1 : 0;
-        }
-    }
-    __syncthreads();
-    if (wave == 0) {
-        Aff tw = aff_identity();
-        bool tf = false;
-        if (lane < nact) {
-            tw = aff_load(sh.tot[lane]);
-            tf = sh.tot_flag[lane] != 0;
-        }
-        const uint64_t th = __builtin_amdgcn_ballot_w64(tf);
-        aff_wave_scan<true>(tw, th, nact, lane);
-        if (lane < nact) {
-            aff_store(sh.pre[lane], tw);
-            sh.pre_flag[lane] = (th & lanes_upto(lane)) != 0ull ? 1 : 0;
-        }
-        wave_lds_sync();
-        // publish this tile's aggregate, then read the earlier tiles' ones
-        const uint32_t tag = (uint32_t)(__builtin_amdgcn_readfirstlane((uint32_t)(prev >> 32))) + 1u;
-        if (lane < kLbWords) lb_store(status + t * kLbWords + lane, tag, sh.pre[nact - 1][lane]);
-        const int64_t f = (int64_t)__builtin_amdgcn_readfirstlane((int)first);
-        const Aff carry = lb_carry_in(status, f, t, tag);
-        if (lane == 0) aff_store(carry_sh, carry);
-    }
-    __syncthreads();
+    const Aff X = block_prefix_windows(m, heads, nact, active, sh, carry_sh, status, t, first, prev);
     if (!active) return;
-    // frame entering the wave, then entering each lane
-    const Aff carry = aff_load(carry_sh);
-    Aff cw = carry;
-    if (wave > 0) cw = aff_seg_after(carry, aff_load(sh.pre[wave - 1]), sh.pre_flag[wave - 1] != 0);
-    Aff e = aff_dpp_z<kDppWaveShr1>(m);
-    if (lane == 0) e = aff_identity();
-    const bool fe = (heads & lanes_below(lane)) != 0ull;
-    const Aff X = fe ? e : aff_compose(cw, e);
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         if (j < first_head) {

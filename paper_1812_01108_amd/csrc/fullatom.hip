@@ -580,67 +580,65 @@ __device__ __forceinline__ void fa_emit_residue(const FATable &tab, const FAType
     emit_frame(tab, ft, 2, cur, sg, aloc);
 }
 
-// STG: atoms go through the per-wave LDS stage; otherwise straight to
-// global memory (schedules whose stage does not fit the LDS).
-template <int K, bool MULTI, int LB, bool STG = true>
-__global__ __launch_bounds__(LB) void fa_forward_kernel(
-    const float *__restrict__ ang, float *__restrict__ xyz, const int32_t *__restrict__ tile_res,
-    const uint32_t *__restrict__ head_bits, const int32_t *__restrict__ res_aoff,
-    const uint8_t *__restrict__ seq, const FATable *__restrict__ gtab, int64_t R, int64_t A,
-    BBParams P0, int stage_atoms)
+// Forward over fixed windows of the packed batch (window t: residues
+// [t C, t C + C), C = 64 W K, whatever the chains), as the backbone forward:
+// the spine scan hands frames across window edges by window look-back; then
+// every lane re-walks its residues from its prefix frame, building the spine
+// and side frames and writing each atom into the wave's LDS stage, which is
+// copied out with coalesced stores (STG; otherwise, for schedules whose
+// stage does not fit the LDS, straight to global memory).
+template <int K, int LB, bool STG = true>
+__global__ __launch_bounds__(LB) void fa_forward_flat_kernel(
+    const float *__restrict__ ang, float *__restrict__ xyz, const uint32_t *__restrict__ head_bits,
+    const int32_t *__restrict__ res_aoff, const uint8_t *__restrict__ seq,
+    const FATable *__restrict__ gtab, const int32_t *__restrict__ look_first,
+    uint64_t *__restrict__ status, int64_t R, int64_t A, BBParams P, int stage_atoms)
 {
     extern __shared__ float stage_mem[];
     __shared__ __align__(16) FATable tab;
-    __shared__ FwdShared sh[2];
-    const int64_t ts = tile_res[2 * blockIdx.x], te = tile_res[2 * blockIdx.x + 1];
-    // one-chunk tiles read the chunk's inputs before the table copy, so that
-    // the two latencies overlap (the copy ends in a workgroup barrier)
-    FAChunk k0{};
-    LaneRun<K> L0{};
-    SpineAngles<K> a0{};
-    LaneRes<K, true> lr0{};
-    if (!MULTI) {
-        k0 = fa_chunk<K>(ts, te, 0);
-        L0 = lane_run<K>(k0, head_bits, res_aoff);
-        if (L0.active) a0 = load_spine_angles<K>(ang, R, L0.rs, L0.cnt);
-        lr0 = load_lane_res<K, true>(L0, seq, res_aoff, ang, R);
-    }
-    load_table(tab, gtab);
+    __shared__ FwdShared sh;
+    __shared__ float carry_sh[12];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const Stage lds{stage_mem + (size_t)wave * 3 * stage_atoms, stage_atoms};
-    // MULTI = false: every tile is one chunk (straight-line code)
-    const int nch = MULTI ? fa_chunks<K>(ts, te) : 1;
-    Aff carry = aff_identity();
-    for (int c = 0; c < nch; ++c) {
-        // the same arithmetic as the adjoint kernels' recomputation
-        const BBParams P = MULTI ? opaque_params(P0) : P0;
-        const FAChunk k = MULTI ? fa_chunk<K>(ts, te, c) : k0;
-        const LaneRun<K> L = MULTI ? lane_run<K>(k, head_bits, res_aoff) : L0;
-        ResidueIn in[K];
-        int first_head = K;
-        Aff m = aff_identity();
-        if (L.active)
-            m = fa_lane_aggregate<K>(MULTI ? load_spine_angles<K>(ang, R, L.rs, L.cnt) : a0,
-                                     L.cnt, L.hm, P, in, first_head);
-        // issued after the spine angles (whose wait would otherwise cover them)
-        const LaneRes<K, true> lr = MULTI ? load_lane_res<K, true>(L, seq, res_aoff, ang, R) : lr0;
-        const Aff X = block_exclusive_prefix<MULTI>(m, first_head < K, k.nact, sh[c & 1], carry);
-        if (!L.active) continue;
-        const Stage sg = STG ? lds : Stage{xyz + L.A0, A};
-        Aff cur = X;
+    const int nw = blockDim.x >> 6;
+    const int64_t t = blockIdx.x;
+    FAChunk k;
+    k.cs = t * kWave * K * nw;
+    k.ce = min(k.cs + (int64_t)kWave * K * nw, R);
+    k.nact = (int)((k.ce - k.cs + kWave * K - 1) / (kWave * K));
+    const LaneRun<K> L = lane_run<K>(k, head_bits, res_aoff);
+    uint64_t prev = 0;
+    int64_t first = t;
+    if (wave == 0) {
+        prev = lb_load(status + t * kLbWords);
+        first = look_first[t];
+    }
+    // the window's inputs ahead of the table copy (which ends in a barrier)
+    SpineAngles<K> a{};
+    if (L.active) a = load_spine_angles<K>(ang, R, L.rs, L.cnt);
+    const LaneRes<K, true> lr = load_lane_res<K, true>(L, seq, res_aoff, ang, R);
+    load_table(tab, gtab);
+    ResidueIn in[K];
+    int first_head = K;
+    Aff m = aff_identity();
+    if (L.active) m = fa_lane_aggregate<K>(a, L.cnt, L.hm, P, in, first_head);
+    const uint64_t heads = __builtin_amdgcn_ballot_w64(first_head < K);
+    const Aff X = block_prefix_windows(m, heads, k.nact, L.active, sh, carry_sh, status, t, first,
+                                       prev);
+    if (!L.active) return;
+    const Stage sg = STG ? Stage{stage_mem + (size_t)wave * 3 * stage_atoms, stage_atoms}
+                         : Stage{xyz + L.A0, A};
+    Aff cur = X;
 #pragma unroll
-        for (int j = 0; j < K; ++j) {
-            if (j < L.cnt) {
-                if ((L.hm >> j) & 1u) cur = aff_identity();
-                fa_emit_residue(tab, tab.t[lr.type[j]], cur, in[j], lr.chi[j], P, sg,
-                                lr.aoff[j] - (int)L.A0);
-            }
+    for (int j = 0; j < K; ++j) {
+        if (j < L.cnt) {
+            if ((L.hm >> j) & 1u) cur = aff_identity();
+            fa_emit_residue(tab, tab.t[lr.type[j]], cur, in[j], lr.chi[j], P, sg,
+                            lr.aoff[j] - (int)L.A0);
         }
-        if (STG) {
-            wave_lds_sync();
-            lds_to_run(sg, xyz, A, L.A0, L.natoms);
-            wave_lds_sync();
-        }
+    }
+    if (STG) {
+        wave_lds_sync();
+        lds_to_run(sg, xyz, A, L.A0, L.natoms);
     }
 }
 
@@ -933,30 +931,29 @@ __global__ __launch_bounds__(LB) void fa_backward_kernel(
     }
 }
 
-template <int K, bool MULTI, int LB, bool STG>
-hipError_t fa_fwd_kml(const a2c_plan &p, const float *ang, float *xyz, hipStream_t s)
+template <int K, int LB, bool STG>
+hipError_t fa_fwd_kl(const a2c_plan &p, const float *ang, float *xyz, hipStream_t s)
 {
     const size_t lds = STG ? (size_t)p.fs.W * 3 * p.fs.fa_stage_atoms * sizeof(float) : 0;
-    hipLaunchKernelGGL((fa_forward_kernel<K, MULTI, LB, STG>), dim3(p.fs.n_tiles), dim3(p.fs.W * kWave),
-                       lds, s, ang, xyz, p.fs.d_tile_res, p.d_head_bits, p.d_res_atom_off, p.d_seq,
-                       p.d_fa, p.R, p.A, p.bb, p.fs.fa_stage_atoms);
+    hipLaunchKernelGGL((fa_forward_flat_kernel<K, LB, STG>), dim3(p.fs.n_win), dim3(p.fs.W * kWave),
+                       lds, s, ang, xyz, p.d_head_bits, p.d_res_atom_off, p.d_seq, p.d_fa,
+                       p.fs.d_look, p.fs.d_status, p.R, p.A, p.bb, p.fs.fa_stage_atoms);
     return hipGetLastError();
 }
 
 template <int K, bool STG>
 hipError_t fa_fwd_ks(const a2c_plan &p, const float *ang, float *xyz, hipStream_t s)
 {
-    const bool small = p.fs.W * kWave <= kLbSmall;
-    if (p.fs.multi_chunk)
-        return small ? fa_fwd_kml<K, true, kLbSmall, STG>(p, ang, xyz, s)
-                     : fa_fwd_kml<K, true, kLbLarge, STG>(p, ang, xyz, s);
-    return small ? fa_fwd_kml<K, false, kLbSmall, STG>(p, ang, xyz, s)
-                 : fa_fwd_kml<K, false, kLbLarge, STG>(p, ang, xyz, s);
+    const int threads = p.fs.W * kWave;
+    if (threads <= 256) return fa_fwd_kl<K, 256, STG>(p, ang, xyz, s);
+    if (threads <= kLbSmall) return fa_fwd_kl<K, kLbSmall, STG>(p, ang, xyz, s);
+    return fa_fwd_kl<K, kLbLarge, STG>(p, ang, xyz, s);
 }
 
 template <int K>
 hipError_t fa_fwd_k(const a2c_plan &p, const float *ang, float *xyz, hipStream_t s)
 {
+    if (!p.fs.d_look) return hipErrorInvalidValue;
     return p.fs.fa_unstaged ? fa_fwd_ks<K, false>(p, ang, xyz, s) : fa_fwd_ks<K, true>(p, ang, xyz, s);
 }
 
@@ -1061,7 +1058,7 @@ static void allow_lds(F kernel)
 template <int K, bool MULTI, int LB>
 static void allow_lds_km()
 {
-    allow_lds(fa_forward_kernel<K, MULTI, LB>);
+    allow_lds(fa_forward_flat_kernel<K, LB>);
     allow_lds(fa_backward_kernel<K, false, MULTI, LB>);
     allow_lds(fa_backward_kernel<K, true, MULTI, LB>);
     allow_lds(fa_backward_kernel<K, true, MULTI, LB, kGradMse, true>);
@@ -1071,6 +1068,8 @@ void fa_allow_large_lds()
 {
     static bool done = false;
     if (done) return;
+    allow_lds(fa_forward_flat_kernel<1, 256>);
+    allow_lds(fa_forward_flat_kernel<2, 256>);
     allow_lds_km<1, false, kLbSmall>();
     allow_lds_km<1, true, kLbSmall>();
     allow_lds_km<2, false, kLbSmall>();

@@ -767,6 +767,61 @@ __device__ __forceinline__ Aff lb_carry_in(const uint64_t *status, int64_t first
 }
 
 
+// The frame preceding each lane in window t of a launch over fixed windows:
+// segmented scan of the lane aggregates m inside each wave, then of the wave
+// totals by wave 0, which publishes the window's aggregate and composes those
+// of the earlier windows its first chain spans (lb_carry_in).  heads: the
+// wave's lanes holding a chain head; prev, first (read by wave 0 early): the
+// window's own first tagged word and the first window of its look-back.
+// Every thread of the block calls it; inactive waves get the identity.
+__device__ __forceinline__ Aff block_prefix_windows(Aff m, uint64_t heads, int nact, bool active,
+                                                    FwdShared &sh, float (&carry_sh)[12],
+                                                    uint64_t *__restrict__ status, int64_t t,
+                                                    int64_t first, uint64_t prev)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (active) {
+        aff_wave_scan<false>(m, heads, kWave, lane);
+        if (lane == kWave - 1) {
+            aff_store(sh.tot[wave], m);
+            sh.tot_flag[wave] = heads != 0ull ? 1 : 0;
+        }
+    }
+    __syncthreads();
+    if (wave == 0) {
+        Aff tw = aff_identity();
+        bool tf = false;
+        if (lane < nact) {
+            tw = aff_load(sh.tot[lane]);
+            tf = sh.tot_flag[lane] != 0;
+        }
+        const uint64_t th = __builtin_amdgcn_ballot_w64(tf);
+        aff_wave_scan<true>(tw, th, nact, lane);
+        if (lane < nact) {
+            aff_store(sh.pre[lane], tw);
+            sh.pre_flag[lane] = (th & lanes_upto(lane)) != 0ull ? 1 : 0;
+        }
+        wave_lds_sync();
+        // publish this window's aggregate, then read the earlier windows' ones
+        const uint32_t tag = (uint32_t)(__builtin_amdgcn_readfirstlane((uint32_t)(prev >> 32))) + 1u;
+        if (lane < kLbWords) lb_store(status + t * kLbWords + lane, tag, sh.pre[nact - 1][lane]);
+        const int64_t f = (int64_t)__builtin_amdgcn_readfirstlane((int)first);
+        const Aff carry = lb_carry_in(status, f, t, tag);
+        if (lane == 0) aff_store(carry_sh, carry);
+    }
+    __syncthreads();
+    if (!active) return aff_identity();
+    // frame entering the wave, then entering each lane
+    const Aff carry = aff_load(carry_sh);
+    Aff cw = carry;
+    if (wave > 0) cw = aff_seg_after(carry, aff_load(sh.pre[wave - 1]), sh.pre_flag[wave - 1] != 0);
+    Aff e = aff_dpp_z<kDppWaveShr1>(m);
+    if (lane == 0) e = aff_identity();
+    const bool fe = (heads & lanes_below(lane)) != 0ull;
+    return fe ? e : aff_compose(cw, e);
+}
+
 // Sum of v over the 64 lanes of a wave in a fixed order (deterministic);
 // wave-uniform result.
 __device__ __forceinline__ float wave_sum_fixed(float v)

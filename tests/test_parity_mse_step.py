@@ -2,14 +2,10 @@
 L = sum |r - t|^2 and its angle gradient in one kernel, against
 
 * the FP64 oracle: forward, g = 2 (r - t) in float64, O(N) adjoint;
-* the unfused GPU path on the same schedule: a2c_forward, g = 2 (r - t) in
-  float32 by torch, a2c_backward recomputing the frames.  The fused kernel
-  performs the same float32 operations; the compiler may contract a
-  multiply-add differently in the two kernels, which changes a last bit, and
-  the gradient's moment sums u . (m - o x g) cancel large terms, so the two
-  agree to 1e-5 A and 1e-4 (normwise per chain), not bit for bit, where they
-  share tiles (full-atom); the backbone forward runs on fixed windows, so
-  there both are held to the oracle bounds only.
+* the unfused GPU path: a2c_forward, g = 2 (r - t) in float32 by torch,
+  a2c_backward recomputing the frames.  The forward runs on fixed windows of
+  the packed batch and the fused step on tiles of whole chains, so their
+  scans associate differently: both are held to the oracle bounds.
 
 Loss tolerance: the coordinates carry float32 rounding of up to ~1e-3 A
 against residuals |r - t| of order 1-10 A, and the sum runs in float32 over
@@ -58,7 +54,7 @@ def _oracle(model, off, seq, ang, t):
     return r, float(np.sum((r - t.astype(np.float64)) ** 2)), ga
 
 
-def _run(plan, model, off, seq, ang, t, label, coord_tol=COORD_TOL_A, same_schedule=True):
+def _run(plan, model, off, seq, ang, t, label, coord_tol=COORD_TOL_A):
     import torch
     a, td = to_dev(ang), to_dev(t)
     coords = torch.empty((3, plan.n_atoms), dtype=torch.float32, device=a.device)
@@ -74,13 +70,12 @@ def _run(plan, model, off, seq, ang, t, label, coord_tol=COORD_TOL_A, same_sched
     lerr = abs(float(loss) - L) / max(L, 1e-30)
     print(f"{label}: max|dr|={cerr:.3e} A grad_rel={gerr:.3e} loss_rel={lerr:.3e}", flush=True)
     assert cerr <= coord_tol and gerr <= GRAD_TOL_REL and lerr <= LOSS_RTOL
-    # The same association (bitwise-close results) needs the same tiles: the
-    # full-atom forward and fused step share the schedule's tiles, while the
-    # backbone forward always runs on fixed windows and the fused step on
-    # tiles of whole chains, so there only the oracle bounds above apply.
-    if same_schedule and model == "fullatom":
-        assert float(np.max(np.abs(xyz - c2.cpu().numpy()))) <= 1e-5
-        assert grad_rel_err(gr, g2.cpu().numpy().astype(np.float64), off) <= 1e-4
+    # The forward runs on fixed windows and the fused step on tiles of whole
+    # chains, so the two scans associate differently even at one schedule:
+    # the unfused path is held to the same oracle bounds.
+    c2n, g2n = c2.cpu().numpy(), g2.cpu().numpy()
+    assert float(np.max(np.abs(c2n - r))) <= coord_tol
+    assert grad_rel_err(g2n, ga, off) <= GRAD_TOL_REL
 
 
 @pytest.mark.parametrize("K,W", [(1, 16), (2, 8), (4, 4), (1, 1), (2, 3), (4, 16)])
@@ -115,7 +110,7 @@ def test_separate_adjoint_schedule(model):
     plan.set_schedule(1, 4)
     plan.set_adjoint_schedule(2, 8)
     assert plan.adjoint_schedule["n_tiles"] != plan.schedule["n_tiles"]
-    _run(plan, model, off, seq, ang, t, f"{model} fwd (1,4) adj (2,8)", same_schedule=False)
+    _run(plan, model, off, seq, ang, t, f"{model} fwd (1,4) adj (2,8)")
 
 
 def test_training_workload_full_size():
