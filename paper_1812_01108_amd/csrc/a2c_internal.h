@@ -69,9 +69,10 @@ struct FATable {
 // layouts built for them: tiles (chains of at most one chunk of 64 W K
 // residues packed whole into tiles of at most one chunk; a longer chain
 // alone) and/or fixed windows [t C, t C + C) of one chunk C with a look-back
-// table (backbone forward: windows only; backbone adjoint: both, windows for
-// the adjoint from coordinates).  n_tiles counts the layout the schedule
-// reports: windows for the backbone forward, tiles otherwise.
+// table (forwards and the full-atom adjoint: windows only; backbone adjoint:
+// both, windows for the adjoint from coordinates, tiles for the recomputing
+// adjoint and the fused step).  n_tiles counts the layout the schedule
+// reports: windows where there are no tiles.
 struct Sched {
     int32_t K = 4, W = 4, n_tiles = 0;
     int32_t n_win = 0;                   // fixed windows (0: none)
@@ -79,6 +80,12 @@ struct Sched {
                                          // aggregate window t composes; adjoint, the
                                          // last window whose wrench it adds (t: none)
     uint64_t *d_status = nullptr;        // n_win x kLbWords tagged words
+    // full-atom adjoint: the spine pass that finds the frame entering each
+    // window looks back like a forward (its own table and words) and stores
+    // the frames for the adjoint
+    int32_t *d_look_fwd = nullptr;       // n_win, first window to compose
+    uint64_t *d_status_fwd = nullptr;    // n_win x kLbWords tagged words
+    float *d_carry = nullptr;            // n_win x 12 frames entering the windows
     int32_t fa_stage_atoms = 0;          // per-wave staging (floats per plane)
     bool fa_unstaged = false;            // stage too large for the LDS: direct I/O
     bool multi_chunk = false;            // some tile spans several chunks

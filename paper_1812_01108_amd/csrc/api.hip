@@ -46,11 +46,17 @@ void free_sched(Sched &S)
     (void)hipFree(S.d_loss_count);
     (void)hipFree(S.d_look);
     (void)hipFree(S.d_status);
+    (void)hipFree(S.d_look_fwd);
+    (void)hipFree(S.d_status_fwd);
+    (void)hipFree(S.d_carry);
     S.d_tile_res = nullptr;
     S.d_loss_part = nullptr;
     S.d_loss_count = nullptr;
     S.d_look = nullptr;
     S.d_status = nullptr;
+    S.d_look_fwd = nullptr;
+    S.d_status_fwd = nullptr;
+    S.d_carry = nullptr;
 }
 
 // Fixed windows of `cap` residues.  Forward (look_back): for each window t
@@ -59,7 +65,8 @@ void free_sched(Sched &S)
 // when a chain starts there).  Adjoint: the last window whose wrench it adds,
 // i.e. the window holding the end of the chain of its last residue (t itself
 // when a chain ends there).  The tagged words start at tag 0.
-a2c_status build_windows(const a2c_plan *p, int64_t cap, bool look_back, Sched &S, hipStream_t s)
+a2c_status build_windows(const a2c_plan *p, int64_t cap, bool look_back, int32_t *&d_look,
+                         uint64_t *&d_status, int32_t &n_win, hipStream_t s)
 {
     const int64_t n = (p->R + cap - 1) / cap;
     std::vector<int32_t> look((size_t)n);
@@ -69,12 +76,12 @@ a2c_status build_windows(const a2c_plan *p, int64_t cap, bool look_back, Sched &
         while (p->res_off[c + 1] <= r) ++c;
         look[(size_t)t] = (int32_t)(look_back ? p->res_off[c] / cap : (p->res_off[c + 1] - 1) / cap);
     }
-    S.n_win = (int32_t)n;
-    a2c_status st = upload((void **)&S.d_look, look.data(), look.size() * sizeof(int32_t), s);
+    n_win = (int32_t)n;
+    a2c_status st = upload((void **)&d_look, look.data(), look.size() * sizeof(int32_t), s);
     if (st != A2C_OK) return st;
     const size_t words = (size_t)std::max<int64_t>(1, n) * kLbWords * sizeof(uint64_t);
-    hipError_t e = hipMalloc((void **)&S.d_status, words);
-    if (e == hipSuccess) e = hipMemsetAsync(S.d_status, 0, words, s);
+    hipError_t e = hipMalloc((void **)&d_status, words);
+    if (e == hipSuccess) e = hipMemsetAsync(d_status, 0, words, s);
     if (e != hipSuccess) return hip_fail(e, "look-back words");
     return A2C_OK;
 }
@@ -115,8 +122,8 @@ enum SchedRole { kRoleForward, kRoleAdjoint };
 a2c_status build_sched(const a2c_plan *p, int32_t K, int32_t W, Sched &out, hipStream_t s,
                        SchedRole role)
 {
-    const bool windows = p->model == A2C_BACKBONE || role == kRoleForward;
-    const bool flat = role == kRoleForward;  // windows only
+    const bool flat = role == kRoleForward || p->model == A2C_FULLATOM;  // windows only
+    const bool windows = flat || p->model == A2C_BACKBONE;
     const int64_t cap = (int64_t)kWave * W * K;  // residues per chunk
     if (p->max_len > cap * kMaxChunks)
         return fail(A2C_ERR_UNSUPPORTED, "a chain of " + std::to_string(p->max_len) +
@@ -128,7 +135,8 @@ a2c_status build_sched(const a2c_plan *p, int32_t K, int32_t W, Sched &out, hipS
         S.K = K;
         S.W = W;
         if (p->model == A2C_FULLATOM) {
-            // per-wave LDS stage of three planes: the most atoms of one
+            // per-wave LDS stage of three planes (the adjoint from
+            // coordinates stages six where they fit): the most atoms of one
             // wave's run of 64 K residues
             int64_t most = 1;
             for (int64_t rb = 0; rb < p->R; rb += (int64_t)kWave * K) {
@@ -140,8 +148,21 @@ a2c_status build_sched(const a2c_plan *p, int32_t K, int32_t W, Sched &out, hipS
             else
                 S.fa_stage_atoms = (int32_t)most;
         }
-        a2c_status st = build_windows(p, cap, true, S, s);
+        const bool fwd = role == kRoleForward;
+        a2c_status st = build_windows(p, cap, fwd, S.d_look, S.d_status, S.n_win, s);
         S.n_tiles = S.n_win;
+        if (st == A2C_OK && !fwd) {
+            // the full-atom adjoint: the frame pass's windows and frames
+            // (the fused step's loss shares travel in the adjoint's own
+            // tagged words)
+            int32_t n2 = 0;
+            st = build_windows(p, cap, true, S.d_look_fwd, S.d_status_fwd, n2, s);
+            if (st == A2C_OK) {
+                const hipError_t e = hipMalloc((void **)&S.d_carry,
+                                               std::max<size_t>(1, S.n_win) * 12 * sizeof(float));
+                if (e != hipSuccess) st = hip_fail(e, "adjoint window frames");
+            }
+        }
         if (st == A2C_OK) {
             const hipError_t e = hipStreamSynchronize(s);
             if (e != hipSuccess) st = hip_fail(e, "hipStreamSynchronize");
@@ -203,7 +224,7 @@ a2c_status build_sched(const a2c_plan *p, int32_t K, int32_t W, Sched &out, hipS
         pairs[2 * t + 1] = tiles[order[t] + 1];
     }
     a2c_status st = upload((void **)&S.d_tile_res, pairs.data(), pairs.size() * sizeof(int32_t), s);
-    if (st == A2C_OK && windows) st = build_windows(p, cap, false, S, s);
+    if (st == A2C_OK && windows) st = build_windows(p, cap, false, S.d_look, S.d_status, S.n_win, s);
     // the fused step's per-tile loss shares and its count of finished tiles
     // (zero: the last tile of every launch sets it back to zero)
     if (st == A2C_OK) {
@@ -230,13 +251,17 @@ a2c_status build_sched(const a2c_plan *p, int32_t K, int32_t W, Sched &out, hipS
 void retire_sched(a2c_plan *p, Sched &S)
 {
     for (void *q : {(void *)S.d_tile_res, (void *)S.d_loss_part, (void *)S.d_loss_count,
-                    (void *)S.d_look, (void *)S.d_status})
+                    (void *)S.d_look, (void *)S.d_status, (void *)S.d_look_fwd,
+                    (void *)S.d_status_fwd, (void *)S.d_carry})
         if (q) p->retired.push_back(q);
     S.d_tile_res = nullptr;
     S.d_loss_part = nullptr;
     S.d_loss_count = nullptr;
     S.d_look = nullptr;
     S.d_status = nullptr;
+    S.d_look_fwd = nullptr;
+    S.d_status_fwd = nullptr;
+    S.d_carry = nullptr;
 }
 
 // Replace one of the plan's schedules; on failure it stays as it was.  The

@@ -557,51 +557,9 @@ __global__ __launch_bounds__(LB) void bb_backward_coords_flat_kernel(
             }
         }
     }
-    // segmented suffix scan: inside each wave, then the wave totals by wave 0
     const uint64_t ends = __builtin_amdgcn_ballot_w64(f);
-    if (active) {
-        wrench_wave_rscan<false>(agg, ends, kWave, lane);
-        if (lane == 0) {
-            wrench_store(sh.tot[wave], agg);
-            sh.tot_flag[wave] = ends != 0ull ? 1 : 0;
-        }
-    }
-    __syncthreads();
-    if (wave == 0) {
-        Wrench tw = wrench_zero();
-        bool tf = false;
-        if (lane < nact) {
-            tw = wrench_load(sh.tot[lane]);
-            tf = sh.tot_flag[lane] != 0;
-        }
-        const uint64_t th = __builtin_amdgcn_ballot_w64(tf);
-        wrench_wave_rscan<true>(tw, th, nact, lane);
-        if (lane < nact) {
-            wrench_store(sh.suf[lane], tw);
-            sh.suf_flag[lane] = (th & (~0ull << lane)) != 0ull ? 1 : 0;
-        }
-        wave_lds_sync();
-        // publish this window's wrench, then read the later windows' ones
-        const uint32_t tag = (uint32_t)(__builtin_amdgcn_readfirstlane((uint32_t)(prev >> 32))) + 1u;
-        if (lane < kLbWrenchWords) lb_store(status + t * kLbWords + lane, tag, sh.suf[0][lane]);
-        const int64_t l = (int64_t)__builtin_amdgcn_readfirstlane((int)last);
-        const Wrench carry = lb_carry_after(status, t, l, tag);
-        if (lane == 0) wrench_store(carry_sh, carry);
-    }
-    __syncthreads();
+    Wrench S = block_suffix_windows(agg, ends, nact, active, sh, carry_sh, status, t, last, prev);
     if (!active) return;
-    // everything after the wave up to the end of its last chain
-    const Wrench carry = wrench_load(carry_sh);
-    Wrench cw = carry;
-    if (wave + 1 < nact) {
-        cw = wrench_load(sh.suf[wave + 1]);
-        if (sh.suf_flag[wave + 1] == 0) wrench_add(cw, carry);
-    }
-    // everything after lane l inside the wave: the inclusive value of lane
-    // l + 1, complete when a chain ends in lanes after l
-    Wrench S = wrench_dpp_z<kDppWaveShl1>(agg);
-    if (lane == kWave - 1) S = wrench_zero();
-    if (!(lane < kWave - 1 && (ends >> (lane + 1)) != 0ull)) wrench_add(S, cw);
     float gr[3][K];
 #pragma unroll
     for (int j = K - 1; j >= 0; --j) {

@@ -703,221 +703,255 @@ __device__ __forceinline__ void fa_store_grads(float *__restrict__ gang, int64_t
     S_out = S;
 }
 
-// Backward: the side chains' subtree sums give the chi gradients, the spine
-// groups feed a reverse scan over residues, chunks last to first.
-// RECOMPUTE: frames from the angles (tiles of several chunks first record
-// each chunk's forward carry); otherwise positions and axes from the
+// Frames entering the windows of the full-atom adjoint.  The recomputing
+// adjoints take their windows last to first (for the wrench look-back), so
+// they cannot look back for frames themselves: this spine-only pass of the
+// forward over the same windows, first to last with window look-back, stores
+// the frame entering each window (12 floats) for them.
+template <int K, int LB>
+__global__ __launch_bounds__(LB) void fa_spine_carry_kernel(
+    const float *__restrict__ ang, const uint32_t *__restrict__ head_bits,
+    const int32_t *__restrict__ look_first, uint64_t *__restrict__ status,
+    float *__restrict__ carry_out, int64_t R, BBParams P)
+{
+    __shared__ FwdShared sh;
+    __shared__ float carry_sh[12];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nw = blockDim.x >> 6;
+    const int64_t t = blockIdx.x;
+    FAChunk k;
+    k.cs = t * kWave * K * nw;
+    k.ce = min(k.cs + (int64_t)kWave * K * nw, R);
+    k.nact = (int)((k.ce - k.cs + kWave * K - 1) / (kWave * K));
+    const bool active = wave < k.nact;
+    const int64_t rs = k.cs + (int64_t)threadIdx.x * K;
+    const int cnt = (int)max((int64_t)0, min((int64_t)K, k.ce - rs));
+    const uint32_t hm = lane_head_mask<K>(head_bits, rs, k.ce, cnt);
+    uint64_t prev = 0;
+    int64_t first = t;
+    if (wave == 0) {
+        prev = lb_load(status + t * kLbWords);
+        first = look_first[t];
+    }
+    ResidueIn in[K];
+    int first_head = K;
+    Aff m = aff_identity();
+    if (active) m = fa_lane_aggregate<K>(load_spine_angles<K>(ang, R, rs, cnt), cnt, hm, P, in,
+                                         first_head);
+    const uint64_t heads = __builtin_amdgcn_ballot_w64(first_head < K);
+    (void)block_prefix_windows(m, heads, k.nact, active, sh, carry_sh, status, t, first, prev);
+    if (threadIdx.x < 12) carry_out[t * 12 + threadIdx.x] = carry_sh[threadIdx.x];
+}
+
+// Backward over fixed windows of the packed batch, last window first: the
+// side chains' subtree sums give the chi gradients, the spine groups feed a
+// reverse scan over residues (window look-back for the wrench of later
+// windows), and u . (S_m - o x S_g) gives phi, psi, omega.
+// RECOMPUTE: frames from the angles, the frame entering the window from
+// carry_in (fa_spine_carry_kernel); otherwise positions and axes from the
 // forward's coordinates.
 // GM = kGradMse (with RECOMPUTE): g points at a target t and the upstream
 // gradient is 2 (r - t), formed from the recomputed positions (the fused
 // training step); xyz_out (may be NULL) receives the positions, loss_out
-// (may be NULL) the batch's sum of |r - t|^2 (from the tiles' shares in
-// loss_part, counted in loss_count).
-template <int K, bool RECOMPUTE, bool MULTI, int LB, int GM = kGradLoad, bool STG = true>
-__global__ __launch_bounds__(LB) void fa_backward_kernel(
+// (may be NULL) the batch's sum of |r - t|^2 (lb_loss_commit).
+// STG: atoms go through the per-wave LDS stage; otherwise global memory is
+// addressed directly (schedules whose stage does not fit the LDS).
+template <int K, bool RECOMPUTE, int LB, int GM = kGradLoad, bool STG = true>
+__global__ __launch_bounds__(LB) void fa_backward_flat_kernel(
     const float *__restrict__ ang, const float *__restrict__ xyz, const float *__restrict__ g,
     float *__restrict__ gang, float *__restrict__ xyz_out, float *__restrict__ loss_out,
-    float *__restrict__ loss_part, uint32_t *__restrict__ loss_count,
-    const int32_t *__restrict__ tile_res,
     const uint32_t *__restrict__ head_bits, const int32_t *__restrict__ res_aoff,
-    const uint8_t *__restrict__ seq, const FATable *__restrict__ gtab, int64_t R, int64_t A,
-    BBParams P0, int stage_atoms)
+    const uint8_t *__restrict__ seq, const FATable *__restrict__ gtab,
+    const float *__restrict__ carry_in, const int32_t *__restrict__ look_last,
+    uint64_t *__restrict__ status, int64_t R, int64_t A, BBParams P, int stage_atoms)
 {
     static_assert(GM == kGradLoad || RECOMPUTE, "the fused step recomputes the frames");
     extern __shared__ float stage_mem[];
     __shared__ __align__(16) FATable tab;
-    __shared__ FwdShared shf[2];
-    __shared__ BwdShared shb[2];
-    __shared__ float fwd_carry[RECOMPUTE ? kMaxChunks : 1][12];
+    __shared__ FwdShared shf;
+    __shared__ BwdShared shb;
+    __shared__ float rcarry_sh[6];
     __shared__ float loss_tot[GM == kGradMse ? kMaxWaves : 1];
     float loss = 0.f;
-    const int64_t ts = tile_res[2 * blockIdx.x], te = tile_res[2 * blockIdx.x + 1];
-    load_table(tab, gtab);
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nw = blockDim.x >> 6;
+    const int64_t t = (int64_t)gridDim.x - 1 - blockIdx.x;  // last window first
+    FAChunk k;
+    k.cs = t * kWave * K * nw;
+    k.ce = min(k.cs + (int64_t)kWave * K * nw, R);
+    k.nact = (int)((k.ce - k.cs + kWave * K - 1) / (kWave * K));
+    const LaneRun<K> L = lane_run<K>(k, head_bits, res_aoff);
+    uint64_t prev = 0;
+    int64_t last = t;
+    if (wave == 0) {
+        prev = lb_load(status + t * kLbWords);
+        last = look_last[t];
+    }
+    // the window's inputs ahead of the table copy (which ends in a barrier)
+    SpineAngles<K> a{};
+    if (RECOMPUTE && L.active) a = load_spine_angles<K>(ang, R, L.rs, L.cnt);
+    const LaneRes<K, RECOMPUTE> lr = load_lane_res<K, RECOMPUTE>(L, seq, res_aoff, ang, R);
+    Aff fcarry = aff_identity();
+    if (RECOMPUTE) fcarry = aff_load(carry_in + t * 12);
+    load_table(tab, gtab);
     const int planes = RECOMPUTE ? 3 : 6;
     const Stage lds{stage_mem + (size_t)wave * planes * stage_atoms, stage_atoms};
-    // MULTI = false: every tile is one chunk (straight-line code)
-    const int nch = MULTI ? fa_chunks<K>(ts, te) : 1;
-    if (RECOMPUTE && nch > 1) {
-        Aff carry = aff_identity();
-        for (int c = 0; c < nch; ++c) {
-            const BBParams P = MULTI ? opaque_params(P0) : P0;
-            if (threadIdx.x == 0) aff_store(fwd_carry[c], carry);
-            const FAChunk k = fa_chunk<K>(ts, te, c);
-            const LaneRun<K> L = lane_run<K>(k, head_bits, res_aoff);
-            ResidueIn in[K];
-            int first_head = K;
-            Aff m = aff_identity();
-            if (L.active) m = fa_lane_aggregate<K>(ang, R, L.rs, L.cnt, L.hm, P, in, first_head);
-            (void)block_exclusive_prefix<MULTI>(m, first_head < K, k.nact, shf[c & 1], carry);
-        }
-    }
-    Wrench rcarry = wrench_zero();
-    for (int c = nch - 1; c >= 0; --c) {
-        const BBParams P = MULTI ? opaque_params(P0) : P0;
-        const FAChunk k = fa_chunk<K>(ts, te, c);
-        const LaneRun<K> L = lane_run<K>(k, head_bits, res_aoff);
-        Aff X = aff_identity();
-        ResidueIn in[K];
-        int first_head = K;
+    Aff X = aff_identity();
+    ResidueIn in[K];
+    int first_head = K;
+    if (RECOMPUTE) {
         Aff m = aff_identity();
-        if (RECOMPUTE && L.active)
-            m = fa_lane_aggregate<K>(ang, R, L.rs, L.cnt, L.hm, P, in, first_head);
-        // issued after the spine angles (whose wait would otherwise cover them)
-        const LaneRes<K, RECOMPUTE> lr = load_lane_res<K, RECOMPUTE>(L, seq, res_aoff, ang, R);
-        if (RECOMPUTE) {
-            Aff fcarry = aff_identity();
-            if (nch > 1) fcarry = aff_load(fwd_carry[c]);
-            // buffers alternate with the pass above: its last chunk used shf[(nch-1) & 1]
-            X = block_exclusive_prefix<MULTI>(m, first_head < K, k.nact, shf[(c + 1) & 1], fcarry);
+        if (L.active) m = fa_lane_aggregate<K>(a, L.cnt, L.hm, P, in, first_head);
+        X = block_exclusive_prefix<true>(m, first_head < K, k.nact, shf, fcarry);
+    }
+    // the C atom before the lane's first residue (coordinate mode): in
+    // the staged run for lanes > 0, from global memory for lane 0
+    float pcx = 0.f, pcy = 0.f, pcz = 0.f;
+    if (!RECOMPUTE && lane == 0 && L.cnt > 0 && !(L.hm & 1u)) {
+        const int64_t ac = res_aoff[L.rs - 1] + 2;
+        pcx = xyz[ac]; pcy = xyz[A + ac]; pcz = xyz[2 * A + ac];
+    }
+    SpineGrad sp[K];
+    Wrench agg = wrench_zero();
+    bool f_end = false;
+    // upstream gradient (or target) sg, coordinates sx, positions out sout
+    const Stage sg = STG ? lds : Stage{const_cast<float *>(g) + L.A0, A};
+    const Stage sx = STG ? Stage{lds.st + 3 * lds.ns, lds.ns}
+                         : Stage{const_cast<float *>(xyz) + L.A0, A};
+    const Stage sout = STG ? sg : Stage{xyz_out + L.A0, A};
+    const bool write_so = STG || (GM == kGradMse && xyz_out != nullptr);
+    if (L.active) {
+        if (STG) {
+            run_to_lds(sg, 0, g, A, L.A0, L.natoms);
+            if (!RECOMPUTE) run_to_lds(sg, 3, xyz, A, L.A0, L.natoms);
         }
-        // the C atom before the lane's first residue (coordinate mode): in
-        // the staged run for lanes > 0, from global memory for lane 0
-        float pcx = 0.f, pcy = 0.f, pcz = 0.f;
-        if (!RECOMPUTE && lane == 0 && L.cnt > 0 && !(L.hm & 1u)) {
-            const int64_t ac = res_aoff[L.rs - 1] + 2;
-            pcx = xyz[ac]; pcy = xyz[A + ac]; pcz = xyz[2 * A + ac];
+        wave_lds_sync();
+        // first atom of the residue before the lane: the previous lane's last
+        const int prev_aoff = __builtin_amdgcn_mov_dpp(lr.aoff[K - 1], kDppWaveShr1, 0xf, 0xf, true);
+        if (!RECOMPUTE && lane > 0 && L.cnt > 0 && !(L.hm & 1u)) {
+            const int e = prev_aoff + 2 - (int)L.A0;
+            pcx = sx.st[e]; pcy = sx.st[sx.ns + e]; pcz = sx.st[2 * sx.ns + e];
         }
-        SpineGrad sp[K];
-        Wrench agg = wrench_zero();
-        bool f_end = false;
-        // upstream gradient (or target) sg, coordinates sx, positions out sout
-        const Stage sg = STG ? lds : Stage{const_cast<float *>(g) + L.A0, A};
-        const Stage sx = STG ? Stage{lds.st + 3 * lds.ns, lds.ns}
-                             : Stage{const_cast<float *>(xyz) + L.A0, A};
-        const Stage sout = STG ? sg : Stage{xyz_out + L.A0, A};
-        const bool write_so = STG || (GM == kGradMse && xyz_out != nullptr);
-        if (L.active) {
-            if (STG) {
-                run_to_lds(sg, 0, g, A, L.A0, L.natoms);
-                if (!RECOMPUTE) run_to_lds(sg, 3, xyz, A, L.A0, L.natoms);
-            }
-            wave_lds_sync();
-            // first atom of the residue before the lane: the previous lane's last
-            const int prev_aoff = __builtin_amdgcn_mov_dpp(lr.aoff[K - 1], kDppWaveShr1, 0xf, 0xf, true);
-            if (!RECOMPUTE && lane > 0 && L.cnt > 0 && !(L.hm & 1u)) {
-                const int e = prev_aoff + 2 - (int)L.A0;
-                pcx = sx.st[e]; pcy = sx.st[sx.ns + e]; pcz = sx.st[2 * sx.ns + e];
-            }
-            Aff cur = X;
+        Aff cur = X;
 #pragma unroll
-            for (int j = 0; j < K; ++j) {
-                if (j < L.cnt) {
-                    const FAType &ft = tab.t[lr.type[j]];
-                    const int aloc = lr.aoff[j] - (int)L.A0;
-                    const bool head = (L.hm >> j) & 1u;
-                    // each group's wrench is folded into the axes that move it
-                    // (N: every group; CA: its own, the side chain, C's; C: its
-                    // own; side frame f: frames f and after) and into W
-                    SpineGrad g;
-                    NodeGrad sc[A2C_MAX_SIDE_FRAMES];
-                    Wrench w;
-                    if (RECOMPUTE) {
-                        if (head) cur = aff_identity();
-                        aff_apply_transform(cur, P.ct[0], P.st[0], P.d[0], in[j].co, in[j].so);
-                        g.n = node_of_frame(cur);
-                        w = wrench_zero();
-                        if (GM == kGradMse) frame_wrench_mse(tab, ft, 0, cur, sg, sout, write_so, aloc, w, loss);
-                        else frame_wrench(tab, ft, 0, cur, sg, aloc, w);
-                        node_fold(g.n, w);
-                        g.W = w;
-                        aff_apply_transform(cur, P.ct[1], P.st[1], P.d[1], in[j].cp, in[j].sp);
-                        g.ca = node_of_frame(cur);
-                        w = wrench_zero();
-                        if (GM == kGradMse) frame_wrench_mse(tab, ft, 1, cur, sg, sout, write_so, aloc, w, loss);
-                        else frame_wrench(tab, ft, 1, cur, sg, aloc, w);
-                        node_fold(g.n, w);
-                        node_fold(g.ca, w);
-                        wrench_add(g.W, w);
-                        Aff sf = cur;
-                        aff_rot_x(sf, ft.pre_c, ft.pre_s);
-#pragma unroll
-                        for (int f = 0; f < A2C_MAX_SIDE_FRAMES; ++f) {
-                            if (f < tab.max_side && f < ft.n_side) {
-                                side_step(sf, ft, f, lr.chi[j][f]);
-                                sc[f] = node_of_frame(sf);
-                                w = wrench_zero();
-                                if (GM == kGradMse) frame_wrench_mse(tab, ft, 3 + f, sf, sg, sout, write_so, aloc, w, loss);
-                                else frame_wrench(tab, ft, 3 + f, sf, sg, aloc, w);
-#pragma unroll
-                                for (int q = 0; q <= f; ++q) node_fold(sc[q], w);
-                                node_fold(g.n, w);
-                                node_fold(g.ca, w);
-                                wrench_add(g.W, w);
-                            }
-                        }
-                        aff_apply_transform(cur, P.ct[2], P.st[2], P.d[2], in[j].cs, in[j].ss);
-                        g.cc = node_of_frame(cur);
-                        w = wrench_zero();
-                        if (GM == kGradMse) frame_wrench_mse(tab, ft, 2, cur, sg, sout, write_so, aloc, w, loss);
-                        else frame_wrench(tab, ft, 2, cur, sg, aloc, w);
-                    } else {
-                        const float *px = sx.st, *py = sx.st + sx.ns, *pz = sx.st + 2 * sx.ns;
-                        const float nx = px[aloc], ny = py[aloc], nz = pz[aloc];
-                        const float cax = px[aloc + 1], cay = py[aloc + 1], caz = pz[aloc + 1];
-                        const float cx = px[aloc + 2], cy = py[aloc + 2], cz = pz[aloc + 2];
-                        if (head) { pcx = 0.f; pcy = 0.f; pcz = 0.f; }
-                        g.n = node_at(nx, ny, nz, (nx - pcx) * P.inv_d[0], (ny - pcy) * P.inv_d[0],
-                                      (nz - pcz) * P.inv_d[0]);
-                        g.ca = node_at(cax, cay, caz, (cax - nx) * P.inv_d[1],
-                                       (cay - ny) * P.inv_d[1], (caz - nz) * P.inv_d[1]);
-                        g.cc = node_at(cx, cy, cz, (cx - cax) * P.inv_d[2], (cy - cay) * P.inv_d[2],
-                                       (cz - caz) * P.inv_d[2]);
-                        w = wrench_zero();
-                        frame_wrench_xyz(tab, ft, 0, sg, sx, aloc, w);
-                        node_fold(g.n, w);
-                        g.W = w;
-                        w = wrench_zero();
-                        frame_wrench_xyz(tab, ft, 1, sg, sx, aloc, w);
-                        node_fold(g.n, w);
-                        node_fold(g.ca, w);
-                        wrench_add(g.W, w);
-                        float ppx = cax, ppy = cay, ppz = caz;
-#pragma unroll
-                        for (int f = 0; f < A2C_MAX_SIDE_FRAMES; ++f) {
-                            if (f < tab.max_side && f < ft.n_side) {
-                                const int eo = aloc + ft.origin_slot[3 + f];
-                                const float ox = px[eo], oy = py[eo], oz = pz[eo];
-                                sc[f] = node_at(ox, oy, oz, (ox - ppx) * ft.inv_d[f],
-                                                (oy - ppy) * ft.inv_d[f], (oz - ppz) * ft.inv_d[f]);
-                                ppx = ox; ppy = oy; ppz = oz;
-                                w = wrench_zero();
-                                frame_wrench_xyz(tab, ft, 3 + f, sg, sx, aloc, w);
-#pragma unroll
-                                for (int q = 0; q <= f; ++q) node_fold(sc[q], w);
-                                node_fold(g.n, w);
-                                node_fold(g.ca, w);
-                                wrench_add(g.W, w);
-                            }
-                        }
-                        w = wrench_zero();
-                        frame_wrench_xyz(tab, ft, 2, sg, sx, aloc, w);
-                        pcx = cx; pcy = cy; pcz = cz;
-                    }
-                    // the C group (with O)
+        for (int j = 0; j < K; ++j) {
+            if (j < L.cnt) {
+                const FAType &ft = tab.t[lr.type[j]];
+                const int aloc = lr.aoff[j] - (int)L.A0;
+                const bool head = (L.hm >> j) & 1u;
+                // each group's wrench is folded into the axes that move it
+                // (N: every group; CA: its own, the side chain, C's; C: its
+                // own; side frame f: frames f and after) and into W
+                SpineGrad g;
+                NodeGrad sc[A2C_MAX_SIDE_FRAMES];
+                Wrench w;
+                if (RECOMPUTE) {
+                    if (head) cur = aff_identity();
+                    aff_apply_transform(cur, P.ct[0], P.st[0], P.d[0], in[j].co, in[j].so);
+                    g.n = node_of_frame(cur);
+                    w = wrench_zero();
+                    if (GM == kGradMse) frame_wrench_mse(tab, ft, 0, cur, sg, sout, write_so, aloc, w, loss);
+                    else frame_wrench(tab, ft, 0, cur, sg, aloc, w);
+                    node_fold(g.n, w);
+                    g.W = w;
+                    aff_apply_transform(cur, P.ct[1], P.st[1], P.d[1], in[j].cp, in[j].sp);
+                    g.ca = node_of_frame(cur);
+                    w = wrench_zero();
+                    if (GM == kGradMse) frame_wrench_mse(tab, ft, 1, cur, sg, sout, write_so, aloc, w, loss);
+                    else frame_wrench(tab, ft, 1, cur, sg, aloc, w);
                     node_fold(g.n, w);
                     node_fold(g.ca, w);
-                    node_fold(g.cc, w);
                     wrench_add(g.W, w);
-                    // chi gradients are complete here (their subtrees end in the residue)
+                    Aff sf = cur;
+                    aff_rot_x(sf, ft.pre_c, ft.pre_s);
 #pragma unroll
-                    for (int f = 0; f < A2C_MAX_SIDE_FRAMES; ++f)
-                        gang[(3 + f) * R + L.rs + j] =
-                            (f < tab.max_side && f < ft.n_side && ft.side_chi[f]) ? sc[f].c : 0.f;
-                    sp[j] = g;
-                    if (!f_end) wrench_add(agg, g.W);
-                    if ((L.lm >> j) & 1u) f_end = true;
+                    for (int f = 0; f < A2C_MAX_SIDE_FRAMES; ++f) {
+                        if (f < tab.max_side && f < ft.n_side) {
+                            side_step(sf, ft, f, lr.chi[j][f]);
+                            sc[f] = node_of_frame(sf);
+                            w = wrench_zero();
+                            if (GM == kGradMse) frame_wrench_mse(tab, ft, 3 + f, sf, sg, sout, write_so, aloc, w, loss);
+                            else frame_wrench(tab, ft, 3 + f, sf, sg, aloc, w);
+#pragma unroll
+                            for (int q = 0; q <= f; ++q) node_fold(sc[q], w);
+                            node_fold(g.n, w);
+                            node_fold(g.ca, w);
+                            wrench_add(g.W, w);
+                        }
+                    }
+                    aff_apply_transform(cur, P.ct[2], P.st[2], P.d[2], in[j].cs, in[j].ss);
+                    g.cc = node_of_frame(cur);
+                    w = wrench_zero();
+                    if (GM == kGradMse) frame_wrench_mse(tab, ft, 2, cur, sg, sout, write_so, aloc, w, loss);
+                    else frame_wrench(tab, ft, 2, cur, sg, aloc, w);
+                } else {
+                    const float *px = sx.st, *py = sx.st + sx.ns, *pz = sx.st + 2 * sx.ns;
+                    const float nx = px[aloc], ny = py[aloc], nz = pz[aloc];
+                    const float cax = px[aloc + 1], cay = py[aloc + 1], caz = pz[aloc + 1];
+                    const float cx = px[aloc + 2], cy = py[aloc + 2], cz = pz[aloc + 2];
+                    if (head) { pcx = 0.f; pcy = 0.f; pcz = 0.f; }
+                    g.n = node_at(nx, ny, nz, (nx - pcx) * P.inv_d[0], (ny - pcy) * P.inv_d[0],
+                                  (nz - pcz) * P.inv_d[0]);
+                    g.ca = node_at(cax, cay, caz, (cax - nx) * P.inv_d[1],
+                                   (cay - ny) * P.inv_d[1], (caz - nz) * P.inv_d[1]);
+                    g.cc = node_at(cx, cy, cz, (cx - cax) * P.inv_d[2], (cy - cay) * P.inv_d[2],
+                                   (cz - caz) * P.inv_d[2]);
+                    w = wrench_zero();
+                    frame_wrench_xyz(tab, ft, 0, sg, sx, aloc, w);
+                    node_fold(g.n, w);
+                    g.W = w;
+                    w = wrench_zero();
+                    frame_wrench_xyz(tab, ft, 1, sg, sx, aloc, w);
+                    node_fold(g.n, w);
+                    node_fold(g.ca, w);
+                    wrench_add(g.W, w);
+                    float ppx = cax, ppy = cay, ppz = caz;
+#pragma unroll
+                    for (int f = 0; f < A2C_MAX_SIDE_FRAMES; ++f) {
+                        if (f < tab.max_side && f < ft.n_side) {
+                            const int eo = aloc + ft.origin_slot[3 + f];
+                            const float ox = px[eo], oy = py[eo], oz = pz[eo];
+                            sc[f] = node_at(ox, oy, oz, (ox - ppx) * ft.inv_d[f],
+                                            (oy - ppy) * ft.inv_d[f], (oz - ppz) * ft.inv_d[f]);
+                            ppx = ox; ppy = oy; ppz = oz;
+                            w = wrench_zero();
+                            frame_wrench_xyz(tab, ft, 3 + f, sg, sx, aloc, w);
+#pragma unroll
+                            for (int q = 0; q <= f; ++q) node_fold(sc[q], w);
+                            node_fold(g.n, w);
+                            node_fold(g.ca, w);
+                            wrench_add(g.W, w);
+                        }
+                    }
+                    w = wrench_zero();
+                    frame_wrench_xyz(tab, ft, 2, sg, sx, aloc, w);
+                    pcx = cx; pcy = cy; pcz = cz;
                 }
-            }
-            wave_lds_sync();
-            if (STG && GM == kGradMse && xyz_out) {
-                lds_to_run(sg, xyz_out, A, L.A0, L.natoms);  // the stage now holds r
-                wave_lds_sync();
+                // the C group (with O)
+                node_fold(g.n, w);
+                node_fold(g.ca, w);
+                node_fold(g.cc, w);
+                wrench_add(g.W, w);
+                // chi gradients are complete here (their subtrees end in the residue)
+#pragma unroll
+                for (int f = 0; f < A2C_MAX_SIDE_FRAMES; ++f)
+                    gang[(3 + f) * R + L.rs + j] =
+                        (f < tab.max_side && f < ft.n_side && ft.side_chi[f]) ? sc[f].c : 0.f;
+                sp[j] = g;
+                if (!f_end) wrench_add(agg, g.W);
+                if ((L.lm >> j) & 1u) f_end = true;
             }
         }
-        Wrench S = block_exclusive_suffix<MULTI>(agg, f_end, k.nact, shb[c & 1], rcarry);
-        if (!L.active) continue;
+        wave_lds_sync();
+        if (STG && GM == kGradMse && xyz_out) {
+            lds_to_run(sg, xyz_out, A, L.A0, L.natoms);  // the stage now holds r
+            wave_lds_sync();
+        }
+    }
+    Wrench S = block_suffix_windows(agg, __builtin_amdgcn_ballot_w64(f_end), k.nact, L.active, shb,
+                                    rcarry_sh, status, t, last, prev);
+    if (L.active) {
 #pragma unroll
         for (int j = K - 1; j >= 0; --j) {
             if (j < L.cnt) {
@@ -927,7 +961,7 @@ __global__ __launch_bounds__(LB) void fa_backward_kernel(
         }
     }
     if constexpr (GM == kGradMse) {
-        if (loss_out) loss_commit(loss, loss_part, loss_count, loss_out, loss_tot);
+        if (loss_out) lb_loss_commit(loss, status, t, gridDim.x, prev, loss_out, loss_tot);
     }
 }
 
@@ -957,17 +991,41 @@ hipError_t fa_fwd_k(const a2c_plan &p, const float *ang, float *xyz, hipStream_t
     return p.fs.fa_unstaged ? fa_fwd_ks<K, false>(p, ang, xyz, s) : fa_fwd_ks<K, true>(p, ang, xyz, s);
 }
 
-template <int K, bool RECOMPUTE, bool MULTI, int LB, int GM, bool STG>
+// The frame pass covers the adjoint's windows (C = 64 W K residues) with
+// more residues per lane where C allows (8 or 4 per lane, fewer waves): it
+// only walks the spine, so the per-residue walk is cheap and the scan is
+// shared by more residues.
+template <int K>
+void fa_carry_launch(const a2c_plan &p, const float *ang, hipStream_t s)
+{
+    const int64_t C = (int64_t)kWave * K * p.bs.W;
+    const dim3 grid(p.bs.n_win);
+    if (C % (kWave * 8) == 0)
+        hipLaunchKernelGGL((fa_spine_carry_kernel<8, 1024>), grid, dim3(C / 8), 0, s, ang,
+                           p.d_head_bits, p.bs.d_look_fwd, p.bs.d_status_fwd, p.bs.d_carry, p.R,
+                           p.bb);
+    else if (C % (kWave * 4) == 0)
+        hipLaunchKernelGGL((fa_spine_carry_kernel<4, 1024>), grid, dim3(C / 4), 0, s, ang,
+                           p.d_head_bits, p.bs.d_look_fwd, p.bs.d_status_fwd, p.bs.d_carry, p.R,
+                           p.bb);
+    else
+        hipLaunchKernelGGL((fa_spine_carry_kernel<K, 1024>), grid, dim3(C / K), 0, s, ang,
+                           p.d_head_bits, p.bs.d_look_fwd, p.bs.d_status_fwd, p.bs.d_carry, p.R,
+                           p.bb);
+}
+
+template <int K, bool RECOMPUTE, int LB, int GM, bool STG>
 void fa_bwd_launch(const a2c_plan &p, const float *ang, const float *xyz, const float *g,
                    float *gang, hipStream_t s, float *xyz_out, float *loss_out)
 {
+    if (RECOMPUTE) fa_carry_launch<K>(p, ang, s);
     const size_t lds =
         STG ? (size_t)p.bs.W * (RECOMPUTE ? 3 : 6) * p.bs.fa_stage_atoms * sizeof(float) : 0;
-    hipLaunchKernelGGL((fa_backward_kernel<K, RECOMPUTE, MULTI, LB, GM, STG>), dim3(p.bs.n_tiles),
+    hipLaunchKernelGGL((fa_backward_flat_kernel<K, RECOMPUTE, LB, GM, STG>), dim3(p.bs.n_win),
                        dim3(p.bs.W * kWave), lds, s, ang, xyz, g, gang, xyz_out, loss_out,
-                       p.bs.d_loss_part, p.bs.d_loss_count, p.bs.d_tile_res, p.d_head_bits,
-                       p.d_res_atom_off, p.d_seq, p.d_fa, p.R, p.A,
-                       p.bb, p.bs.fa_stage_atoms);
+                       p.d_head_bits, p.d_res_atom_off,
+                       p.d_seq, p.d_fa, p.bs.d_carry, p.bs.d_look, p.bs.d_status, p.R, p.A, p.bb,
+                       p.bs.fa_stage_atoms);
 }
 
 // mode 0: adjoint from coordinates, 1: recompute, 2: fused squared-distance step
@@ -977,14 +1035,11 @@ void fa_bwd_dispatch(const a2c_plan &p, const float *ang, const float *xyz, cons
 {
     constexpr bool RC = MODE != 0;
     constexpr int GM = MODE == 2 ? kGradMse : kGradLoad;
-    const bool small = p.bs.W * kWave <= kLbSmall;
-    if (p.bs.multi_chunk) {
-        if (small) fa_bwd_launch<K, RC, true, kLbSmall, GM, STG>(p, ang, xyz, g, gang, s, xyz_out, loss_out);
-        else fa_bwd_launch<K, RC, true, kLbLarge, GM, STG>(p, ang, xyz, g, gang, s, xyz_out, loss_out);
-    } else {
-        if (small) fa_bwd_launch<K, RC, false, kLbSmall, GM, STG>(p, ang, xyz, g, gang, s, xyz_out, loss_out);
-        else fa_bwd_launch<K, RC, false, kLbLarge, GM, STG>(p, ang, xyz, g, gang, s, xyz_out, loss_out);
-    }
+    const int threads = p.bs.W * kWave;
+    if (threads <= 256) fa_bwd_launch<K, RC, 256, GM, STG>(p, ang, xyz, g, gang, s, xyz_out, loss_out);
+    else if (threads <= kLbSmall)
+        fa_bwd_launch<K, RC, kLbSmall, GM, STG>(p, ang, xyz, g, gang, s, xyz_out, loss_out);
+    else fa_bwd_launch<K, RC, kLbLarge, GM, STG>(p, ang, xyz, g, gang, s, xyz_out, loss_out);
 }
 
 template <int K, int MODE>
@@ -1055,29 +1110,25 @@ static void allow_lds(F kernel)
                               kMaxDynamicLds);
 }
 
-template <int K, bool MULTI, int LB>
-static void allow_lds_km()
+template <int K, int LB>
+static void allow_lds_kl()
 {
     allow_lds(fa_forward_flat_kernel<K, LB>);
-    allow_lds(fa_backward_kernel<K, false, MULTI, LB>);
-    allow_lds(fa_backward_kernel<K, true, MULTI, LB>);
-    allow_lds(fa_backward_kernel<K, true, MULTI, LB, kGradMse, true>);
+    allow_lds(fa_backward_flat_kernel<K, false, LB>);
+    allow_lds(fa_backward_flat_kernel<K, true, LB>);
+    allow_lds(fa_backward_flat_kernel<K, true, LB, kGradMse, true>);
 }
 
 void fa_allow_large_lds()
 {
     static bool done = false;
     if (done) return;
-    allow_lds(fa_forward_flat_kernel<1, 256>);
-    allow_lds(fa_forward_flat_kernel<2, 256>);
-    allow_lds_km<1, false, kLbSmall>();
-    allow_lds_km<1, true, kLbSmall>();
-    allow_lds_km<2, false, kLbSmall>();
-    allow_lds_km<2, true, kLbSmall>();
-    allow_lds_km<1, false, kLbLarge>();
-    allow_lds_km<1, true, kLbLarge>();
-    allow_lds_km<2, false, kLbLarge>();
-    allow_lds_km<2, true, kLbLarge>();
+    allow_lds_kl<1, 256>();
+    allow_lds_kl<2, 256>();
+    allow_lds_kl<1, kLbSmall>();
+    allow_lds_kl<2, kLbSmall>();
+    allow_lds_kl<1, kLbLarge>();
+    allow_lds_kl<2, kLbLarge>();
     done = true;
 }
 

@@ -879,4 +879,117 @@ __device__ __forceinline__ Wrench lb_carry_after(const uint64_t *status, int64_t
     return carry;
 }
 
+
+// The wrench of everything after each lane, up to the end of its chain, in
+// window t of a launch over fixed windows taken last to first: segmented
+// suffix scan of the lane aggregates (agg: the lane's atoms up to and
+// including its first chain end; ends: lanes where a chain ends) inside each
+// wave, then of the wave totals by wave 0, which publishes the window's
+// wrench (from its start to its first chain end) and adds those of the later
+// windows its last chain runs into (lb_carry_after).  prev, last (read by
+// wave 0 early): the window's own first tagged word and the last window of
+// its look-ahead.  Every thread of the block calls it; inactive waves get 0.
+__device__ __forceinline__ Wrench block_suffix_windows(Wrench agg, uint64_t ends, int nact,
+                                                       bool active, BwdShared &sh,
+                                                       float (&carry_sh)[6],
+                                                       uint64_t *__restrict__ status, int64_t t,
+                                                       int64_t last, uint64_t prev)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (active) {
+        wrench_wave_rscan<false>(agg, ends, kWave, lane);
+        if (lane == 0) {
+            wrench_store(sh.tot[wave], agg);
+            sh.tot_flag[wave] = ends != 0ull ? 1 : 0;
+        }
+    }
+    __syncthreads();
+    if (wave == 0) {
+        Wrench tw = wrench_zero();
+        bool tf = false;
+        if (lane < nact) {
+            tw = wrench_load(sh.tot[lane]);
+            tf = sh.tot_flag[lane] != 0;
+        }
+        const uint64_t th = __builtin_amdgcn_ballot_w64(tf);
+        wrench_wave_rscan<true>(tw, th, nact, lane);
+        if (lane < nact) {
+            wrench_store(sh.suf[lane], tw);
+            sh.suf_flag[lane] = (th & (~0ull << lane)) != 0ull ? 1 : 0;
+        }
+        wave_lds_sync();
+        // publish this window's wrench, then read the later windows' ones
+        const uint32_t tag = (uint32_t)(__builtin_amdgcn_readfirstlane((uint32_t)(prev >> 32))) + 1u;
+        if (lane < kLbWrenchWords) lb_store(status + t * kLbWords + lane, tag, sh.suf[0][lane]);
+        const int64_t l = (int64_t)__builtin_amdgcn_readfirstlane((int)last);
+        const Wrench carry = lb_carry_after(status, t, l, tag);
+        if (lane == 0) wrench_store(carry_sh, carry);
+    }
+    __syncthreads();
+    if (!active) return wrench_zero();
+    // everything after the wave up to the end of its last chain
+    const Wrench carry = wrench_load(carry_sh);
+    Wrench cw = carry;
+    if (wave + 1 < nact) {
+        cw = wrench_load(sh.suf[wave + 1]);
+        if (sh.suf_flag[wave + 1] == 0) wrench_add(cw, carry);
+    }
+    // everything after lane l inside the wave: the inclusive value of lane
+    // l + 1, complete when a chain ends in lanes after l
+    Wrench S = wrench_dpp_z<kDppWaveShl1>(agg);
+    if (lane == kWave - 1) S = wrench_zero();
+    if (!(lane < kWave - 1 && (ends >> (lane + 1)) != 0ull)) wrench_add(S, cw);
+    return S;
+}
+
+
+// A launch over fixed windows taken last to first: the sum of one float per
+// window (each window's share of a loss) without a counter or a fence.
+// Every window publishes its share (block sum in a fixed order) as tagged
+// word kLbLossWord of its look-back words, with the tag of this launch;
+// window 0, taken last, waits for all shares and adds them in window order
+// into *out.  Every thread of the block calls it (one barrier).
+constexpr int kLbLossWord = kLbWrenchWords;
+
+__device__ __forceinline__ void lb_loss_commit(float v, uint64_t *__restrict__ status, int64_t t,
+                                               int64_t n_win, uint64_t prev,
+                                               float *__restrict__ out,
+                                               float (&wave_tot)[kMaxWaves])
+{
+    const float share = block_sum(v, wave_tot);  // meaningful in thread 0
+    const uint32_t tag = (uint32_t)(__builtin_amdgcn_readfirstlane((uint32_t)(prev >> 32))) + 1u;
+    if (threadIdx.x == 0) lb_store(status + t * kLbWords + kLbLossWord, tag, share);
+    if (t != 0 || threadIdx.x >= kWave) return;
+    // wave 0 of window 0: lane l adds windows l, l + 64, ... in order, then
+    // the lanes' sums are added in a fixed order; the words are read 16 per
+    // lane at a time before any is checked (one memory latency per batch)
+    constexpr int kBatch = 16;
+    const int lane = threadIdx.x;
+    float sum = 0.f;
+    for (int64_t b = 0; b < n_win; b += (int64_t)kWave * kBatch) {
+        uint64_t x[kBatch];
+#pragma unroll
+        for (int i = 0; i < kBatch; ++i) {
+            const int64_t u = b + lane + (int64_t)kWave * i;
+            x[i] = u < n_win ? lb_load(status + u * kLbWords + kLbLossWord) : (uint64_t)tag << 32;
+        }
+#pragma unroll
+        for (int i = 0; i < kBatch; ++i) {
+            const int64_t u = b + lane + (int64_t)kWave * i;
+            for (int spins = 0; (uint32_t)(x[i] >> 32) != tag; ++spins) {
+                if (spins >= kLbSpinLimit) {
+                    x[i] = (uint64_t)__float_as_uint(__builtin_nanf(""));
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+                x[i] = lb_load(status + u * kLbWords + kLbLossWord);
+            }
+            sum += __uint_as_float((uint32_t)x[i]);
+        }
+    }
+    const float total = wave_sum_fixed(sum);
+    if (lane == 0) *out = total;
+}
+
 }  // namespace a2c
