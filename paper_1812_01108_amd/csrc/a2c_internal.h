@@ -80,12 +80,11 @@ struct Sched {
                                          // aggregate window t composes; adjoint, the
                                          // last window whose wrench it adds (t: none)
     uint64_t *d_status = nullptr;        // n_win x kLbWords tagged words
-    // full-atom adjoint: the spine pass that finds the frame entering each
-    // window looks back like a forward (its own table and words) and stores
-    // the frames for the adjoint
+    // full-atom adjoint: a spine pass publishes each window's aggregate in
+    // its own tagged words; each window of the adjoint composes those of the
+    // windows its first chain spans (from d_look_fwd[t] to t - 1)
     int32_t *d_look_fwd = nullptr;       // n_win, first window to compose
     uint64_t *d_status_fwd = nullptr;    // n_win x kLbWords tagged words
-    float *d_carry = nullptr;            // n_win x 12 frames entering the windows
     int32_t fa_stage_atoms = 0;          // per-wave staging (floats per plane)
     bool fa_unstaged = false;            // stage too large for the LDS: direct I/O
     bool multi_chunk = false;            // some tile spans several chunks

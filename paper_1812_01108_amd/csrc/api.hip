@@ -48,7 +48,6 @@ void free_sched(Sched &S)
     (void)hipFree(S.d_status);
     (void)hipFree(S.d_look_fwd);
     (void)hipFree(S.d_status_fwd);
-    (void)hipFree(S.d_carry);
     S.d_tile_res = nullptr;
     S.d_loss_part = nullptr;
     S.d_loss_count = nullptr;
@@ -56,7 +55,6 @@ void free_sched(Sched &S)
     S.d_status = nullptr;
     S.d_look_fwd = nullptr;
     S.d_status_fwd = nullptr;
-    S.d_carry = nullptr;
 }
 
 // Fixed windows of `cap` residues.  Forward (look_back): for each window t
@@ -152,16 +150,11 @@ a2c_status build_sched(const a2c_plan *p, int32_t K, int32_t W, Sched &out, hipS
         a2c_status st = build_windows(p, cap, fwd, S.d_look, S.d_status, S.n_win, s);
         S.n_tiles = S.n_win;
         if (st == A2C_OK && !fwd) {
-            // the full-atom adjoint: the frame pass's windows and frames
-            // (the fused step's loss shares travel in the adjoint's own
-            // tagged words)
+            // the full-atom adjoint: the spine pass's words and the windows
+            // whose aggregates each window composes (the fused step's loss
+            // shares travel in the adjoint's own tagged words)
             int32_t n2 = 0;
             st = build_windows(p, cap, true, S.d_look_fwd, S.d_status_fwd, n2, s);
-            if (st == A2C_OK) {
-                const hipError_t e = hipMalloc((void **)&S.d_carry,
-                                               std::max<size_t>(1, S.n_win) * 12 * sizeof(float));
-                if (e != hipSuccess) st = hip_fail(e, "adjoint window frames");
-            }
         }
         if (st == A2C_OK) {
             const hipError_t e = hipStreamSynchronize(s);
@@ -252,7 +245,7 @@ void retire_sched(a2c_plan *p, Sched &S)
 {
     for (void *q : {(void *)S.d_tile_res, (void *)S.d_loss_part, (void *)S.d_loss_count,
                     (void *)S.d_look, (void *)S.d_status, (void *)S.d_look_fwd,
-                    (void *)S.d_status_fwd, (void *)S.d_carry})
+                    (void *)S.d_status_fwd})
         if (q) p->retired.push_back(q);
     S.d_tile_res = nullptr;
     S.d_loss_part = nullptr;
@@ -261,7 +254,6 @@ void retire_sched(a2c_plan *p, Sched &S)
     S.d_status = nullptr;
     S.d_look_fwd = nullptr;
     S.d_status_fwd = nullptr;
-    S.d_carry = nullptr;
 }
 
 // Replace one of the plan's schedules; on failure it stays as it was.  The

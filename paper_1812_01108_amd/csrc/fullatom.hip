@@ -703,19 +703,20 @@ __device__ __forceinline__ void fa_store_grads(float *__restrict__ gang, int64_t
     S_out = S;
 }
 
-// Frames entering the windows of the full-atom adjoint.  The recomputing
-// adjoints take their windows last to first (for the wrench look-back), so
-// they cannot look back for frames themselves: this spine-only pass of the
-// forward over the same windows, first to last with window look-back, stores
-// the frame entering each window (12 floats) for them.
+// Spine aggregates for the recomputing full-atom adjoints.  Those take their
+// windows last to first (for the wrench look-back), so they cannot wait on
+// earlier windows' frames themselves: this spine-only pass over the same
+// windows publishes each window's aggregate (the product of its spine
+// transforms from its last chain head, or its start, to its end) as tagged
+// words and waits on nothing; the adjoint then composes the aggregates of
+// the windows its first chain spans, all complete by then (lb_carry_in).
 template <int K, int LB>
-__global__ __launch_bounds__(LB) void fa_spine_carry_kernel(
+__global__ __launch_bounds__(LB) void fa_spine_aggregate_kernel(
     const float *__restrict__ ang, const uint32_t *__restrict__ head_bits,
-    const int32_t *__restrict__ look_first, uint64_t *__restrict__ status,
-    float *__restrict__ carry_out, int64_t R, BBParams P)
+    uint64_t *__restrict__ status, int64_t R, BBParams P)
 {
     __shared__ FwdShared sh;
-    __shared__ float carry_sh[12];
+    const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nw = blockDim.x >> 6;
     const int64_t t = blockIdx.x;
@@ -728,27 +729,43 @@ __global__ __launch_bounds__(LB) void fa_spine_carry_kernel(
     const int cnt = (int)max((int64_t)0, min((int64_t)K, k.ce - rs));
     const uint32_t hm = lane_head_mask<K>(head_bits, rs, k.ce, cnt);
     uint64_t prev = 0;
-    int64_t first = t;
-    if (wave == 0) {
-        prev = lb_load(status + t * kLbWords);
-        first = look_first[t];
-    }
+    if (wave == 0) prev = lb_load(status + t * kLbWords);
     ResidueIn in[K];
     int first_head = K;
     Aff m = aff_identity();
     if (active) m = fa_lane_aggregate<K>(load_spine_angles<K>(ang, R, rs, cnt), cnt, hm, P, in,
                                          first_head);
     const uint64_t heads = __builtin_amdgcn_ballot_w64(first_head < K);
-    (void)block_prefix_windows(m, heads, k.nact, active, sh, carry_sh, status, t, first, prev);
-    if (threadIdx.x < 12) carry_out[t * 12 + threadIdx.x] = carry_sh[threadIdx.x];
+    if (active) {
+        aff_wave_scan<false>(m, heads, kWave, lane);
+        if (lane == kWave - 1) {
+            aff_store(sh.tot[wave], m);
+            sh.tot_flag[wave] = heads != 0ull ? 1 : 0;
+        }
+    }
+    __syncthreads();
+    if (wave != 0) return;
+    Aff tw = aff_identity();
+    bool tf = false;
+    if (lane < k.nact) {
+        tw = aff_load(sh.tot[lane]);
+        tf = sh.tot_flag[lane] != 0;
+    }
+    const uint64_t th = __builtin_amdgcn_ballot_w64(tf);
+    aff_wave_scan<true>(tw, th, k.nact, lane);
+    if (lane == k.nact - 1) aff_store(sh.pre[0], tw);
+    wave_lds_sync();
+    const uint32_t tag = (uint32_t)(__builtin_amdgcn_readfirstlane((uint32_t)(prev >> 32))) + 1u;
+    if (lane < kLbWords) lb_store(status + t * kLbWords + lane, tag, sh.pre[0][lane]);
 }
 
 // Backward over fixed windows of the packed batch, last window first: the
 // side chains' subtree sums give the chi gradients, the spine groups feed a
 // reverse scan over residues (window look-back for the wrench of later
 // windows), and u . (S_m - o x S_g) gives phi, psi, omega.
-// RECOMPUTE: frames from the angles, the frame entering the window from
-// carry_in (fa_spine_carry_kernel); otherwise positions and axes from the
+// RECOMPUTE: frames from the angles, the frame entering the window composed
+// from the aggregates fa_spine_aggregate_kernel published (status_fwd,
+// windows look_fwd[t] .. t - 1); otherwise positions and axes from the
 // forward's coordinates.
 // GM = kGradMse (with RECOMPUTE): g points at a target t and the upstream
 // gradient is 2 (r - t), formed from the recomputed positions (the fused
@@ -762,8 +779,9 @@ __global__ __launch_bounds__(LB) void fa_backward_flat_kernel(
     float *__restrict__ gang, float *__restrict__ xyz_out, float *__restrict__ loss_out,
     const uint32_t *__restrict__ head_bits, const int32_t *__restrict__ res_aoff,
     const uint8_t *__restrict__ seq, const FATable *__restrict__ gtab,
-    const float *__restrict__ carry_in, const int32_t *__restrict__ look_last,
-    uint64_t *__restrict__ status, int64_t R, int64_t A, BBParams P, int stage_atoms)
+    const uint64_t *__restrict__ status_fwd, const int32_t *__restrict__ look_fwd,
+    const int32_t *__restrict__ look_last, uint64_t *__restrict__ status, int64_t R, int64_t A,
+    BBParams P, int stage_atoms)
 {
     static_assert(GM == kGradLoad || RECOMPUTE, "the fused step recomputes the frames");
     extern __shared__ float stage_mem[];
@@ -788,21 +806,35 @@ __global__ __launch_bounds__(LB) void fa_backward_flat_kernel(
         prev = lb_load(status + t * kLbWords);
         last = look_last[t];
     }
-    // the window's inputs ahead of the table copy (which ends in a barrier)
+    // the window's inputs, and the upstream gradients (or targets) and
+    // coordinates into the stage, ahead of the table copy (which ends in a
+    // barrier) so that their latencies overlap
     SpineAngles<K> a{};
     if (RECOMPUTE && L.active) a = load_spine_angles<K>(ang, R, L.rs, L.cnt);
     const LaneRes<K, RECOMPUTE> lr = load_lane_res<K, RECOMPUTE>(L, seq, res_aoff, ang, R);
-    Aff fcarry = aff_identity();
-    if (RECOMPUTE) fcarry = aff_load(carry_in + t * 12);
-    load_table(tab, gtab);
     const int planes = RECOMPUTE ? 3 : 6;
     const Stage lds{stage_mem + (size_t)wave * planes * stage_atoms, stage_atoms};
+    if (STG && L.active) {
+        run_to_lds(lds, 0, g, A, L.A0, L.natoms);
+        if (!RECOMPUTE) run_to_lds(lds, 3, xyz, A, L.A0, L.natoms);
+    }
+    // the frame entering the window (wave 0; the aggregates are complete)
+    __shared__ float fcarry_sh[12];
+    if (RECOMPUTE && wave == 0) {
+        const uint32_t tag_f =
+            (uint32_t)(__builtin_amdgcn_readfirstlane((uint32_t)(lb_load(status_fwd + t * kLbWords) >> 32)));
+        const int64_t f = (int64_t)__builtin_amdgcn_readfirstlane(look_fwd[t]);
+        const Aff c = lb_carry_in(status_fwd, f, t, tag_f);
+        if (lane == 0) aff_store(fcarry_sh, c);
+    }
+    load_table(tab, gtab);
     Aff X = aff_identity();
     ResidueIn in[K];
     int first_head = K;
     if (RECOMPUTE) {
         Aff m = aff_identity();
         if (L.active) m = fa_lane_aggregate<K>(a, L.cnt, L.hm, P, in, first_head);
+        Aff fcarry = aff_load(fcarry_sh);
         X = block_exclusive_prefix<true>(m, first_head < K, k.nact, shf, fcarry);
     }
     // the C atom before the lane's first residue (coordinate mode): in
@@ -822,10 +854,6 @@ __global__ __launch_bounds__(LB) void fa_backward_flat_kernel(
     const Stage sout = STG ? sg : Stage{xyz_out + L.A0, A};
     const bool write_so = STG || (GM == kGradMse && xyz_out != nullptr);
     if (L.active) {
-        if (STG) {
-            run_to_lds(sg, 0, g, A, L.A0, L.natoms);
-            if (!RECOMPUTE) run_to_lds(sg, 3, xyz, A, L.A0, L.natoms);
-        }
         wave_lds_sync();
         // first atom of the residue before the lane: the previous lane's last
         const int prev_aoff = __builtin_amdgcn_mov_dpp(lr.aoff[K - 1], kDppWaveShr1, 0xf, 0xf, true);
@@ -991,41 +1019,38 @@ hipError_t fa_fwd_k(const a2c_plan &p, const float *ang, float *xyz, hipStream_t
     return p.fs.fa_unstaged ? fa_fwd_ks<K, false>(p, ang, xyz, s) : fa_fwd_ks<K, true>(p, ang, xyz, s);
 }
 
-// The frame pass covers the adjoint's windows (C = 64 W K residues) with
+// The spine pass covers the adjoint's windows (C = 64 W K residues) with
 // more residues per lane where C allows (8 or 4 per lane, fewer waves): it
 // only walks the spine, so the per-residue walk is cheap and the scan is
 // shared by more residues.
 template <int K>
-void fa_carry_launch(const a2c_plan &p, const float *ang, hipStream_t s)
+void fa_spine_launch(const a2c_plan &p, const float *ang, hipStream_t s)
 {
     const int64_t C = (int64_t)kWave * K * p.bs.W;
     const dim3 grid(p.bs.n_win);
     if (C % (kWave * 8) == 0)
-        hipLaunchKernelGGL((fa_spine_carry_kernel<8, 1024>), grid, dim3(C / 8), 0, s, ang,
-                           p.d_head_bits, p.bs.d_look_fwd, p.bs.d_status_fwd, p.bs.d_carry, p.R,
-                           p.bb);
+        hipLaunchKernelGGL((fa_spine_aggregate_kernel<8, 1024>), grid, dim3(C / 8), 0, s, ang,
+                           p.d_head_bits, p.bs.d_status_fwd, p.R, p.bb);
     else if (C % (kWave * 4) == 0)
-        hipLaunchKernelGGL((fa_spine_carry_kernel<4, 1024>), grid, dim3(C / 4), 0, s, ang,
-                           p.d_head_bits, p.bs.d_look_fwd, p.bs.d_status_fwd, p.bs.d_carry, p.R,
-                           p.bb);
+        hipLaunchKernelGGL((fa_spine_aggregate_kernel<4, 1024>), grid, dim3(C / 4), 0, s, ang,
+                           p.d_head_bits, p.bs.d_status_fwd, p.R, p.bb);
     else
-        hipLaunchKernelGGL((fa_spine_carry_kernel<K, 1024>), grid, dim3(C / K), 0, s, ang,
-                           p.d_head_bits, p.bs.d_look_fwd, p.bs.d_status_fwd, p.bs.d_carry, p.R,
-                           p.bb);
+        hipLaunchKernelGGL((fa_spine_aggregate_kernel<K, 1024>), grid, dim3(C / K), 0, s, ang,
+                           p.d_head_bits, p.bs.d_status_fwd, p.R, p.bb);
 }
 
 template <int K, bool RECOMPUTE, int LB, int GM, bool STG>
 void fa_bwd_launch(const a2c_plan &p, const float *ang, const float *xyz, const float *g,
                    float *gang, hipStream_t s, float *xyz_out, float *loss_out)
 {
-    if (RECOMPUTE) fa_carry_launch<K>(p, ang, s);
+    if (RECOMPUTE) fa_spine_launch<K>(p, ang, s);
     const size_t lds =
         STG ? (size_t)p.bs.W * (RECOMPUTE ? 3 : 6) * p.bs.fa_stage_atoms * sizeof(float) : 0;
     hipLaunchKernelGGL((fa_backward_flat_kernel<K, RECOMPUTE, LB, GM, STG>), dim3(p.bs.n_win),
                        dim3(p.bs.W * kWave), lds, s, ang, xyz, g, gang, xyz_out, loss_out,
                        p.d_head_bits, p.d_res_atom_off,
-                       p.d_seq, p.d_fa, p.bs.d_carry, p.bs.d_look, p.bs.d_status, p.R, p.A, p.bb,
-                       p.bs.fa_stage_atoms);
+                       p.d_seq, p.d_fa, p.bs.d_status_fwd, p.bs.d_look_fwd, p.bs.d_look,
+                       p.bs.d_status, p.R, p.A, p.bb, p.bs.fa_stage_atoms);
 }
 
 // mode 0: adjoint from coordinates, 1: recompute, 2: fused squared-distance step
