@@ -66,8 +66,8 @@ def parse():
                    help="adjoint reads the forward's coordinates, or recomputes the frames "
                         "(default: coords; recompute for the training-step workload)")
     p.add_argument("--schedule", default=None, help="K,W (residues per lane, waves per group) "
-                   "for both the forward and the adjoint, or K,W,aK,aW (forward, adjoint); "
-                   "default: autotuned")
+                   "for both the forward and the adjoint, or K,W,aK,aW (forward, adjoint; the "
+                   "backbone forward also takes K = 8); default: autotuned")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 256 MiB device copy (HBM counter calibration)")
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -323,7 +323,8 @@ def chain_grad_rel(gpu, ref, off):
     return worst
 
 
-def cpu_baseline(model, inp, g_np, gpu_coords, gpu_grad, budget_s=12.0, single_budget_s=4.0):
+def cpu_baseline(model, inp, g_np, gpu_coords, gpu_grad, budget_s=12.0, single_budget_s=4.0,
+                 quat_coords=None):
     """The FP64 oracle (forward + O(N) adjoint, OpenMP over chains) on the
     full batch, repeated for about budget_s seconds of host time on every
     host core, then on one thread for about single_budget_s seconds (whole
@@ -363,6 +364,8 @@ def cpu_baseline(model, inp, g_np, gpu_coords, gpu_grad, budget_s=12.0, single_b
               "max_chain_len": int(lens.max()) if len(lens) else 0,
               "chains_len_ge_900": int(np.sum(lens >= 900)),
               "compared": "every atom and every angle gradient of the batch"}
+    if quat_coords is not None:
+        parity["quaternion_state_max_abs_coord_A"] = float(np.max(np.abs(quat_coords - ref)))
     return {"value": n * R / t_total, "unit": "residues/s", "cores": cores, "kind": "oracle",
             "sample": f"full batch ({R} residues) x {n} repeats, FP64 {model} forward + O(N) "
                       f"adjoint, OpenMP over chains",
@@ -435,13 +438,15 @@ def main():
         sv = [int(v) for v in args.schedule.split(",")]
         if len(sv) not in (2, 4):
             sys.exit("--schedule takes K,W or K,W,aK,aW")
-        plan.set_schedule(sv[0], sv[1])
-        if len(sv) == 4:
+        if len(sv) == 2:
+            plan.set_schedule(sv[0], sv[1])
+        else:
+            plan.set_forward_schedule(sv[0], sv[1])
             plan.set_adjoint_schedule(sv[2], sv[3])
     elif args.fused:
-        plan.autotune(angles, reps=5, mse_target=target)
+        plan.autotune(angles, reps=20, mse_target=target)
     else:
-        plan.autotune(angles, grad_up, from_coords=mode == "coords", reps=5)
+        plan.autotune(angles, grad_up, from_coords=mode == "coords", reps=20)
 
     # scan form, whole step in one graph
     loss = args.loss if training else None
@@ -559,6 +564,19 @@ def main():
                  "form": "one workgroup per chain, sequential product storing M_i, "
                          "O(atoms x angles) gradient"}
 
+    # the comparison form with the quaternion + translation scan state
+    # (forward only): duration on the forward's schedule, error in parity
+    quat, quat_np = None, None
+    if model == "backbone":
+        qbuf = torch.empty_like(coords_buf)
+        plan.forward(angles, qbuf, variant="scan_quat")
+        q_us = kernel_avg_us(lambda: plan.forward(angles, qbuf, variant="scan_quat"),
+                             args.kernel_reps)
+        quat_np = qbuf.cpu().numpy()
+        quat = {"forward_us": round(q_us, 3), "affine_forward_us": round(fwd_us, 3),
+                "GBs": round(algorithmic_bytes(model, "forward", R) / (q_us * 1e-6) / 1e9, 1),
+                "state": "unit quaternion + translation (7 floats) in the scans and look-back"}
+
     cpu, parity = (None, None)
     if not args.no_cpu_baseline:
         if loss == "lrmsd":
@@ -569,7 +587,7 @@ def main():
             g_np = olr.lrmsd_grad_batch(target.cpu().numpy().astype(np.float64),
                                         gpu_coords.astype(np.float64), ca,
                                         np.ones(plan.n_chains)).astype(np.float32)
-        cpu, parity = cpu_baseline(model, inp, g_np, gpu_coords, gpu_grad)
+        cpu, parity = cpu_baseline(model, inp, g_np, gpu_coords, gpu_grad, quat_coords=quat_np)
 
     sched, asched = plan.schedule, plan.adjoint_schedule
     line = {
@@ -589,6 +607,7 @@ def main():
         "lrmsd": lr_info,
         "inverse_map": inverse,
         "plain_gpu": plain,
+        "quaternion_state": quat,
         "speedup_vs_plain": (value / plain["value"]) if plain else None,
         "cold": cold,
         "cpu_baseline": cpu,

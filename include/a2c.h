@@ -74,7 +74,20 @@ typedef enum { A2C_BACKBONE = 0, A2C_FULLATOM = 1 } a2c_model;
  *   one workgroup per chain, a sequential transform product that stores M_i
  *   for every atom, and the O(atoms x angles) gradient sum of
  *   Eq. BackboneGradOutput.  Needs a workspace (a2c_plan_workspace_bytes). */
-typedef enum { A2C_SCAN = 0, A2C_PLAIN = 1 } a2c_variant;
+/* A2C_SCAN_QUAT: the scan form with a different scan state, kept as a
+ *   measured comparison (backbone a2c_forward only; a2c_backward refuses it
+ *   with A2C_ERR_UNSUPPORTED): the state the scans and the window look-back
+ *   combine is a unit quaternion and a translation (7 floats, the quaternion
+ *   form of the transforms in the "Loss function" section) instead of the
+ *   3x4 affine.  The lane walk is the same; each lane aggregate, after its
+ *   polar step, is converted (Shepperd's method, normalised) and the lane's
+ *   prefix is converted back to place its atoms.  In float32 the rotation a
+ *   quaternion holds carries a larger rounding error that similar residues
+ *   repeat: at L = 1000 its coordinates drift further (8.2e-4 A against
+ *   5.8e-4 A for A2C_SCAN on 64 mixture chains, 8 residues per lane), too
+ *   close to the 1e-3 A bound for a forward only a few percent faster; the
+ *   library's results use A2C_SCAN. */
+typedef enum { A2C_SCAN = 0, A2C_PLAIN = 1, A2C_SCAN_QUAT = 2 } a2c_variant;
 
 typedef struct a2c_plan a2c_plan;
 

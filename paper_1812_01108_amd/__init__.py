@@ -20,7 +20,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import A2C_BACKBONE, A2C_FULLATOM, A2C_PLAIN, A2C_SCAN, A2CError, check
+from ._lib import A2C_BACKBONE, A2C_FULLATOM, A2C_PLAIN, A2C_SCAN, A2C_SCAN_QUAT, A2CError, check
 
 __all__ = ["Plan", "Angles2Coords", "angles_to_coords", "LRMSD", "lrmsd", "A2CError",
            "library_version", "DEFAULT_GEOMETRY", "PAPER_LITERAL_GEOMETRY"]
@@ -44,7 +44,7 @@ PAPER_LITERAL_GEOMETRY = {
     "bond_CA_C": 1.525, "angle_N_CA_C": 2.0610 * _RAD,    # transform placing C_j
 }
 
-_VARIANTS = {"scan": A2C_SCAN, "plain": A2C_PLAIN}
+_VARIANTS = {"scan": A2C_SCAN, "plain": A2C_PLAIN, "scan_quat": A2C_SCAN_QUAT}
 
 
 def library_version() -> str:

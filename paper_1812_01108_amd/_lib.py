@@ -16,7 +16,7 @@ A2C_OK = 0
 STATUS = {0: "A2C_OK", -1: "A2C_ERR_INVALID_ARG", -2: "A2C_ERR_UNSUPPORTED",
           -3: "A2C_ERR_WORKSPACE", -4: "A2C_ERR_HIP", -5: "A2C_ERR_STATE"}
 A2C_BACKBONE, A2C_FULLATOM = 0, 1
-A2C_SCAN, A2C_PLAIN = 0, 1
+A2C_SCAN, A2C_PLAIN, A2C_SCAN_QUAT = 0, 1, 2
 A2C_TUNE_MSE_STEP = 2
 NUM_RESIDUE_TYPES = 20
 MAX_SIDE_FRAMES = 4

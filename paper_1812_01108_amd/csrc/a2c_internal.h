@@ -149,7 +149,9 @@ void unit_pair(double t, float &c, float &s);
 a2c_status hip_fail(hipError_t e, const char *what);
 
 // Launchers (each returns hipSuccess or the launch error)
-hipError_t launch_bb_forward_scan(const a2c_plan &p, const float *ang, float *xyz, hipStream_t s);
+// quat: the comparison form with the quaternion + translation scan state
+hipError_t launch_bb_forward_scan(const a2c_plan &p, const float *ang, float *xyz, hipStream_t s,
+                                  bool quat = false);
 hipError_t launch_bb_backward_scan(const a2c_plan &p, const float *ang, const float *xyz,
                                    const float *g, float *gang, hipStream_t s);
 hipError_t launch_bb_forward_plain(const a2c_plan &p, const float *ang, float *xyz, float *ws,

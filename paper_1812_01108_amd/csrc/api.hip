@@ -622,7 +622,7 @@ a2c_status a2c_plan_keep_coords(const a2c_plan *p, int32_t *keep)
 a2c_status a2c_plan_workspace_bytes(const a2c_plan *p, int32_t v, size_t *bytes)
 {
     if (!p || !bytes) return fail(A2C_ERR_INVALID_ARG, "plan or bytes is NULL");
-    if (v == A2C_SCAN) *bytes = 0;
+    if (v == A2C_SCAN || v == A2C_SCAN_QUAT) *bytes = 0;
     else if (v == A2C_PLAIN) *bytes = (size_t)p->A * 12 * sizeof(float);
     else return fail(A2C_ERR_INVALID_ARG, "unknown variant");
     return A2C_OK;
@@ -678,9 +678,12 @@ a2c_status a2c_forward(a2c_plan *p, int32_t v, const float *d_angles, float *d_c
                        void *d_workspace, void *stream)
 {
     if (!p) return fail(A2C_ERR_INVALID_ARG, "plan is NULL");
-    if (v != A2C_SCAN && v != A2C_PLAIN) return fail(A2C_ERR_INVALID_ARG, "unknown variant");
+    if (v != A2C_SCAN && v != A2C_PLAIN && v != A2C_SCAN_QUAT)
+        return fail(A2C_ERR_INVALID_ARG, "unknown variant");
     if (v == A2C_PLAIN && p->model != A2C_BACKBONE)
         return fail(A2C_ERR_UNSUPPORTED, "the plain form is the backbone comparison only");
+    if (v == A2C_SCAN_QUAT && p->model != A2C_BACKBONE)
+        return fail(A2C_ERR_UNSUPPORTED, "the quaternion scan state is a backbone comparison only");
     if (p->R == 0) return A2C_OK;
     if (!d_angles || !d_coords) return fail(A2C_ERR_INVALID_ARG, "NULL angles or coords");
     if (v == A2C_PLAIN && !d_workspace)
@@ -689,7 +692,8 @@ a2c_status a2c_forward(a2c_plan *p, int32_t v, const float *d_angles, float *d_c
     hipStream_t s = (hipStream_t)stream;
     hipError_t e;
     if (v == A2C_PLAIN) e = launch_bb_forward_plain(*p, d_angles, d_coords, (float *)d_workspace, s);
-    else if (p->model == A2C_BACKBONE) e = launch_bb_forward_scan(*p, d_angles, d_coords, s);
+    else if (p->model == A2C_BACKBONE)
+        e = launch_bb_forward_scan(*p, d_angles, d_coords, s, v == A2C_SCAN_QUAT);
     else e = launch_fa_forward_scan(*p, d_angles, d_coords, s);
     if (e != hipSuccess) return hip_fail(e, "forward launch");
     return A2C_OK;
@@ -700,6 +704,8 @@ a2c_status a2c_backward(a2c_plan *p, int32_t v, const float *d_angles, const flo
                         void *stream)
 {
     if (!p) return fail(A2C_ERR_INVALID_ARG, "plan is NULL");
+    if (v == A2C_SCAN_QUAT)
+        return fail(A2C_ERR_UNSUPPORTED, "the quaternion scan state is a forward comparison only");
     if (v != A2C_SCAN && v != A2C_PLAIN) return fail(A2C_ERR_INVALID_ARG, "unknown variant");
     if (v == A2C_PLAIN && p->model != A2C_BACKBONE)
         return fail(A2C_ERR_UNSUPPORTED, "the plain form is the backbone comparison only");

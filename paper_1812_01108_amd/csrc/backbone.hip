@@ -237,7 +237,10 @@ __device__ __forceinline__ void load_angles(float *buf, const float *__restrict_
 //      composes the aggregates of the earlier tiles its first chain spans;
 //   4. each lane maps the positions before its first chain head through its
 //      exclusive prefix frame; LDS transpose, coalesced stores of x, y, z.
-template <int K, int LB>
+// QUAT: the comparison form with a unit quaternion + translation scan state
+// (Quat) in place of the 3x4 affine (lane aggregates converted after their
+// polar step).
+template <int K, int LB, bool QUAT = false>
 __global__ __launch_bounds__(LB, 4) void bb_forward_flat_kernel(
     const float *__restrict__ ang, float *__restrict__ xyz, const uint32_t *__restrict__ head_bits,
     const int32_t *__restrict__ look_first, uint64_t *__restrict__ status, int64_t R, BBParams P)
@@ -329,7 +332,12 @@ __global__ __launch_bounds__(LB, 4) void bb_forward_flat_kernel(
         aff_orthonormalise(m);
     }
     const uint64_t heads = __builtin_amdgcn_ballot_w64(first_head < K);
-    const Aff X = block_prefix_windows(m, heads, nact, active, sh, carry_sh, status, t, first, prev);
+    Aff X;
+    if constexpr (QUAT)
+        X = block_prefix_windows_quat(quat_from_aff(m), heads, nact, active, sh, carry_sh, status, t,
+                                      first, prev);
+    else
+        X = block_prefix_windows(m, heads, nact, active, sh, carry_sh, status, t, first, prev);
     if (!active) return;
 #pragma unroll
     for (int j = 0; j < K; ++j) {
@@ -687,22 +695,28 @@ __global__ __launch_bounds__(kPlainBlock) void bb_backward_plain_kernel(
     if (active) gang[(int64_t)slot_plane((int)(i % 3)) * R + r0 + i / 3] = acc;
 }
 
-template <int K, int LB>
+template <int K, int LB, bool QUAT>
 hipError_t fwd_kl(const a2c_plan &p, const float *ang, float *xyz, hipStream_t s)
 {
     const dim3 grid(p.fs.n_win), block(p.fs.W * kWave);
-    hipLaunchKernelGGL((bb_forward_flat_kernel<K, LB>), grid, block, stage_bytes<K>(p.fs.W), s, ang,
-                       xyz, p.d_head_bits, p.fs.d_look, p.fs.d_status, p.R, p.bb);
+    hipLaunchKernelGGL((bb_forward_flat_kernel<K, LB, QUAT>), grid, block, stage_bytes<K>(p.fs.W), s,
+                       ang, xyz, p.d_head_bits, p.fs.d_look, p.fs.d_status, p.R, p.bb);
     return hipGetLastError();
 }
 
-template <int K>
-hipError_t fwd_k(const a2c_plan &p, const float *ang, float *xyz, hipStream_t s)
+template <int K, bool QUAT>
+hipError_t fwd_kq(const a2c_plan &p, const float *ang, float *xyz, hipStream_t s)
 {
     const int threads = p.fs.W * kWave;
-    if (threads <= 256) return fwd_kl<K, 256>(p, ang, xyz, s);
-    if (threads <= kLbSmall) return fwd_kl<K, kLbSmall>(p, ang, xyz, s);
-    return fwd_kl<K, kLbLarge>(p, ang, xyz, s);
+    if (threads <= 256) return fwd_kl<K, 256, QUAT>(p, ang, xyz, s);
+    if (threads <= kLbSmall) return fwd_kl<K, kLbSmall, QUAT>(p, ang, xyz, s);
+    return fwd_kl<K, kLbLarge, QUAT>(p, ang, xyz, s);
+}
+
+template <int K>
+hipError_t fwd_k(const a2c_plan &p, const float *ang, float *xyz, hipStream_t s, bool quat)
+{
+    return quat ? fwd_kq<K, true>(p, ang, xyz, s) : fwd_kq<K, false>(p, ang, xyz, s);
 }
 
 template <int K, bool MULTI, int LB>
@@ -764,20 +778,23 @@ void bb_allow_large_lds()
     static bool done = false;
     if (done) return;
     for (const void *k : {(const void *)bb_forward_flat_kernel<8, kLbSmall>,
-                          (const void *)bb_forward_flat_kernel<8, kLbLarge>})
+                          (const void *)bb_forward_flat_kernel<8, kLbLarge>,
+                          (const void *)bb_forward_flat_kernel<8, kLbSmall, true>,
+                          (const void *)bb_forward_flat_kernel<8, kLbLarge, true>})
         (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)stage_bytes<8>(kMaxWaves));
     done = true;
 }
 
-hipError_t launch_bb_forward_scan(const a2c_plan &p, const float *ang, float *xyz, hipStream_t s)
+hipError_t launch_bb_forward_scan(const a2c_plan &p, const float *ang, float *xyz, hipStream_t s,
+                                  bool quat)
 {
     if (p.fs.n_win != p.fs.n_tiles || !p.fs.d_look) return hipErrorInvalidValue;
     switch (p.fs.K) {
-    case 1: return fwd_k<1>(p, ang, xyz, s);
-    case 2: return fwd_k<2>(p, ang, xyz, s);
-    case 4: return fwd_k<4>(p, ang, xyz, s);
-    case 8: return fwd_k<8>(p, ang, xyz, s);
+    case 1: return fwd_k<1>(p, ang, xyz, s, quat);
+    case 2: return fwd_k<2>(p, ang, xyz, s, quat);
+    case 4: return fwd_k<4>(p, ang, xyz, s, quat);
+    case 8: return fwd_k<8>(p, ang, xyz, s, quat);
     default: return hipErrorInvalidValue;
     }
 }

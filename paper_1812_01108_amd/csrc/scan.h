@@ -992,4 +992,239 @@ __device__ __forceinline__ void lb_loss_commit(float v, uint64_t *__restrict__ s
     if (lane == 0) *out = total;
 }
 
+
+// ------------------------------------------- quaternion scan state (variant)
+// The comparison form of the forward scan: a rigid transform held as a unit
+// quaternion q = (w, x, y, z) and a translation t (7 floats instead of 12),
+// composed as (qa, ta) . (qb, tb) = (qa qb, ta + rot(qa) tb).  Lane
+// aggregates (3x4, from the walk, after their polar step) are converted to it
+// and normalised, the scans and the window look-back run on it, and the
+// lane's prefix is converted back to a 3x4 to place its atoms.
+struct Quat {
+    float w, x, y, z, t0, t1, t2;
+};
+constexpr int kQuatWords = 7;
+
+__device__ __forceinline__ Quat quat_identity()
+{
+    Quat q;
+    q.w = 1.f; q.x = q.y = q.z = 0.f;
+    q.t0 = q.t1 = q.t2 = 0.f;
+    return q;
+}
+
+// rot(q) v = v + w c + u x c with c = 2 u x v, u = (x, y, z)
+__device__ __forceinline__ void quat_rotate(const Quat &q, float vx, float vy, float vz, float &ox,
+                                            float &oy, float &oz)
+{
+    const float cx = 2.f * fmaf(q.y, vz, -(q.z * vy));
+    const float cy = 2.f * fmaf(q.z, vx, -(q.x * vz));
+    const float cz = 2.f * fmaf(q.x, vy, -(q.y * vx));
+    ox = fmaf(q.w, cx, vx) + fmaf(q.y, cz, -(q.z * cy));
+    oy = fmaf(q.w, cy, vy) + fmaf(q.z, cx, -(q.x * cz));
+    oz = fmaf(q.w, cz, vz) + fmaf(q.x, cy, -(q.y * cx));
+}
+
+// a . b (a applied after b)
+__device__ __forceinline__ Quat quat_compose(const Quat &a, const Quat &b)
+{
+    Quat c;
+    c.w = fmaf(a.w, b.w, -fmaf(a.x, b.x, fmaf(a.y, b.y, a.z * b.z)));
+    c.x = fmaf(a.w, b.x, fmaf(a.x, b.w, fmaf(a.y, b.z, -(a.z * b.y))));
+    c.y = fmaf(a.w, b.y, fmaf(-a.x, b.z, fmaf(a.y, b.w, a.z * b.x)));
+    c.z = fmaf(a.w, b.z, fmaf(a.x, b.y, fmaf(-a.y, b.x, a.z * b.w)));
+    float rx, ry, rz;
+    quat_rotate(a, b.t0, b.t1, b.t2, rx, ry, rz);
+    c.t0 = a.t0 + rx; c.t1 = a.t1 + ry; c.t2 = a.t2 + rz;
+    return c;
+}
+
+__device__ __forceinline__ Quat quat_select(bool take_a, const Quat &a, const Quat &b)
+{
+    Quat o;
+    o.w = take_a ? a.w : b.w; o.x = take_a ? a.x : b.x; o.y = take_a ? a.y : b.y;
+    o.z = take_a ? a.z : b.z; o.t0 = take_a ? a.t0 : b.t0; o.t1 = take_a ? a.t1 : b.t1;
+    o.t2 = take_a ? a.t2 : b.t2;
+    return o;
+}
+
+template <int CTRL>
+__device__ __forceinline__ Quat quat_dpp_z(const Quat &a)
+{
+    Quat o;
+    o.w = dpp_z<CTRL>(a.w); o.x = dpp_z<CTRL>(a.x); o.y = dpp_z<CTRL>(a.y); o.z = dpp_z<CTRL>(a.z);
+    o.t0 = dpp_z<CTRL>(a.t0); o.t1 = dpp_z<CTRL>(a.t1); o.t2 = dpp_z<CTRL>(a.t2);
+    return o;
+}
+
+__device__ __forceinline__ Quat quat_readlane(const Quat &a, int l)
+{
+    Quat o;
+    o.w = lane_bcast(a.w, l); o.x = lane_bcast(a.x, l); o.y = lane_bcast(a.y, l);
+    o.z = lane_bcast(a.z, l); o.t0 = lane_bcast(a.t0, l); o.t1 = lane_bcast(a.t1, l);
+    o.t2 = lane_bcast(a.t2, l);
+    return o;
+}
+
+__device__ __forceinline__ void quat_store(float *d, const Quat &q)
+{
+    d[0] = q.w; d[1] = q.x; d[2] = q.y; d[3] = q.z; d[4] = q.t0; d[5] = q.t1; d[6] = q.t2;
+}
+
+__device__ __forceinline__ Quat quat_load(const float *s)
+{
+    Quat q;
+    q.w = s[0]; q.x = s[1]; q.y = s[2]; q.z = s[3]; q.t0 = s[4]; q.t1 = s[5]; q.t2 = s[6];
+    return q;
+}
+
+// Rotation part of a 3x4 to a unit quaternion by Shepperd's method (the
+// largest of 1 + trace and 1 + 2 r_kk - trace chooses the component taken from
+// the square root, the others from differences and sums of off-diagonal
+// entries), then normalised; the translation is copied.
+__device__ __forceinline__ Quat quat_from_aff(const Aff &m)
+{
+    const float d0 = 1.f + m.r00 + m.r11 + m.r22, d1 = 1.f + m.r00 - m.r11 - m.r22;
+    const float d2 = 1.f - m.r00 + m.r11 - m.r22, d3 = 1.f - m.r00 - m.r11 + m.r22;
+    const float a = m.r21 - m.r12, b = m.r02 - m.r20, c = m.r10 - m.r01;
+    const float p = m.r01 + m.r10, q = m.r02 + m.r20, r = m.r12 + m.r21;
+    float w, x, y, z;
+    if (d0 >= d1 && d0 >= d2 && d0 >= d3) {
+        const float s = 2.f * sqrtf(d0), inv = 1.f / s;
+        w = 0.25f * s; x = a * inv; y = b * inv; z = c * inv;
+    } else if (d1 >= d2 && d1 >= d3) {
+        const float s = 2.f * sqrtf(d1), inv = 1.f / s;
+        w = a * inv; x = 0.25f * s; y = p * inv; z = q * inv;
+    } else if (d2 >= d3) {
+        const float s = 2.f * sqrtf(d2), inv = 1.f / s;
+        w = b * inv; x = p * inv; y = 0.25f * s; z = r * inv;
+    } else {
+        const float s = 2.f * sqrtf(d3), inv = 1.f / s;
+        w = c * inv; x = q * inv; y = r * inv; z = 0.25f * s;
+    }
+    const float n = rsqrtf(fmaf(w, w, fmaf(x, x, fmaf(y, y, z * z))));
+    Quat o;
+    o.w = w * n; o.x = x * n; o.y = y * n; o.z = z * n;
+    o.t0 = m.t0; o.t1 = m.t1; o.t2 = m.t2;
+    return o;
+}
+
+__device__ __forceinline__ Aff aff_from_quat(const Quat &q)
+{
+    const float xx = q.x * q.x, yy = q.y * q.y, zz = q.z * q.z;
+    const float xy = q.x * q.y, xz = q.x * q.z, yz = q.y * q.z;
+    const float wx = q.w * q.x, wy = q.w * q.y, wz = q.w * q.z;
+    Aff m;
+    m.r00 = 1.f - 2.f * (yy + zz); m.r01 = 2.f * (xy - wz); m.r02 = 2.f * (xz + wy);
+    m.r10 = 2.f * (xy + wz); m.r11 = 1.f - 2.f * (xx + zz); m.r12 = 2.f * (yz - wx);
+    m.r20 = 2.f * (xz - wy); m.r21 = 2.f * (yz + wx); m.r22 = 1.f - 2.f * (xx + yy);
+    m.t0 = q.t0; m.t1 = q.t1; m.t2 = q.t2;
+    return m;
+}
+
+template <int CTRL>
+__device__ __forceinline__ void quat_scan_step(Quat &m, bool take)
+{
+    const Quat c = quat_compose(quat_dpp_z<CTRL>(m), m);
+    m = quat_select(take, c, m);
+}
+
+// as aff_wave_scan, on the quaternion state
+template <bool ROW0>
+__device__ __forceinline__ void quat_wave_scan(Quat &m, uint64_t heads, int n, int lane)
+{
+    const int s = last_head_upto(heads, lane);
+    const int row = lane & ~15;
+    const int dist = lane - max(s, row);
+    if (!ROW0 || n > 1) quat_scan_step<kDppRowShr + 1>(m, dist >= 1);
+    if (!ROW0 || n > 2) quat_scan_step<kDppRowShr + 2>(m, dist >= 2);
+    if (!ROW0 || n > 4) quat_scan_step<kDppRowShr + 4>(m, dist >= 4);
+    if (!ROW0 || n > 8) quat_scan_step<kDppRowShr + 8>(m, dist >= 8);
+    if (!ROW0) {
+        quat_scan_step<kDppBcast15>(m, (lane & 16) != 0 && s < row);
+        quat_scan_step<kDppBcast31>(m, lane >= 32 && s < 32);
+    }
+}
+
+__device__ __forceinline__ Quat lb_wait_quat(const uint64_t *w, uint32_t tag)
+{
+    float v[kQuatWords];
+    for (int spins = 0;; ++spins) {
+        bool ok = true;
+#pragma unroll
+        for (int k = 0; k < kQuatWords; ++k) {
+            const uint64_t x = lb_load(w + k);
+            ok = ok && (uint32_t)(x >> 32) == tag;
+            v[k] = __uint_as_float((uint32_t)x);
+        }
+        if (ok) break;
+        if (spins >= kLbSpinLimit) {
+#pragma unroll
+            for (int k = 0; k < kQuatWords; ++k) v[k] = __builtin_nanf("");
+            break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+    return quat_load(v);
+}
+
+// block_prefix_windows on the quaternion state; the lane's prefix returned
+// as a 3x4.
+__device__ __forceinline__ Aff block_prefix_windows_quat(Quat m, uint64_t heads, int nact,
+                                                         bool active, FwdShared &sh,
+                                                         float (&carry_sh)[12],
+                                                         uint64_t *__restrict__ status, int64_t t,
+                                                         int64_t first, uint64_t prev)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (active) {
+        quat_wave_scan<false>(m, heads, kWave, lane);
+        if (lane == kWave - 1) {
+            quat_store(sh.tot[wave], m);
+            sh.tot_flag[wave] = heads != 0ull ? 1 : 0;
+        }
+    }
+    __syncthreads();
+    if (wave == 0) {
+        Quat tw = quat_identity();
+        bool tf = false;
+        if (lane < nact) {
+            tw = quat_load(sh.tot[lane]);
+            tf = sh.tot_flag[lane] != 0;
+        }
+        const uint64_t th = __builtin_amdgcn_ballot_w64(tf);
+        quat_wave_scan<true>(tw, th, nact, lane);
+        if (lane < nact) {
+            quat_store(sh.pre[lane], tw);
+            sh.pre_flag[lane] = (th & lanes_upto(lane)) != 0ull ? 1 : 0;
+        }
+        wave_lds_sync();
+        const uint32_t tag = (uint32_t)(__builtin_amdgcn_readfirstlane((uint32_t)(prev >> 32))) + 1u;
+        if (lane < kQuatWords) lb_store(status + t * kLbWords + lane, tag, sh.pre[nact - 1][lane]);
+        const int64_t f = (int64_t)__builtin_amdgcn_readfirstlane((int)first);
+        Quat carry = quat_identity();
+        for (int64_t b = f; b < t; b += kWave) {
+            const int n = (int)min((int64_t)kWave, t - b);
+            Quat a = quat_identity();
+            if (lane < n) a = lb_wait_quat(status + (b + lane) * kLbWords, tag);
+            if (n > 1) quat_wave_scan<false>(a, 1ull, kWave, lane);
+            carry = quat_compose(carry, quat_readlane(a, n - 1));
+        }
+        if (lane == 0) quat_store(carry_sh, carry);
+    }
+    __syncthreads();
+    if (!active) return aff_identity();
+    const Quat carry = quat_load(carry_sh);
+    Quat cw = carry;
+    if (wave > 0) {
+        const Quat p = quat_load(sh.pre[wave - 1]);
+        cw = sh.pre_flag[wave - 1] != 0 ? p : quat_compose(carry, p);
+    }
+    Quat e = quat_dpp_z<kDppWaveShr1>(m);
+    if (lane == 0) e = quat_identity();
+    const bool fe = (heads & lanes_below(lane)) != 0ull;
+    return aff_from_quat(fe ? e : quat_compose(cw, e));
+}
+
 }  // namespace a2c
