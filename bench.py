@@ -265,6 +265,11 @@ def kernel_source_sha(model):
     return h.hexdigest()[:16]
 
 
+def profile_key(kernel_key, schedule):
+    """Key of a committed counter record: workload:kernel@K,W."""
+    return f"{kernel_key}@{schedule[0]},{schedule[1]}"
+
+
 def traffic_from_profiles(kernel_key, model, n_units, schedule):
     """HBM bytes per launch from committed rocprofv3 counter summaries, valid
     only while the kernel source they were taken from is unchanged and for
@@ -273,7 +278,7 @@ def traffic_from_profiles(kernel_key, model, n_units, schedule):
     if not os.path.exists(path):
         return None
     try:
-        rec = json.load(open(path)).get(kernel_key)
+        rec = json.load(open(path)).get(profile_key(kernel_key, schedule))
         sha = kernel_source_sha(model)
         if (not rec or rec.get("source_sha") != sha or rec.get("units") != n_units
                 or rec.get("schedule") != list(schedule)):
@@ -297,7 +302,7 @@ def valu_issue_from_profiles(kernel_key, model, schedule, kernel_us):
     if not os.path.exists(path):
         return None
     try:
-        rec = json.load(open(path)).get(kernel_key)
+        rec = json.load(open(path)).get(profile_key(kernel_key, schedule))
         if (not rec or rec.get("source_sha") != kernel_source_sha(model)
                 or rec.get("schedule") != list(schedule)):
             return None

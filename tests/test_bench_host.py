@@ -67,7 +67,9 @@ def test_inverse_map_bytes():
 
 def test_traffic_only_for_the_profiled_sources_and_schedule():
     rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
-    key, r = next(iter(rec.items()))
+    full_key, r = next(iter(rec.items()))
+    key = full_key.split("@")[0]   # records are keyed workload:kernel@K,W
+    assert full_key == bench.profile_key(key, r["schedule"])
     model = "fullatom" if "fullatom" in key else "backbone"
     got = bench.traffic_from_profiles(key, model, r["units"], tuple(r["schedule"]))
     if r["source_sha"] == bench.kernel_source_sha(model):
@@ -82,14 +84,16 @@ def test_traffic_only_for_the_profiled_sources_and_schedule():
 
 def test_valu_issue_only_for_the_profiled_sources_and_schedule():
     rec = json.load(open(os.path.join(ROOT, "profiles", "valu.json")))
-    key, r = next(iter(rec.items()))
-    got = bench.valu_issue_from_profiles(key, "backbone", tuple(r["schedule"]), 10.0)
-    if r["source_sha"] == bench.kernel_source_sha("backbone"):
+    full_key, r = next(iter(rec.items()))
+    key = full_key.split("@")[0]
+    model = "fullatom" if "fullatom" in key else "backbone"
+    got = bench.valu_issue_from_profiles(key, model, tuple(r["schedule"]), 10.0)
+    if r["source_sha"] == bench.kernel_source_sha(model):
         issue_us = r["waves"] * r["valu_per_wave"] * 4 / (1024 * 2400.0)
         assert got["issue_us"] == round(issue_us, 3)
         assert got["frac"] == round(issue_us / 10.0, 4)
     else:
         assert got is None
     K, W = r["schedule"]
-    assert bench.valu_issue_from_profiles(key, "backbone", (K, W + 1), 10.0) is None
-    assert bench.valu_issue_from_profiles("no_such_workload:forward", "backbone", (K, W), 10.0) is None
+    assert bench.valu_issue_from_profiles(key, model, (K, W + 1), 10.0) is None
+    assert bench.valu_issue_from_profiles("no_such_workload:forward", model, (K, W), 10.0) is None
