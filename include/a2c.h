@@ -206,22 +206,29 @@ a2c_status a2c_plan_workspace_bytes(const a2c_plan *plan, int32_t variant,
 /* Scan schedule: residues per lane (1, 2 or 4 for A2C_BACKBONE; 1 or 2 for
  * A2C_FULLATOM) and waves of 64 lanes per workgroup (1..16).  A chunk is
  * 64 * waves * res_per_lane consecutive residues.
- *   - The backbone forward (a2c_forward, A2C_SCAN) and the backbone adjoint
- *     from coordinates (a2c_backward with d_coords) run on fixed windows:
- *     workgroup t takes residues [t C, t C + C) of the packed batch, C one
- *     chunk, whatever the chain boundaries.  A chain entering a window from
- *     earlier ones gets its frame from those windows' aggregates (forward),
- *     and a chain running on into later windows gets their wrench sums
- *     (adjoint); every workgroup publishes its own in plan-owned device
- *     memory before it reads any (window look-back), and only waits on
- *     workgroups that were started before it (the adjoint takes the windows
- *     last to first).  Consequently two such calls on one plan must not run
- *     at the same time (on different streams).
- *   - Every other kernel packs chains of at most one chunk whole, in order,
- *     into tiles of at most one chunk; a longer chain gets a tile of its own,
- *     which one workgroup walks chunk by chunk (at most 64 chunks), carrying
- *     the frame (forward) and the wrench (adjoint) from chunk to chunk.  One
- *     workgroup per tile, longest tiles dispatched first.
+ *   - The forwards of both models (a2c_forward, A2C_SCAN), the backbone
+ *     adjoint from coordinates (a2c_backward with d_coords) and every
+ *     full-atom adjoint (a2c_backward, a2c_mse_step) run on windows:
+ *     workgroup t takes residues [s_t, s_t+1) of the packed batch, at most
+ *     one chunk C.  Where every chain fits in one chunk, the windows hold
+ *     whole chains, packed in order; otherwise they are fixed,
+ *     [t C, t C + C), whatever the chain boundaries.  A chain entering a
+ *     window from earlier ones gets its frame from those windows' aggregates
+ *     (forward), and a chain running on into later windows gets their
+ *     wrench sums (adjoint); every workgroup publishes its own in plan-owned
+ *     device memory before it reads any (window look-back), and only waits
+ *     on workgroups that were started before it (the adjoints take the
+ *     windows last to first; the full-atom ones that recompute the frames
+ *     first run a spine-only pass over the same windows, which waits on
+ *     nothing).  Consequently two such calls on one plan must not run at the
+ *     same time (on different streams).
+ *   - The backbone adjoint that recomputes the frames (a2c_backward without
+ *     d_coords) and the backbone a2c_mse_step pack chains of at most one
+ *     chunk whole, in order, into tiles of at most one chunk; a longer chain
+ *     gets a tile of its own, which one workgroup walks chunk by chunk (at
+ *     most 64 chunks), carrying the frame (forward) and the wrench (adjoint)
+ *     from chunk to chunk.  One workgroup per tile, longest tiles dispatched
+ *     first.
  * Re-packs and re-uploads the tables (synchronises `stream`).
  * The tables of the schedule it replaces stay allocated until
  * a2c_plan_destroy, so a graph captured before the change replays the

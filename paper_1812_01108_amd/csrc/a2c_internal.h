@@ -68,14 +68,16 @@ struct FATable {
 // One scan schedule: K residues per lane, W waves per workgroup, and the
 // layouts built for them: tiles (chains of at most one chunk of 64 W K
 // residues packed whole into tiles of at most one chunk; a longer chain
-// alone) and/or fixed windows [t C, t C + C) of one chunk C with a look-back
-// table (forwards and the full-atom adjoint: windows only; backbone adjoint:
-// both, windows for the adjoint from coordinates, tiles for the recomputing
-// adjoint and the fused step).  n_tiles counts the layout the schedule
-// reports: windows where there are no tiles.
+// alone) and/or windows of at most one chunk C with a look-back table
+// (forwards and the full-atom adjoint: windows only; backbone adjoint: both,
+// windows for the adjoint from coordinates, tiles for the recomputing
+// adjoint and the fused step).  Windows hold whole chains where every chain
+// fits in one, and are fixed, [t C, t C + C), otherwise.  n_tiles counts the
+// layout the schedule reports: windows where there are no tiles.
 struct Sched {
     int32_t K = 4, W = 4, n_tiles = 0;
-    int32_t n_win = 0;                   // fixed windows (0: none)
+    int32_t n_win = 0;                   // windows (0: none)
+    int32_t *d_wstart = nullptr;         // n_win + 1 window boundaries (residues)
     int32_t *d_look = nullptr;           // n_win: forward, the first window whose
                                          // aggregate window t composes; adjoint, the
                                          // last window whose wrench it adds (t: none)

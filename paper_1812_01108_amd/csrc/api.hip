@@ -44,6 +44,7 @@ void free_sched(Sched &S)
     (void)hipFree(S.d_tile_res);
     (void)hipFree(S.d_loss_part);
     (void)hipFree(S.d_loss_count);
+    (void)hipFree(S.d_wstart);
     (void)hipFree(S.d_look);
     (void)hipFree(S.d_status);
     (void)hipFree(S.d_look_fwd);
@@ -51,28 +52,70 @@ void free_sched(Sched &S)
     S.d_tile_res = nullptr;
     S.d_loss_part = nullptr;
     S.d_loss_count = nullptr;
+    S.d_wstart = nullptr;
     S.d_look = nullptr;
     S.d_status = nullptr;
     S.d_look_fwd = nullptr;
     S.d_status_fwd = nullptr;
 }
 
-// Fixed windows of `cap` residues.  Forward (look_back): for each window t
-// the first window whose aggregate its carry-in needs, i.e. the window
-// holding the head of the chain that residue t * cap belongs to (t itself
-// when a chain starts there).  Adjoint: the last window whose wrench it adds,
-// i.e. the window holding the end of the chain of its last residue (t itself
-// when a chain ends there).  The tagged words start at tag 0.
-a2c_status build_windows(const a2c_plan *p, int64_t cap, bool look_back, int32_t *&d_look,
-                         uint64_t *&d_status, int32_t &n_win, hipStream_t s)
+// Window boundaries for windows of at most `cap` residues (n_win + 1
+// entries; none for an empty batch).  Where every chain fits in a window and
+// packing whole chains greedily, in order, takes at most 1/8 more windows
+// than cutting the batch into fixed windows [t cap, t cap + cap), the
+// windows hold whole chains: no chain crosses a window edge and no window
+// waits on another.  Otherwise the fixed windows, wherever the chains fall.
+// Zero-length chains take no space.
+std::vector<int64_t> window_starts(const a2c_plan *p, int64_t cap)
 {
-    const int64_t n = (p->R + cap - 1) / cap;
+    std::vector<int64_t> st;
+    if (p->R == 0) return st;
+    const int64_t n_fixed = (p->R + cap - 1) / cap;
+    if (p->max_len <= cap) {
+        st.push_back(0);
+        int64_t cur = 0;  // residues in the open window
+        for (size_t c = 0; c + 1 < p->res_off.size(); ++c) {
+            const int64_t L = p->res_off[c + 1] - p->res_off[c];
+            if (L == 0) continue;
+            if (cur + L > cap) {
+                st.push_back(p->res_off[c]);
+                cur = 0;
+            }
+            cur += L;
+        }
+        st.push_back(p->R);
+        if ((int64_t)st.size() - 1 <= n_fixed + n_fixed / 8) return st;
+        st.clear();
+    }
+    for (int64_t b = 0; b < p->R; b += cap) st.push_back(b);
+    st.push_back(p->R);
+    return st;
+}
+
+// The window holding residue r (starts as from window_starts).
+int32_t window_of(const std::vector<int64_t> &starts, int64_t r)
+{
+    return (int32_t)(std::upper_bound(starts.begin(), starts.end() - 1, r) - starts.begin()) - 1;
+}
+
+// Look-back table and tagged words of the windows given by starts.  Forward
+// (look_back): for each window t the first window whose aggregate its
+// carry-in needs, i.e. the window holding the head of the chain its first
+// residue belongs to (t itself when a chain starts there).  Adjoint: the last
+// window whose wrench it adds, i.e. the window holding the end of the chain
+// of its last residue (t itself when a chain ends there).  The tagged words
+// start at tag 0.
+a2c_status build_windows(const a2c_plan *p, const std::vector<int64_t> &starts, bool look_back,
+                         int32_t *&d_look, uint64_t *&d_status, int32_t &n_win, hipStream_t s)
+{
+    const int64_t n = starts.empty() ? 0 : (int64_t)starts.size() - 1;
     std::vector<int32_t> look((size_t)n);
     size_t c = 0;  // non-empty chain holding the residue: res_off[c] <= r < res_off[c + 1]
     for (int64_t t = 0; t < n; ++t) {
-        const int64_t r = look_back ? t * cap : std::min<int64_t>(t * cap + cap, p->R) - 1;
+        const int64_t r = look_back ? starts[(size_t)t] : starts[(size_t)t + 1] - 1;
         while (p->res_off[c + 1] <= r) ++c;
-        look[(size_t)t] = (int32_t)(look_back ? p->res_off[c] / cap : (p->res_off[c + 1] - 1) / cap);
+        look[(size_t)t] =
+            window_of(starts, look_back ? p->res_off[c] : (int64_t)p->res_off[c + 1] - 1);
     }
     n_win = (int32_t)n;
     a2c_status st = upload((void **)&d_look, look.data(), look.size() * sizeof(int32_t), s);
@@ -82,6 +125,13 @@ a2c_status build_windows(const a2c_plan *p, int64_t cap, bool look_back, int32_t
     if (e == hipSuccess) e = hipMemsetAsync(d_status, 0, words, s);
     if (e != hipSuccess) return hip_fail(e, "look-back words");
     return A2C_OK;
+}
+
+// The window boundaries as int32 on the device.
+a2c_status upload_starts(const std::vector<int64_t> &starts, int32_t *&d_wstart, hipStream_t s)
+{
+    std::vector<int32_t> v(starts.begin(), starts.end());
+    return upload((void **)&d_wstart, v.data(), v.size() * sizeof(int32_t), s);
 }
 
 // Pack the tiles of schedule (K, W) and upload its tile table into out
@@ -128,6 +178,7 @@ a2c_status build_sched(const a2c_plan *p, int32_t K, int32_t W, Sched &out, hipS
                                              " residues needs more than " +
                                              std::to_string(kMaxChunks) + " chunks of " +
                                              std::to_string(cap) + " residues");
+    const std::vector<int64_t> starts = windows ? window_starts(p, cap) : std::vector<int64_t>();
     if (flat) {
         Sched S;
         S.K = K;
@@ -137,24 +188,26 @@ a2c_status build_sched(const a2c_plan *p, int32_t K, int32_t W, Sched &out, hipS
             // coordinates stages six where they fit): the most atoms of one
             // wave's run of 64 K residues
             int64_t most = 1;
-            for (int64_t rb = 0; rb < p->R; rb += (int64_t)kWave * K) {
-                const int64_t re = std::min<int64_t>(rb + (int64_t)kWave * K, p->R);
-                most = std::max<int64_t>(most, p->res_atom_off[re] - p->res_atom_off[rb]);
-            }
+            for (size_t t = 0; t + 1 < starts.size(); ++t)
+                for (int64_t rb = starts[t]; rb < starts[t + 1]; rb += (int64_t)kWave * K) {
+                    const int64_t re = std::min<int64_t>(rb + (int64_t)kWave * K, starts[t + 1]);
+                    most = std::max<int64_t>(most, p->res_atom_off[re] - p->res_atom_off[rb]);
+                }
             if ((size_t)W * 3 * most * sizeof(float) > (size_t)kMaxDynamicLds)
                 S.fa_unstaged = true;  // atoms straight to global memory
             else
                 S.fa_stage_atoms = (int32_t)most;
         }
         const bool fwd = role == kRoleForward;
-        a2c_status st = build_windows(p, cap, fwd, S.d_look, S.d_status, S.n_win, s);
+        a2c_status st = upload_starts(starts, S.d_wstart, s);
+        if (st == A2C_OK) st = build_windows(p, starts, fwd, S.d_look, S.d_status, S.n_win, s);
         S.n_tiles = S.n_win;
         if (st == A2C_OK && !fwd) {
             // the full-atom adjoint: the spine pass's words and the windows
             // whose aggregates each window composes (the fused step's loss
             // shares travel in the adjoint's own tagged words)
             int32_t n2 = 0;
-            st = build_windows(p, cap, true, S.d_look_fwd, S.d_status_fwd, n2, s);
+            st = build_windows(p, starts, true, S.d_look_fwd, S.d_status_fwd, n2, s);
         }
         if (st == A2C_OK) {
             const hipError_t e = hipStreamSynchronize(s);
@@ -217,7 +270,8 @@ a2c_status build_sched(const a2c_plan *p, int32_t K, int32_t W, Sched &out, hipS
         pairs[2 * t + 1] = tiles[order[t] + 1];
     }
     a2c_status st = upload((void **)&S.d_tile_res, pairs.data(), pairs.size() * sizeof(int32_t), s);
-    if (st == A2C_OK && windows) st = build_windows(p, cap, false, S.d_look, S.d_status, S.n_win, s);
+    if (st == A2C_OK && windows) st = upload_starts(starts, S.d_wstart, s);
+    if (st == A2C_OK && windows) st = build_windows(p, starts, false, S.d_look, S.d_status, S.n_win, s);
     // the fused step's per-tile loss shares and its count of finished tiles
     // (zero: the last tile of every launch sets it back to zero)
     if (st == A2C_OK) {
@@ -244,12 +298,13 @@ a2c_status build_sched(const a2c_plan *p, int32_t K, int32_t W, Sched &out, hipS
 void retire_sched(a2c_plan *p, Sched &S)
 {
     for (void *q : {(void *)S.d_tile_res, (void *)S.d_loss_part, (void *)S.d_loss_count,
-                    (void *)S.d_look, (void *)S.d_status, (void *)S.d_look_fwd,
-                    (void *)S.d_status_fwd})
+                    (void *)S.d_wstart, (void *)S.d_look, (void *)S.d_status,
+                    (void *)S.d_look_fwd, (void *)S.d_status_fwd})
         if (q) p->retired.push_back(q);
     S.d_tile_res = nullptr;
     S.d_loss_part = nullptr;
     S.d_loss_count = nullptr;
+    S.d_wstart = nullptr;
     S.d_look = nullptr;
     S.d_status = nullptr;
     S.d_look_fwd = nullptr;

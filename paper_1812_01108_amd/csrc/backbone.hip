@@ -224,11 +224,13 @@ __device__ __forceinline__ void load_angles(float *buf, const float *__restrict_
     to_blocked<K>(buf, v2, nres, om);
 }
 
-// Forward over fixed windows of the packed batch: tile t covers residues
-// [t C, t C + C), C = 64 W K, whatever the chains; lane l of wave w owns K
-// consecutive residues.  A chain that enters the tile from an earlier one
-// gets its frame from those tiles' published aggregates (window look-back);
-// every lane holds K residues except in the batch's last wave.
+// Forward over windows of the packed batch: window t covers residues
+// [wstart[t], wstart[t + 1]), at most C = 64 W K of them (fixed windows
+// [t C, t C + C) whatever the chains, or whole chains where every chain
+// fits in one); lane l of wave w owns K consecutive residues.  A chain that
+// enters the window from an earlier one gets its frame from those windows'
+// published aggregates (window look-back); every lane holds K residues
+// except in a window's last wave.
 //   1. angles: coalesced loads of the three planes, LDS transpose to lanes;
 //   2. per lane: sincos, walk from the identity over its 3K transforms
 //      (restarting at chain heads), local positions, one polar step;
@@ -243,7 +245,8 @@ __device__ __forceinline__ void load_angles(float *buf, const float *__restrict_
 template <int K, int LB, bool QUAT = false>
 __global__ __launch_bounds__(LB, 4) void bb_forward_flat_kernel(
     const float *__restrict__ ang, float *__restrict__ xyz, const uint32_t *__restrict__ head_bits,
-    const int32_t *__restrict__ look_first, uint64_t *__restrict__ status, int64_t R, BBParams P)
+    const int32_t *__restrict__ wstart, const int32_t *__restrict__ look_first,
+    uint64_t *__restrict__ status, int64_t R, BBParams P)
 {
     extern __shared__ float stage_mem[];
     __shared__ FwdShared sh;
@@ -251,9 +254,8 @@ __global__ __launch_bounds__(LB, 4) void bb_forward_flat_kernel(
     constexpr int RUN = kWave * K;  // residues per wave
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int nw = blockDim.x >> 6;
     const int64_t t = blockIdx.x;
-    const int64_t ts = t * RUN * nw, te = min(ts + (int64_t)RUN * nw, R);
+    const int64_t ts = wstart[t], te = wstart[t + 1];
     const int nact = (int)((te - ts + RUN - 1) / RUN);
     const int64_t rbase = ts + (int64_t)wave * RUN;
     const int nres = (int)max((int64_t)0, min((int64_t)RUN, te - rbase));
@@ -469,8 +471,8 @@ __global__ __launch_bounds__(LB) void bb_backward_recompute_kernel(
     }
 }
 
-// Adjoint from the coordinates the forward produced, over fixed windows of
-// the packed batch (as the forward), last window first.  A window publishes
+// Adjoint from the coordinates the forward produced, over windows of the
+// packed batch (as the forward), last window first.  A window publishes
 // the wrench sum from its start up to its first chain end, then adds those of
 // the later windows its last chain runs into (window look-back; a window only
 // waits on later windows, which start no later than it does).
@@ -484,8 +486,8 @@ __global__ __launch_bounds__(LB) void bb_backward_recompute_kernel(
 template <int K, int LB>
 __global__ __launch_bounds__(LB) void bb_backward_coords_flat_kernel(
     const float *__restrict__ xyz, const float *__restrict__ g, float *__restrict__ gang,
-    const uint32_t *__restrict__ head_bits, const int32_t *__restrict__ look_last,
-    uint64_t *__restrict__ status, int64_t R, BBParams P)
+    const uint32_t *__restrict__ head_bits, const int32_t *__restrict__ wstart,
+    const int32_t *__restrict__ look_last, uint64_t *__restrict__ status, int64_t R, BBParams P)
 {
     extern __shared__ float stage_mem[];
     __shared__ BwdShared sh;
@@ -493,9 +495,8 @@ __global__ __launch_bounds__(LB) void bb_backward_coords_flat_kernel(
     constexpr int RUN = kWave * K;  // residues per wave
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int nw = blockDim.x >> 6;
     const int64_t t = (int64_t)gridDim.x - 1 - blockIdx.x;  // last window first
-    const int64_t ts = t * RUN * nw, te = min(ts + (int64_t)RUN * nw, R);
+    const int64_t ts = wstart[t], te = wstart[t + 1];
     const int nact = (int)((te - ts + RUN - 1) / RUN);
     const int64_t rbase = ts + (int64_t)wave * RUN;
     const int nres = (int)max((int64_t)0, min((int64_t)RUN, te - rbase));
@@ -700,7 +701,8 @@ hipError_t fwd_kl(const a2c_plan &p, const float *ang, float *xyz, hipStream_t s
 {
     const dim3 grid(p.fs.n_win), block(p.fs.W * kWave);
     hipLaunchKernelGGL((bb_forward_flat_kernel<K, LB, QUAT>), grid, block, stage_bytes<K>(p.fs.W), s,
-                       ang, xyz, p.d_head_bits, p.fs.d_look, p.fs.d_status, p.R, p.bb);
+                       ang, xyz, p.d_head_bits, p.fs.d_wstart, p.fs.d_look, p.fs.d_status, p.R,
+                       p.bb);
     return hipGetLastError();
 }
 
@@ -727,7 +729,8 @@ hipError_t bwd_kml(const a2c_plan &p, const float *ang, const float *xyz, const 
     const size_t lds = stage_bytes<K>(p.bs.W);
     if (xyz)
         hipLaunchKernelGGL((bb_backward_coords_flat_kernel<K, LB>), dim3(p.bs.n_win), block, lds, s,
-                           xyz, g, gang, p.d_head_bits, p.bs.d_look, p.bs.d_status, p.R, p.bb);
+                           xyz, g, gang, p.d_head_bits, p.bs.d_wstart, p.bs.d_look, p.bs.d_status,
+                           p.R, p.bb);
     else
         hipLaunchKernelGGL((bb_backward_recompute_kernel<K, MULTI, LB, kGradLoad>), grid, block,
                            lds, s, ang, g, gang, nullptr, nullptr, nullptr, nullptr,

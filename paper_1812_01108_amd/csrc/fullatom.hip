@@ -580,8 +580,8 @@ __device__ __forceinline__ void fa_emit_residue(const FATable &tab, const FAType
     emit_frame(tab, ft, 2, cur, sg, aloc);
 }
 
-// Forward over fixed windows of the packed batch (window t: residues
-// [t C, t C + C), C = 64 W K, whatever the chains), as the backbone forward:
+// Forward over windows of the packed batch (window t: residues
+// [wstart[t], wstart[t + 1]), at most C = 64 W K), as the backbone forward:
 // the spine scan hands frames across window edges by window look-back; then
 // every lane re-walks its residues from its prefix frame, building the spine
 // and side frames and writing each atom into the wave's LDS stage, which is
@@ -590,8 +590,9 @@ __device__ __forceinline__ void fa_emit_residue(const FATable &tab, const FAType
 template <int K, int LB, bool STG = true>
 __global__ __launch_bounds__(LB) void fa_forward_flat_kernel(
     const float *__restrict__ ang, float *__restrict__ xyz, const uint32_t *__restrict__ head_bits,
-    const int32_t *__restrict__ res_aoff, const uint8_t *__restrict__ seq,
-    const FATable *__restrict__ gtab, const int32_t *__restrict__ look_first,
+    const int32_t *__restrict__ wstart, const int32_t *__restrict__ res_aoff,
+    const uint8_t *__restrict__ seq, const FATable *__restrict__ gtab,
+    const int32_t *__restrict__ look_first,
     uint64_t *__restrict__ status, int64_t R, int64_t A, BBParams P, int stage_atoms)
 {
     extern __shared__ float stage_mem[];
@@ -599,11 +600,10 @@ __global__ __launch_bounds__(LB) void fa_forward_flat_kernel(
     __shared__ FwdShared sh;
     __shared__ float carry_sh[12];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int nw = blockDim.x >> 6;
     const int64_t t = blockIdx.x;
     FAChunk k;
-    k.cs = t * kWave * K * nw;
-    k.ce = min(k.cs + (int64_t)kWave * K * nw, R);
+    k.cs = wstart[t];
+    k.ce = wstart[t + 1];
     k.nact = (int)((k.ce - k.cs + kWave * K - 1) / (kWave * K));
     const LaneRun<K> L = lane_run<K>(k, head_bits, res_aoff);
     uint64_t prev = 0;
@@ -713,16 +713,15 @@ __device__ __forceinline__ void fa_store_grads(float *__restrict__ gang, int64_t
 template <int K, int LB>
 __global__ __launch_bounds__(LB) void fa_spine_aggregate_kernel(
     const float *__restrict__ ang, const uint32_t *__restrict__ head_bits,
-    uint64_t *__restrict__ status, int64_t R, BBParams P)
+    const int32_t *__restrict__ wstart, uint64_t *__restrict__ status, int64_t R, BBParams P)
 {
     __shared__ FwdShared sh;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int nw = blockDim.x >> 6;
     const int64_t t = blockIdx.x;
     FAChunk k;
-    k.cs = t * kWave * K * nw;
-    k.ce = min(k.cs + (int64_t)kWave * K * nw, R);
+    k.cs = wstart[t];
+    k.ce = wstart[t + 1];
     k.nact = (int)((k.ce - k.cs + kWave * K - 1) / (kWave * K));
     const bool active = wave < k.nact;
     const int64_t rs = k.cs + (int64_t)threadIdx.x * K;
@@ -759,7 +758,7 @@ __global__ __launch_bounds__(LB) void fa_spine_aggregate_kernel(
     if (lane < kLbWords) lb_store(status + t * kLbWords + lane, tag, sh.pre[0][lane]);
 }
 
-// Backward over fixed windows of the packed batch, last window first: the
+// Backward over windows of the packed batch, last window first: the
 // side chains' subtree sums give the chi gradients, the spine groups feed a
 // reverse scan over residues (window look-back for the wrench of later
 // windows), and u . (S_m - o x S_g) gives phi, psi, omega.
@@ -777,9 +776,10 @@ template <int K, bool RECOMPUTE, int LB, int GM = kGradLoad, bool STG = true>
 __global__ __launch_bounds__(LB) void fa_backward_flat_kernel(
     const float *__restrict__ ang, const float *__restrict__ xyz, const float *__restrict__ g,
     float *__restrict__ gang, float *__restrict__ xyz_out, float *__restrict__ loss_out,
-    const uint32_t *__restrict__ head_bits, const int32_t *__restrict__ res_aoff,
-    const uint8_t *__restrict__ seq, const FATable *__restrict__ gtab,
-    const uint64_t *__restrict__ status_fwd, const int32_t *__restrict__ look_fwd,
+    const uint32_t *__restrict__ head_bits, const int32_t *__restrict__ wstart,
+    const int32_t *__restrict__ res_aoff, const uint8_t *__restrict__ seq,
+    const FATable *__restrict__ gtab, const uint64_t *__restrict__ status_fwd,
+    const int32_t *__restrict__ look_fwd,
     const int32_t *__restrict__ look_last, uint64_t *__restrict__ status, int64_t R, int64_t A,
     BBParams P, int stage_atoms)
 {
@@ -793,11 +793,10 @@ __global__ __launch_bounds__(LB) void fa_backward_flat_kernel(
     float loss = 0.f;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int nw = blockDim.x >> 6;
     const int64_t t = (int64_t)gridDim.x - 1 - blockIdx.x;  // last window first
     FAChunk k;
-    k.cs = t * kWave * K * nw;
-    k.ce = min(k.cs + (int64_t)kWave * K * nw, R);
+    k.cs = wstart[t];
+    k.ce = wstart[t + 1];
     k.nact = (int)((k.ce - k.cs + kWave * K - 1) / (kWave * K));
     const LaneRun<K> L = lane_run<K>(k, head_bits, res_aoff);
     uint64_t prev = 0;
@@ -998,8 +997,8 @@ hipError_t fa_fwd_kl(const a2c_plan &p, const float *ang, float *xyz, hipStream_
 {
     const size_t lds = STG ? (size_t)p.fs.W * 3 * p.fs.fa_stage_atoms * sizeof(float) : 0;
     hipLaunchKernelGGL((fa_forward_flat_kernel<K, LB, STG>), dim3(p.fs.n_win), dim3(p.fs.W * kWave),
-                       lds, s, ang, xyz, p.d_head_bits, p.d_res_atom_off, p.d_seq, p.d_fa,
-                       p.fs.d_look, p.fs.d_status, p.R, p.A, p.bb, p.fs.fa_stage_atoms);
+                       lds, s, ang, xyz, p.d_head_bits, p.fs.d_wstart, p.d_res_atom_off, p.d_seq,
+                       p.d_fa, p.fs.d_look, p.fs.d_status, p.R, p.A, p.bb, p.fs.fa_stage_atoms);
     return hipGetLastError();
 }
 
@@ -1030,13 +1029,13 @@ void fa_spine_launch(const a2c_plan &p, const float *ang, hipStream_t s)
     const dim3 grid(p.bs.n_win);
     if (C % (kWave * 8) == 0)
         hipLaunchKernelGGL((fa_spine_aggregate_kernel<8, 1024>), grid, dim3(C / 8), 0, s, ang,
-                           p.d_head_bits, p.bs.d_status_fwd, p.R, p.bb);
+                           p.d_head_bits, p.bs.d_wstart, p.bs.d_status_fwd, p.R, p.bb);
     else if (C % (kWave * 4) == 0)
         hipLaunchKernelGGL((fa_spine_aggregate_kernel<4, 1024>), grid, dim3(C / 4), 0, s, ang,
-                           p.d_head_bits, p.bs.d_status_fwd, p.R, p.bb);
+                           p.d_head_bits, p.bs.d_wstart, p.bs.d_status_fwd, p.R, p.bb);
     else
         hipLaunchKernelGGL((fa_spine_aggregate_kernel<K, 1024>), grid, dim3(C / K), 0, s, ang,
-                           p.d_head_bits, p.bs.d_status_fwd, p.R, p.bb);
+                           p.d_head_bits, p.bs.d_wstart, p.bs.d_status_fwd, p.R, p.bb);
 }
 
 template <int K, bool RECOMPUTE, int LB, int GM, bool STG>
@@ -1048,7 +1047,7 @@ void fa_bwd_launch(const a2c_plan &p, const float *ang, const float *xyz, const 
         STG ? (size_t)p.bs.W * (RECOMPUTE ? 3 : 6) * p.bs.fa_stage_atoms * sizeof(float) : 0;
     hipLaunchKernelGGL((fa_backward_flat_kernel<K, RECOMPUTE, LB, GM, STG>), dim3(p.bs.n_win),
                        dim3(p.bs.W * kWave), lds, s, ang, xyz, g, gang, xyz_out, loss_out,
-                       p.d_head_bits, p.d_res_atom_off,
+                       p.d_head_bits, p.bs.d_wstart, p.d_res_atom_off,
                        p.d_seq, p.d_fa, p.bs.d_status_fwd, p.bs.d_look_fwd, p.bs.d_look,
                        p.bs.d_status, p.R, p.A, p.bb, p.bs.fa_stage_atoms);
 }

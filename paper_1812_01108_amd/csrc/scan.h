@@ -589,11 +589,11 @@ __device__ __forceinline__ void stage_store(float *buf, const float (&in)[N], fl
 }
 
 
-// ------------------------------------------------- staging for fixed windows
-// Same transposes as above for wave runs that start at a multiple of the run
-// length (fixed windows), with every LDS and global address formed from a
-// per-lane base and compile-time offsets.  `full` (wave-uniform): all 64 N
-// elements are valid; otherwise only the first n are (the batch's last wave).
+// ------------------------------------------------------- staging for windows
+// Same transposes as above for the wave runs of a window, with every LDS and
+// global address formed from a per-lane base and compile-time offsets.
+// `full` (wave-uniform): all 64 N elements are valid; otherwise only the
+// first n are (a window's last wave).
 
 constexpr int cgcd(int a, int b) { return b == 0 ? a : cgcd(b, a % b); }
 
@@ -685,7 +685,7 @@ __device__ __forceinline__ void lanes_to_run(float *buf, const float (&in)[N],
 }
 
 // ------------------------------------------------------ window look-back
-// Fixed windows (tiles) of a packed batch hand the scan state across window
+// Windows (tiles) of a packed batch hand the scan state across window
 // edges through device memory.  Every tile publishes its aggregate (the
 // product of its transforms from its last chain head, or from its start if it
 // has none, to its end) as kLbWords tagged 64-bit words: high half the launch
@@ -767,7 +767,7 @@ __device__ __forceinline__ Aff lb_carry_in(const uint64_t *status, int64_t first
 }
 
 
-// The frame preceding each lane in window t of a launch over fixed windows:
+// The frame preceding each lane in window t of a launch over windows:
 // segmented scan of the lane aggregates m inside each wave, then of the wave
 // totals by wave 0, which publishes the window's aggregate and composes those
 // of the earlier windows its first chain spans (lb_carry_in).  heads: the
@@ -881,7 +881,7 @@ __device__ __forceinline__ Wrench lb_carry_after(const uint64_t *status, int64_t
 
 
 // The wrench of everything after each lane, up to the end of its chain, in
-// window t of a launch over fixed windows taken last to first: segmented
+// window t of a launch over windows taken last to first: segmented
 // suffix scan of the lane aggregates (agg: the lane's atoms up to and
 // including its first chain end; ends: lanes where a chain ends) inside each
 // wave, then of the wave totals by wave 0, which publishes the window's
@@ -944,7 +944,7 @@ __device__ __forceinline__ Wrench block_suffix_windows(Wrench agg, uint64_t ends
 }
 
 
-// A launch over fixed windows taken last to first: the sum of one float per
+// A launch over windows taken last to first: the sum of one float per
 // window (each window's share of a loss) without a counter or a fence.
 // Every window publishes its share (block sum in a fixed order) as tagged
 // word kLbLossWord of its look-back words, with the tag of this launch;

@@ -11,6 +11,23 @@ COORD_TOL_A = 1e-3      # max-abs coordinate error, Angstrom
 GRAD_TOL_REL = 1e-3     # ||g_gpu - g_ref||_inf / ||g_ref||_inf per chain
 
 
+def window_counts(lengths, cap):
+    """(windows when whole chains are packed greedily in order into windows
+    of at most cap residues, fixed windows of cap residues): the plan uses
+    the first layout when every chain fits and it takes at most 1/8 more
+    windows than the second."""
+    n, cur = 0, 0
+    for L in lengths:
+        if L == 0:
+            continue
+        if n == 0 or cur + L > cap:
+            n += 1
+            cur = 0
+        cur += L
+    R = int(sum(lengths))
+    return n, -(-R // cap)
+
+
 def dev():
     return torch.device("cuda:0")
 

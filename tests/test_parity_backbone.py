@@ -5,7 +5,8 @@ import numpy as np
 import pytest
 
 import oracle
-from tests.gpu_util import COORD_TOL_A, GRAD_TOL_REL, grad_rel_err, run_backbone, to_dev
+from tests.gpu_util import (COORD_TOL_A, GRAD_TOL_REL, grad_rel_err, run_backbone, to_dev,
+                            window_counts)
 from workloads import (BACKBONE_GEOMETRY, make_inputs, offsets_from_lengths, upstream_grad,
                        make_angles)
 
@@ -122,6 +123,34 @@ def test_windows_repeat_bitwise(K, W, aK, aW):
     print(f"K={K} W={W} adj=({aK},{aW}): repeat bitwise, max|dr|={err:.2e} A "
           f"grad_rel={gerr:.2e}", flush=True)
     assert err <= COORD_TOL_A and gerr <= GRAD_TOL_REL
+
+
+# Batches whose chains all fit in one window and pack well: the windows hold
+# whole chains (none waits on another), the forward schedule reports that
+# many windows, and a repeated launch gives the same bits.
+WHOLE_CHAIN_CASES = {
+    "short": (lambda rng: [int(v) for v in rng.integers(0, 41, 300)], 2, 4),
+    "near_full": (lambda rng: [700] * 12 + [690, 0, 701, 650], 2, 6),
+    "one_per_lane_wave": (lambda rng: [int(v) for v in rng.integers(1, 65, 400)], 1, 4),
+}
+
+
+@pytest.mark.parametrize("case", sorted(WHOLE_CHAIN_CASES))
+@pytest.mark.parametrize("mode", ["coords", "recompute"])
+def test_whole_chain_windows(case, mode):
+    a2c = _a2c()
+    make, K, W = WHOLE_CHAIN_CASES[case]
+    lengths = make(np.random.Generator(np.random.PCG64(23)))
+    n_whole, n_fixed = window_counts(lengths, 64 * K * W)
+    assert max(lengths) <= 64 * K * W and n_whole <= n_fixed + n_fixed // 8
+    off, ang, g = _batch(lengths, 23)
+    plan = a2c.Plan("backbone", offsets=off)
+    plan.set_schedule(K, W)
+    assert plan.schedule["n_tiles"] == n_whole
+    _check(plan, off, ang, g, mode=mode, label=f"{case} K={K} W={W}")
+    x1, g1 = run_backbone(plan, ang, g, mode=mode)
+    x2, g2 = run_backbone(plan, ang, g, mode=mode)
+    assert np.array_equal(x1, x2) and np.array_equal(g1, g2)
 
 
 def test_default_schedule_small_config_and_plain():

@@ -6,7 +6,8 @@ import numpy as np
 import pytest
 
 import oracle
-from tests.gpu_util import COORD_TOL_A, GRAD_TOL_REL, grad_rel_err, run_fullatom, to_dev
+from tests.gpu_util import (COORD_TOL_A, GRAD_TOL_REL, grad_rel_err, run_fullatom, to_dev,
+                            window_counts)
 from workloads import (BACKBONE_GEOMETRY, make_angles, make_inputs, offsets_from_lengths,
                        random_sequence, upstream_grad)
 
@@ -59,6 +60,23 @@ def test_schedules_all_types(K, W, mode):
     plan = a2c.Plan("fullatom", offsets=off, seq=seq)
     plan.set_schedule(K, W)
     _check(plan, off, seq, ang, mode, label=f"K={K} W={W}")
+
+
+@pytest.mark.parametrize("K,W", [(2, 3), (1, 4)])
+@pytest.mark.parametrize("mode", ["coords", "recompute"])
+def test_whole_chain_windows(K, W, mode):
+    """Short chains that all fit in one window and pack well: the windows
+    hold whole chains (no window composes another's aggregate)."""
+    a2c = _a2c()
+    rng = np.random.Generator(np.random.PCG64(29))
+    lengths = [int(v) for v in rng.integers(0, 26, 200)]
+    n_whole, n_fixed = window_counts(lengths, 64 * K * W)
+    assert n_whole <= n_fixed + n_fixed // 8
+    off, seq, ang = _batch(lengths, 29)
+    plan = a2c.Plan("fullatom", offsets=off, seq=seq)
+    plan.set_schedule(K, W)
+    assert plan.schedule["n_tiles"] == n_whole
+    _check(plan, off, seq, ang, mode, label=f"whole chains K={K} W={W}")
 
 
 @pytest.mark.parametrize("fwd,adj", [((1, 16), (2, 16)), ((2, 4), (1, 1))])

@@ -98,6 +98,17 @@ def test_fullatom_schedules(K, W):
     _run(plan, "fullatom", off, seq, ang, t, f"full-atom K={K} W={W}")
 
 
+def test_fullatom_whole_chain_windows():
+    """Short chains packed whole into the windows of the fused step."""
+    a2c = _a2c()
+    rng = np.random.Generator(np.random.PCG64(311))
+    lengths = [int(v) for v in rng.integers(0, 26, 200)]
+    off, seq, ang, t = _case("fullatom", lengths, 311)
+    plan = a2c.Plan("fullatom", offsets=off, seq=seq)
+    plan.set_schedule(2, 3)
+    _run(plan, "fullatom", off, seq, ang, t, "full-atom whole chains K=2 W=3")
+
+
 @pytest.mark.parametrize("model", ["backbone", "fullatom"])
 def test_separate_adjoint_schedule(model):
     """The fused step runs on the adjoint schedule (its loss shares are one
