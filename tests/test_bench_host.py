@@ -77,7 +77,9 @@ def test_traffic_only_for_the_profiled_sources_and_schedule():
     else:
         assert got is None
     K, W = r["schedule"]
-    assert bench.traffic_from_profiles(key, model, r["units"], (K, W + 1)) is None
+    # a schedule of the same kernel with no record of its own
+    W2 = next(w for w in range(W + 1, 64) if bench.profile_key(key, (K, w)) not in rec)
+    assert bench.traffic_from_profiles(key, model, r["units"], (K, W2)) is None
     assert bench.traffic_from_profiles(key, model, r["units"] + 1, (K, W)) is None
     assert bench.traffic_from_profiles("no_such_workload:forward", model, 1, (K, W)) is None
 
@@ -95,5 +97,6 @@ def test_valu_issue_only_for_the_profiled_sources_and_schedule():
     else:
         assert got is None
     K, W = r["schedule"]
-    assert bench.valu_issue_from_profiles(key, model, (K, W + 1), 10.0) is None
+    W2 = next(w for w in range(W + 1, 64) if bench.profile_key(key, (K, w)) not in rec)
+    assert bench.valu_issue_from_profiles(key, model, (K, W2), 10.0) is None
     assert bench.valu_issue_from_profiles("no_such_workload:forward", model, (K, W), 10.0) is None
