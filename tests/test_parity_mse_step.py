@@ -3,9 +3,10 @@ L = sum |r - t|^2 and its angle gradient in one kernel, against
 
 * the FP64 oracle: forward, g = 2 (r - t) in float64, O(N) adjoint;
 * the unfused GPU path: a2c_forward, g = 2 (r - t) in float32 by torch,
-  a2c_backward recomputing the frames.  The forward runs on fixed windows of
-  the packed batch and the fused step on tiles of whole chains, so their
-  scans associate differently: both are held to the oracle bounds.
+  a2c_backward recomputing the frames.  The forward runs on windows of the
+  packed batch and the backbone fused step on tiles of whole chains (the
+  full-atom one on windows, with a spine pass first), so their scans
+  associate differently: both are held to the oracle bounds.
 
 Loss tolerance: the coordinates carry float32 rounding of up to ~1e-3 A
 against residuals |r - t| of order 1-10 A, and the sum runs in float32 over
@@ -70,9 +71,9 @@ def _run(plan, model, off, seq, ang, t, label, coord_tol=COORD_TOL_A):
     lerr = abs(float(loss) - L) / max(L, 1e-30)
     print(f"{label}: max|dr|={cerr:.3e} A grad_rel={gerr:.3e} loss_rel={lerr:.3e}", flush=True)
     assert cerr <= coord_tol and gerr <= GRAD_TOL_REL and lerr <= LOSS_RTOL
-    # The forward runs on fixed windows and the fused step on tiles of whole
-    # chains, so the two scans associate differently even at one schedule:
-    # the unfused path is held to the same oracle bounds.
+    # The forward and the fused step associate their scans differently even at
+    # one schedule (windows against whole-chain tiles, or a spine pass): the
+    # unfused path is held to the same oracle bounds.
     c2n, g2n = c2.cpu().numpy(), g2.cpu().numpy()
     assert float(np.max(np.abs(c2n - r))) <= coord_tol
     assert grad_rel_err(g2n, ga, off) <= GRAD_TOL_REL
