@@ -153,6 +153,24 @@ def test_whole_chain_windows(case, mode):
     assert np.array_equal(x1, x2) and np.array_equal(g1, g2)
 
 
+@pytest.mark.parametrize("mode", ["coords", "recompute"])
+def test_whole_chains_that_pack_badly_take_fixed_windows(mode):
+    """Chains just over half a window: whole-chain packing would need one
+    window per chain, twice the fixed cut, so the plan keeps fixed windows
+    (chains cross window edges and windows wait on each other)."""
+    a2c = _a2c()
+    K, W = 2, 2
+    cap = 64 * K * W
+    lengths = [cap // 2 + 1 + (i % 7) for i in range(60)]
+    n_whole, n_fixed = window_counts(lengths, cap)
+    assert max(lengths) <= cap and n_whole > n_fixed + n_fixed // 8
+    off, ang, g = _batch(lengths, 31)
+    plan = a2c.Plan("backbone", offsets=off)
+    plan.set_schedule(K, W)
+    assert plan.schedule["n_tiles"] == n_fixed
+    _check(plan, off, ang, g, mode=mode, label="fixed windows, chains over half a window")
+
+
 def test_default_schedule_small_config_and_plain():
     a2c = _a2c()
     inp = make_inputs("backbone_16x64")
