@@ -78,6 +78,8 @@ struct Sched {
     int32_t K = 4, W = 4, n_tiles = 0;
     int32_t n_win = 0;                   // windows (0: none)
     int32_t *d_wstart = nullptr;         // n_win + 1 window boundaries (residues)
+    bool whole_chains = false;           // every window holds whole chains (no
+                                         // window waits on another)
     int32_t *d_look = nullptr;           // n_win: forward, the first window whose
                                          // aggregate window t composes; adjoint, the
                                          // last window whose wrench it adds (t: none)

@@ -64,11 +64,12 @@ void free_sched(Sched &S)
 // packing whole chains greedily, in order, takes at most 1/8 more windows
 // than cutting the batch into fixed windows [t cap, t cap + cap), the
 // windows hold whole chains: no chain crosses a window edge and no window
-// waits on another.  Otherwise the fixed windows, wherever the chains fall.
-// Zero-length chains take no space.
-std::vector<int64_t> window_starts(const a2c_plan *p, int64_t cap)
+// waits on another (whole_chains is set).  Otherwise the fixed windows,
+// wherever the chains fall.  Zero-length chains take no space.
+std::vector<int64_t> window_starts(const a2c_plan *p, int64_t cap, bool &whole_chains)
 {
     std::vector<int64_t> st;
+    whole_chains = false;
     if (p->R == 0) return st;
     const int64_t n_fixed = (p->R + cap - 1) / cap;
     if (p->max_len <= cap) {
@@ -84,7 +85,10 @@ std::vector<int64_t> window_starts(const a2c_plan *p, int64_t cap)
             cur += L;
         }
         st.push_back(p->R);
-        if ((int64_t)st.size() - 1 <= n_fixed + n_fixed / 8) return st;
+        if ((int64_t)st.size() - 1 <= n_fixed + n_fixed / 8) {
+            whole_chains = true;
+            return st;
+        }
         st.clear();
     }
     for (int64_t b = 0; b < p->R; b += cap) st.push_back(b);
@@ -178,11 +182,14 @@ a2c_status build_sched(const a2c_plan *p, int32_t K, int32_t W, Sched &out, hipS
                                              " residues needs more than " +
                                              std::to_string(kMaxChunks) + " chunks of " +
                                              std::to_string(cap) + " residues");
-    const std::vector<int64_t> starts = windows ? window_starts(p, cap) : std::vector<int64_t>();
+    bool whole_chains = false;
+    const std::vector<int64_t> starts =
+        windows ? window_starts(p, cap, whole_chains) : std::vector<int64_t>();
     if (flat) {
         Sched S;
         S.K = K;
         S.W = W;
+        S.whole_chains = whole_chains;
         if (p->model == A2C_FULLATOM) {
             // per-wave LDS stage of three planes (the adjoint from
             // coordinates stages six where they fit): the most atoms of one
@@ -248,6 +255,7 @@ a2c_status build_sched(const a2c_plan *p, int32_t K, int32_t W, Sched &out, hipS
         stage_atoms = 0;
     }
     Sched S;
+    S.whole_chains = whole_chains;
     S.fa_stage_atoms = stage_atoms;
     S.fa_unstaged = unstaged;
     S.multi_chunk = false;

@@ -472,10 +472,14 @@ __global__ __launch_bounds__(LB) void bb_backward_recompute_kernel(
 }
 
 // Adjoint from the coordinates the forward produced, over windows of the
-// packed batch (as the forward), last window first.  A window publishes
-// the wrench sum from its start up to its first chain end, then adds those of
-// the later windows its last chain runs into (window look-back; a window only
-// waits on later windows, which start no later than it does).
+// packed batch (as the forward), last window first (rev).  A window
+// publishes the wrench sum from its start up to its first chain end, then
+// adds those of the later windows its last chain runs into (window
+// look-back; a window only waits on later windows, which start no later than
+// it does).  Windows that hold whole chains wait on none, and go in order
+// (rev = 0): workgroup t then runs on the same XCD as the forward's window t
+// (workgroups are spread over the XCDs round robin), whose L2 still holds
+// the coordinates it wrote.
 //   1. coordinates and upstream gradients: coalesced loads, LDS transpose;
 //   2. per lane: wrench sum of its atoms up to and including its first chain
 //      end; segmented suffix scan across the wave, then of the wave totals by
@@ -487,7 +491,8 @@ template <int K, int LB>
 __global__ __launch_bounds__(LB) void bb_backward_coords_flat_kernel(
     const float *__restrict__ xyz, const float *__restrict__ g, float *__restrict__ gang,
     const uint32_t *__restrict__ head_bits, const int32_t *__restrict__ wstart,
-    const int32_t *__restrict__ look_last, uint64_t *__restrict__ status, int64_t R, BBParams P)
+    const int32_t *__restrict__ look_last, uint64_t *__restrict__ status, int64_t R, BBParams P,
+    int32_t rev)
 {
     extern __shared__ float stage_mem[];
     __shared__ BwdShared sh;
@@ -495,7 +500,7 @@ __global__ __launch_bounds__(LB) void bb_backward_coords_flat_kernel(
     constexpr int RUN = kWave * K;  // residues per wave
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t t = (int64_t)gridDim.x - 1 - blockIdx.x;  // last window first
+    const int64_t t = rev ? (int64_t)gridDim.x - 1 - blockIdx.x : (int64_t)blockIdx.x;
     const int64_t ts = wstart[t], te = wstart[t + 1];
     const int nact = (int)((te - ts + RUN - 1) / RUN);
     const int64_t rbase = ts + (int64_t)wave * RUN;
@@ -730,7 +735,7 @@ hipError_t bwd_kml(const a2c_plan &p, const float *ang, const float *xyz, const 
     if (xyz)
         hipLaunchKernelGGL((bb_backward_coords_flat_kernel<K, LB>), dim3(p.bs.n_win), block, lds, s,
                            xyz, g, gang, p.d_head_bits, p.bs.d_wstart, p.bs.d_look, p.bs.d_status,
-                           p.R, p.bb);
+                           p.R, p.bb, p.bs.whole_chains ? 0 : 1);
     else
         hipLaunchKernelGGL((bb_backward_recompute_kernel<K, MULTI, LB, kGradLoad>), grid, block,
                            lds, s, ang, g, gang, nullptr, nullptr, nullptr, nullptr,

@@ -703,7 +703,7 @@ __device__ __forceinline__ void fa_store_grads(float *__restrict__ gang, int64_t
     S_out = S;
 }
 
-// Spine aggregates for the recomputing full-atom adjoints.  Those take their
+// Spine aggregates for the recomputing full-atom adjoints.  Those take fixed
 // windows last to first (for the wrench look-back), so they cannot wait on
 // earlier windows' frames themselves: this spine-only pass over the same
 // windows publishes each window's aggregate (the product of its spine
@@ -758,7 +758,8 @@ __global__ __launch_bounds__(LB) void fa_spine_aggregate_kernel(
     if (lane < kLbWords) lb_store(status + t * kLbWords + lane, tag, sh.pre[0][lane]);
 }
 
-// Backward over windows of the packed batch, last window first: the
+// Backward over windows of the packed batch, last window first (rev; in
+// order where the windows hold whole chains, as the backbone adjoint): the
 // side chains' subtree sums give the chi gradients, the spine groups feed a
 // reverse scan over residues (window look-back for the wrench of later
 // windows), and u . (S_m - o x S_g) gives phi, psi, omega.
@@ -781,7 +782,7 @@ __global__ __launch_bounds__(LB) void fa_backward_flat_kernel(
     const FATable *__restrict__ gtab, const uint64_t *__restrict__ status_fwd,
     const int32_t *__restrict__ look_fwd,
     const int32_t *__restrict__ look_last, uint64_t *__restrict__ status, int64_t R, int64_t A,
-    BBParams P, int stage_atoms)
+    BBParams P, int stage_atoms, int32_t rev)
 {
     static_assert(GM == kGradLoad || RECOMPUTE, "the fused step recomputes the frames");
     extern __shared__ float stage_mem[];
@@ -793,7 +794,7 @@ __global__ __launch_bounds__(LB) void fa_backward_flat_kernel(
     float loss = 0.f;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t t = (int64_t)gridDim.x - 1 - blockIdx.x;  // last window first
+    const int64_t t = rev ? (int64_t)gridDim.x - 1 - blockIdx.x : (int64_t)blockIdx.x;
     FAChunk k;
     k.cs = wstart[t];
     k.ce = wstart[t + 1];
@@ -1049,7 +1050,8 @@ void fa_bwd_launch(const a2c_plan &p, const float *ang, const float *xyz, const 
                        dim3(p.bs.W * kWave), lds, s, ang, xyz, g, gang, xyz_out, loss_out,
                        p.d_head_bits, p.bs.d_wstart, p.d_res_atom_off,
                        p.d_seq, p.d_fa, p.bs.d_status_fwd, p.bs.d_look_fwd, p.bs.d_look,
-                       p.bs.d_status, p.R, p.A, p.bb, p.bs.fa_stage_atoms);
+                       p.bs.d_status, p.R, p.A, p.bb, p.bs.fa_stage_atoms,
+                       p.bs.whole_chains ? 0 : 1);
 }
 
 // mode 0: adjoint from coordinates, 1: recompute, 2: fused squared-distance step

@@ -944,12 +944,12 @@ __device__ __forceinline__ Wrench block_suffix_windows(Wrench agg, uint64_t ends
 }
 
 
-// A launch over windows taken last to first: the sum of one float per
-// window (each window's share of a loss) without a counter or a fence.
-// Every window publishes its share (block sum in a fixed order) as tagged
-// word kLbLossWord of its look-back words, with the tag of this launch;
-// window 0, taken last, waits for all shares and adds them in window order
-// into *out.  Every thread of the block calls it (one barrier).
+// A launch over windows: the sum of one float per window (each window's
+// share of a loss) without a counter or a fence.  Every window publishes its
+// share (block sum in a fixed order) as tagged word kLbLossWord of its
+// look-back words, with the tag of this launch; the window of the last
+// workgroup, started after all others, waits for all shares and adds them in
+// window order into *out.  Every thread of the block calls it (one barrier).
 constexpr int kLbLossWord = kLbWrenchWords;
 
 __device__ __forceinline__ void lb_loss_commit(float v, uint64_t *__restrict__ status, int64_t t,
@@ -960,10 +960,11 @@ __device__ __forceinline__ void lb_loss_commit(float v, uint64_t *__restrict__ s
     const float share = block_sum(v, wave_tot);  // meaningful in thread 0
     const uint32_t tag = (uint32_t)(__builtin_amdgcn_readfirstlane((uint32_t)(prev >> 32))) + 1u;
     if (threadIdx.x == 0) lb_store(status + t * kLbWords + kLbLossWord, tag, share);
-    if (t != 0 || threadIdx.x >= kWave) return;
-    // wave 0 of window 0: lane l adds windows l, l + 64, ... in order, then
-    // the lanes' sums are added in a fixed order; the words are read 16 per
-    // lane at a time before any is checked (one memory latency per batch)
+    if (blockIdx.x != gridDim.x - 1 || threadIdx.x >= kWave) return;
+    // wave 0 of the last workgroup: lane l adds windows l, l + 64, ... in
+    // order, then the lanes' sums are added in a fixed order; the words are
+    // read 16 per lane at a time before any is checked (one memory latency
+    // per batch)
     constexpr int kBatch = 16;
     const int lane = threadIdx.x;
     float sum = 0.f;
