@@ -449,9 +449,9 @@ def main():
             plan.set_forward_schedule(sv[0], sv[1])
             plan.set_adjoint_schedule(sv[2], sv[3])
     elif args.fused:
-        plan.autotune(angles, reps=20, mse_target=target)
+        plan.autotune(angles, reps=50, mse_target=target)
     else:
-        plan.autotune(angles, grad_up, from_coords=mode == "coords", reps=20)
+        plan.autotune(angles, grad_up, from_coords=mode == "coords", reps=50)
 
     # scan form, whole step in one graph
     loss = args.loss if training else None

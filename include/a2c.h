@@ -265,8 +265,8 @@ a2c_status a2c_plan_get_adjoint_schedule(const a2c_plan *plan, int32_t *res_per_
  * a2c_plan_set_forward_schedule accepts for the plan and keeps the fastest,
  * then the adjoint under every schedule a2c_plan_set_adjoint_schedule
  * accepts, on the caller's buffers (candidates in order of residues per
- * lane, then waves; a later one must be 3 % faster than the best so far to
- * replace it, so near-ties resolve to the smaller schedule).
+ * lane, then waves; a later one must be 1 % faster than the best so far to
+ * replace it, so ties resolve to the smaller schedule).
  *   d_angles, d_coords, d_grad_coords, d_grad_angles: buffers of the plan's
  *     sizes; their contents are overwritten (coords and grad_angles) or read.
  *   backward_from_coords: the adjoint timed: 1 a2c_backward with d_coords

@@ -104,6 +104,7 @@ struct Sched {
 struct a2c_plan {
     a2c_model model;
     int device = 0;
+    int n_cu = 0;                        // compute units of the device
     int32_t n_chains = 0;
     int64_t R = 0, A = 0;
     int32_t max_len = 0;

@@ -62,8 +62,9 @@ void free_sched(Sched &S)
 // Window boundaries for windows of at most `cap` residues (n_win + 1
 // entries; none for an empty batch).  Where every chain fits in a window and
 // packing whole chains greedily, in order, takes at most 1/8 more windows
-// than cutting the batch into fixed windows [t cap, t cap + cap), the
-// windows hold whole chains: no chain crosses a window edge and no window
+// than cutting the batch into fixed windows [t cap, t cap + cap), or no more
+// windows than the device has CUs (a launch that leaves CUs idle anyway),
+// the windows hold whole chains: no chain crosses a window edge and no window
 // waits on another (whole_chains is set).  Otherwise the fixed windows,
 // wherever the chains fall.  Zero-length chains take no space.
 std::vector<int64_t> window_starts(const a2c_plan *p, int64_t cap, bool &whole_chains)
@@ -85,7 +86,8 @@ std::vector<int64_t> window_starts(const a2c_plan *p, int64_t cap, bool &whole_c
             cur += L;
         }
         st.push_back(p->R);
-        if ((int64_t)st.size() - 1 <= n_fixed + n_fixed / 8) {
+        const int64_t n_whole = (int64_t)st.size() - 1;
+        if (n_whole <= n_fixed + n_fixed / 8 || n_whole <= p->n_cu) {
             whole_chains = true;
             return st;
         }
@@ -597,6 +599,11 @@ a2c_status a2c_plan_create(a2c_plan **out, int32_t model_id, int32_t n_chains,
         return hip_fail(e, "hipGetDevice");
     }
     p->device = dev;
+    e = hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) {
+        a2c_plan_destroy(p);
+        return hip_fail(e, "hipDeviceGetAttribute");
+    }
     // chain-head bits, padded by two words so a lane may read one word past
     std::vector<uint32_t> bits((size_t)((R + 64) / 32 + 2), 0u);
     for (int32_t c = 0; c < n_chains; ++c)

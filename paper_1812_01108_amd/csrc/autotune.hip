@@ -192,10 +192,11 @@ extern "C" a2c_status a2c_plan_autotune(a2c_plan *p, const float *d_angles, floa
                 st = time_part(part, t);
                 if (st != A2C_OK) break;
                 // a later candidate (more residues per lane or waves) must be
-                // 3 % faster to win: near-ties keep the smaller schedule, so
-                // the choice does not flip with timing noise
+                // 1 % faster to win: exact ties keep the smaller schedule,
+                // while a margin as large as the timing noise would favour
+                // the smaller schedules (tried first) over better later ones
                 float &best = part == 0 ? best_f : best_b;
-                if (t < 0.97f * best) {
+                if (t < 0.99f * best) {
                     best = t;
                     (part == 0 ? fK : bK) = k;
                     (part == 0 ? fW : bW) = w;

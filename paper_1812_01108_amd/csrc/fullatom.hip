@@ -1043,7 +1043,8 @@ template <int K, bool RECOMPUTE, int LB, int GM, bool STG>
 void fa_bwd_launch(const a2c_plan &p, const float *ang, const float *xyz, const float *g,
                    float *gang, hipStream_t s, float *xyz_out, float *loss_out)
 {
-    if (RECOMPUTE) fa_spine_launch<K>(p, ang, s);
+    // whole-chain windows start at a chain head: none needs the spine pass
+    if (RECOMPUTE && !p.bs.whole_chains) fa_spine_launch<K>(p, ang, s);
     const size_t lds =
         STG ? (size_t)p.bs.W * (RECOMPUTE ? 3 : 6) * p.bs.fa_stage_atoms * sizeof(float) : 0;
     hipLaunchKernelGGL((fa_backward_flat_kernel<K, RECOMPUTE, LB, GM, STG>), dim3(p.bs.n_win),

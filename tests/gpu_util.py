@@ -15,7 +15,8 @@ def window_counts(lengths, cap):
     """(windows when whole chains are packed greedily in order into windows
     of at most cap residues, fixed windows of cap residues): the plan uses
     the first layout when every chain fits and it takes at most 1/8 more
-    windows than the second."""
+    windows than the second, or no more windows than the device has CUs
+    (see uses_whole_chains)."""
     n, cur = 0, 0
     for L in lengths:
         if L == 0:
@@ -26,6 +27,13 @@ def window_counts(lengths, cap):
         cur += L
     R = int(sum(lengths))
     return n, -(-R // cap)
+
+
+def uses_whole_chains(lengths, cap):
+    """The plan's layout rule for windows of at most cap residues."""
+    n_whole, n_fixed = window_counts(lengths, cap)
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    return max(lengths) <= cap and (n_whole <= n_fixed + n_fixed // 8 or n_whole <= n_cu)
 
 
 def dev():

@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 from tests.gpu_util import (COORD_TOL_A, GRAD_TOL_REL, grad_rel_err, run_backbone, to_dev,
-                            window_counts)
+                            uses_whole_chains, window_counts)
 from workloads import (BACKBONE_GEOMETRY, make_inputs, offsets_from_lengths, upstream_grad,
                        make_angles)
 
@@ -153,22 +153,27 @@ def test_whole_chain_windows(case, mode):
     assert np.array_equal(x1, x2) and np.array_equal(g1, g2)
 
 
+@pytest.mark.parametrize("n_chains", [60, 700])
 @pytest.mark.parametrize("mode", ["coords", "recompute"])
-def test_whole_chains_that_pack_badly_take_fixed_windows(mode):
-    """Chains just over half a window: whole-chain packing would need one
-    window per chain, twice the fixed cut, so the plan keeps fixed windows
-    (chains cross window edges and windows wait on each other)."""
+def test_chains_that_pack_badly(n_chains, mode):
+    """Chains just over half a window: whole-chain packing needs one window
+    per chain, twice the fixed cut.  With more windows than the device has
+    CUs the plan keeps fixed windows (chains cross window edges and windows
+    wait on each other); with fewer it packs whole chains anyway, since the
+    launch leaves CUs idle either way."""
     a2c = _a2c()
     K, W = 2, 2
     cap = 64 * K * W
-    lengths = [cap // 2 + 1 + (i % 7) for i in range(60)]
+    lengths = [cap // 2 + 1 + (i % 7) for i in range(n_chains)]
     n_whole, n_fixed = window_counts(lengths, cap)
     assert max(lengths) <= cap and n_whole > n_fixed + n_fixed // 8
+    whole = uses_whole_chains(lengths, cap)
+    assert whole == (n_chains == 60)
     off, ang, g = _batch(lengths, 31)
     plan = a2c.Plan("backbone", offsets=off)
     plan.set_schedule(K, W)
-    assert plan.schedule["n_tiles"] == n_fixed
-    _check(plan, off, ang, g, mode=mode, label="fixed windows, chains over half a window")
+    assert plan.schedule["n_tiles"] == (n_whole if whole else n_fixed)
+    _check(plan, off, ang, g, mode=mode, label=f"{n_chains} chains over half a window")
 
 
 def test_default_schedule_small_config_and_plain():
