@@ -305,7 +305,11 @@ a2c_status a2c_forward(a2c_plan *plan, int32_t variant, const float *d_angles,
  * The result is exact up to float32 rounding: for angle alpha_i of node i,
  *   dL/dalpha_i = u_i . sum_{k in subtree(i)} (r_k - r_i) x dL/dr_k,
  * u_i the unit bond vector the node rotates about, which equals the sums of
- * Eq. BackboneGradOutput / Eq. FAMBackward. */
+ * Eq. BackboneGradOutput / Eq. FAMBackward.
+ * The adjoint on windows writes d_grad_angles with non-temporal stores when
+ * it holds at least 4 MiB (the plan's R x K floats): the caches then keep the
+ * step's coordinates and upstream gradients instead.  The values are the
+ * same either way. */
 a2c_status a2c_backward(a2c_plan *plan, int32_t variant, const float *d_angles,
                         const float *d_coords, const float *d_grad_coords,
                         float *d_grad_angles, void *d_workspace, void *stream);

@@ -28,6 +28,8 @@ constexpr int kGradLoad = 0, kGradMse = 1;
 constexpr int kLbWords = 12;
 // LRMSD: atoms per segment (one workgroup of 256 lanes, 16 atoms per lane)
 constexpr int kLrSegAtoms = 4096;
+// LRMSD gradient pieces: four atoms per thread of a 256-thread workgroup
+constexpr int kLrPieceAtoms = 1024;
 
 // Backbone slot constants in float32, slot order N (omega), CA (phi), C (psi).
 // (ct, st) is a float32 pair chosen so that ct^2 + st^2 is as close to 1 as
@@ -120,6 +122,9 @@ struct a2c_plan {
     // store-vs-recompute threshold: the forward's coordinates (12 bytes per
     // atom) are kept for the adjoint while they fit; 0 = always recompute
     size_t mem_budget = 0;
+    // the adjoints write the angle gradients with non-temporal stores (at
+    // least kNtGradBytes of them)
+    bool nt_grad = false;
     // device tables
     uint32_t *d_head_bits = nullptr;     // bit r: residue r starts a chain (bit R set)
     int32_t *d_res_off = nullptr;        // chain residue offsets (plain form)
@@ -128,20 +133,31 @@ struct a2c_plan {
     a2c::FATable *d_fa = nullptr;        // full-atom constants
     a2c::BBParams bb{};
     a2c::FATable fa_host{};
-    // LRMSD segments: runs of at most kLrSegAtoms atoms of one chain
+    // LRMSD segments (the sums): runs of at most kLrSegAtoms atoms of one
+    // chain; pieces (the gradient): runs of at most kLrPieceAtoms
     int32_t lr_n_seg = 0;
     std::vector<int32_t> lr_seg_atom;    // lr_n_seg + 1 first atoms (last = A)
-    std::vector<int32_t> lr_seg_chain;   // lr_n_seg chain of each segment
     std::vector<int32_t> lr_seg_origin;  // lr_n_seg first atom of each segment's chain
     std::vector<int32_t> lr_chain_seg;   // n_chains + 1 first segment of each chain
+    int32_t lr_n_piece = 0;
+    std::vector<int32_t> lr_piece_atom;  // lr_n_piece + 1 first atoms (last = A)
+    std::vector<int32_t> lr_piece_chain; // lr_n_piece chain of each piece
     int8_t *d_chi_slots = nullptr;       // [20][4][4] chi atom slots (full-atom)
     int32_t *d_lr_seg_atom = nullptr;
-    int32_t *d_lr_seg_chain = nullptr;
     int32_t *d_lr_seg_origin = nullptr;
     int32_t *d_lr_chain_seg = nullptr;
+    int32_t *d_lr_piece_atom = nullptr;
+    int32_t *d_lr_piece_chain = nullptr;
 };
 
 namespace a2c {
+
+// Angle gradients of at least this many bytes are written with non-temporal
+// stores: nothing in a training step reads them before the next step, and
+// on large batches their cache lines would otherwise evict coordinates and
+// upstream gradients that the step reads again.  Below it the cached stores
+// are faster (the whole step then stays in the caches).
+constexpr size_t kNtGradBytes = (size_t)4 << 20;
 
 void set_error(const std::string &msg);
 // the checks a2c_plan_set_schedule (and the adjoint setter) makes on (K, W),

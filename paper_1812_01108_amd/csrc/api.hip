@@ -510,9 +510,10 @@ void a2c_plan_destroy(a2c_plan *p)
     (void)hipFree(p->d_fa);
     (void)hipFree(p->d_chi_slots);
     (void)hipFree(p->d_lr_seg_atom);
-    (void)hipFree(p->d_lr_seg_chain);
     (void)hipFree(p->d_lr_seg_origin);
     (void)hipFree(p->d_lr_chain_seg);
+    (void)hipFree(p->d_lr_piece_atom);
+    (void)hipFree(p->d_lr_piece_chain);
     delete p;
 }
 
@@ -591,6 +592,7 @@ a2c_status a2c_plan_create(a2c_plan **out, int32_t model_id, int32_t n_chains,
             return st;
         }
     }
+    p->nt_grad = (size_t)R * (model == A2C_BACKBONE ? 3 : 7) * sizeof(float) >= kNtGradBytes;
     // host tables are complete: now the device
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -629,14 +631,17 @@ a2c_status a2c_plan_create(a2c_plan **out, int32_t model_id, int32_t n_chains,
         st = upload((void **)&p->d_lr_seg_atom, p->lr_seg_atom.data(),
                     p->lr_seg_atom.size() * sizeof(int32_t), s);
         if (st == A2C_OK)
-            st = upload((void **)&p->d_lr_seg_chain, p->lr_seg_chain.data(),
-                        p->lr_seg_chain.size() * sizeof(int32_t), s);
-        if (st == A2C_OK)
             st = upload((void **)&p->d_lr_seg_origin, p->lr_seg_origin.data(),
                         p->lr_seg_origin.size() * sizeof(int32_t), s);
         if (st == A2C_OK)
             st = upload((void **)&p->d_lr_chain_seg, p->lr_chain_seg.data(),
                         p->lr_chain_seg.size() * sizeof(int32_t), s);
+        if (st == A2C_OK)
+            st = upload((void **)&p->d_lr_piece_atom, p->lr_piece_atom.data(),
+                        p->lr_piece_atom.size() * sizeof(int32_t), s);
+        if (st == A2C_OK)
+            st = upload((void **)&p->d_lr_piece_chain, p->lr_piece_chain.data(),
+                        p->lr_piece_chain.size() * sizeof(int32_t), s);
     }
     if (st == A2C_OK) st = lrmsd_scratch_setup(dev);
     if (st == A2C_OK) {

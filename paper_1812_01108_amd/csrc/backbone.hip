@@ -486,13 +486,14 @@ __global__ __launch_bounds__(LB) void bb_backward_recompute_kernel(
 //      wave 0, which publishes and reads the window wrenches;
 //   3. per lane, last atom first: dL/dalpha = u . (S_rg - r x S_g) with S the
 //      wrench of everything after the atom in its chain, then add the atom;
-//   4. LDS transpose, coalesced stores of the phi, psi, omega planes.
+//   4. LDS transpose, coalesced stores of the phi, psi, omega planes
+//      (non-temporal when nt: large plans).
 template <int K, int LB>
 __global__ __launch_bounds__(LB) void bb_backward_coords_flat_kernel(
     const float *__restrict__ xyz, const float *__restrict__ g, float *__restrict__ gang,
     const uint32_t *__restrict__ head_bits, const int32_t *__restrict__ wstart,
     const int32_t *__restrict__ look_last, uint64_t *__restrict__ status, int64_t R, BBParams P,
-    int32_t rev)
+    int32_t rev, int32_t nt)
 {
     extern __shared__ float stage_mem[];
     __shared__ BwdShared sh;
@@ -594,9 +595,15 @@ __global__ __launch_bounds__(LB) void bb_backward_coords_flat_kernel(
             wrench_add_point(S, x[i], y[i], z[i], gx[i], gy[i], gz[i]);
         }
     }
-    lanes_to_run<K>(buf, gr[1], gang + rbase, nres, full);           // phi  (slot CA)
-    lanes_to_run<K>(buf, gr[2], gang + R + rbase, nres, full);       // psi  (slot C)
-    lanes_to_run<K>(buf, gr[0], gang + 2 * R + rbase, nres, full);   // omega (slot N)
+    if (nt) {
+        lanes_to_run<K, true>(buf, gr[1], gang + rbase, nres, full);          // phi  (slot CA)
+        lanes_to_run<K, true>(buf, gr[2], gang + R + rbase, nres, full);      // psi  (slot C)
+        lanes_to_run<K, true>(buf, gr[0], gang + 2 * R + rbase, nres, full);  // omega (slot N)
+    } else {
+        lanes_to_run<K>(buf, gr[1], gang + rbase, nres, full);
+        lanes_to_run<K>(buf, gr[2], gang + R + rbase, nres, full);
+        lanes_to_run<K>(buf, gr[0], gang + 2 * R + rbase, nres, full);
+    }
 }
 
 // ---------------------------------------------------------------- plain form
@@ -735,7 +742,7 @@ hipError_t bwd_kml(const a2c_plan &p, const float *ang, const float *xyz, const 
     if (xyz)
         hipLaunchKernelGGL((bb_backward_coords_flat_kernel<K, LB>), dim3(p.bs.n_win), block, lds, s,
                            xyz, g, gang, p.d_head_bits, p.bs.d_wstart, p.bs.d_look, p.bs.d_status,
-                           p.R, p.bb, p.bs.whole_chains ? 0 : 1);
+                           p.R, p.bb, p.bs.whole_chains ? 0 : 1, p.nt_grad ? 1 : 0);
     else
         hipLaunchKernelGGL((bb_backward_recompute_kernel<K, MULTI, LB, kGradLoad>), grid, block,
                            lds, s, ang, g, gang, nullptr, nullptr, nullptr, nullptr,

@@ -691,13 +691,20 @@ __device__ __forceinline__ float node_torque(const NodeGrad &g, const Wrench &S)
 
 __device__ __forceinline__ void node_fold(NodeGrad &g, const Wrench &w) { g.c = node_torque(g, w); }
 
+// An angle gradient: a non-temporal store when nt (large plans).
+__device__ __forceinline__ void grad_store(float *p, float v, bool nt)
+{
+    if (nt) out_store<true>(p, v);
+    else out_store<false>(p, v);
+}
+
 __device__ __forceinline__ void fa_store_grads(float *__restrict__ gang, int64_t R, int64_t r,
                                                const SpineGrad &sp, const Wrench &S_after,
-                                               Wrench &S_out)
+                                               Wrench &S_out, bool nt)
 {
-    gang[R + r] = node_torque(sp.cc, S_after);
-    gang[r] = node_torque(sp.ca, S_after);
-    gang[2 * R + r] = node_torque(sp.n, S_after);
+    grad_store(&gang[R + r], node_torque(sp.cc, S_after), nt);
+    grad_store(&gang[r], node_torque(sp.ca, S_after), nt);
+    grad_store(&gang[2 * R + r], node_torque(sp.n, S_after), nt);
     Wrench S = S_after;
     wrench_add(S, sp.W);
     S_out = S;
@@ -771,6 +778,7 @@ __global__ __launch_bounds__(LB) void fa_spine_aggregate_kernel(
 // gradient is 2 (r - t), formed from the recomputed positions (the fused
 // training step); xyz_out (may be NULL) receives the positions, loss_out
 // (may be NULL) the batch's sum of |r - t|^2 (lb_loss_commit).
+// nt: the angle gradients go out with non-temporal stores (large plans).
 // STG: atoms go through the per-wave LDS stage; otherwise global memory is
 // addressed directly (schedules whose stage does not fit the LDS).
 template <int K, bool RECOMPUTE, int LB, int GM = kGradLoad, bool STG = true>
@@ -782,7 +790,7 @@ __global__ __launch_bounds__(LB) void fa_backward_flat_kernel(
     const FATable *__restrict__ gtab, const uint64_t *__restrict__ status_fwd,
     const int32_t *__restrict__ look_fwd,
     const int32_t *__restrict__ look_last, uint64_t *__restrict__ status, int64_t R, int64_t A,
-    BBParams P, int stage_atoms, int32_t rev)
+    BBParams P, int stage_atoms, int32_t rev, int32_t nt)
 {
     static_assert(GM == kGradLoad || RECOMPUTE, "the fused step recomputes the frames");
     extern __shared__ float stage_mem[];
@@ -964,8 +972,9 @@ __global__ __launch_bounds__(LB) void fa_backward_flat_kernel(
                 // chi gradients are complete here (their subtrees end in the residue)
 #pragma unroll
                 for (int f = 0; f < A2C_MAX_SIDE_FRAMES; ++f)
-                    gang[(3 + f) * R + L.rs + j] =
-                        (f < tab.max_side && f < ft.n_side && ft.side_chi[f]) ? sc[f].c : 0.f;
+                    grad_store(&gang[(3 + f) * R + L.rs + j],
+                               (f < tab.max_side && f < ft.n_side && ft.side_chi[f]) ? sc[f].c : 0.f,
+                               nt != 0);
                 sp[j] = g;
                 if (!f_end) wrench_add(agg, g.W);
                 if ((L.lm >> j) & 1u) f_end = true;
@@ -984,7 +993,7 @@ __global__ __launch_bounds__(LB) void fa_backward_flat_kernel(
         for (int j = K - 1; j >= 0; --j) {
             if (j < L.cnt) {
                 if ((L.lm >> j) & 1u) S = wrench_zero();
-                fa_store_grads(gang, R, L.rs + j, sp[j], S, S);
+                fa_store_grads(gang, R, L.rs + j, sp[j], S, S, nt != 0);
             }
         }
     }
@@ -1052,7 +1061,7 @@ void fa_bwd_launch(const a2c_plan &p, const float *ang, const float *xyz, const 
                        p.d_head_bits, p.bs.d_wstart, p.d_res_atom_off,
                        p.d_seq, p.d_fa, p.bs.d_status_fwd, p.bs.d_look_fwd, p.bs.d_look,
                        p.bs.d_status, p.R, p.A, p.bb, p.bs.fa_stage_atoms,
-                       p.bs.whole_chains ? 0 : 1);
+                       p.bs.whole_chains ? 0 : 1, p.nt_grad ? 1 : 0);
 }
 
 // mode 0: adjoint from coordinates, 1: recompute, 2: fused squared-distance step

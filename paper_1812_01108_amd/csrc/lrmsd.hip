@@ -27,8 +27,10 @@
 //               adjugate of T - lambda I (a cyclic Jacobi sweep takes over
 //               when the largest eigenvalue is degenerate), and stores
 //               LRMSD, U, the means and 1 / (N LRMSD) per chain;
-//   lr_grad     one workgroup per segment, streaming: the gradient above,
-//               scaled by the upstream gradient of each chain's LRMSD.
+//   lr_grad     one workgroup per piece (<= kLrPieceAtoms atoms of one
+//               chain, four per thread, all loads issued first): the
+//               gradient above, scaled by the upstream gradient of each
+//               chain's LRMSD.
 #include "a2c_internal.h"
 
 #include <cmath>
@@ -41,6 +43,10 @@ constexpr int kLrThreads = 256;
 constexpr int kLrSolveThreads = 64;  // one lane per chain
 constexpr int kLrPart = 18;  // doubles per segment record (17 used)
 constexpr int kLrState = 16; // floats per chain: U (9), x mean (3), y mean (3), 1/(N LRMSD)
+// The gradient runs on pieces of four atoms per thread, so that a thread's
+// loads are all in flight at once and small batches still spread over many
+// workgroups.
+static_assert(kLrPieceAtoms == 4 * kLrThreads, "four gradient atoms per thread");
 
 // --------------------------------------------------------------- reductions
 
@@ -368,13 +374,13 @@ __global__ __launch_bounds__(kLrSolveThreads) void lr_solve_kernel(
 // ------------------------------------------------------------------ gradient
 
 __global__ __launch_bounds__(kLrThreads) void lr_grad_kernel(
-    const float *__restrict__ y, const float *__restrict__ x, const int32_t *__restrict__ seg_atom,
-    const int32_t *__restrict__ seg_chain, int64_t A, const float *__restrict__ state,
+    const float *__restrict__ y, const float *__restrict__ x, const int32_t *__restrict__ piece_atom,
+    const int32_t *__restrict__ piece_chain, int64_t A, const float *__restrict__ state,
     const float *__restrict__ gout, float *__restrict__ gy)
 {
-    const int s = blockIdx.x;
-    const int a0 = seg_atom[s], a1 = seg_atom[s + 1];
-    const int c = seg_chain[s];
+    const int pc = blockIdx.x;
+    const int64_t a0 = piece_atom[pc], a1 = piece_atom[pc + 1];
+    const int c = piece_chain[pc];
     const float *st = state + (size_t)c * kLrState;
     const float u00 = st[0], u01 = st[1], u02 = st[2];
     const float u10 = st[3], u11 = st[4], u12 = st[5];
@@ -382,9 +388,20 @@ __global__ __launch_bounds__(kLrThreads) void lr_grad_kernel(
     const float xm0 = st[9], xm1 = st[10], xm2 = st[11];
     const float ym0 = st[12], ym1 = st[13], ym2 = st[14];
     const float w = gout[c] * st[15];
-    for (int a = a0 + (int)threadIdx.x; a < a1; a += kLrThreads) {
-        const float px = x[a] - xm0, py = x[A + a] - xm1, pz = x[2 * A + a] - xm2;
-        const float qx = y[a] - ym0, qy = y[A + a] - ym1, qz = y[2 * A + a] - ym2;
+    float fx[4][3], fy[4][3];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int64_t a = a0 + threadIdx.x + j * kLrThreads;
+        const int64_t ac = a < a1 ? a : a0;  // clamped: every load issued
+        fx[j][0] = x[ac]; fx[j][1] = x[A + ac]; fx[j][2] = x[2 * A + ac];
+        fy[j][0] = y[ac]; fy[j][1] = y[A + ac]; fy[j][2] = y[2 * A + ac];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int64_t a = a0 + threadIdx.x + j * kLrThreads;
+        if (a >= a1) continue;
+        const float px = fx[j][0] - xm0, py = fx[j][1] - xm1, pz = fx[j][2] - xm2;
+        const float qx = fy[j][0] - ym0, qy = fy[j][1] - ym1, qz = fy[j][2] - ym2;
         const float rx = qx - (u00 * px + u01 * py + u02 * pz);
         const float ry = qy - (u10 * px + u11 * py + u12 * pz);
         const float rz = qz - (u20 * px + u21 * py + u22 * pz);
@@ -397,7 +414,8 @@ __global__ __launch_bounds__(kLrThreads) void lr_grad_kernel(
 bool lr_ready(const a2c_plan *p)
 {
     return p->n_chains == 0 ||
-           (p->d_lr_chain_seg && (p->lr_n_seg == 0 || (p->d_lr_seg_atom && p->d_lr_seg_origin)));
+           (p->d_lr_chain_seg && (p->lr_n_seg == 0 || (p->d_lr_seg_atom && p->d_lr_seg_origin)) &&
+            (p->lr_n_piece == 0 || (p->d_lr_piece_atom && p->d_lr_piece_chain)));
 }
 
 }  // namespace
@@ -443,24 +461,31 @@ static void *lrmsd_scratch_ptr(int device)
     return g_scratch_dev[device];
 }
 
-// Segments of at most kLrSegAtoms atoms, never across a chain boundary.
+// Segments of at most kLrSegAtoms atoms (the sums) and pieces of at most
+// kLrPieceAtoms (the gradient), never across a chain boundary.
 void build_lrmsd_segments(a2c_plan &p)
 {
     p.lr_seg_atom.clear();
-    p.lr_seg_chain.clear();
     p.lr_seg_origin.clear();
+    p.lr_piece_atom.clear();
+    p.lr_piece_chain.clear();
     p.lr_chain_seg.assign(p.n_chains + 1, 0);
     for (int32_t c = 0; c < p.n_chains; ++c) {
-        p.lr_chain_seg[c] = (int32_t)p.lr_seg_chain.size();
+        p.lr_chain_seg[c] = (int32_t)p.lr_seg_origin.size();
         for (int64_t a = p.chain_atom_off[c]; a < p.chain_atom_off[c + 1]; a += kLrSegAtoms) {
             p.lr_seg_atom.push_back((int32_t)a);
-            p.lr_seg_chain.push_back(c);
             p.lr_seg_origin.push_back(p.chain_atom_off[c]);
         }
+        for (int64_t a = p.chain_atom_off[c]; a < p.chain_atom_off[c + 1]; a += kLrPieceAtoms) {
+            p.lr_piece_atom.push_back((int32_t)a);
+            p.lr_piece_chain.push_back(c);
+        }
     }
-    p.lr_chain_seg[p.n_chains] = (int32_t)p.lr_seg_chain.size();
+    p.lr_chain_seg[p.n_chains] = (int32_t)p.lr_seg_origin.size();
+    p.lr_n_seg = (int32_t)p.lr_seg_origin.size();
     p.lr_seg_atom.push_back((int32_t)p.A);
-    p.lr_n_seg = (int32_t)p.lr_seg_chain.size();
+    p.lr_n_piece = (int32_t)p.lr_piece_chain.size();
+    p.lr_piece_atom.push_back((int32_t)p.A);
 }
 
 }  // namespace a2c
@@ -493,6 +518,11 @@ static a2c_status lr_check(const a2c_plan *p, void *ws)
     if (!lr_ready(p)) {
         set_error("plan has no LRMSD segment tables");
         return A2C_ERR_STATE;
+    }
+    // a launch's work-items are counted in 32 bits
+    if ((uint64_t)p->lr_n_piece * kLrThreads > 0xFFFFFFFFull) {
+        set_error("too many LRMSD pieces for one launch");
+        return A2C_ERR_UNSUPPORTED;
     }
     if (!ws && lrmsd_workspace_bytes(*p) > 0) {
         set_error("the LRMSD workspace is NULL");
@@ -562,7 +592,7 @@ a2c_status a2c_lrmsd_backward(a2c_plan *p, const float *d_coords, const float *d
 {
     a2c_status st = lr_check(p, (void *)d_workspace);
     if (st != A2C_OK) return st;
-    if (p->lr_n_seg == 0) return A2C_OK;
+    if (p->lr_n_piece == 0) return A2C_OK;
     if (!d_coords || !d_target || !d_grad_lrmsd || !d_grad_coords) {
         set_error("a device pointer is NULL");
         return A2C_ERR_INVALID_ARG;
@@ -570,9 +600,9 @@ a2c_status a2c_lrmsd_backward(a2c_plan *p, const float *d_coords, const float *d
     hipStream_t s = (hipStream_t)stream;
     const float *state =
         (const float *)((const char *)d_workspace + (size_t)p->lr_n_seg * kLrPart * sizeof(double));
-    hipLaunchKernelGGL(lr_grad_kernel, dim3(p->lr_n_seg), dim3(kLrThreads), 0, s, d_coords,
-                       d_target, p->d_lr_seg_atom, p->d_lr_seg_chain, p->A, state, d_grad_lrmsd,
-                       d_grad_coords);
+    hipLaunchKernelGGL(lr_grad_kernel, dim3(p->lr_n_piece), dim3(kLrThreads), 0, s, d_coords,
+                       d_target, p->d_lr_piece_atom, p->d_lr_piece_chain, p->A, state,
+                       d_grad_lrmsd, d_grad_coords);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? A2C_OK : hip_fail(e, "lrmsd backward launch");
 }

@@ -645,18 +645,27 @@ __device__ __forceinline__ void run_to_lanes(float *buf, const float (&v)[N], fl
     }
 }
 
+// A store that is non-temporal when NT (an output nothing in the same step
+// reads again, so that it does not take cache lines from inputs that are).
+template <bool NT>
+__device__ __forceinline__ void out_store(float *p, float v)
+{
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
 // run[l N + i] = in[i] of lane l for indices below n, written with 64
 // consecutive floats per instruction.  Rows of N + (N even) floats in LDS;
 // the read address of element e = lane + 64 m repeats with period
 // P = N / gcd(N, 64) in m up to a constant step, so P per-lane bases serve
-// all N reads.
-template <int N>
+// all N reads.  NT: non-temporal stores.
+template <int N, bool NT = false>
 __device__ __forceinline__ void lanes_to_run(float *buf, const float (&in)[N],
                                              float *__restrict__ run, int n, bool full)
 {
     const int lane = threadIdx.x & 63;
     if constexpr (N == 1) {
-        if (full || lane < n) run[lane] = in[0];
+        if (full || lane < n) out_store<NT>(&run[lane], in[0]);
     } else {
         constexpr int S = (N & 1) ? N : N + 1;
         constexpr int P = N / cgcd(N, 64);
@@ -672,12 +681,13 @@ __device__ __forceinline__ void lanes_to_run(float *buf, const float (&in)[N],
         }
         if (full) {
 #pragma unroll
-            for (int m = 0; m < N; ++m) run[lane + 64 * m] = buf[base[m % P] + (m / P) * STEP];
+            for (int m = 0; m < N; ++m)
+                out_store<NT>(&run[lane + 64 * m], buf[base[m % P] + (m / P) * STEP]);
         } else {
 #pragma unroll
             for (int m = 0; m < N; ++m) {
                 const int e = lane + 64 * m;
-                if (e < n) run[e] = buf[base[m % P] + (m / P) * STEP];
+                if (e < n) out_store<NT>(&run[e], buf[base[m % P] + (m / P) * STEP]);
             }
         }
         wave_lds_sync();
