@@ -216,12 +216,15 @@ a2c_status a2c_plan_workspace_bytes(const a2c_plan *plan, int32_t variant,
  *     window from earlier ones gets its frame from those windows' aggregates
  *     (forward), and a chain running on into later windows gets their
  *     wrench sums (adjoint); every workgroup publishes its own in plan-owned
- *     device memory before it reads any (window look-back), and only waits
- *     on workgroups that were started before it (the adjoints take fixed
- *     windows last to first, whole-chain ones in order; the full-atom ones
- *     that recompute the frames first run a spine-only pass over the same
- *     windows, which waits on nothing).  Consequently two such calls on one
- *     plan must not run at the same time (on different streams).
+ *     device memory before it reads any (window look-back), and waits only
+ *     on workgroups started before it or at most 7 places after it (the
+ *     adjoints take fixed windows last to first, in each class of workgroup
+ *     index mod 8 separately, and whole-chain ones in order; the full-atom
+ *     ones that recompute the frames first run a spine-only pass over the
+ *     same windows, which waits on nothing); a launch therefore progresses
+ *     whenever the device holds 8 of its workgroups at once.  Consequently
+ *     two such calls on one plan must not run at the same time (on
+ *     different streams).
  *   - The backbone adjoint that recomputes the frames (a2c_backward without
  *     d_coords) and the backbone a2c_mse_step pack chains of at most one
  *     chunk whole, in order, into tiles of at most one chunk; a longer chain

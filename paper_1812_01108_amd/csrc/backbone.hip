@@ -472,14 +472,14 @@ __global__ __launch_bounds__(LB) void bb_backward_recompute_kernel(
 }
 
 // Adjoint from the coordinates the forward produced, over windows of the
-// packed batch (as the forward), last window first (rev).  A window
-// publishes the wrench sum from its start up to its first chain end, then
-// adds those of the later windows its last chain runs into (window
-// look-back; a window only waits on later windows, which start no later than
-// it does).  Windows that hold whole chains wait on none, and go in order
-// (rev = 0): workgroup t then runs on the same XCD as the forward's window t
-// (workgroups are spread over the XCDs round robin), whose L2 still holds
-// the coordinates it wrote.
+// packed batch (as the forward), last window first (rev: reverse_window,
+// which keeps window t on the XCD of the forward's window t where the two
+// schedules cut the same windows).  A window publishes the wrench sum from
+// its start up to its first chain end, then adds those of the later windows
+// its last chain runs into (window look-back).  Windows that hold whole
+// chains wait on none, and go in order (rev = 0): workgroup t then runs on
+// the same XCD as the forward's window t (workgroups are spread over the
+// XCDs round robin), whose L2 still holds the coordinates it wrote.
 //   1. coordinates and upstream gradients: coalesced loads, LDS transpose;
 //   2. per lane: wrench sum of its atoms up to and including its first chain
 //      end; segmented suffix scan across the wave, then of the wave totals by
@@ -501,7 +501,7 @@ __global__ __launch_bounds__(LB) void bb_backward_coords_flat_kernel(
     constexpr int RUN = kWave * K;  // residues per wave
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t t = rev ? (int64_t)gridDim.x - 1 - blockIdx.x : (int64_t)blockIdx.x;
+    const int64_t t = rev ? reverse_window(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
     const int64_t ts = wstart[t], te = wstart[t + 1];
     const int nact = (int)((te - ts + RUN - 1) / RUN);
     const int64_t rbase = ts + (int64_t)wave * RUN;

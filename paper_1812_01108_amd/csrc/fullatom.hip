@@ -765,8 +765,10 @@ __global__ __launch_bounds__(LB) void fa_spine_aggregate_kernel(
     if (lane < kLbWords) lb_store(status + t * kLbWords + lane, tag, sh.pre[0][lane]);
 }
 
-// Backward over windows of the packed batch, last window first (rev; in
-// order where the windows hold whole chains, as the backbone adjoint): the
+// Backward over windows of the packed batch, last window first (rev:
+// reverse_window, so that window t runs on the XCD where the spine pass's
+// window t read the same angles; in order where the windows hold whole
+// chains, as the backbone adjoint): the
 // side chains' subtree sums give the chi gradients, the spine groups feed a
 // reverse scan over residues (window look-back for the wrench of later
 // windows), and u . (S_m - o x S_g) gives phi, psi, omega.
@@ -802,7 +804,7 @@ __global__ __launch_bounds__(LB) void fa_backward_flat_kernel(
     float loss = 0.f;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t t = rev ? (int64_t)gridDim.x - 1 - blockIdx.x : (int64_t)blockIdx.x;
+    const int64_t t = rev ? reverse_window(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
     FAChunk k;
     k.cs = wstart[t];
     k.ce = wstart[t + 1];

@@ -694,6 +694,21 @@ __device__ __forceinline__ void lanes_to_run(float *buf, const float (&in)[N],
     }
 }
 
+// Window of workgroup b in a launch that takes its n windows last to first.
+// Workgroups are spread over the eight XCDs round robin (b mod 8), so within
+// each class b mod 8 the windows go last to first: window t then runs on the
+// XCD (t mod 8) that ran window t of a launch over the same windows in
+// order, whose L2 may still hold what that launch read or wrote.  A window
+// waits only on later windows, whose workgroups are at most 7 places further
+// in dispatch order; each publishes before it waits, so the launch makes
+// progress whenever the device holds 8 of its workgroups at once.
+__device__ __forceinline__ int64_t reverse_window(int64_t b, int64_t n)
+{
+    const int64_t x = b & 7;
+    const int64_t c = (n - x + 7) >> 3;  // windows (and workgroups) of class x
+    return ((c - 1 - (b >> 3)) << 3) + x;
+}
+
 // ------------------------------------------------------ window look-back
 // Windows (tiles) of a packed batch hand the scan state across window
 // edges through device memory.  Every tile publishes its aggregate (the
@@ -703,7 +718,8 @@ __device__ __forceinline__ void lanes_to_run(float *buf, const float (&in)[N],
 // tile reads the aggregates of the tiles back to the one holding that head
 // (a host table) and composes them in order.  Each tile publishes before it
 // reads, so no wait depends on another wait; a tile only waits on tiles of
-// lower index, which start no later than it does.  Words are written and
+// lower index, which start no later than it does (the adjoints, which wait on
+// later windows, take them in reverse: reverse_window).  Words are written and
 // read with relaxed device-scope atomics (each word carries its own tag, so
 // no ordering between words is needed).  The tag of a launch is one more than
 // the one a tile finds in its own words (all tiles start from 0 and every
