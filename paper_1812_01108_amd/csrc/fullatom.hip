@@ -878,29 +878,23 @@ __global__ __launch_bounds__(LB) void fa_backward_flat_kernel(
                 const FAType &ft = tab.t[lr.type[j]];
                 const int aloc = lr.aoff[j] - (int)L.A0;
                 const bool head = (L.hm >> j) & 1u;
-                // each group's wrench is folded into the axes that move it
-                // (N: every group; CA: its own, the side chain, C's; C: its
-                // own; side frame f: frames f and after) and into W
+                // each group's wrench goes to the axes that move it once the
+                // residue is walked (N: every group; CA: its own, the side
+                // chain, C's; C: its own; side frame f: frames f and after)
                 SpineGrad g;
                 NodeGrad sc[A2C_MAX_SIDE_FRAMES];
-                Wrench w;
+                Wrench wn = wrench_zero(), wca = wrench_zero(), wc = wrench_zero();
+                Wrench ws[A2C_MAX_SIDE_FRAMES];
                 if (RECOMPUTE) {
                     if (head) cur = aff_identity();
                     aff_apply_transform(cur, P.ct[0], P.st[0], P.d[0], in[j].co, in[j].so);
                     g.n = node_of_frame(cur);
-                    w = wrench_zero();
-                    if (GM == kGradMse) frame_wrench_mse(tab, ft, 0, cur, sg, sout, write_so, aloc, w, loss);
-                    else frame_wrench(tab, ft, 0, cur, sg, aloc, w);
-                    node_fold(g.n, w);
-                    g.W = w;
+                    if (GM == kGradMse) frame_wrench_mse(tab, ft, 0, cur, sg, sout, write_so, aloc, wn, loss);
+                    else frame_wrench(tab, ft, 0, cur, sg, aloc, wn);
                     aff_apply_transform(cur, P.ct[1], P.st[1], P.d[1], in[j].cp, in[j].sp);
                     g.ca = node_of_frame(cur);
-                    w = wrench_zero();
-                    if (GM == kGradMse) frame_wrench_mse(tab, ft, 1, cur, sg, sout, write_so, aloc, w, loss);
-                    else frame_wrench(tab, ft, 1, cur, sg, aloc, w);
-                    node_fold(g.n, w);
-                    node_fold(g.ca, w);
-                    wrench_add(g.W, w);
+                    if (GM == kGradMse) frame_wrench_mse(tab, ft, 1, cur, sg, sout, write_so, aloc, wca, loss);
+                    else frame_wrench(tab, ft, 1, cur, sg, aloc, wca);
                     Aff sf = cur;
                     aff_rot_x(sf, ft.pre_c, ft.pre_s);
 #pragma unroll
@@ -908,21 +902,15 @@ __global__ __launch_bounds__(LB) void fa_backward_flat_kernel(
                         if (f < tab.max_side && f < ft.n_side) {
                             side_step(sf, ft, f, lr.chi[j][f]);
                             sc[f] = node_of_frame(sf);
-                            w = wrench_zero();
-                            if (GM == kGradMse) frame_wrench_mse(tab, ft, 3 + f, sf, sg, sout, write_so, aloc, w, loss);
-                            else frame_wrench(tab, ft, 3 + f, sf, sg, aloc, w);
-#pragma unroll
-                            for (int q = 0; q <= f; ++q) node_fold(sc[q], w);
-                            node_fold(g.n, w);
-                            node_fold(g.ca, w);
-                            wrench_add(g.W, w);
+                            ws[f] = wrench_zero();
+                            if (GM == kGradMse) frame_wrench_mse(tab, ft, 3 + f, sf, sg, sout, write_so, aloc, ws[f], loss);
+                            else frame_wrench(tab, ft, 3 + f, sf, sg, aloc, ws[f]);
                         }
                     }
                     aff_apply_transform(cur, P.ct[2], P.st[2], P.d[2], in[j].cs, in[j].ss);
                     g.cc = node_of_frame(cur);
-                    w = wrench_zero();
-                    if (GM == kGradMse) frame_wrench_mse(tab, ft, 2, cur, sg, sout, write_so, aloc, w, loss);
-                    else frame_wrench(tab, ft, 2, cur, sg, aloc, w);
+                    if (GM == kGradMse) frame_wrench_mse(tab, ft, 2, cur, sg, sout, write_so, aloc, wc, loss);
+                    else frame_wrench(tab, ft, 2, cur, sg, aloc, wc);
                 } else {
                     const float *px = sx.st, *py = sx.st + sx.ns, *pz = sx.st + 2 * sx.ns;
                     const float nx = px[aloc], ny = py[aloc], nz = pz[aloc];
@@ -935,15 +923,8 @@ __global__ __launch_bounds__(LB) void fa_backward_flat_kernel(
                                    (cay - ny) * P.inv_d[1], (caz - nz) * P.inv_d[1]);
                     g.cc = node_at(cx, cy, cz, (cx - cax) * P.inv_d[2], (cy - cay) * P.inv_d[2],
                                    (cz - caz) * P.inv_d[2]);
-                    w = wrench_zero();
-                    frame_wrench_xyz(tab, ft, 0, sg, sx, aloc, w);
-                    node_fold(g.n, w);
-                    g.W = w;
-                    w = wrench_zero();
-                    frame_wrench_xyz(tab, ft, 1, sg, sx, aloc, w);
-                    node_fold(g.n, w);
-                    node_fold(g.ca, w);
-                    wrench_add(g.W, w);
+                    frame_wrench_xyz(tab, ft, 0, sg, sx, aloc, wn);
+                    frame_wrench_xyz(tab, ft, 1, sg, sx, aloc, wca);
                     float ppx = cax, ppy = cay, ppz = caz;
 #pragma unroll
                     for (int f = 0; f < A2C_MAX_SIDE_FRAMES; ++f) {
@@ -953,24 +934,30 @@ __global__ __launch_bounds__(LB) void fa_backward_flat_kernel(
                             sc[f] = node_at(ox, oy, oz, (ox - ppx) * ft.inv_d[f],
                                             (oy - ppy) * ft.inv_d[f], (oz - ppz) * ft.inv_d[f]);
                             ppx = ox; ppy = oy; ppz = oz;
-                            w = wrench_zero();
-                            frame_wrench_xyz(tab, ft, 3 + f, sg, sx, aloc, w);
-#pragma unroll
-                            for (int q = 0; q <= f; ++q) node_fold(sc[q], w);
-                            node_fold(g.n, w);
-                            node_fold(g.ca, w);
-                            wrench_add(g.W, w);
+                            ws[f] = wrench_zero();
+                            frame_wrench_xyz(tab, ft, 3 + f, sg, sx, aloc, ws[f]);
                         }
                     }
-                    w = wrench_zero();
-                    frame_wrench_xyz(tab, ft, 2, sg, sx, aloc, w);
+                    frame_wrench_xyz(tab, ft, 2, sg, sx, aloc, wc);
                     pcx = cx; pcy = cy; pcz = cz;
                 }
-                // the C group (with O)
-                node_fold(g.n, w);
-                node_fold(g.ca, w);
-                node_fold(g.cc, w);
-                wrench_add(g.W, w);
+                // side frame f moves frames f and after: their wrench, summed
+                // from the last frame back, folds into each axis once
+                Wrench side = wrench_zero();
+#pragma unroll
+                for (int f = A2C_MAX_SIDE_FRAMES - 1; f >= 0; --f) {
+                    if (f < tab.max_side && f < ft.n_side) {
+                        wrench_add(side, ws[f]);
+                        node_fold(sc[f], side);
+                    }
+                }
+                node_fold(g.cc, wc);      // C: the C group (with O)
+                wrench_add(wca, side);
+                wrench_add(wca, wc);
+                node_fold(g.ca, wca);     // CA: its group, the side chain, the C group
+                g.W = wn;
+                wrench_add(g.W, wca);
+                node_fold(g.n, g.W);      // N: the whole residue
                 // chi gradients are complete here (their subtrees end in the residue)
 #pragma unroll
                 for (int f = 0; f < A2C_MAX_SIDE_FRAMES; ++f)
