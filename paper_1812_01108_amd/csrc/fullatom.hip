@@ -134,17 +134,20 @@ a2c_status convert_residue_table(const a2c_residue_table *table, const double sp
         }
         for (int k = 0; k < nframes; ++k)
             if (ft.origin_slot[k] < 0) return bad_table(t, "every frame needs an atom at its origin");
+        // each frame's list starts with its origin atom (the kernels place it
+        // at the frame's translation without a product)
         int n = 0;
         for (int k = 0; k < 7; ++k) {
             ft.fbegin[k] = n;
-            for (int a = 0; a < rd.n_atoms; ++a)
-                if (rd.atoms[a].frame == k) {
-                    ft.atom[n].slot = a;
-                    ft.atom[n].x = (float)local[a].x;
-                    ft.atom[n].y = (float)local[a].y;
-                    ft.atom[n].z = (float)local[a].z;
-                    ++n;
-                }
+            for (int pass = 0; pass < 2; ++pass)
+                for (int a = 0; a < rd.n_atoms; ++a)
+                    if (rd.atoms[a].frame == k && (a == ft.origin_slot[k]) == (pass == 0)) {
+                        ft.atom[n].slot = a;
+                        ft.atom[n].x = (float)local[a].x;
+                        ft.atom[n].y = (float)local[a].y;
+                        ft.atom[n].z = (float)local[a].z;
+                        ++n;
+                    }
             ft.fcount[k] = n - ft.fbegin[k];
             T.max_count[k] = std::max(T.max_count[k], ft.fcount[k]);
         }
@@ -301,10 +304,18 @@ __device__ __forceinline__ void lds_to_run(const Stage &sg, float *__restrict__ 
 }
 
 // Emit the atoms of frame k of type t placed by F into the staging buffer.
+// The frame's first atom is its origin: F's translation, no product.  Frame
+// k exists for the type (every existing frame holds its origin atom).
 __device__ __forceinline__ void emit_frame(const FATable &tab, const FAType &ft, int k,
                                            const Aff &F, const Stage &sg, int aloc)
 {
-    for (int i = 0; i < tab.max_count[k]; ++i) {
+    {
+        const int e = aloc + ft.atom[ft.fbegin[k]].slot;
+        sg.st[e] = F.t0;
+        sg.st[sg.ns + e] = F.t1;
+        sg.st[2 * sg.ns + e] = F.t2;
+    }
+    for (int i = 1; i < tab.max_count[k]; ++i) {
         if (i < ft.fcount[k]) {
             const FAAtom at = ft.atom[ft.fbegin[k] + i];
             float x, y, z;
@@ -318,11 +329,15 @@ __device__ __forceinline__ void emit_frame(const FATable &tab, const FAType &ft,
 }
 
 // Wrench of the atoms of frame k placed by F, upstream gradients staged in
-// planes 0..2.
+// planes 0..2 (the origin atom first, at F's translation).
 __device__ __forceinline__ void frame_wrench(const FATable &tab, const FAType &ft, int k,
                                              const Aff &F, const Stage &sg, int aloc, Wrench &w)
 {
-    for (int i = 0; i < tab.max_count[k]; ++i) {
+    {
+        const int e = aloc + ft.atom[ft.fbegin[k]].slot;
+        wrench_add_point(w, F.t0, F.t1, F.t2, sg.st[e], sg.st[sg.ns + e], sg.st[2 * sg.ns + e]);
+    }
+    for (int i = 1; i < tab.max_count[k]; ++i) {
         if (i < ft.fcount[k]) {
             const FAAtom at = ft.atom[ft.fbegin[k] + i];
             float x, y, z;
@@ -337,24 +352,30 @@ __device__ __forceinline__ void frame_wrench(const FATable &tab, const FAType &f
 // wrench of frame k's atoms takes the loss gradient 2 (r - t), the loss
 // accumulates |r - t|^2, and the staged target is replaced by r (so the
 // stage ends up holding the coordinates).
+__device__ __forceinline__ void atom_mse(float x, float y, float z, int e, const Stage &sg,
+                                         const Stage &so, bool write, Wrench &w, float &loss)
+{
+    const float dx = x - sg.st[e], dy = y - sg.st[sg.ns + e], dz = z - sg.st[2 * sg.ns + e];
+    loss += dx * dx + dy * dy + dz * dz;
+    wrench_add_point(w, x, y, z, 2.f * dx, 2.f * dy, 2.f * dz);
+    if (write) {
+        so.st[e] = x;
+        so.st[so.ns + e] = y;
+        so.st[2 * so.ns + e] = z;
+    }
+}
+
 __device__ __forceinline__ void frame_wrench_mse(const FATable &tab, const FAType &ft, int k,
                                                  const Aff &F, const Stage &sg, const Stage &so,
                                                  bool write, int aloc, Wrench &w, float &loss)
 {
-    for (int i = 0; i < tab.max_count[k]; ++i) {
+    atom_mse(F.t0, F.t1, F.t2, aloc + ft.atom[ft.fbegin[k]].slot, sg, so, write, w, loss);
+    for (int i = 1; i < tab.max_count[k]; ++i) {
         if (i < ft.fcount[k]) {
             const FAAtom at = ft.atom[ft.fbegin[k] + i];
             float x, y, z;
             aff_point(F, at.x, at.y, at.z, x, y, z);
-            const int e = aloc + at.slot;
-            const float dx = x - sg.st[e], dy = y - sg.st[sg.ns + e], dz = z - sg.st[2 * sg.ns + e];
-            loss += dx * dx + dy * dy + dz * dz;
-            wrench_add_point(w, x, y, z, 2.f * dx, 2.f * dy, 2.f * dz);
-            if (write) {
-                so.st[e] = x;
-                so.st[so.ns + e] = y;
-                so.st[2 * so.ns + e] = z;
-            }
+            atom_mse(x, y, z, aloc + at.slot, sg, so, write, w, loss);
         }
     }
 }
@@ -646,9 +667,10 @@ __global__ __launch_bounds__(LB) void fa_forward_flat_kernel(
 // the derivative of sum g.r over the atoms a rotation about the axis u
 // through o moves is u . (m - o x g) = u . m - v . g with v = u x o, summed
 // over the wrenches (g, m) of the atom groups it moves.  It is linear in the
-// wrench, so each group's wrench is folded into c as soon as the walk has it
-// (nothing per group is kept), and the wrench S of everything after the
-// residue enters later as c + u . S.m - v . S.g.  7 floats per axis.
+// wrench, so the wrenches of the residue's groups an axis moves are summed
+// and folded into c once the residue is walked, and the wrench S of
+// everything after the residue enters later as c + u . S.m - v . S.g.
+// 7 floats per axis.
 struct NodeGrad {
     float c, u0, u1, u2, v0, v1, v2;
 };

@@ -185,9 +185,9 @@ def test_fullatom_backbone_matches_backbone_model():
 @pytest.mark.parametrize("mode", ["coords", "recompute"])
 def test_nan_stays_in_its_chain(mode):
     """A NaN chi1 poisons only its own residue's side chain; a NaN phi poisons
-    its chain from that residue's CA on (CA does not depend on phi, but it is
-    emitted through the residue frame phi rotates, and NaN * 0 is NaN); other
-    chains (packed in the same tile) stay finite, forward and adjoint."""
+    its chain from that residue's CA frame on (the CA atom, at the origin of
+    the frame phi rotates, is not checked); other chains (packed in the same
+    tile) stay finite, forward and adjoint."""
     a2c = _a2c()
     off, seq, ang = _batch([50, 60, 70, 40], 113)
     info = oracle.load_residue_table()[1]
