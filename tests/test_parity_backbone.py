@@ -153,6 +153,37 @@ def test_whole_chain_windows(case, mode):
     assert np.array_equal(x1, x2) and np.array_equal(g1, g2)
 
 
+def window_order_lengths(n_win, cap):
+    """Chains filling exactly n_win fixed windows of cap residues: the first
+    crosses several windows (so the windows cannot hold whole chains), the
+    others end inside windows."""
+    R = cap * n_win - 37
+    first = min(R, 3 * cap + 11)
+    rest = R - first
+    lengths = [first] + ([rest // 3, rest - 2 * (rest // 3), rest // 3] if rest > 0 else [])
+    assert sum(lengths) == R and window_counts(lengths, cap)[1] == n_win
+    return lengths
+
+
+@pytest.mark.parametrize("n_win", [2, 7, 8, 9, 16, 17])
+def test_adjoint_window_order(n_win):
+    """The adjoint from coordinates takes fixed windows last to first within
+    each class of window index mod 8: window counts around multiples of 8,
+    with a chain crossing several windows; a repeat gives the same bits."""
+    a2c = _a2c()
+    K, W = 2, 1
+    lengths = window_order_lengths(n_win, 64 * K * W)
+    assert not uses_whole_chains(lengths, 64 * K * W)
+    off, ang, g = _batch(lengths, 37 + n_win)
+    plan = a2c.Plan("backbone", offsets=off)
+    plan.set_schedule(K, W)
+    assert plan.schedule["n_tiles"] == n_win
+    _check(plan, off, ang, g, mode="coords", label=f"{n_win} windows")
+    x1, g1 = run_backbone(plan, ang, g, mode="coords")
+    x2, g2 = run_backbone(plan, ang, g, mode="coords")
+    assert np.array_equal(x1, x2) and np.array_equal(g1, g2)
+
+
 @pytest.mark.parametrize("n_chains", [60, 700])
 @pytest.mark.parametrize("mode", ["coords", "recompute"])
 def test_chains_that_pack_badly(n_chains, mode):

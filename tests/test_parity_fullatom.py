@@ -79,6 +79,23 @@ def test_whole_chain_windows(K, W, mode):
     _check(plan, off, seq, ang, mode, label=f"whole chains K={K} W={W}")
 
 
+@pytest.mark.parametrize("n_win", [2, 7, 8, 9, 17])
+@pytest.mark.parametrize("mode", ["coords", "recompute"])
+def test_adjoint_window_order(n_win, mode):
+    """The full-atom adjoints take fixed windows last to first within each
+    class of window index mod 8: window counts around multiples of 8, with a
+    chain crossing several windows."""
+    from tests.test_parity_backbone import window_order_lengths
+    a2c = _a2c()
+    K, W = 2, 1
+    lengths = window_order_lengths(n_win, 64 * K * W)
+    off, seq, ang = _batch(lengths, 41 + n_win)
+    plan = a2c.Plan("fullatom", offsets=off, seq=seq)
+    plan.set_schedule(K, W)
+    assert plan.schedule["n_tiles"] == n_win
+    _check(plan, off, seq, ang, mode, label=f"{n_win} windows")
+
+
 @pytest.mark.parametrize("fwd,adj", [((1, 16), (2, 16)), ((2, 4), (1, 1))])
 @pytest.mark.parametrize("mode", ["coords", "recompute"])
 def test_separate_forward_and_adjoint_schedules(fwd, adj, mode):
